@@ -1,0 +1,20 @@
+"""CPU oracle for the sum-factorized Q_p operators and their solvers.
+
+TEST INFRASTRUCTURE ONLY.  This package is the plain, slow, FP64 reference that
+the HIP library is checked against.  Only the test suite, the smoke check and the
+CPU-baseline leg of the benchmark may import it; the product path (the C-ABI
+library and its Python binding) never does, and shares no code with it.
+
+Contents:
+  quadrature  Gauss-Legendre / Gauss-Lobatto-Legendre rules, Lagrange basis (Section 3.1)
+  fem         dense element operators M, K(nu), alpha M + beta K(nu), their diagonal,
+              load vector, adjoint-gradient integrand (Section 3, Section 3.1)
+  solvers     Jacobi-PCG, FP32-inner iterative refinement, adjoint gradient
+              (Section 5, Section 5.3)
+
+Pins (tests/test_oracle_*.py) tie each part to closed forms and invariants;
+nothing here is "parity unpinned".
+"""
+from .quadrature import gauss_legendre, gll, lagrange_values, lagrange_derivs, legendre_p  # noqa: F401
+from .fem import Discretization, OP_MASS, OP_DIFFUSION, OP_HELMHOLTZ, op_coeffs  # noqa: F401
+from .solvers import pcg, ir_pcg, adjoint_gradient, objective  # noqa: F401

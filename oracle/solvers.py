@@ -1,0 +1,114 @@
+"""Oracle iterative solvers (test infrastructure).
+
+* Jacobi-preconditioned conjugate gradients (the Krylov solver of Section 5 for
+  the SPD mass / Poisson / Helmholtz sub-problems of Section 5.3), with the
+  preconditioner taken as the exact diagonal of the constrained operator.
+  Stopping test on the recursive residual, ||r||_2 <= rtol ||b||_2, x0 = 0 by
+  default (the relative-residual convention of Section 7.1).
+* Mixed-precision iterative refinement: residual in FP64, correction from an
+  FP32 Jacobi-PCG (vectors and operator in float32, dot products accumulated in
+  float64), x += ||r|| d in FP64.
+* Adjoint gradient of J(nu) = 0.5 ||u(nu) - u_t||^2 with A(nu) u = b:
+  lambda solves A lambda = u - u_t (A is symmetric), and
+  dJ/dnu_{e,Q} = -lambda^T (dA/dnu_{e,Q}) u, the pointwise integrand of
+  Discretization.grad_nu.  K is linear in nu through the quadrature-point factor of
+  Section 3.1, which gives that derivative.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def pcg(apply, b, dinv, rtol=1e-10, maxit=10000, x0=None, dtype=np.float64, dot_dtype=np.float64):
+    """Jacobi-PCG.  Returns (x, iters, rel_res_recursive).  ``apply`` maps a vector to A v."""
+    b = np.asarray(b, dtype=dtype)
+    dinv = np.asarray(dinv, dtype=dtype)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=dtype, copy=True)
+
+    def dot(u, v):
+        return float(np.dot(u.astype(dot_dtype), v.astype(dot_dtype)))
+
+    bnorm = np.sqrt(dot(b, b))
+    if bnorm == 0.0:
+        return np.zeros_like(b), 0, 0.0
+    r = b - apply(x) if x0 is not None else b.copy()
+    z = (dinv * r).astype(dtype)
+    p = z.copy()
+    rho = dot(r, z)
+    rr = dot(r, r)
+    it = 0
+    while np.sqrt(rr) > rtol * bnorm and it < maxit:
+        w = apply(p)
+        pw = dot(p, w)
+        if not pw > 0.0:
+            raise FloatingPointError("CG breakdown: p^T A p <= 0")
+        alpha = rho / pw
+        x = (x + dtype(alpha) * p).astype(dtype)
+        r = (r - dtype(alpha) * w).astype(dtype)
+        z = (dinv * r).astype(dtype)
+        rho_new = dot(r, z)
+        rr = dot(r, r)
+        beta = rho_new / rho
+        rho = rho_new
+        p = (z + dtype(beta) * p).astype(dtype)
+        it += 1
+    return x, it, np.sqrt(rr) / bnorm
+
+
+def ir_pcg(apply64, apply32, dinv32, b, rtol=1e-10, inner_rtol=1e-5, max_outer=20, inner_maxit=10000):
+    """FP64 iterative refinement around an FP32 Jacobi-PCG.
+
+    Returns (x, outer_iters, total_inner_iters, true_rel_res).
+    """
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b)
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0:
+        return x, 0, 0, 0.0
+    inner_total = 0
+    outer = 0
+    r = b.copy()
+    rnorm = bnorm
+    while rnorm > rtol * bnorm and outer < max_outer:
+        rs = (r / rnorm).astype(np.float32)
+        d, it, _ = pcg(apply32, rs, dinv32, rtol=inner_rtol, maxit=inner_maxit,
+                       dtype=np.float32, dot_dtype=np.float64)
+        inner_total += it
+        x = x + rnorm * d.astype(np.float64)
+        r = b - apply64(x)
+        rnorm = np.linalg.norm(r)
+        outer += 1
+    return x, outer, inner_total, rnorm / bnorm
+
+
+def adjoint_gradient(disc, nu, b, u_target, alpha, beta, rtol=1e-12, direct=False):
+    """J(nu) and dJ/dnu [NE, Q] for J = 0.5 ||u - u_t||^2, A(nu) u = b (constrained Helmholtz)."""
+    if direct:
+        import scipy.sparse.linalg as spla
+        A = disc.assemble(alpha, beta, nu).tocsc()
+        lu = spla.splu(A)
+        solve = lu.solve
+    else:
+        dinv = 1.0 / disc.diagonal(alpha, beta, nu)
+
+        def solve(rhs):
+            return pcg(lambda v: disc.apply(v, alpha, beta, nu), rhs, dinv, rtol=rtol)[0]
+    u = solve(b)
+    res = u - u_target
+    res[disc.ess] = 0.0
+    J = 0.5 * float(res @ res)
+    lam = solve(res)
+    return J, disc.grad_nu(u, lam, beta), u, lam
+
+
+def objective(disc, nu, b, u_target, alpha, beta, rtol=1e-13, direct=False):
+    """J(nu) alone (for finite differences)."""
+    if direct:
+        import scipy.sparse.linalg as spla
+        u = spla.spsolve(disc.assemble(alpha, beta, nu).tocsc(), b)
+    else:
+        dinv = 1.0 / disc.diagonal(alpha, beta, nu)
+        u = pcg(lambda v: disc.apply(v, alpha, beta, nu), b, dinv, rtol=rtol)[0]
+    res = u - u_target
+    res[disc.ess] = 0.0
+    return 0.5 * float(res @ res)
