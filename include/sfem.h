@@ -1,0 +1,187 @@
+/*
+ * sfem.h -- C ABI of the MI355X (gfx950) library for matrix-free, sum-factorized
+ * high-order hexahedral Q_p operators and the Jacobi-preconditioned CG that drives
+ * the Poisson and Helmholtz solves of a projection step.
+ *
+ * The operations follow the method's statement of the problem:
+ *   - mesh + order -> setup that stores the geometric factors at quadrature
+ *     points (Section 3.1, after eq. tensorGradient: setup O(p^d), the Jacobian
+ *     kept at quadrature points);
+ *   - operator action of the mass, diffusion and Helmholtz operators
+ *     (eq. vectorMass, eq. vectorDiffusion, eq. localStiffnessMapped, the
+ *     Helmholtz combination A = c M + L of Section 5.2 and eq. proj-helmholtz),
+ *     evaluated by sum factorization (eq. sumFactorized, eq. B1D, eq. D1D,
+ *     eq. tensorGradient, L^K = G^T W G);
+ *   - the exact diagonal of the assembled operator (Jacobi preconditioner);
+ *   - Jacobi-PCG to a relative residual tolerance (Section 5, Section 5.3,
+ *     the residual convention of Section 7.1), optionally with an FP32 inner
+ *     solve inside FP64 iterative refinement;
+ *   - the adjoint gradient of an objective with respect to a per-quadrature-point
+ *     coefficient nu (K depends linearly on nu through the factor W of Section 3.1).
+ *
+ * Conventions shared by every call:
+ *   - Array arguments are DEVICE pointers owned by the caller, on the context's
+ *     device, contiguous, unless stated otherwise.  The library never keeps or frees
+ *     a caller pointer after a call returns; what it needs later it copies.
+ *   - All device work is enqueued on the context's stream (sfem_create /
+ *     sfem_set_stream).  apply, diagonal, load, grad_nu, qpoint_coords and
+ *     set_coeffs are asynchronous with respect to the host.  setup synchronizes
+ *     (it validates the mesh on the host); pcg synchronizes at its convergence
+ *     checks and at exit.
+ *   - No exception crosses the ABI.  Every call returns an sfem_status: 0 on
+ *     success, negative on error (sfem_last_error(ctx) describes it), and the
+ *     positive SFEM_NOCONV warning from pcg.  On error the output arrays are
+ *     unspecified.  A context is not thread-safe; distinct contexts are independent.
+ *   - Element geometry: trilinear hexahedra, vertex v = i + 2j + 4k at reference
+ *     corner (2i-1, 2j-1, 2k-1).  Element DoFs: local l = i + n (j + n k), n = p + 1,
+ *     i along xi_1 (GLL nodes).  Quadrature: Gauss-Legendre, q points per direction,
+ *     point index a + q (b + q c); only q = p + 2 is built.
+ *   - Essential (Dirichlet) DoFs: the operator is the constrained one,
+ *     A_c = P A P + (I - P) with P zeroing essential DoFs, so (A_c x)_i = x_i and
+ *     diag_i = 1 on them.  For homogeneous data the caller passes b_i = 0 there.
+ *   - Batched vectors are [nbatch][ndof] (member-major).  Per-quadrature-point
+ *     fields are [nfield][nelem][q^3] in the caller's element order.
+ */
+#ifndef SFEM_H
+#define SFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SFEM_ABI_VERSION 1
+#define SFEM_MAX_P 8
+
+typedef struct sfem_ctx sfem_ctx;
+
+typedef enum {
+  SFEM_OK = 0,
+  SFEM_NOCONV = 1,         /* warning: maxit reached; x holds the last iterate, info is filled */
+  SFEM_E_ARG = -1,         /* invalid argument (null pointer, bad size, bad enum, aliasing) */
+  SFEM_E_MESH = -2,        /* invalid mesh: det J <= 0 at a quadrature point, bad DoF map */
+  SFEM_E_HIP = -3,         /* a HIP runtime call or kernel launch failed */
+  SFEM_E_NOMEM = -4,       /* device or host allocation failed */
+  SFEM_E_UNSUPPORTED = -5, /* (p, q) not instantiated (p in 1..8, q = p + 2 only) */
+  SFEM_E_NAN = -6,         /* non-finite value met in a solve */
+  SFEM_E_BREAKDOWN = -7,   /* CG breakdown: p^T A p <= 0 (operator not SPD) */
+  SFEM_E_STATE = -8        /* call out of order (e.g. apply before setup) */
+} sfem_status;
+
+typedef enum { SFEM_F64 = 0, SFEM_F32 = 1 } sfem_prec;
+
+/* Operator kinds.  MASS: y = M x.  DIFFUSION: y = K(nu) x.  HELMHOLTZ:
+ * y = alpha M x + beta K(nu) x with alpha, beta, nu from sfem_set_coeffs. */
+typedef enum { SFEM_MASS = 0, SFEM_DIFFUSION = 1, SFEM_HELMHOLTZ = 2 } sfem_op;
+
+/* Library ABI version (SFEM_ABI_VERSION). */
+int sfem_abi_version(void);
+
+/* Create a context on HIP device `device` whose work goes to `stream` (a
+ * hipStream_t; NULL = the default stream).  *out receives a library-owned handle,
+ * released by sfem_destroy.  On failure *out is NULL and sfem_last_error(NULL)
+ * holds the message. */
+sfem_status sfem_create(int device, void *stream, sfem_ctx **out);
+
+/* Release every device and host resource of the context.  NULL is a no-op.
+ * Waits for the context's stream to finish. */
+void sfem_destroy(sfem_ctx *ctx);
+
+/* Change the stream later calls enqueue on. */
+sfem_status sfem_set_stream(sfem_ctx *ctx, void *stream);
+
+/* Message of the last error on ctx (ctx = NULL: of the last failed sfem_create in
+ * this process).  The string is owned by the library, valid until the next call. */
+const char *sfem_last_error(const sfem_ctx *ctx);
+
+/* Mesh + order setup (Section 3.1: geometric factors stored at quadrature points).
+ *   p          polynomial order, 1..SFEM_MAX_P;  q: Gauss points per direction (= p + 2)
+ *   nelem      number of hexahedra (>= 0)
+ *   elem_xyz   [nelem][8][3] float64 vertex coordinates (device)
+ *   elem_dofs  [nelem][(p+1)^3] int32 global DoF of each local node (device);
+ *              values in [0, ndof), no DoF twice in one element, every DoF used
+ *   ndof       number of global DoFs (< 2^30)
+ *   ess_mask   [ndof] uint8, nonzero = essential DoF (device), or NULL (none)
+ * Computes per quadrature point w|J| and w|J| J^{-1} J^{-T} (FP64), colors the
+ * elements so that no two elements of one color share a DoF, and resets the
+ * coefficients to alpha = 1, beta = 1, nu = 1.  Returns SFEM_E_MESH if some
+ * det J <= 0 or the map is invalid.  May be called again to replace the mesh. */
+sfem_status sfem_setup(sfem_ctx *ctx, int p, int q, int64_t nelem, const double *elem_xyz,
+                       const int32_t *elem_dofs, int64_t ndof, const uint8_t *ess_mask);
+
+/* Physical coordinates of every quadrature point: xq[3][nelem * q^3] (device,
+ * float64), element order of the caller. */
+sfem_status sfem_qpoint_coords(sfem_ctx *ctx, double *xq);
+
+/* Helmholtz coefficients A = alpha M + beta K(nu) (Section 5.2, eq. proj-helmholtz).
+ *   nu_q       [nbatch_nu][nelem * q^3] float64 per-quadrature-point viscosity
+ *              (device, copied), or NULL for nu = 1
+ *   nbatch_nu  number of nu fields (>= 1); with more than one field, a batched
+ *              apply / solve must use nbatch == nbatch_nu and member m uses field m
+ * Recomputes the folded quadrature data and the operator diagonals. */
+sfem_status sfem_set_coeffs(sfem_ctx *ctx, double alpha, double beta, const double *nu_q,
+                            int nbatch_nu);
+
+/* y = A x for nbatch vectors.  x, y: [nbatch][ndof] of float64 (SFEM_F64) or
+ * float32 (SFEM_F32), device, not aliased.  FP32 uses float32 copies of the 1D
+ * tables and the quadrature data rounded from FP64. */
+sfem_status sfem_apply(sfem_ctx *ctx, int op, int prec, int nbatch, const void *x, void *y);
+
+/* Exact diagonal of the constrained assembled operator (1 on essential DoFs).
+ * diag: [nfield][ndof] with nfield = 1 for MASS (and when nu is NULL), otherwise
+ * the number of nu fields; float64 or float32 per prec (device). */
+sfem_status sfem_diagonal(sfem_ctx *ctx, int op, int prec, void *diag);
+
+/* Load vector b_i = sum_e sum_q w|J| f_q phi_i for nbatch sources,
+ * f_q: [nbatch][nelem * q^3] float64, b: [nbatch][ndof] float64 (device);
+ * essential entries of b are set to 0. */
+sfem_status sfem_load(sfem_ctx *ctx, int nbatch, const double *f_q, double *b);
+
+typedef struct {
+  double rtol;       /* stop when ||r||_2 <= rtol ||b||_2, per batch member */
+  int maxit;         /* iteration cap (mode 1: cap on the total inner iterations) */
+  int mode;          /* 0: FP64 Jacobi-PCG; 1: FP32 inner Jacobi-PCG inside FP64 iterative refinement */
+  double inner_rtol; /* mode 1: relative tolerance of each inner solve (e.g. 1e-5) */
+  int max_outer;     /* mode 1: cap on refinement steps */
+  int check_every;   /* iterations between host convergence checks (>= 1) */
+  int x0_zero;       /* nonzero: ignore x on entry and start from x = 0 */
+} sfem_pcg_opts;
+
+typedef struct {
+  int iters;           /* CG iterations (mode 1: total inner iterations) */
+  int outer;           /* mode 1: refinement steps; mode 0: 0 */
+  double rel_res;      /* last recursive (mode 0) or true (mode 1) ||r|| / ||b|| */
+  double true_rel_res; /* ||b - A_c x|| / ||b|| recomputed in FP64 at exit */
+  int status;          /* per-member sfem_status */
+} sfem_pcg_info;
+
+/* Solve A x = b for nbatch right-hand sides by Jacobi-PCG (preconditioner: the
+ * exact operator diagonal).  b: [nbatch][ndof] float64; x: [nbatch][ndof]
+ * float64, initial guess on entry (unless opts->x0_zero), solution on exit.
+ * info: host array of nbatch entries (may be NULL).  Returns SFEM_OK when every
+ * member converged, SFEM_NOCONV if some did not (x = last iterate), or an error. */
+sfem_status sfem_pcg(sfem_ctx *ctx, int op, int nbatch, const double *b, double *x,
+                     const sfem_pcg_opts *opts, sfem_pcg_info *info);
+
+/* Adjoint gradient integrand for a per-quadrature-point nu:
+ *   g_q = -beta * w|J| (J^{-T} grad lam) . (J^{-T} grad u)
+ * so that dJ/dnu_q = g_q when A(nu) u = b and A lam = dJ/du.
+ * u, lam: [nbatch][ndof] float64; g: [nbatch][nelem * q^3] float64 (device). */
+sfem_status sfem_grad_nu(sfem_ctx *ctx, int nbatch, const double *u, const double *lam, double *g);
+
+typedef struct {
+  int p, q;
+  int64_t nelem, ndof;
+  int ncolors;
+  int nfields;            /* nu fields set by sfem_set_coeffs (1 when nu is NULL) */
+  int64_t device_bytes;   /* device memory held by the context */
+} sfem_ctx_info;
+
+/* Sizes and counters of a set-up context (host struct). */
+sfem_status sfem_get_info(const sfem_ctx *ctx, sfem_ctx_info *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFEM_H */

@@ -1,0 +1,198 @@
+"""MI355X (gfx950) library for matrix-free, sum-factorized high-order hexahedral operators.
+
+Python binding of the C ABI in ``include/sfem.h``: argument marshalling only.
+Every step of the apply, diagonal, load, gradient and PCG runs in the HIP kernels
+of ``libsfem.so``; PyTorch provides device memory and the stream.  If the library
+is missing the import of this package still works, but creating an Operator raises
+ImportError -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch  # loads the HIP runtime the library binds to
+
+from . import _lib
+from ._lib import F32, F64, MASS, DIFFUSION, HELMHOLTZ, SfemError, PcgOpts, PcgInfo, CtxInfo  # noqa: F401
+
+__all__ = ["Operator", "SfemError", "MASS", "DIFFUSION", "HELMHOLTZ", "F64", "F32", "PcgResult"]
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else None
+
+
+class PcgResult:
+    """Per-member solver outcome (iterations, refinement steps, residuals, status)."""
+
+    def __init__(self, infos, status):
+        self.status = status
+        self.iters = [i.iters for i in infos]
+        self.outer = [i.outer for i in infos]
+        self.rel_res = [i.rel_res for i in infos]
+        self.true_rel_res = [i.true_rel_res for i in infos]
+        self.member_status = [i.status for i in infos]
+
+    @property
+    def converged(self):
+        return self.status == _lib.SFEM_OK
+
+    def __repr__(self):
+        return (f"PcgResult(status={_lib.STATUS_NAMES.get(self.status)}, iters={self.iters}, "
+                f"outer={self.outer}, true_rel_res={self.true_rel_res})")
+
+
+class Operator:
+    """A set-up context: mesh + order p, quadrature data, coefficients.
+
+    elem_xyz  [nelem, 8, 3] float64, elem_dofs [nelem, (p+1)^3] int32 (any array-likes;
+    moved to the GPU), ndof, p, ess [ndof] (nonzero = essential) or None.
+    """
+
+    def __init__(self, elem_xyz, elem_dofs, ndof, p, ess=None, q=None, device=None):
+        self._lib = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the sfem library runs on MI355X (gfx950) only")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.p = int(p)
+        self.q = self.p + 2 if q is None else int(q)
+        self.ndof = int(ndof)
+        dev = self.device
+        xyz = torch.as_tensor(elem_xyz, dtype=torch.float64).to(dev).contiguous()
+        dofs = torch.as_tensor(elem_dofs, dtype=torch.int32).to(dev).contiguous()
+        self.nelem = int(xyz.shape[0]) if xyz.ndim == 3 else 0
+        essd = None
+        if ess is not None:
+            essd = torch.as_tensor(ess).to(dev).to(torch.uint8).contiguous()
+        h = C.c_void_p()
+        with torch.cuda.device(dev):
+            st = self._lib.sfem_create(dev.index, C.c_void_p(torch.cuda.current_stream(dev).cuda_stream),
+                                       C.byref(h))
+        if st != 0:
+            raise SfemError(st, self._lib.sfem_last_error(None).decode())
+        self._h = h
+        self._check(self._lib.sfem_setup(h, self.p, self.q, self.nelem, _ptr(xyz), _ptr(dofs),
+                                         self.ndof, _ptr(essd)))
+        self.nq = self.nelem * self.q ** 3
+        self.nfields = 1
+
+    # ---------------------------------------------------------------- plumbing
+    def _check(self, st):
+        if st < 0:
+            raise SfemError(st, self._lib.sfem_last_error(self._h).decode())
+        return st
+
+    def _sync_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        self._lib.sfem_set_stream(self._h, C.c_void_p(s))
+
+    def _vec(self, t, dtype, name):
+        if not isinstance(t, torch.Tensor):
+            t = torch.as_tensor(t)
+        t = t.to(device=self.device, dtype=dtype).contiguous()
+        if t.shape[-1] != self.ndof:
+            raise ValueError(f"{name}: last dimension must be ndof={self.ndof}")
+        return t
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sfem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        ci = CtxInfo()
+        self._check(self._lib.sfem_get_info(self._h, C.byref(ci)))
+        return {k: getattr(ci, k) for k, _ in CtxInfo._fields_}
+
+    # ---------------------------------------------------------------- operations
+    def qpoint_coords(self):
+        """Physical quadrature-point coordinates [3, nelem * q^3] (float64)."""
+        self._sync_stream()
+        out = torch.empty(3, self.nq, dtype=torch.float64, device=self.device)
+        self._check(self._lib.sfem_qpoint_coords(self._h, _ptr(out)))
+        return out
+
+    def set_coeffs(self, alpha, beta, nu=None):
+        """A = alpha M + beta K(nu); nu: [nelem, q^3], [nelem * q^3] or [nfield, nelem * q^3]."""
+        self._sync_stream()
+        nf = 1
+        nud = None
+        if nu is not None:
+            nud = torch.as_tensor(nu).to(device=self.device, dtype=torch.float64).contiguous()
+            if nud.numel() % self.nq != 0 or nud.numel() == 0:
+                raise ValueError("nu must hold nelem * q^3 values per field")
+            nf = nud.numel() // self.nq
+        self._check(self._lib.sfem_set_coeffs(self._h, float(alpha), float(beta), _ptr(nud), nf))
+        self.nfields = nf
+        self.alpha, self.beta = float(alpha), float(beta)
+
+    def apply(self, x, op=HELMHOLTZ, out=None):
+        """y = A x; x float64 or float32, shape [ndof] or [nbatch, ndof]."""
+        self._sync_stream()
+        dtype = x.dtype if isinstance(x, torch.Tensor) and x.dtype in (torch.float32, torch.float64) \
+            else torch.float64
+        xv = self._vec(x, dtype, "x")
+        nb = 1 if xv.ndim == 1 else xv.shape[0]
+        y = torch.empty_like(xv) if out is None else out
+        aliased = xv.numel() > 0 and y.data_ptr() == xv.data_ptr()
+        if y.dtype != dtype or not y.is_contiguous() or y.shape != xv.shape or aliased:
+            raise ValueError("out must be a distinct contiguous tensor of x's shape and dtype")
+        prec = F32 if dtype == torch.float32 else F64
+        self._check(self._lib.sfem_apply(self._h, op, prec, nb, _ptr(xv), _ptr(y)))
+        return y
+
+    def diagonal(self, op=HELMHOLTZ, dtype=torch.float64):
+        """Exact diagonal of the constrained operator: [ndof] or [nfield, ndof]."""
+        self._sync_stream()
+        nf = 1 if op == MASS else self.nfields
+        d = torch.empty(nf, self.ndof, dtype=dtype, device=self.device)
+        prec = F32 if dtype == torch.float32 else F64
+        self._check(self._lib.sfem_diagonal(self._h, op, prec, _ptr(d)))
+        return d[0] if nf == 1 else d
+
+    def load(self, f_q):
+        """b = sum_q w|J| f_q phi (essential entries 0); f_q [nelem*q^3] or [nb, nelem*q^3]."""
+        self._sync_stream()
+        f = torch.as_tensor(f_q).to(device=self.device, dtype=torch.float64).contiguous()
+        nb = 1 if f.numel() == self.nq else f.numel() // self.nq
+        if f.numel() != nb * self.nq:
+            raise ValueError("f_q must hold nelem * q^3 values per source")
+        b = torch.empty(nb, self.ndof, dtype=torch.float64, device=self.device)
+        self._check(self._lib.sfem_load(self._h, nb, _ptr(f), _ptr(b)))
+        return b[0] if nb == 1 and f.ndim <= 1 else b
+
+    def grad_nu(self, u, lam):
+        """-beta (Gq grad lam).grad u per quadrature point: [nbatch, nelem * q^3] (or 1-D)."""
+        self._sync_stream()
+        uu = self._vec(u, torch.float64, "u")
+        ll = self._vec(lam, torch.float64, "lam")
+        if uu.shape != ll.shape:
+            raise ValueError("u and lam must have the same shape")
+        nb = 1 if uu.ndim == 1 else uu.shape[0]
+        g = torch.empty(nb, self.nq, dtype=torch.float64, device=self.device)
+        self._check(self._lib.sfem_grad_nu(self._h, nb, _ptr(uu), _ptr(ll), _ptr(g)))
+        return g[0] if uu.ndim == 1 else g
+
+    def pcg(self, b, x=None, op=HELMHOLTZ, rtol=1e-10, maxit=10000, mode=0, inner_rtol=1e-5,
+            max_outer=30, check_every=8):
+        """Jacobi-PCG (mode 0) or FP32-inner PCG inside FP64 refinement (mode 1).
+
+        Returns (x, PcgResult).  Raises SfemError on errors; a non-converged solve
+        returns the last iterate with status SFEM_NOCONV.
+        """
+        self._sync_stream()
+        bv = self._vec(b, torch.float64, "b")
+        nb = 1 if bv.ndim == 1 else bv.shape[0]
+        x0_zero = x is None
+        xv = torch.empty_like(bv) if x0_zero else self._vec(x, torch.float64, "x").clone()
+        opts = PcgOpts(float(rtol), int(maxit), int(mode), float(inner_rtol), int(max_outer),
+                       int(check_every), 1 if x0_zero else 0)
+        infos = (PcgInfo * nb)()
+        st = self._check(self._lib.sfem_pcg(self._h, op, nb, _ptr(bv), _ptr(xv), C.byref(opts), infos))
+        return xv, PcgResult(list(infos), st)

@@ -1,0 +1,851 @@
+// C ABI of the sfem library: context, mesh setup (coloring, scatter flags, geometric
+// factors), operator apply / diagonal / load / adjoint gradient dispatch, and the
+// Jacobi-PCG and FP32-inner iterative-refinement drivers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace sfem;
+
+namespace {
+
+std::string g_create_error;  // message of the last failed sfem_create
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct sfem_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // ---- mesh
+  bool ready = false;
+  int p = 0, q = 0;
+  int64_t nelem = 0, ndof = 0;
+  int ncolors = 0;
+  std::vector<int64_t> color_off;  // [ncolors + 1], internal element order
+  Rules1D rules;
+  int32_t *d_map = nullptr;        // [nelem][n^3] flagged
+  int32_t *d_perm = nullptr;       // internal -> caller element id
+  double *d_xyz = nullptr;         // [nelem][8][3] internal order
+  double *d_qd = nullptr;          // [nelem][7][q^3]
+  float *d_qd32 = nullptr;
+
+  // ---- coefficients
+  double alpha = 1.0, beta = 1.0;
+  int nfield = 1;
+  bool has_nu = false;
+  double *d_fold64 = nullptr;  // [nfield][nelem][7][q^3]
+  float *d_fold32 = nullptr;
+  double *d_nu64 = nullptr;    // [nfield][nelem][q^3]
+  float *d_nu32 = nullptr;
+
+  // ---- diagonals per operator kind: [nf][ndof]
+  bool diag_ok[3] = {false, false, false};
+  double *d_diag[3] = {nullptr, nullptr, nullptr};
+  double *d_dinv[3] = {nullptr, nullptr, nullptr};
+  float *d_diag32[3] = {nullptr, nullptr, nullptr};
+  float *d_dinv32[3] = {nullptr, nullptr, nullptr};
+
+  // ---- solver workspace (grown on demand)
+  DevBuf ws;
+  void *h_pinned = nullptr;
+  size_t h_pinned_bytes = 0;
+
+  std::vector<DevBuf> owned;  // every device allocation of the mesh/coeff state
+  int64_t bytes = 0;
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+sfem_status fail(sfem_ctx *c, sfem_status st, const std::string &msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+#define HIPCHK(c, expr)                                                                   \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail((c), SFEM_E_HIP, std::string(#expr) + " failed: " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+sfem_status dalloc(sfem_ctx *c, T **out, int64_t count) {
+  *out = nullptr;
+  if (count <= 0) return SFEM_OK;
+  void *p = nullptr;
+  const size_t bytes = (size_t)count * sizeof(T);
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, SFEM_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  c->owned.push_back({p, bytes});
+  c->bytes += (int64_t)bytes;
+  *out = (T *)p;
+  return SFEM_OK;
+}
+
+void dfree(sfem_ctx *c, void *p) {
+  if (!p) return;
+  for (size_t i = 0; i < c->owned.size(); ++i) {
+    if (c->owned[i].p == p) {
+      c->bytes -= (int64_t)c->owned[i].bytes;
+      (void)hipFree(p);
+      c->owned.erase(c->owned.begin() + i);
+      return;
+    }
+  }
+}
+
+void free_coeffs(sfem_ctx *c) {
+  dfree(c, c->d_fold64);
+  dfree(c, c->d_fold32);
+  dfree(c, c->d_nu64);
+  dfree(c, c->d_nu32);
+  c->d_fold64 = nullptr;
+  c->d_fold32 = nullptr;
+  c->d_nu64 = nullptr;
+  c->d_nu32 = nullptr;
+  for (int o = 0; o < 3; ++o) {
+    dfree(c, c->d_diag[o]);
+    dfree(c, c->d_dinv[o]);
+    dfree(c, c->d_diag32[o]);
+    dfree(c, c->d_dinv32[o]);
+    c->d_diag[o] = c->d_dinv[o] = nullptr;
+    c->d_diag32[o] = c->d_dinv32[o] = nullptr;
+    c->diag_ok[o] = false;
+  }
+}
+
+void free_all(sfem_ctx *c) {
+  for (auto &b : c->owned) (void)hipFree(b.p);
+  c->owned.clear();
+  c->bytes = 0;
+  c->d_map = nullptr;
+  c->d_perm = nullptr;
+  c->d_xyz = nullptr;
+  c->d_qd = nullptr;
+  c->d_qd32 = nullptr;
+  c->d_fold64 = nullptr;
+  c->d_fold32 = nullptr;
+  c->d_nu64 = nullptr;
+  c->d_nu32 = nullptr;
+  for (int o = 0; o < 3; ++o) {
+    c->d_diag[o] = c->d_dinv[o] = nullptr;
+    c->d_diag32[o] = c->d_dinv32[o] = nullptr;
+    c->diag_ok[o] = false;
+  }
+  if (c->ws.p) (void)hipFree(c->ws.p);
+  c->ws = DevBuf{};
+  c->ready = false;
+}
+
+int64_t q3_of(const sfem_ctx *c) { return (int64_t)c->q * c->q * c->q; }
+
+// Number of coefficient fields an operator kind uses.
+int nfields_of(const sfem_ctx *c, int op) { return op == SFEM_MASS ? 1 : c->nfield; }
+
+sfem_status fold_coeffs(sfem_ctx *c, const double *nu_user, int nfield, double alpha,
+                        double beta) {
+  free_coeffs(c);
+  c->alpha = alpha;
+  c->beta = beta;
+  c->nfield = nfield;
+  c->has_nu = nu_user != nullptr;
+  const int64_t nq = c->nelem * q3_of(c);
+  sfem_status st;
+  if ((st = dalloc(c, &c->d_fold64, nq * kQdSlots * nfield)) != SFEM_OK) return st;
+  if ((st = dalloc(c, &c->d_fold32, nq * kQdSlots * nfield)) != SFEM_OK) return st;
+  if ((st = dalloc(c, &c->d_nu64, nq * nfield)) != SFEM_OK) return st;
+  if ((st = dalloc(c, &c->d_nu32, nq * nfield)) != SFEM_OK) return st;
+  HIPCHK(c, launch_fold(c->q, c->d_qd, nu_user, c->d_perm, c->nelem, nfield, alpha, beta,
+                        c->d_fold64, c->d_fold32, c->d_nu64, c->d_nu32, c->stream));
+  return SFEM_OK;
+}
+
+// Compute (lazily) the diagonal of operator kind op for every field.
+sfem_status ensure_diag(sfem_ctx *c, int op) {
+  if (c->diag_ok[op]) return SFEM_OK;
+  const int nf = nfields_of(c, op);
+  const int64_t n = c->ndof * nf;
+  sfem_status st;
+  if (!c->d_diag[op]) {
+    if ((st = dalloc(c, &c->d_diag[op], n)) != SFEM_OK) return st;
+    if ((st = dalloc(c, &c->d_dinv[op], n)) != SFEM_OK) return st;
+    if ((st = dalloc(c, &c->d_diag32[op], n)) != SFEM_OK) return st;
+    if ((st = dalloc(c, &c->d_dinv32[op], n)) != SFEM_OK) return st;
+  }
+  double a = 1.0, b = 0.0;
+  if (op == SFEM_DIFFUSION) {
+    a = 0.0;
+    b = 1.0;
+  } else if (op == SFEM_HELMHOLTZ) {
+    a = c->alpha;
+    b = c->beta;
+  }
+  for (int f = 0; f < nf; ++f) {
+    DiagArgs da;
+    da.p = c->p;
+    da.map = c->d_map;
+    da.qd = c->d_qd;
+    da.nu = (op != SFEM_MASS && c->has_nu) ? c->d_nu64 + (int64_t)f * c->nelem * q3_of(c) : nullptr;
+    da.alpha = a;
+    da.beta = b;
+    da.diag = c->d_diag[op] + (int64_t)f * c->ndof;
+    da.B = c->rules.B.data();
+    da.G = c->rules.G.data();
+    for (int col = 0; col < c->ncolors; ++col)
+      HIPCHK(c, launch_diag(da, c->color_off[col], c->color_off[col + 1], c->stream));
+  }
+  HIPCHK(c, VecOps<double>::recip(c->d_diag[op], c->d_dinv[op], n, c->stream));
+  HIPCHK(c, VecOps<float>::recip(c->d_diag[op], c->d_dinv32[op], n, c->stream));
+  HIPCHK(c, launch_cast_f32(c->d_diag[op], c->d_diag32[op], n, c->stream));
+  c->diag_ok[op] = true;
+  return SFEM_OK;
+}
+
+sfem_status check_op_batch(sfem_ctx *c, int op, int nbatch) {
+  if (op < 0 || op > 2) return fail(c, SFEM_E_ARG, "op must be SFEM_MASS, SFEM_DIFFUSION or SFEM_HELMHOLTZ");
+  if (nbatch < 0) return fail(c, SFEM_E_ARG, "nbatch must be >= 0");
+  if (op != SFEM_MASS && c->nfield > 1 && nbatch != c->nfield && nbatch != 0)
+    return fail(c, SFEM_E_ARG, "with " + std::to_string(c->nfield) +
+                                   " nu fields, nbatch must equal the number of fields");
+  return SFEM_OK;
+}
+
+// Enqueue y = A x on the context stream (no argument checks).
+sfem_status do_apply(sfem_ctx *c, int op, bool f32, int nbatch, const void *x, void *y) {
+  if (nbatch == 0 || c->ndof == 0) return SFEM_OK;
+  ApplyArgs a;
+  a.p = c->p;
+  a.op = op;
+  a.map = c->d_map;
+  a.ndof = c->ndof;
+  a.nbatch = nbatch;
+  a.x = x;
+  a.y = y;
+  a.B = c->rules.B.data();
+  a.G = c->rules.G.data();
+  a.nu = nullptr;
+  a.qd_mstride = 0;
+  a.nu_mstride = 0;
+  const int64_t nq = c->nelem * q3_of(c);
+  const bool per_member = c->nfield > 1;
+  if (op == SFEM_HELMHOLTZ) {
+    a.qd = f32 ? (const void *)c->d_fold32 : (const void *)c->d_fold64;
+    a.qd_mstride = per_member ? nq * kQdSlots : 0;
+  } else {
+    a.qd = f32 ? (const void *)c->d_qd32 : (const void *)c->d_qd;
+    if (op == SFEM_DIFFUSION && c->has_nu) {
+      a.nu = f32 ? (const void *)c->d_nu32 : (const void *)c->d_nu64;
+      a.nu_mstride = per_member ? nq : 0;
+    }
+  }
+  for (int col = 0; col < c->ncolors; ++col) {
+    const hipError_t e = f32 ? launch_apply_f32(a, c->color_off[col], c->color_off[col + 1], c->stream)
+                             : launch_apply_f64(a, c->color_off[col], c->color_off[col + 1], c->stream);
+    if (e != hipSuccess) return fail(c, SFEM_E_HIP, std::string("apply launch: ") + hipGetErrorString(e));
+  }
+  return SFEM_OK;
+}
+
+sfem_status ensure_ws(sfem_ctx *c, size_t bytes) {
+  if (c->ws.bytes >= bytes) return SFEM_OK;
+  if (c->ws.p) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    (void)hipFree(c->ws.p);
+    c->ws = DevBuf{};
+  }
+  void *p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, SFEM_E_NOMEM, "solver workspace allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  c->ws.p = p;
+  c->ws.bytes = bytes;
+  return SFEM_OK;
+}
+
+sfem_status ensure_pinned(sfem_ctx *c, size_t bytes) {
+  if (c->h_pinned_bytes >= bytes) return SFEM_OK;
+  if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+  c->h_pinned = nullptr;
+  c->h_pinned_bytes = 0;
+  HIPCHK(c, hipHostMalloc(&c->h_pinned, bytes, hipHostMallocDefault));
+  c->h_pinned_bytes = bytes;
+  return SFEM_OK;
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Carve a workspace into named pieces.
+struct Carver {
+  char *base;
+  size_t off = 0;
+  template <typename T>
+  T *take(int64_t count) {
+    T *p = (T *)(base + off);
+    off = align_up(off + (size_t)count * sizeof(T));
+    return p;
+  }
+};
+
+template <typename T>
+struct PcgWork {
+  T *r, *p, *w;
+  double *part;
+  PcgScalars *sc;
+  int nblk;
+};
+
+template <typename T>
+size_t pcg_work_bytes(int64_t n, int nb) {
+  const int nblk = vec_nblk(n);
+  return 3 * align_up((size_t)n * nb * sizeof(T)) + align_up((size_t)nb * 3 * nblk * sizeof(double)) +
+         align_up((size_t)nb * sizeof(PcgScalars));
+}
+
+template <typename T>
+PcgWork<T> carve_pcg(Carver &cv, int64_t n, int nb) {
+  PcgWork<T> w;
+  w.nblk = vec_nblk(n);
+  w.r = cv.take<T>(n * nb);
+  w.p = cv.take<T>(n * nb);
+  w.w = cv.take<T>(n * nb);
+  w.part = cv.take<double>((int64_t)nb * 3 * w.nblk);
+  w.sc = cv.take<PcgScalars>(nb);
+  return w;
+}
+
+// Jacobi-PCG on the context stream.  On return hs[] holds the final scalars.
+template <typename T>
+sfem_status run_pcg(sfem_ctx *c, int op, int nb, const T *b, T *x, bool x0_zero, double rtol,
+                    int maxit, int check_every, const T *dinv, int64_t dms, PcgWork<T> &w,
+                    PcgScalars *hs) {
+  const int64_t n = c->ndof;
+  const bool f32 = sizeof(T) == 4;
+  hipStream_t s = c->stream;
+  sfem_status st;
+  if (x0_zero) {
+    HIPCHK(c, VecOps<T>::start(b, nullptr, x, w.r, dinv, dms, w.p, w.part, w.nblk, n, nb, s));
+  } else {
+    if ((st = do_apply(c, op, f32, nb, x, w.w)) != SFEM_OK) return st;
+    HIPCHK(c, VecOps<T>::start(b, w.w, nullptr, w.r, dinv, dms, w.p, w.part, w.nblk, n, nb, s));
+  }
+  HIPCHK(c, launch_pcg_init(w.part, w.nblk, nb, rtol, w.sc, s));
+  auto all_done = [&]() -> sfem_status {
+    HIPCHK(c, hipMemcpyAsync(hs, w.sc, sizeof(PcgScalars) * nb, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return SFEM_OK;
+  };
+  if ((st = all_done()) != SFEM_OK) return st;
+  for (int m = 0; m < nb; ++m)  // b = 0: the solution is x = 0
+    if (hs[m].bb == 0.0 && !x0_zero) HIPCHK(c, VecOps<T>::fill(x + (int64_t)m * n, T(0), n, s));
+  auto any_active = [&]() {
+    for (int m = 0; m < nb; ++m)
+      if (hs[m].active) return true;
+    return false;
+  };
+  if (!any_active()) return SFEM_OK;
+  for (int it = 0; it < maxit; ++it) {
+    if ((st = do_apply(c, op, f32, nb, w.p, w.w)) != SFEM_OK) return st;
+    HIPCHK(c, VecOps<T>::dot(w.p, w.w, w.part, w.nblk, n, nb, s));
+    HIPCHK(c, launch_pcg_alpha(w.part, w.nblk, nb, w.sc, s));
+    HIPCHK(c, VecOps<T>::update(x, w.p, w.r, w.w, dinv, dms, w.sc, w.part, w.nblk, n, nb, s));
+    HIPCHK(c, launch_pcg_beta(w.part, w.nblk, nb, w.sc, s));
+    HIPCHK(c, VecOps<T>::newdir(w.r, dinv, dms, w.p, w.sc, n, nb, s));
+    if ((it + 1) % check_every == 0 || it + 1 == maxit) {
+      if ((st = all_done()) != SFEM_OK) return st;
+      if (!any_active()) break;
+    }
+  }
+  return SFEM_OK;
+}
+
+sfem_status require_ready(sfem_ctx *c) {
+  if (!c) return SFEM_E_ARG;
+  if (!c->ready) return fail(c, SFEM_E_STATE, "sfem_setup has not succeeded on this context");
+  return SFEM_OK;
+}
+
+}  // namespace
+
+// ===================================================================================
+extern "C" {
+
+int sfem_abi_version(void) { return SFEM_ABI_VERSION; }
+
+sfem_status sfem_create(int device, void *stream, sfem_ctx **out) {
+  if (!out) {
+    g_create_error = "out must not be NULL";
+    return SFEM_E_ARG;
+  }
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    g_create_error = "no HIP device available";
+    return SFEM_E_HIP;
+  }
+  if (device < 0 || device >= ndev) {
+    g_create_error = "device index out of range";
+    return SFEM_E_ARG;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    g_create_error = "hipGetDeviceProperties failed";
+    return SFEM_E_HIP;
+  }
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    g_create_error = std::string("device is ") + prop.gcnArchName + ", the library is built for gfx950";
+    return SFEM_E_UNSUPPORTED;
+  }
+  sfem_ctx *c = new (std::nothrow) sfem_ctx();
+  if (!c) {
+    g_create_error = "host allocation failed";
+    return SFEM_E_NOMEM;
+  }
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  *out = c;
+  return SFEM_OK;
+}
+
+void sfem_destroy(sfem_ctx *c) {
+  if (!c) return;
+  {
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+  }
+  delete c;
+}
+
+sfem_status sfem_set_stream(sfem_ctx *c, void *stream) {
+  if (!c) return SFEM_E_ARG;
+  c->stream = (hipStream_t)stream;
+  return SFEM_OK;
+}
+
+const char *sfem_last_error(const sfem_ctx *c) {
+  return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+sfem_status sfem_setup(sfem_ctx *c, int p, int q, int64_t nelem, const double *elem_xyz,
+                       const int32_t *elem_dofs, int64_t ndof, const uint8_t *ess_mask) {
+  if (!c) return SFEM_E_ARG;
+  DeviceGuard g(c->device);
+  if (p < 1 || p > SFEM_MAX_P || q != p + 2)
+    return fail(c, SFEM_E_UNSUPPORTED, "supported orders: p = 1..8 with q = p + 2");
+  if (nelem < 0 || ndof < 0 || ndof > kDofMask)
+    return fail(c, SFEM_E_ARG, "nelem must be >= 0 and 0 <= ndof < 2^30");
+  if (nelem > 0 && (!elem_xyz || !elem_dofs))
+    return fail(c, SFEM_E_ARG, "elem_xyz and elem_dofs must not be NULL");
+  if (nelem == 0 && ndof > 0)
+    return fail(c, SFEM_E_MESH, "DoFs without elements: every DoF must belong to an element");
+  const int n = p + 1;
+  const int64_t n3 = (int64_t)n * n * n;
+  if (nelem > (int64_t)INT32_MAX / 8 || nelem * n3 > ((int64_t)1 << 40))
+    return fail(c, SFEM_E_ARG, "mesh too large");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  free_all(c);
+
+  // ---- host copies
+  std::vector<double> xyz((size_t)nelem * 24);
+  std::vector<int32_t> dofs((size_t)(nelem * n3));
+  std::vector<uint8_t> ess((size_t)ndof, 0);
+  if (nelem > 0) {
+    HIPCHK(c, hipMemcpyAsync(xyz.data(), elem_xyz, xyz.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dofs.data(), elem_dofs, dofs.size() * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  }
+  if (ess_mask && ndof > 0)
+    HIPCHK(c, hipMemcpyAsync(ess.data(), ess_mask, (size_t)ndof, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+
+  // ---- validate the map: range, no repeated DoF inside an element, every DoF used
+  std::vector<int64_t> deg((size_t)ndof + 1, 0);
+  {
+    std::vector<int64_t> stamp((size_t)ndof, -1);
+    for (int64_t e = 0; e < nelem; ++e) {
+      for (int64_t l = 0; l < n3; ++l) {
+        const int32_t gd = dofs[(size_t)(e * n3 + l)];
+        if (gd < 0 || gd >= ndof)
+          return fail(c, SFEM_E_MESH, "elem_dofs[" + std::to_string(e) + "][" + std::to_string(l) +
+                                          "] = " + std::to_string(gd) + " is outside [0, ndof)");
+        if (stamp[gd] == e)
+          return fail(c, SFEM_E_MESH, "element " + std::to_string(e) + " references DoF " +
+                                          std::to_string(gd) + " twice");
+        stamp[gd] = e;
+        deg[gd]++;
+      }
+    }
+    for (int64_t gd = 0; gd < ndof; ++gd)
+      if (deg[gd] == 0)
+        return fail(c, SFEM_E_MESH, "DoF " + std::to_string(gd) + " belongs to no element");
+  }
+  // ---- DoF -> element incidence (CSR)
+  std::vector<int64_t> off((size_t)ndof + 1, 0);
+  for (int64_t gd = 0; gd < ndof; ++gd) off[gd + 1] = off[gd] + deg[gd];
+  std::vector<int32_t> inc((size_t)off[ndof]);
+  {
+    std::vector<int64_t> pos(off.begin(), off.end() - 1);
+    for (int64_t e = 0; e < nelem; ++e)
+      for (int64_t l = 0; l < n3; ++l) inc[(size_t)pos[dofs[(size_t)(e * n3 + l)]]++] = (int32_t)e;
+  }
+  // ---- greedy coloring in element order: no two elements sharing a DoF get one color
+  constexpr int kMaxColors = 64;
+  std::vector<int> color((size_t)nelem, -1);
+  int ncolors = 0;
+  {
+    std::vector<int64_t> used(kMaxColors, -1);
+    for (int64_t e = 0; e < nelem; ++e) {
+      for (int64_t l = 0; l < n3; ++l) {
+        const int32_t gd = dofs[(size_t)(e * n3 + l)];
+        for (int64_t k = off[gd]; k < off[gd + 1]; ++k) {
+          const int32_t e2 = inc[(size_t)k];
+          if (e2 < e) used[color[e2]] = e;
+        }
+      }
+      int col = 0;
+      while (col < kMaxColors && used[col] == e) ++col;
+      if (col == kMaxColors) return fail(c, SFEM_E_MESH, "element coloring needs more than 64 colors");
+      color[e] = col;
+      ncolors = std::max(ncolors, col + 1);
+    }
+  }
+  // ---- internal order: by color, stable in caller order
+  std::vector<int64_t> coff((size_t)ncolors + 1, 0);
+  for (int64_t e = 0; e < nelem; ++e) coff[color[e] + 1]++;
+  for (int col = 0; col < ncolors; ++col) coff[col + 1] += coff[col];
+  std::vector<int32_t> perm((size_t)nelem);
+  {
+    std::vector<int64_t> pos(coff.begin(), coff.end() - 1);
+    for (int64_t e = 0; e < nelem; ++e) perm[(size_t)pos[color[e]]++] = (int32_t)e;
+  }
+  // ---- first writer of each DoF = the (unique) element of the smallest color touching it
+  std::vector<int> firstc((size_t)ndof, kMaxColors);
+  for (int64_t gd = 0; gd < ndof; ++gd)
+    for (int64_t k = off[gd]; k < off[gd + 1]; ++k) firstc[gd] = std::min(firstc[gd], color[inc[(size_t)k]]);
+  std::vector<int32_t> imap((size_t)(nelem * n3));
+  std::vector<double> ixyz((size_t)nelem * 24);
+  for (int64_t s = 0; s < nelem; ++s) {
+    const int64_t e = perm[(size_t)s];
+    for (int64_t l = 0; l < n3; ++l) {
+      const int32_t gd = dofs[(size_t)(e * n3 + l)];
+      int32_t v = gd;
+      if (color[e] == firstc[gd]) v |= kFirstBit;
+      if (ess[gd]) v |= (int32_t)0x80000000u;
+      imap[(size_t)(s * n3 + l)] = v;
+    }
+    std::memcpy(&ixyz[(size_t)s * 24], &xyz[(size_t)e * 24], 24 * sizeof(double));
+  }
+
+  // ---- rules
+  if (!make_rules(p, q, c->rules)) return fail(c, SFEM_E_HIP, "1D rule construction failed");
+  c->p = p;
+  c->q = q;
+  c->nelem = nelem;
+  c->ndof = ndof;
+  c->ncolors = ncolors;
+  c->color_off = coff;
+
+  // ---- upload + geometric factors
+  sfem_status st;
+  const int64_t q3 = (int64_t)q * q * q;
+  if ((st = dalloc(c, &c->d_map, nelem * n3)) != SFEM_OK) return st;
+  if ((st = dalloc(c, &c->d_perm, nelem)) != SFEM_OK) return st;
+  if ((st = dalloc(c, &c->d_xyz, nelem * 24)) != SFEM_OK) return st;
+  if ((st = dalloc(c, &c->d_qd, nelem * q3 * kQdSlots)) != SFEM_OK) return st;
+  if ((st = dalloc(c, &c->d_qd32, nelem * q3 * kQdSlots)) != SFEM_OK) return st;
+  int *d_bad = nullptr;
+  if ((st = dalloc(c, &d_bad, 1)) != SFEM_OK) return st;
+  if (nelem > 0) {
+    HIPCHK(c, hipMemcpyAsync(c->d_map, imap.data(), imap.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_perm, perm.data(), perm.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_xyz, ixyz.data(), ixyz.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  }
+  int h_bad = 0;
+  if (d_bad) {
+    HIPCHK(c, VecOps<float>::fill((float *)d_bad, 0.0f, 1, c->stream));
+    HIPCHK(c, launch_qdata_setup(q, c->rules.gauss_x.data(), c->rules.gauss_w.data(), c->d_xyz,
+                                 nelem, c->d_qd, d_bad, c->stream));
+    HIPCHK(c, launch_cast_f32(c->d_qd, c->d_qd32, nelem * q3 * kQdSlots, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&h_bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  dfree(c, d_bad);
+  if (h_bad) {
+    free_all(c);
+    return fail(c, SFEM_E_MESH, "det J <= 0 (or not finite) at some quadrature point: inverted or degenerate element");
+  }
+  if ((st = fold_coeffs(c, nullptr, 1, 1.0, 1.0)) != SFEM_OK) return st;
+  c->ready = true;
+  return SFEM_OK;
+}
+
+sfem_status sfem_qpoint_coords(sfem_ctx *c, double *xq) {
+  sfem_status st = require_ready(c);
+  if (st != SFEM_OK) return st;
+  if (c->nelem > 0 && !xq) return fail(c, SFEM_E_ARG, "xq must not be NULL");
+  DeviceGuard g(c->device);
+  HIPCHK(c, launch_qpoint_coords(c->q, c->rules.gauss_x.data(), c->rules.gauss_w.data(), c->d_xyz,
+                                 c->d_perm, c->nelem, xq, c->stream));
+  return SFEM_OK;
+}
+
+sfem_status sfem_set_coeffs(sfem_ctx *c, double alpha, double beta, const double *nu_q, int nbatch_nu) {
+  sfem_status st = require_ready(c);
+  if (st != SFEM_OK) return st;
+  if (nbatch_nu < 1) return fail(c, SFEM_E_ARG, "nbatch_nu must be >= 1");
+  if (!nu_q && nbatch_nu != 1) return fail(c, SFEM_E_ARG, "nbatch_nu must be 1 when nu_q is NULL");
+  if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(c, SFEM_E_ARG, "alpha and beta must be finite");
+  DeviceGuard g(c->device);
+  return fold_coeffs(c, nu_q, nbatch_nu, alpha, beta);
+}
+
+sfem_status sfem_apply(sfem_ctx *c, int op, int prec, int nbatch, const void *x, void *y) {
+  sfem_status st = require_ready(c);
+  if (st != SFEM_OK) return st;
+  if ((st = check_op_batch(c, op, nbatch)) != SFEM_OK) return st;
+  if (prec != SFEM_F64 && prec != SFEM_F32) return fail(c, SFEM_E_ARG, "prec must be SFEM_F64 or SFEM_F32");
+  if (nbatch > 0 && c->ndof > 0) {
+    if (!x || !y) return fail(c, SFEM_E_ARG, "x and y must not be NULL");
+    if (x == y) return fail(c, SFEM_E_ARG, "x and y must not alias");
+  }
+  DeviceGuard g(c->device);
+  return do_apply(c, op, prec == SFEM_F32, nbatch, x, y);
+}
+
+sfem_status sfem_diagonal(sfem_ctx *c, int op, int prec, void *diag) {
+  sfem_status st = require_ready(c);
+  if (st != SFEM_OK) return st;
+  if ((st = check_op_batch(c, op, 0)) != SFEM_OK) return st;
+  if (prec != SFEM_F64 && prec != SFEM_F32) return fail(c, SFEM_E_ARG, "prec must be SFEM_F64 or SFEM_F32");
+  if (c->ndof > 0 && !diag) return fail(c, SFEM_E_ARG, "diag must not be NULL");
+  DeviceGuard g(c->device);
+  if ((st = ensure_diag(c, op)) != SFEM_OK) return st;
+  const int64_t n = c->ndof * nfields_of(c, op);
+  if (n == 0) return SFEM_OK;
+  if (prec == SFEM_F64)
+    HIPCHK(c, hipMemcpyAsync(diag, c->d_diag[op], n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  else
+    HIPCHK(c, hipMemcpyAsync(diag, c->d_diag32[op], n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+  return SFEM_OK;
+}
+
+sfem_status sfem_load(sfem_ctx *c, int nbatch, const double *f_q, double *b) {
+  sfem_status st = require_ready(c);
+  if (st != SFEM_OK) return st;
+  if (nbatch < 0) return fail(c, SFEM_E_ARG, "nbatch must be >= 0");
+  if (nbatch == 0 || c->ndof == 0) return SFEM_OK;
+  if (!f_q || !b) return fail(c, SFEM_E_ARG, "f_q and b must not be NULL");
+  DeviceGuard g(c->device);
+  LoadArgs a;
+  a.p = c->p;
+  a.map = c->d_map;
+  a.perm = c->d_perm;
+  a.qd = c->d_qd;
+  a.ndof = c->ndof;
+  a.nei = c->nelem;
+  a.nbatch = nbatch;
+  a.f = f_q;
+  a.b = b;
+  a.B = c->rules.B.data();
+  a.G = c->rules.G.data();
+  for (int col = 0; col < c->ncolors; ++col)
+    HIPCHK(c, launch_load(a, c->color_off[col], c->color_off[col + 1], c->stream));
+  return SFEM_OK;
+}
+
+sfem_status sfem_grad_nu(sfem_ctx *c, int nbatch, const double *u, const double *lam, double *gq) {
+  sfem_status st = require_ready(c);
+  if (st != SFEM_OK) return st;
+  if (nbatch < 0) return fail(c, SFEM_E_ARG, "nbatch must be >= 0");
+  if (nbatch == 0 || c->nelem == 0) return SFEM_OK;
+  if (!u || !lam || !gq) return fail(c, SFEM_E_ARG, "u, lam and g must not be NULL");
+  DeviceGuard g(c->device);
+  GradArgs a;
+  a.p = c->p;
+  a.map = c->d_map;
+  a.perm = c->d_perm;
+  a.qd = c->d_qd;
+  a.beta = c->beta;
+  a.ndof = c->ndof;
+  a.nei = c->nelem;
+  a.nbatch = nbatch;
+  a.u = u;
+  a.lam = lam;
+  a.g = gq;
+  a.B = c->rules.B.data();
+  a.G = c->rules.G.data();
+  HIPCHK(c, launch_grad(a, c->stream));
+  return SFEM_OK;
+}
+
+sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x,
+                     const sfem_pcg_opts *opts, sfem_pcg_info *info) {
+  sfem_status st = require_ready(c);
+  if (st != SFEM_OK) return st;
+  if ((st = check_op_batch(c, op, nbatch)) != SFEM_OK) return st;
+  if (!opts) return fail(c, SFEM_E_ARG, "opts must not be NULL");
+  if (!(opts->rtol >= 0.0) || opts->maxit < 0 || opts->check_every < 1 ||
+      (opts->mode != 0 && opts->mode != 1))
+    return fail(c, SFEM_E_ARG, "invalid options (rtol >= 0, maxit >= 0, check_every >= 1, mode 0/1)");
+  if (opts->mode == 1 && (!(opts->inner_rtol > 0.0) || opts->max_outer < 1))
+    return fail(c, SFEM_E_ARG, "mode 1 needs inner_rtol > 0 and max_outer >= 1");
+  const int nb = nbatch;
+  const int64_t n = c->ndof;
+  if (nb == 0) return SFEM_OK;
+  if (n == 0) {
+    if (info)
+      for (int m = 0; m < nb; ++m) info[m] = sfem_pcg_info{0, 0, 0.0, 0.0, SFEM_OK};
+    return SFEM_OK;
+  }
+  if (!b || !x) return fail(c, SFEM_E_ARG, "b and x must not be NULL");
+  if ((const void *)b == (const void *)x) return fail(c, SFEM_E_ARG, "b and x must not alias");
+  DeviceGuard g(c->device);
+  if ((st = ensure_diag(c, op)) != SFEM_OK) return st;
+  const int64_t dms = nfields_of(c, op) > 1 ? n : 0;
+  hipStream_t s = c->stream;
+  const int nblk = vec_nblk(n);
+  std::vector<int> iters(nb, 0), status(nb, 0);
+  std::vector<double> rel(nb, 0.0), trel(nb, 0.0);
+  int outer = 0;
+
+  if (opts->mode == 0) {
+    const size_t bytes = pcg_work_bytes<double>(n, nb) + align_up((size_t)nb * sizeof(double));
+    if ((st = ensure_ws(c, bytes)) != SFEM_OK) return st;
+    if ((st = ensure_pinned(c, std::max(sizeof(PcgScalars), sizeof(double)) * nb)) != SFEM_OK) return st;
+    Carver cv{(char *)c->ws.p};
+    PcgWork<double> w = carve_pcg<double>(cv, n, nb);
+    double *d_out = cv.take<double>(nb);
+    PcgScalars *hs = (PcgScalars *)c->h_pinned;
+    if ((st = run_pcg<double>(c, op, nb, b, x, opts->x0_zero != 0, opts->rtol, opts->maxit,
+                              opts->check_every, c->d_dinv[op], dms, w, hs)) != SFEM_OK)
+      return st;
+    std::vector<PcgScalars> fin(hs, hs + nb);
+    // true residual ||b - A x|| in FP64
+    if ((st = do_apply(c, op, false, nb, x, w.w)) != SFEM_OK) return st;
+    HIPCHK(c, launch_sub_norm(b, w.w, nullptr, w.part, nblk, n, nb, s));
+    HIPCHK(c, launch_reduce1(w.part, nblk, nb, d_out, s));
+    std::vector<double> tr(nb);
+    HIPCHK(c, hipMemcpyAsync(tr.data(), d_out, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (int m = 0; m < nb; ++m) {
+      iters[m] = fin[m].iters;
+      const double bb = fin[m].bb;
+      rel[m] = bb > 0 ? std::sqrt(fin[m].rr / bb) : 0.0;
+      trel[m] = bb > 0 ? std::sqrt(tr[m] / bb) : 0.0;
+      status[m] = fin[m].status;
+      if (status[m] == 0 && fin[m].active) status[m] = SFEM_NOCONV;
+    }
+  } else {
+    // FP64 iterative refinement around an FP32 Jacobi-PCG
+    const size_t bytes = pcg_work_bytes<float>(n, nb) + 2 * align_up((size_t)n * nb * sizeof(double)) +
+                         2 * align_up((size_t)n * nb * sizeof(float)) +
+                         align_up((size_t)nb * 3 * sizeof(double)) +
+                         align_up((size_t)nb * nblk * sizeof(double));
+    if ((st = ensure_ws(c, bytes)) != SFEM_OK) return st;
+    if ((st = ensure_pinned(c, std::max(sizeof(PcgScalars), 3 * sizeof(double)) * nb)) != SFEM_OK) return st;
+    Carver cv{(char *)c->ws.p};
+    PcgWork<float> w = carve_pcg<float>(cv, n, nb);
+    double *r64 = cv.take<double>(n * nb);
+    double *w64 = cv.take<double>(n * nb);
+    float *r32 = cv.take<float>(n * nb);
+    float *d32 = cv.take<float>(n * nb);
+    double *ir = cv.take<double>((int64_t)nb * 3);
+    double *part = cv.take<double>((int64_t)nb * nblk);
+    std::vector<double> hir(3 * nb);
+    std::vector<int> conv(nb, 0);
+    int total_inner = 0;
+    // ||b||^2
+    HIPCHK(c, launch_sub_norm(b, nullptr, nullptr, part, nblk, n, nb, s));
+    HIPCHK(c, launch_ir_norm(part, nblk, nb, 1, opts->rtol, ir, s));
+    if (opts->x0_zero) HIPCHK(c, VecOps<double>::fill(x, 0.0, n * nb, s));
+    for (;;) {
+      // outer residual in FP64 with the FP64 operator
+      if ((st = do_apply(c, op, false, nb, x, w64)) != SFEM_OK) return st;
+      HIPCHK(c, launch_sub_norm(b, w64, r64, part, nblk, n, nb, s));
+      HIPCHK(c, launch_ir_norm(part, nblk, nb, 0, opts->rtol, ir, s));
+      HIPCHK(c, hipMemcpyAsync(hir.data(), ir, 3 * nb * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      bool all = true;
+      for (int m = 0; m < nb; ++m) {
+        const double rn2 = hir[3 * m], bb = hir[3 * m + 1];
+        if (!std::isfinite(rn2) || !std::isfinite(bb)) {
+          status[m] = SFEM_E_NAN;
+          conv[m] = 1;
+        }
+        rel[m] = trel[m] = bb > 0 ? std::sqrt(rn2 / bb) : 0.0;
+        if (!conv[m] && hir[3 * m + 2] == 0.0) conv[m] = 1;
+        all = all && conv[m];
+      }
+      if (all || outer >= opts->max_outer || total_inner >= opts->maxit) break;
+      HIPCHK(c, launch_ir_cast(r64, ir, r32, n, nb, s));
+      PcgScalars *hs = (PcgScalars *)c->h_pinned;
+      if ((st = run_pcg<float>(c, op, nb, r32, d32, true, opts->inner_rtol,
+                               opts->maxit - total_inner, opts->check_every, c->d_dinv32[op], dms,
+                               w, hs)) != SFEM_OK)
+        return st;
+      int mx = 0;
+      for (int m = 0; m < nb; ++m) {
+        iters[m] += hs[m].iters;
+        mx = std::max(mx, hs[m].iters);
+        if (hs[m].status != 0 && status[m] == 0) status[m] = hs[m].status;
+      }
+      total_inner += std::max(mx, 1);
+      HIPCHK(c, launch_ir_accum(x, d32, ir, n, nb, s));
+      ++outer;
+    }
+    for (int m = 0; m < nb; ++m)
+      if (status[m] == 0 && !conv[m]) status[m] = SFEM_NOCONV;
+  }
+  sfem_status ret = SFEM_OK;
+  for (int m = 0; m < nb; ++m) {
+    if (info) info[m] = sfem_pcg_info{iters[m], outer, rel[m], trel[m], status[m]};
+    if (status[m] < 0 && (ret >= 0 || status[m] < ret)) ret = (sfem_status)status[m];
+    if (status[m] == SFEM_NOCONV && ret == SFEM_OK) ret = SFEM_NOCONV;
+  }
+  if (ret < 0) fail(c, ret, ret == SFEM_E_BREAKDOWN ? "CG breakdown: p^T A p <= 0" : "non-finite value in the solve");
+  return ret;
+}
+
+sfem_status sfem_get_info(const sfem_ctx *c, sfem_ctx_info *out) {
+  if (!c || !out) return SFEM_E_ARG;
+  out->p = c->p;
+  out->q = c->q;
+  out->nelem = c->nelem;
+  out->ndof = c->ndof;
+  out->ncolors = c->ncolors;
+  out->nfields = c->nfield;
+  out->device_bytes = c->bytes + (int64_t)c->ws.bytes;
+  return SFEM_OK;
+}
+
+}  // extern "C"

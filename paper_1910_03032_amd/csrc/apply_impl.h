@@ -1,0 +1,419 @@
+// Sum-factorized element kernels for Q_p hexahedra on gfx950.
+//
+// Per element (Section 3.1, eq. sumFactorized and L^K = G^T W G):
+//   gather x_e -> contract xi_1 with B, G -> contract xi_2 -> contract xi_3
+//   -> pointwise quadrature function with the stored factors
+//      (v = m u,  g = Gq grad_ref u)
+//   -> transposed contractions xi_3 -> xi_2 -> xi_1 -> scatter into y.
+//
+// Work decomposition: one element is owned by q^2 threads; in every stage a thread
+// owns one 1D line of the tensor along the direction being contracted, holds the
+// n (or q) inputs of that line in registers and produces the whole output line, so
+// LDS is read once per input value and the 1D tables (compile-time sized, passed
+// in the kernel argument segment) are wave-uniform operands.  Intermediates
+// between stages live in LDS, one buffer per element.  Several elements share a
+// workgroup (E = 256 / q^2).
+//
+// Scatter: the elements of one launch all have the same color, so no two of them
+// share a DoF.  Each map entry says whether this element is the first (in color
+// order) to write its DoF -- it then stores -- or accumulates onto what an earlier
+// color stored.  No atomics; the result is bitwise deterministic.  Essential DoFs
+// read as 0 in the gather and receive y = x from their first writer.
+//
+// LDS layouts inside an element buffer (a, b, c: quadrature indices along
+// xi_1..3; i, j, k: node indices):
+//   nodal         [k][j][i]
+//   after xi_1    [k][j][a]      (two fields: B- and G-contracted)
+//   after xi_2    [k][b][a]      (three fields)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace sfem {
+
+template <int P>
+struct Dims {
+  static constexpr int N = P + 1, Q = P + 2;
+  static constexpr int N2 = N * N, N3 = N * N * N, Q2 = Q * Q, Q3 = Q * Q * Q;
+  static constexpr int QN2 = Q * N2, NQ2 = N * Q2;
+  static constexpr int TPE = Q2;  // threads per element
+  static constexpr int E = (256 / TPE) > 0 ? (256 / TPE) : 1;
+  static constexpr int mx(int a, int b) { return a > b ? a : b; }
+  static constexpr int BUF = mx(N3, mx(2 * Q * N2, 3 * Q2 * N));
+  static constexpr int THREADS = E * TPE;
+};
+
+template <int P, typename T>
+struct Tab {
+  T B[P + 2][P + 1];
+  T G[P + 2][P + 1];
+};
+
+template <int P, typename T>
+inline Tab<P, T> make_tab(const double *B, const double *G) {
+  Tab<P, T> t;
+  for (int a = 0; a < P + 2; ++a)
+    for (int i = 0; i < P + 1; ++i) {
+      t.B[a][i] = (T)B[a * (P + 1) + i];
+      t.G[a][i] = (T)G[a * (P + 1) + i];
+    }
+  return t;
+}
+
+// Gather the element's nodal values (essential DoFs as 0) into buf[k][j][i].
+template <int P, typename T>
+__device__ __forceinline__ void gather_e(T *buf, int t, bool active, const int32_t *emap,
+                                         const T *__restrict__ xm) {
+  using D = Dims<P>;
+  if (active) {
+    for (int l = t; l < D::N3; l += D::TPE) {
+      const int32_t c = emap[l];
+      buf[l] = (c < 0) ? T(0) : xm[c & kDofMask];
+    }
+  }
+  __syncthreads();
+}
+
+// xi_1 contraction: [k][j][i] -> [k][j][a] with B (field 0) and, if DIFF, G (field 1).
+template <int P, typename T, bool DIFF>
+__device__ __forceinline__ void fwd_x(T *buf, int t, const Tab<P, T> &tb) {
+  using D = Dims<P>;
+  constexpr int N = D::N, Q = D::Q;
+  const bool w = t < D::N2;
+  const int j = t % N, k = t / N;
+  T ob[Q], og[Q];
+  if (w) {
+    T in[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) in[i] = buf[(k * N + j) * N + i];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      T sb = 0, sg = 0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        sb += tb.B[a][i] * in[i];
+        if constexpr (DIFF) sg += tb.G[a][i] * in[i];
+      }
+      ob[a] = sb;
+      og[a] = sg;
+    }
+  }
+  __syncthreads();
+  if (w) {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      buf[(k * N + j) * Q + a] = ob[a];
+      if constexpr (DIFF) buf[D::QN2 + (k * N + j) * Q + a] = og[a];
+    }
+  }
+  __syncthreads();
+}
+
+// xi_2 contraction: [k][j][a] -> [k][b][a]: field 0 = B(B x), and if DIFF
+// field 1 = G_y(B_x x) (for d/dxi_2), field 2 = B_y(G_x x) (for d/dxi_1).
+template <int P, typename T, bool DIFF>
+__device__ __forceinline__ void fwd_y(T *buf, int t, const Tab<P, T> &tb) {
+  using D = Dims<P>;
+  constexpr int N = D::N, Q = D::Q;
+  const bool w = t < Q * N;
+  const int a = t % Q, k = t / Q;
+  T obb[Q], ogb[Q], obg[Q];
+  if (w) {
+    T ib[N], ig[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      ib[j] = buf[(k * N + j) * Q + a];
+      if constexpr (DIFF) ig[j] = buf[D::QN2 + (k * N + j) * Q + a];
+    }
+#pragma unroll
+    for (int b = 0; b < Q; ++b) {
+      T s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        s0 += tb.B[b][j] * ib[j];
+        if constexpr (DIFF) {
+          s1 += tb.G[b][j] * ib[j];
+          s2 += tb.B[b][j] * ig[j];
+        }
+      }
+      obb[b] = s0;
+      ogb[b] = s1;
+      obg[b] = s2;
+    }
+  }
+  __syncthreads();
+  if (w) {
+#pragma unroll
+    for (int b = 0; b < Q; ++b) {
+      buf[(k * Q + b) * Q + a] = obb[b];
+      if constexpr (DIFF) {
+        buf[D::NQ2 + (k * Q + b) * Q + a] = ogb[b];
+        buf[2 * D::NQ2 + (k * Q + b) * Q + a] = obg[b];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Read the xi_3 lines of thread t = a + q b (no barrier).
+template <int P, typename T, bool DIFF>
+__device__ __forceinline__ void load_z(const T *buf, int t, T (&zbb)[P + 1], T (&zgb)[P + 1],
+                                       T (&zbg)[P + 1]) {
+  using D = Dims<P>;
+#pragma unroll
+  for (int k = 0; k < D::N; ++k) {
+    zbb[k] = buf[k * D::Q2 + t];
+    if constexpr (DIFF) {
+      zgb[k] = buf[D::NQ2 + k * D::Q2 + t];
+      zbg[k] = buf[2 * D::NQ2 + k * D::Q2 + t];
+    }
+  }
+}
+
+// Transposed xi_2: [k][b][a] (fields p1, p2, p3) -> [k][j][a] (fields r1, r2) with
+// r1 = B^T p1 + G^T p2 and r2 = B^T p3.
+template <int P, typename T, bool DIFF>
+__device__ __forceinline__ void bwd_y(T *buf, int t, const Tab<P, T> &tb) {
+  using D = Dims<P>;
+  constexpr int N = D::N, Q = D::Q;
+  const bool w = t < Q * N;
+  const int a = t % Q, k = t / Q;
+  T r1[N], r2[N];
+  if (w) {
+    T i1[Q], i2[Q], i3[Q];
+#pragma unroll
+    for (int b = 0; b < Q; ++b) {
+      i1[b] = buf[(k * Q + b) * Q + a];
+      if constexpr (DIFF) {
+        i2[b] = buf[D::NQ2 + (k * Q + b) * Q + a];
+        i3[b] = buf[2 * D::NQ2 + (k * Q + b) * Q + a];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      T s1 = 0, s2 = 0;
+#pragma unroll
+      for (int b = 0; b < Q; ++b) {
+        s1 += tb.B[b][j] * i1[b];
+        if constexpr (DIFF) {
+          s1 += tb.G[b][j] * i2[b];
+          s2 += tb.B[b][j] * i3[b];
+        }
+      }
+      r1[j] = s1;
+      r2[j] = s2;
+    }
+  }
+  __syncthreads();
+  if (w) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      buf[(k * N + j) * Q + a] = r1[j];
+      if constexpr (DIFF) buf[D::QN2 + (k * N + j) * Q + a] = r2[j];
+    }
+  }
+  __syncthreads();
+}
+
+// Transposed xi_1: [k][j][a] (r1, r2) -> nodal [k][j][i] = B^T r1 + G^T r2.
+template <int P, typename T, bool DIFF>
+__device__ __forceinline__ void bwd_x(T *buf, int t, const Tab<P, T> &tb) {
+  using D = Dims<P>;
+  constexpr int N = D::N, Q = D::Q;
+  const bool w = t < D::N2;
+  const int j = t % N, k = t / N;
+  T yo[N];
+  if (w) {
+    T i1[Q], i2[Q];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      i1[a] = buf[(k * N + j) * Q + a];
+      if constexpr (DIFF) i2[a] = buf[D::QN2 + (k * N + j) * Q + a];
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      T s = 0;
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        s += tb.B[a][i] * i1[a];
+        if constexpr (DIFF) s += tb.G[a][i] * i2[a];
+      }
+      yo[i] = s;
+    }
+  }
+  __syncthreads();
+  if (w) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) buf[(k * N + j) * N + i] = yo[i];
+  }
+  __syncthreads();
+}
+
+// Colored scatter of buf[l] into ym; essential DoFs get ess_val(g) from their first writer.
+template <int P, typename T, typename EssVal>
+__device__ __forceinline__ void scatter_e(const T *buf, int t, bool active, const int32_t *emap,
+                                          T *__restrict__ ym, EssVal ess_val) {
+  using D = Dims<P>;
+  if (active) {
+    for (int l = t; l < D::N3; l += D::TPE) {
+      const int32_t c = emap[l];
+      const int64_t g = c & kDofMask;
+      if (c < 0) {
+        if (c & kFirstBit) ym[g] = ess_val(g);
+      } else if (c & kFirstBit) {
+        ym[g] = buf[l];
+      } else {
+        ym[g] += buf[l];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// OP: 0 mass, 1 diffusion, 2 helmholtz (matches sfem_op)
+template <int P, typename T, int OP>
+__global__ void __launch_bounds__(Dims<P>::THREADS)
+apply_kernel(const Tab<P, T> tb, const int32_t *__restrict__ map, const T *__restrict__ qd,
+             int64_t qd_mstride, const T *__restrict__ nu, int64_t nu_mstride, int64_t e_begin,
+             int64_t e_end, int nbatch, int64_t ndof, const T *__restrict__ x, T *__restrict__ y) {
+  using D = Dims<P>;
+  constexpr int N = D::N, Q = D::Q, Q2 = D::Q2, Q3 = D::Q3;
+  constexpr int TPE = D::TPE, E = D::E;
+  constexpr bool MASS = (OP == 0) || (OP == 2);
+  constexpr bool DIFF = (OP == 1) || (OP == 2);
+
+  __shared__ T smem[E * D::BUF];
+  const int le = threadIdx.x / TPE;
+  const int t = threadIdx.x - le * TPE;
+  const int64_t e = e_begin + (int64_t)blockIdx.x * E + le;
+  const bool active = e < e_end;
+  const int64_t es = active ? e : e_begin;
+  T *buf = smem + le * D::BUF;
+  const int32_t *emap = map + es * (int64_t)D::N3;
+
+  for (int m = 0; m < nbatch; ++m) {
+    const T *xm = x + (int64_t)m * ndof;
+    T *ym = y + (int64_t)m * ndof;
+
+    gather_e<P, T>(buf, t, active, emap, xm);
+    fwd_x<P, T, DIFF>(buf, t, tb);
+    fwd_y<P, T, DIFF>(buf, t, tb);
+
+    // xi_3 contraction, quadrature function, transposed xi_3: thread = line (a, b)
+    {
+      T zbb[N], zgb[N], zbg[N];
+      load_z<P, T, DIFF>(buf, t, zbb, zgb, zbg);
+      T p1[N], p2[N], p3[N];
+#pragma unroll
+      for (int k = 0; k < N; ++k) p1[k] = p2[k] = p3[k] = T(0);
+      const T *qe = qd + (int64_t)m * qd_mstride + es * (int64_t)(kQdSlots * Q3);
+      const T *ne = nullptr;
+      if constexpr (OP == 1) {
+        if (nu) ne = nu + (int64_t)m * nu_mstride + es * (int64_t)Q3;
+      }
+#pragma unroll
+      for (int c = 0; c < Q; ++c) {
+        const int qi = c * Q2 + t;
+        T u = 0, dx = 0, dy = 0, dz = 0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          if constexpr (MASS) u += tb.B[c][k] * zbb[k];
+          if constexpr (DIFF) {
+            dz += tb.G[c][k] * zbb[k];
+            dy += tb.B[c][k] * zgb[k];
+            dx += tb.B[c][k] * zbg[k];
+          }
+        }
+        T v = 0, g1 = 0, g2 = 0, g3 = 0;
+        if (active) {
+          if constexpr (MASS) v = qe[qi] * u;
+          if constexpr (DIFF) {
+            const T G11 = qe[1 * Q3 + qi], G22 = qe[2 * Q3 + qi], G33 = qe[3 * Q3 + qi];
+            const T G12 = qe[4 * Q3 + qi], G13 = qe[5 * Q3 + qi], G23 = qe[6 * Q3 + qi];
+            g1 = G11 * dx + G12 * dy + G13 * dz;
+            g2 = G12 * dx + G22 * dy + G23 * dz;
+            g3 = G13 * dx + G23 * dy + G33 * dz;
+            if constexpr (OP == 1) {
+              if (ne) {
+                const T s = ne[qi];
+                g1 *= s;
+                g2 *= s;
+                g3 *= s;
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          if constexpr (MASS) p1[k] += tb.B[c][k] * v;
+          if constexpr (DIFF) {
+            p1[k] += tb.G[c][k] * g3;
+            p2[k] += tb.B[c][k] * g2;
+            p3[k] += tb.B[c][k] * g1;
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        buf[k * Q2 + t] = p1[k];
+        if constexpr (DIFF) {
+          buf[D::NQ2 + k * Q2 + t] = p2[k];
+          buf[2 * D::NQ2 + k * Q2 + t] = p3[k];
+        }
+      }
+      __syncthreads();
+    }
+
+    bwd_y<P, T, DIFF>(buf, t, tb);
+    bwd_x<P, T, DIFF>(buf, t, tb);
+    scatter_e<P, T>(buf, t, active, emap, ym, [&](int64_t g) { return xm[g]; });
+  }
+}
+
+template <int P, typename T>
+hipError_t launch_apply_pt(const ApplyArgs &a, int64_t e_begin, int64_t e_end, hipStream_t s) {
+  using D = Dims<P>;
+  const int64_t ne = e_end - e_begin;
+  if (ne <= 0) return hipSuccess;
+  const Tab<P, T> tb = make_tab<P, T>(a.B, a.G);
+  dim3 grid((unsigned)((ne + D::E - 1) / D::E));
+  dim3 block(D::THREADS);
+  const T *qd = (const T *)a.qd;
+  const T *nu = (const T *)a.nu;
+  const T *x = (const T *)a.x;
+  T *y = (T *)a.y;
+  switch (a.op) {
+    case SFEM_MASS:
+      hipLaunchKernelGGL((apply_kernel<P, T, 0>), grid, block, 0, s, tb, a.map, qd, a.qd_mstride,
+                         nu, a.nu_mstride, e_begin, e_end, a.nbatch, a.ndof, x, y);
+      break;
+    case SFEM_DIFFUSION:
+      hipLaunchKernelGGL((apply_kernel<P, T, 1>), grid, block, 0, s, tb, a.map, qd, a.qd_mstride,
+                         nu, a.nu_mstride, e_begin, e_end, a.nbatch, a.ndof, x, y);
+      break;
+    default:
+      hipLaunchKernelGGL((apply_kernel<P, T, 2>), grid, block, 0, s, tb, a.map, qd, a.qd_mstride,
+                         nu, a.nu_mstride, e_begin, e_end, a.nbatch, a.ndof, x, y);
+      break;
+  }
+  return hipGetLastError();
+}
+
+#define SFEM_DISPATCH_P(p, CALL) \
+  switch (p) {                   \
+    case 1: return CALL(1);      \
+    case 2: return CALL(2);      \
+    case 3: return CALL(3);      \
+    case 4: return CALL(4);      \
+    case 5: return CALL(5);      \
+    case 6: return CALL(6);      \
+    case 7: return CALL(7);      \
+    case 8: return CALL(8);      \
+    default: return hipErrorInvalidValue; \
+  }
+
+}  // namespace sfem

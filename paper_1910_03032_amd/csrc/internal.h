@@ -1,0 +1,153 @@
+// Internal declarations of the sfem library (host side + kernel launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "sfem.h"
+
+namespace sfem {
+
+// Encoding of the library-owned element->DoF map entries (int32):
+//   bits 0..29  global DoF
+//   bit 30      "first touch": this (element, local node) is the first writer of
+//               the DoF in color order, so it stores instead of accumulating
+//   bit 31      essential DoF (entry is negative)
+constexpr int32_t kDofMask = 0x3fffffff;
+constexpr int32_t kFirstBit = 0x40000000;
+
+// Quadrature-data slots per point, layout [elem][kQdSlots][q^3]:
+//   0: w|J|      1..6: w|J| (J^-1 J^-T) as (11, 22, 33, 12, 13, 23)
+constexpr int kQdSlots = 7;
+
+// 1D tables for order P (n = P + 1 GLL nodes, q = P + 2 Gauss points), row-major
+// [q][n]: B(a, i) = phi_i(xi_a), G(a, i) = phi_i'(xi_a).
+struct Rules1D {
+  int p = 0, q = 0;
+  std::vector<double> gll_x, gll_w, gauss_x, gauss_w;
+  std::vector<double> B, G;
+};
+// Host computation of the rules (Newton iterations on Legendre recurrences,
+// barycentric Lagrange weights).  Returns false if a Newton iteration fails.
+bool make_rules(int p, int q, Rules1D &out);
+
+// Per-member PCG scalars kept on the device.
+struct PcgScalars {
+  double rho;     // r^T z
+  double rr;      // r^T r
+  double bb;      // b^T b
+  double pw;      // p^T A p
+  double alpha, beta;
+  double tol2;    // (rtol ||b||)^2
+  int active;     // 1 while iterating
+  int status;     // 0 ok, SFEM_E_BREAKDOWN, SFEM_E_NAN
+  int iters;      // completed iterations
+  int pad;
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (implemented in the .hip files).  Every launcher enqueues on
+// `s` and returns the hipError_t of the launch.  B, G are HOST pointers to the
+// row-major [q][n] FP64 tables; they are passed to the kernels by value.
+// ---------------------------------------------------------------------------
+struct ApplyArgs {
+  int p;
+  int op;                   // SFEM_MASS / SFEM_DIFFUSION / SFEM_HELMHOLTZ
+  const int32_t *map;       // [nei][n^3] flagged map, internal element order
+  const void *qd;           // quadrature data, [nei][7][q^3] (slot layout above)
+  int64_t qd_mstride;       // elements of qd between batch members (0 = shared)
+  const void *nu;           // DIFFUSION only: [nei][q^3] or null
+  int64_t nu_mstride;
+  int64_t ndof;
+  int nbatch;
+  const void *x;
+  void *y;
+  const double *B, *G;
+};
+// Launch the apply over elements [e_begin, e_end) of one color.
+hipError_t launch_apply_f64(const ApplyArgs &a, int64_t e_begin, int64_t e_end, hipStream_t s);
+hipError_t launch_apply_f32(const ApplyArgs &a, int64_t e_begin, int64_t e_end, hipStream_t s);
+
+struct DiagArgs {
+  int p;
+  const int32_t *map;
+  const double *qd;         // base quadrature data (FP64)
+  const double *nu;         // [nei][q^3] or null
+  double alpha, beta;       // coefficients of the mass and diffusion terms
+  double *diag;             // [ndof]
+  const double *B, *G;
+};
+hipError_t launch_diag(const DiagArgs &a, int64_t e_begin, int64_t e_end, hipStream_t s);
+
+hipError_t launch_qdata_setup(int q, const double *gx, const double *gw, const double *xyz,
+                              int64_t nei, double *qd, int *bad, hipStream_t s);
+hipError_t launch_qpoint_coords(int q, const double *gx, const double *gw, const double *xyz,
+                                const int32_t *perm, int64_t nei, double *xq, hipStream_t s);
+hipError_t launch_fold(int q, const double *qd, const double *nu_user, const int32_t *perm,
+                       int64_t nei, int nfield, double alpha, double beta, double *fold64,
+                       float *fold32, double *nu64, float *nu32, hipStream_t s);
+hipError_t launch_cast_f32(const double *src, float *dst, int64_t n, hipStream_t s);
+
+struct GradArgs {
+  int p;
+  const int32_t *map;
+  const int32_t *perm;
+  const double *qd;
+  double beta;
+  int64_t ndof, nei;
+  int nbatch;
+  const double *u, *lam;
+  double *g;                // [nbatch][nelem][q^3] caller order
+  const double *B, *G;
+};
+hipError_t launch_grad(const GradArgs &a, hipStream_t s);
+
+struct LoadArgs {
+  int p;
+  const int32_t *map;
+  const int32_t *perm;
+  const double *qd;
+  int64_t ndof, nei;
+  int nbatch;
+  const double *f;          // [nbatch][nelem][q^3] caller order
+  double *b;
+  const double *B, *G;
+};
+hipError_t launch_load(const LoadArgs &a, int64_t e_begin, int64_t e_end, hipStream_t s);
+
+// Vector kernels of the PCG (T = double or float).  Partial-sum buffers hold
+// [nb][nv][nblk] doubles.  dinv may be shared by all members (dms = 0) or per member
+// (dms = n).
+template <typename T>
+struct VecOps {
+  static hipError_t start(const T *b, const T *w, T *x, T *r, const T *dinv, int64_t dms, T *p,
+                          double *part, int nblk, int64_t n, int nb, hipStream_t s);
+  static hipError_t dot(const T *a, const T *c, double *part, int nblk, int64_t n, int nb,
+                        hipStream_t s);
+  static hipError_t update(T *x, const T *p, T *r, const T *w, const T *dinv, int64_t dms,
+                           const PcgScalars *sc, double *part, int nblk, int64_t n, int nb,
+                           hipStream_t s);
+  static hipError_t newdir(const T *r, const T *dinv, int64_t dms, T *p, const PcgScalars *sc,
+                           int64_t n, int nb, hipStream_t s);
+  static hipError_t fill(T *p, T v, int64_t n, hipStream_t s);
+  static hipError_t recip(const double *d, T *out, int64_t n, hipStream_t s);
+};
+int vec_nblk(int64_t n);
+hipError_t launch_sub_norm(const double *b, const double *w, double *r, double *part, int nblk,
+                           int64_t n, int nb, hipStream_t s);
+hipError_t launch_pcg_init(const double *part, int nblk, int nb, double rtol, PcgScalars *sc,
+                           hipStream_t s);
+hipError_t launch_pcg_alpha(const double *part, int nblk, int nb, PcgScalars *sc, hipStream_t s);
+hipError_t launch_pcg_beta(const double *part, int nblk, int nb, PcgScalars *sc, hipStream_t s);
+hipError_t launch_reduce1(const double *part, int nblk, int nb, double *out, hipStream_t s);
+hipError_t launch_ir_norm(const double *part, int nblk, int nb, int set_bb, double rtol, double *ir,
+                          hipStream_t s);
+hipError_t launch_ir_cast(const double *r, const double *ir, float *r32, int64_t n, int nb,
+                          hipStream_t s);
+hipError_t launch_ir_accum(double *x, const float *d, const double *ir, int64_t n, int nb,
+                           hipStream_t s);
+
+}  // namespace sfem

@@ -1,0 +1,378 @@
+// Vector kernels of the Jacobi-preconditioned CG (Section 5, Section 5.3) and of the
+// FP64 iterative refinement around an FP32 inner CG.
+//
+// All dot products accumulate in float64, also for float32 vectors.  Reductions are
+// two-level and in a fixed order (per-block partial sums, then one block per batch
+// member), so every result is bitwise reproducible for a given size.  The CG scalars
+// (rho, alpha, beta, ...) stay on the device; the host only reads them at its
+// convergence checks.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.h"
+
+namespace sfem {
+namespace {
+
+constexpr int VB = 256;
+
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV]) {
+  __shared__ double sh[NV][VB];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) sh[k][threadIdx.x] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int s = VB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = sh[k][0];
+}
+
+template <int NV>
+__device__ __forceinline__ void write_part(double (&v)[NV], double *part, int nblk) {
+  block_sum<NV>(v);
+  if (threadIdx.x == 0) {
+    const int m = blockIdx.y;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) part[((int64_t)m * NV + k) * nblk + blockIdx.x] = v[k];
+  }
+}
+
+// Sum of the nblk partials of quantity k of member blockIdx.x (one block per member).
+template <int NV>
+__device__ __forceinline__ void reduce_parts(const double *part, int nblk, double (&v)[NV]) {
+  const int m = blockIdx.x;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += VB) s += part[((int64_t)m * NV + k) * nblk + i];
+    v[k] = s;
+  }
+  block_sum<NV>(v);
+}
+
+// r = b - w (w may be null: r = b); x = 0 if xzero; p = dinv r;
+// partials: r.p (rho), r.r, b.b
+template <typename T>
+__global__ void start_kernel(const T *__restrict__ b, const T *__restrict__ w, T *__restrict__ x,
+                             T *__restrict__ r, const T *__restrict__ dinv, int64_t dinv_mstride,
+                             T *__restrict__ p, double *__restrict__ part, int nblk, int64_t n) {
+  const int64_t off = (int64_t)blockIdx.y * n;
+  const T *dm = dinv + (int64_t)blockIdx.y * dinv_mstride;
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)nblk * VB) {
+    const T bi = b[off + i];
+    const T ri = w ? (T)(bi - w[off + i]) : bi;
+    const T pi = dm[i] * ri;
+    r[off + i] = ri;
+    p[off + i] = pi;
+    if (x) x[off + i] = T(0);
+    v[0] += (double)ri * (double)pi;
+    v[1] += (double)ri * (double)ri;
+    v[2] += (double)bi * (double)bi;
+  }
+  write_part<3>(v, part, nblk);
+}
+
+template <typename T>
+__global__ void dot_kernel(const T *__restrict__ a, const T *__restrict__ c,
+                           double *__restrict__ part, int nblk, int64_t n) {
+  const int64_t off = (int64_t)blockIdx.y * n;
+  double v[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)nblk * VB)
+    v[0] += (double)a[off + i] * (double)c[off + i];
+  write_part<1>(v, part, nblk);
+}
+
+// x += alpha p; r -= alpha w; partials: r.(dinv r), r.r
+template <typename T>
+__global__ void update_kernel(T *__restrict__ x, const T *__restrict__ p, T *__restrict__ r,
+                              const T *__restrict__ w, const T *__restrict__ dinv,
+                              int64_t dinv_mstride, const PcgScalars *__restrict__ sc,
+                              double *__restrict__ part, int nblk, int64_t n) {
+  const int m = blockIdx.y;
+  const int64_t off = (int64_t)m * n;
+  const T *dm = dinv + (int64_t)m * dinv_mstride;
+  const T alpha = (T)sc[m].alpha;
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)nblk * VB) {
+    x[off + i] += alpha * p[off + i];
+    const T ri = r[off + i] - alpha * w[off + i];
+    r[off + i] = ri;
+    v[0] += (double)ri * (double)(dm[i] * ri);
+    v[1] += (double)ri * (double)ri;
+  }
+  write_part<2>(v, part, nblk);
+}
+
+// p = dinv r + beta p
+template <typename T>
+__global__ void newdir_kernel(const T *__restrict__ r, const T *__restrict__ dinv,
+                              int64_t dinv_mstride, T *__restrict__ p,
+                              const PcgScalars *__restrict__ sc, int64_t n) {
+  const int m = blockIdx.y;
+  const int64_t off = (int64_t)m * n;
+  const T *dm = dinv + (int64_t)m * dinv_mstride;
+  const T beta = (T)sc[m].beta;
+  for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * VB)
+    p[off + i] = dm[i] * r[off + i] + beta * p[off + i];
+}
+
+// r = b - w with partial r.r (w may be null: r = b); r may be null (norm only)
+__global__ void sub_norm_kernel(const double *__restrict__ b, const double *__restrict__ w,
+                                double *__restrict__ r, double *__restrict__ part, int nblk,
+                                int64_t n) {
+  const int64_t off = (int64_t)blockIdx.y * n;
+  double v[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)nblk * VB) {
+    const double ri = w ? b[off + i] - w[off + i] : b[off + i];
+    if (r) r[off + i] = ri;
+    v[0] += ri * ri;
+  }
+  write_part<1>(v, part, nblk);
+}
+
+__global__ void init_scalars_kernel(const double *__restrict__ part, int nblk, double rtol,
+                                    PcgScalars *__restrict__ sc) {
+  double v[3];
+  reduce_parts<3>(part, nblk, v);
+  if (threadIdx.x == 0) {
+    PcgScalars &s = sc[blockIdx.x];
+    s.rho = v[0];
+    s.rr = v[1];
+    s.bb = v[2];
+    s.pw = 0.0;
+    s.alpha = 0.0;
+    s.beta = 0.0;
+    s.tol2 = rtol * rtol * v[2];
+    s.iters = 0;
+    const bool finite = isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]);
+    s.status = finite ? 0 : SFEM_E_NAN;
+    s.active = (finite && v[2] > 0.0 && v[1] > s.tol2) ? 1 : 0;
+  }
+}
+
+__global__ void alpha_kernel(const double *__restrict__ part, int nblk,
+                             PcgScalars *__restrict__ sc) {
+  double v[1];
+  reduce_parts<1>(part, nblk, v);
+  if (threadIdx.x == 0) {
+    PcgScalars &s = sc[blockIdx.x];
+    s.pw = v[0];
+    s.alpha = 0.0;
+    if (s.active) {
+      if (!isfinite(v[0])) {
+        s.status = SFEM_E_NAN;
+        s.active = 0;
+      } else if (!(v[0] > 0.0)) {
+        s.status = SFEM_E_BREAKDOWN;
+        s.active = 0;
+      } else {
+        s.alpha = s.rho / v[0];
+      }
+    }
+  }
+}
+
+__global__ void beta_kernel(const double *__restrict__ part, int nblk,
+                            PcgScalars *__restrict__ sc) {
+  double v[2];
+  reduce_parts<2>(part, nblk, v);
+  if (threadIdx.x == 0) {
+    PcgScalars &s = sc[blockIdx.x];
+    s.beta = 0.0;
+    if (s.active) {
+      s.iters += 1;
+      if (!isfinite(v[0]) || !isfinite(v[1])) {
+        s.status = SFEM_E_NAN;
+        s.active = 0;
+      } else {
+        s.beta = v[0] / s.rho;
+        s.rho = v[0];
+        s.rr = v[1];
+        if (v[1] <= s.tol2) s.active = 0;
+      }
+    }
+  }
+}
+
+// out[m * nv + k] = sum of partials
+template <int NV>
+__global__ void reduce_out_kernel(const double *__restrict__ part, int nblk,
+                                  double *__restrict__ out) {
+  double v[NV];
+  reduce_parts<NV>(part, nblk, v);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) out[(int64_t)blockIdx.x * NV + k] = v[k];
+  }
+}
+
+// IR state per member: [0] = ||r||^2, [1] = ||b||^2, [2] = scale (||r|| while refining, else 0)
+__global__ void ir_norm_kernel(const double *__restrict__ part, int nblk, int set_bb, double rtol,
+                               double *__restrict__ ir) {
+  double v[1];
+  reduce_parts<1>(part, nblk, v);
+  if (threadIdx.x == 0) {
+    double *s = ir + 3 * (int64_t)blockIdx.x;
+    s[0] = v[0];
+    if (set_bb) s[1] = v[0];
+    s[2] = (v[0] > rtol * rtol * s[1]) ? sqrt(v[0]) : 0.0;
+  }
+}
+
+__global__ void ir_cast_kernel(const double *__restrict__ r, const double *__restrict__ ir,
+                               float *__restrict__ r32, int64_t n) {
+  const int m = blockIdx.y;
+  const double sc = ir[3 * m + 2];
+  const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
+  const int64_t off = (int64_t)m * n;
+  for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * VB)
+    r32[off + i] = (float)(r[off + i] * inv);
+}
+
+__global__ void ir_accum_kernel(double *__restrict__ x, const float *__restrict__ d,
+                                const double *__restrict__ ir, int64_t n) {
+  const int m = blockIdx.y;
+  const double sc = ir[3 * m + 2];
+  if (sc == 0.0) return;
+  const int64_t off = (int64_t)m * n;
+  for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * VB)
+    x[off + i] += sc * (double)d[off + i];
+}
+
+template <typename T>
+__global__ void fill_kernel(T *__restrict__ p, T v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * VB)
+    p[i] = v;
+}
+
+template <typename T>
+__global__ void recip_kernel(const double *__restrict__ d, T *__restrict__ out, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * VB)
+    out[i] = (T)(1.0 / d[i]);
+}
+
+unsigned grid_for(int64_t n) {
+  int64_t b = (n + VB * 4 - 1) / (VB * 4);
+  if (b < 1) b = 1;
+  if (b > 4096) b = 4096;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+int vec_nblk(int64_t n) {
+  int64_t b = (n + VB * 8 - 1) / (VB * 8);
+  if (b < 1) b = 1;
+  if (b > 1024) b = 1024;
+  return (int)b;
+}
+
+template <typename T>
+hipError_t VecOps<T>::start(const T *b, const T *w, T *x, T *r, const T *dinv, int64_t dms, T *p,
+                            double *part, int nblk, int64_t n, int nb, hipStream_t s) {
+  hipLaunchKernelGGL((start_kernel<T>), dim3(nblk, nb), dim3(VB), 0, s, b, w, x, r, dinv, dms, p,
+                     part, nblk, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t VecOps<T>::dot(const T *a, const T *c, double *part, int nblk, int64_t n, int nb,
+                          hipStream_t s) {
+  hipLaunchKernelGGL((dot_kernel<T>), dim3(nblk, nb), dim3(VB), 0, s, a, c, part, nblk, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t VecOps<T>::update(T *x, const T *p, T *r, const T *w, const T *dinv, int64_t dms,
+                             const PcgScalars *sc, double *part, int nblk, int64_t n, int nb,
+                             hipStream_t s) {
+  hipLaunchKernelGGL((update_kernel<T>), dim3(nblk, nb), dim3(VB), 0, s, x, p, r, w, dinv, dms, sc,
+                     part, nblk, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t VecOps<T>::newdir(const T *r, const T *dinv, int64_t dms, T *p, const PcgScalars *sc,
+                             int64_t n, int nb, hipStream_t s) {
+  hipLaunchKernelGGL((newdir_kernel<T>), dim3(grid_for(n), nb), dim3(VB), 0, s, r, dinv, dms, p, sc,
+                     n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t VecOps<T>::fill(T *p, T v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((fill_kernel<T>), dim3(grid_for(n)), dim3(VB), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t VecOps<T>::recip(const double *d, T *out, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((recip_kernel<T>), dim3(grid_for(n)), dim3(VB), 0, s, d, out, n);
+  return hipGetLastError();
+}
+
+template struct VecOps<double>;
+template struct VecOps<float>;
+
+hipError_t launch_sub_norm(const double *b, const double *w, double *r, double *part, int nblk,
+                           int64_t n, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(sub_norm_kernel, dim3(nblk, nb), dim3(VB), 0, s, b, w, r, part, nblk, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_init(const double *part, int nblk, int nb, double rtol, PcgScalars *sc,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(init_scalars_kernel, dim3(nb), dim3(VB), 0, s, part, nblk, rtol, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_alpha(const double *part, int nblk, int nb, PcgScalars *sc, hipStream_t s) {
+  hipLaunchKernelGGL(alpha_kernel, dim3(nb), dim3(VB), 0, s, part, nblk, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_beta(const double *part, int nblk, int nb, PcgScalars *sc, hipStream_t s) {
+  hipLaunchKernelGGL(beta_kernel, dim3(nb), dim3(VB), 0, s, part, nblk, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce1(const double *part, int nblk, int nb, double *out, hipStream_t s) {
+  hipLaunchKernelGGL((reduce_out_kernel<1>), dim3(nb), dim3(VB), 0, s, part, nblk, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ir_norm(const double *part, int nblk, int nb, int set_bb, double rtol, double *ir,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(ir_norm_kernel, dim3(nb), dim3(VB), 0, s, part, nblk, set_bb, rtol, ir);
+  return hipGetLastError();
+}
+
+hipError_t launch_ir_cast(const double *r, const double *ir, float *r32, int64_t n, int nb,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(ir_cast_kernel, dim3(grid_for(n), nb), dim3(VB), 0, s, r, ir, r32, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_ir_accum(double *x, const float *d, const double *ir, int64_t n, int nb,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(ir_accum_kernel, dim3(grid_for(n), nb), dim3(VB), 0, s, x, d, ir, n);
+  return hipGetLastError();
+}
+
+}  // namespace sfem

@@ -1,0 +1,62 @@
+"""The C-ABI library loads and exports every call include/sfem.h declares (CPU only:
+no HIP device call is made here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sfem.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sfem_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("sfem_create", "sfem_setup", "sfem_apply", "sfem_diagonal", "sfem_pcg", "sfem_grad_nu",
+              "sfem_set_coeffs", "sfem_load", "sfem_qpoint_coords", "sfem_destroy", "sfem_last_error"):
+        assert n in names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch  # noqa: F401  (the binding always loads torch's HIP runtime first)
+    from paper_1910_03032_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libsfem.so is not built: run `python -m paper_1910_03032_amd.build`")
+    return _lib.load()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_1910_03032_amd import _lib
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(_lib.EXPORTED) == declared_functions()
+
+
+def test_pure_host_calls(lib):
+    assert lib.sfem_abi_version() == 1
+    assert isinstance(lib.sfem_last_error(None), bytes)
+    from paper_1910_03032_amd._lib import CtxInfo
+    ci = CtxInfo()
+    assert lib.sfem_get_info(None, C.byref(ci)) == -1  # SFEM_E_ARG on a NULL context
+    assert lib.sfem_set_stream(None, None) == -1
+    lib.sfem_destroy(None)  # no-op
+
+
+def test_structs_match_header_layout():
+    from paper_1910_03032_amd._lib import PcgOpts, PcgInfo
+    # double, int, int, double, int, int, int -> 40 bytes with natural alignment
+    assert C.sizeof(PcgOpts) == 40
+    assert C.sizeof(PcgInfo) == 32
+
+
+def test_library_is_gfx950_code_object():
+    from paper_1910_03032_amd import _lib
+    data = open(_lib.LIB_PATH, "rb").read()
+    assert b"gfx950" in data

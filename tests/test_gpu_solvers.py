@@ -1,0 +1,202 @@
+"""Jacobi-PCG, FP32-inner iterative refinement and the adjoint gradient on the GPU,
+checked against the oracle (direct solves, oracle PCG, oracle gradient), central
+finite differences and the homogeneity identity; plus error paths forced from the host."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import torch
+
+from gpu_common import case, gpu, host, rel, say, nu_c2_gpu
+from oracle import pcg as oracle_pcg, adjoint_gradient
+from workloads import rhs_uniform, nu_uniform, f_manufactured, u_manufactured, uniform
+
+pytestmark = pytest.mark.gpu
+
+
+def test_poisson_p2_4e_pcg_vs_direct_and_oracle_pcg():
+    m, d, op = case(4, 2)
+    xq = d.qpoint_coords()
+    f = f_manufactured(xq[..., 0], xq[..., 1], xq[..., 2])
+    b_o = d.load(f)
+    b_g = op.load(gpu(f.reshape(-1)))
+    assert rel(host(b_g), b_o) <= 1e-12
+    x, res = op.pcg(b_g, op=1, rtol=1e-12, check_every=1)
+    assert res.converged and res.true_rel_res[0] <= 1e-11
+    A = d.assemble(0.0, 1.0)
+    xd = spla.spsolve(A.tocsc(), b_o)
+    assert rel(host(x), xd) <= 1e-10
+    _, it_o, _ = oracle_pcg(lambda v: d.apply(v, 0.0, 1.0), b_o, 1.0 / d.diagonal(0.0, 1.0), rtol=1e-12)
+    say(f"  iterations gpu {res.iters[0]} oracle {it_o}")
+    assert abs(res.iters[0] - it_o) <= 2
+    # discretization error of the GPU solution is the oracle's
+    assert abs(d.l2_error(host(x), u_manufactured) - d.l2_error(xd, u_manufactured)) < 1e-10
+
+
+def test_helmholtz_pcg_and_ir_reduced():
+    m, d, op = case(4, 4)
+    nu = nu_uniform(m.nelem, d.q, seed=2)
+    op.set_coeffs(1e3, 1.0, gpu(nu))
+    b = rhs_uniform(m, seed=1)[0]
+    x64, r64 = op.pcg(gpu(b), rtol=1e-12, check_every=1)
+    xir, rir = op.pcg(gpu(b), rtol=1e-12, mode=1, inner_rtol=1e-5, check_every=1)
+    say(f"  fp64 {r64}  ir {rir}")
+    assert r64.converged and rir.converged
+    assert rir.true_rel_res[0] <= 1e-12 and rir.outer[0] >= 2
+    A = d.assemble(1e3, 1.0, nu)
+    xd = spla.spsolve(A.tocsc(), b)
+    assert rel(host(x64), xd) <= 1e-10
+    assert rel(host(xir), xd) <= 1e-10
+    assert np.linalg.norm(b - A @ host(xir)) <= 1e-11 * np.linalg.norm(b)
+
+
+def test_vector_helmholtz_batched_pcg_matches_single():
+    m, d, op = case(3, 3)
+    op.set_coeffs(1e3, 1.0, nu_c2_gpu(op))
+    B = rhs_uniform(m, seed=1, nbatch=3)
+    X, res = op.pcg(gpu(B), rtol=1e-10, check_every=2)
+    assert res.converged
+    for k in range(3):
+        xk, rk = op.pcg(gpu(B[k]), rtol=1e-10, check_every=2)
+        assert rk.iters[0] == res.iters[k]
+        assert torch.equal(xk, X[k])
+    Xi, ri = op.pcg(gpu(B), rtol=1e-10, mode=1)
+    assert ri.converged and max(ri.true_rel_res) <= 1e-10
+    assert rel(host(Xi), host(X)) <= 1e-8
+
+
+def test_pcg_from_nonzero_initial_guess():
+    m, d, op = case(3, 2)
+    op.set_coeffs(1e3, 1.0, None)
+    b = rhs_uniform(m, seed=1)[0]
+    x, r = op.pcg(gpu(b), rtol=1e-11)
+    x2, r2 = op.pcg(gpu(b), x=x, rtol=1e-11)
+    assert r2.iters[0] <= 2 and r2.true_rel_res[0] <= 1e-10
+
+
+def test_adjoint_gradient_vs_oracle_p5_reduced():
+    """The adjoint-gradient workload (p = 5) on a reduced 3^3 mesh: GPU gradient vs oracle."""
+    m, d, op = case(3, 5)
+    alpha, beta = 1e3, 1.0
+    nu = nu_uniform(m.nelem, d.q, seed=2)
+    nu_star = nu_uniform(m.nelem, d.q, seed=3)
+    b = rhs_uniform(m, seed=1)[0]
+    u_t = spla.spsolve(d.assemble(alpha, beta, nu_star).tocsc(), b)
+    J, g_o, u_o, lam_o = adjoint_gradient(d, nu, b, u_t, alpha, beta, direct=True)
+    op.set_coeffs(alpha, beta, gpu(nu))
+    u, _ = op.pcg(gpu(b), rtol=1e-13)
+    res = u - gpu(u_t)
+    res[torch.as_tensor(m.ess.astype(bool), device="cuda")] = 0
+    lam, _ = op.pcg(res, rtol=1e-13)
+    g = host(op.grad_nu(u, lam))
+    e = rel(g, g_o.reshape(-1))
+    say(f"  gradient rel err vs oracle {e:.2e}")
+    assert e <= 1e-9
+
+
+@pytest.mark.parametrize("alpha", [1e3, 0.0])
+def test_autograd_vs_central_differences(alpha):
+    from paper_1910_03032_amd.autograd import helmholtz_solve
+    m, d, op = case(3, 2)
+    q3 = d.nqp
+    nu = gpu(nu_uniform(m.nelem, d.q, seed=2)).requires_grad_(True)
+    b = gpu(rhs_uniform(m, seed=1)[0])
+    op.set_coeffs(alpha, 1.0, gpu(nu_uniform(m.nelem, d.q, seed=3)))
+    u_t, _ = op.pcg(b, rtol=1e-13)
+    ess = torch.as_tensor(m.ess.astype(bool), device="cuda")
+
+    def J(nu_):
+        u = helmholtz_solve(nu_, b, op, alpha=alpha, beta=1.0, rtol=1e-13)
+        r = torch.where(ess, torch.zeros_like(u), u - u_t)
+        return 0.5 * (r * r).sum()
+
+    Jv = J(nu)
+    Jv.backward()
+    g = nu.grad.detach().clone()
+    eps = 1e-6
+    for k in range(4):
+        dirn = gpu(np.random.default_rng(100 + k).uniform(-1, 1, (m.nelem, q3)))
+        with torch.no_grad():
+            fd = (J(nu + eps * dirn) - J(nu - eps * dirn)).item() / (2 * eps)
+        ad = float((g * dirn).sum())
+        say(f"  dir {k}: fd {fd:.10e} ad {ad:.10e}")
+        assert abs(fd - ad) <= 1e-5 * abs(ad)
+
+
+def test_gradient_homogeneity_identity_p5_20e():
+    """Full 20^3, p = 5 adjoint workload: sum nu dJ/dnu = -beta lam^T K(nu) u (K linear in nu)."""
+    m, d, op = case(20, 5)
+    alpha, beta = 1e3, 1.0
+    nu = gpu(nu_uniform(m.nelem, d.q, seed=2))
+    op.set_coeffs(alpha, beta, gpu(nu_uniform(m.nelem, d.q, seed=3)))
+    b = gpu(rhs_uniform(m, seed=1)[0])
+    u_t, _ = op.pcg(b, rtol=1e-12)
+    op.set_coeffs(alpha, beta, nu)
+    u, r1 = op.pcg(b, rtol=1e-12)
+    ess = torch.as_tensor(m.ess.astype(bool), device="cuda")
+    res = torch.where(ess, torch.zeros_like(u), u - u_t)
+    lam, r2 = op.pcg(res, rtol=1e-12)
+    say(f"  forward {r1} adjoint {r2}")
+    g = op.grad_nu(u, lam)
+    lhs = float((nu.reshape(-1) * g).sum())
+    uf = torch.where(ess, torch.zeros_like(u), u)
+    lf = torch.where(ess, torch.zeros_like(lam), lam)
+    Ku = op.apply(uf, op=1)  # K(nu) with the same nu field
+    rhs = -beta * float((lf * Ku).sum())
+    say(f"  identity lhs {lhs:.12e} rhs {rhs:.12e}")
+    assert abs(lhs - rhs) <= 1e-10 * abs(rhs)
+
+
+# ------------------------------------------------------------------ error paths
+def test_error_inverted_element():
+    from paper_1910_03032_amd import Operator, SfemError
+    from workloads import BoxMesh
+    m = BoxMesh(2, 2)
+    xyz = m.elem_xyz.copy()
+    xyz[3] = xyz[3][[1, 0, 3, 2, 5, 4, 7, 6]]  # mirror element 3 -> det J < 0
+    with pytest.raises(SfemError) as ei:
+        Operator(xyz, m.elem_dofs, m.ndof, 2, ess=m.ess)
+    assert ei.value.status == -2
+
+
+def test_error_unsupported_order_and_bad_map():
+    from paper_1910_03032_amd import Operator, SfemError
+    from workloads import BoxMesh
+    m = BoxMesh(2, 2)
+    with pytest.raises(SfemError) as ei:
+        Operator(m.elem_xyz, m.elem_dofs, m.ndof, 2, q=3)
+    assert ei.value.status == -5
+    bad = m.elem_dofs.copy()
+    bad[1, 0] = m.ndof + 5
+    with pytest.raises(SfemError) as ei:
+        Operator(m.elem_xyz, bad, m.ndof, 2)
+    assert ei.value.status == -2
+    dup = m.elem_dofs.copy()
+    dup[0, 1] = dup[0, 0]
+    with pytest.raises(SfemError):
+        Operator(m.elem_xyz, dup, m.ndof, 2)
+
+
+def test_error_nan_noconv_breakdown():
+    from paper_1910_03032_amd import SfemError
+    m, d, op = case(3, 2)
+    b = gpu(rhs_uniform(m, seed=1)[0])
+    x, r = op.pcg(b, maxit=1, rtol=1e-12)
+    assert r.status == 1 and r.iters[0] == 1  # SFEM_NOCONV with the last iterate
+    bn = b.clone()
+    bn[m.ndof // 2] = float("nan")
+    with pytest.raises(SfemError) as ei:
+        op.pcg(bn)
+    assert ei.value.status == -6
+    op.set_coeffs(-1e6, 1.0, None)  # negative definite: p^T A p < 0
+    with pytest.raises(SfemError) as ei:
+        op.pcg(b)
+    assert ei.value.status == -7
+    op.set_coeffs(1e3, 1.0, None)
+    x, r = op.pcg(torch.zeros_like(b))
+    assert r.converged and float(x.abs().max()) == 0.0
+
+
+def test_empty_inputs():
+    m, d, op = case(2, 1)
+    e = torch.empty(0, m.ndof, dtype=torch.float64, device="cuda")
+    assert op.apply(e, op=2).shape == (0, m.ndof)
