@@ -42,6 +42,8 @@ struct sfem_ctx {
   double *d_xyz = nullptr;         // [nelem][8][3] internal order
   double *d_qd = nullptr;          // [nelem][7][q^3]
   float *d_qd32 = nullptr;
+  int32_t *d_off = nullptr;        // [ndof + 1] DoF -> E-vector slots (CSR), empty for essential
+  int32_t *d_slot = nullptr;       // E-vector slot (internal element * n^3 + local node)
 
   // ---- coefficients
   double alpha = 1.0, beta = 1.0;
@@ -59,7 +61,8 @@ struct sfem_ctx {
   float *d_diag32[3] = {nullptr, nullptr, nullptr};
   float *d_dinv32[3] = {nullptr, nullptr, nullptr};
 
-  // ---- solver workspace (grown on demand)
+  // ---- E-vector of the apply and solver workspace (grown on demand)
+  DevBuf evec;
   DevBuf ws;
   void *h_pinned = nullptr;
   size_t h_pinned_bytes = 0;
@@ -151,6 +154,8 @@ void free_all(sfem_ctx *c) {
   c->d_xyz = nullptr;
   c->d_qd = nullptr;
   c->d_qd32 = nullptr;
+  c->d_off = nullptr;
+  c->d_slot = nullptr;
   c->d_fold64 = nullptr;
   c->d_fold32 = nullptr;
   c->d_nu64 = nullptr;
@@ -162,6 +167,8 @@ void free_all(sfem_ctx *c) {
   }
   if (c->ws.p) (void)hipFree(c->ws.p);
   c->ws = DevBuf{};
+  if (c->evec.p) (void)hipFree(c->evec.p);
+  c->evec = DevBuf{};
   c->ready = false;
 }
 
@@ -238,17 +245,42 @@ sfem_status check_op_batch(sfem_ctx *c, int op, int nbatch) {
   return SFEM_OK;
 }
 
-// Enqueue y = A x on the context stream (no argument checks).
-sfem_status do_apply(sfem_ctx *c, int op, bool f32, int nbatch, const void *x, void *y) {
+sfem_status ensure_evec(sfem_ctx *c, size_t bytes) {
+  if (c->evec.bytes >= bytes) return SFEM_OK;
+  if (c->evec.p) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    (void)hipFree(c->evec.p);
+    c->evec = DevBuf{};
+  }
+  void *p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, SFEM_E_NOMEM, "E-vector allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  c->evec.p = p;
+  c->evec.bytes = bytes;
+  return SFEM_OK;
+}
+
+// Enqueue y = A x on the context stream (no argument checks).  With part != null the
+// assembly also leaves the partial sums of x . y (nblk blocks per member) in part.
+sfem_status do_apply(sfem_ctx *c, int op, bool f32, int nbatch, const void *x, void *y,
+                     double *part = nullptr, int nblk = 0) {
   if (nbatch == 0 || c->ndof == 0) return SFEM_OK;
+  const int64_t n3 = (int64_t)(c->p + 1) * (c->p + 1) * (c->p + 1);
+  const int64_t estride = c->nelem * n3;
+  const size_t esz = f32 ? sizeof(float) : sizeof(double);
+  sfem_status st;
+  if ((st = ensure_evec(c, (size_t)estride * nbatch * esz)) != SFEM_OK) return st;
   ApplyArgs a;
   a.p = c->p;
   a.op = op;
   a.map = c->d_map;
   a.ndof = c->ndof;
   a.nbatch = nbatch;
+  a.nelem = c->nelem;
   a.x = x;
-  a.y = y;
+  a.evec = c->evec.p;
   a.B = c->rules.B.data();
   a.G = c->rules.G.data();
   a.nu = nullptr;
@@ -266,11 +298,15 @@ sfem_status do_apply(sfem_ctx *c, int op, bool f32, int nbatch, const void *x, v
       a.nu_mstride = per_member ? nq : 0;
     }
   }
-  for (int col = 0; col < c->ncolors; ++col) {
-    const hipError_t e = f32 ? launch_apply_f32(a, c->color_off[col], c->color_off[col + 1], c->stream)
-                             : launch_apply_f64(a, c->color_off[col], c->color_off[col + 1], c->stream);
-    if (e != hipSuccess) return fail(c, SFEM_E_HIP, std::string("apply launch: ") + hipGetErrorString(e));
-  }
+  hipError_t e = f32 ? launch_apply_f32(a, c->stream) : launch_apply_f64(a, c->stream);
+  if (e != hipSuccess) return fail(c, SFEM_E_HIP, std::string("apply launch: ") + hipGetErrorString(e));
+  if (f32)
+    e = launch_assemble<float>(c->d_off, c->d_slot, (const float *)c->evec.p, estride,
+                               (const float *)x, (float *)y, c->ndof, nbatch, part, nblk, c->stream);
+  else
+    e = launch_assemble<double>(c->d_off, c->d_slot, (const double *)c->evec.p, estride,
+                                (const double *)x, (double *)y, c->ndof, nbatch, part, nblk, c->stream);
+  if (e != hipSuccess) return fail(c, SFEM_E_HIP, std::string("assembly launch: ") + hipGetErrorString(e));
   return SFEM_OK;
 }
 
@@ -373,8 +409,7 @@ sfem_status run_pcg(sfem_ctx *c, int op, int nb, const T *b, T *x, bool x0_zero,
   };
   if (!any_active()) return SFEM_OK;
   for (int it = 0; it < maxit; ++it) {
-    if ((st = do_apply(c, op, f32, nb, w.p, w.w)) != SFEM_OK) return st;
-    HIPCHK(c, VecOps<T>::dot(w.p, w.w, w.part, w.nblk, n, nb, s));
+    if ((st = do_apply(c, op, f32, nb, w.p, w.w, w.part, w.nblk)) != SFEM_OK) return st;
     HIPCHK(c, launch_pcg_alpha(w.part, w.nblk, nb, w.sc, s));
     HIPCHK(c, VecOps<T>::update(x, w.p, w.r, w.w, dinv, dms, w.sc, w.part, w.nblk, n, nb, s));
     HIPCHK(c, launch_pcg_beta(w.part, w.nblk, nb, w.sc, s));
@@ -471,7 +506,7 @@ sfem_status sfem_setup(sfem_ctx *c, int p, int q, int64_t nelem, const double *e
     return fail(c, SFEM_E_MESH, "DoFs without elements: every DoF must belong to an element");
   const int n = p + 1;
   const int64_t n3 = (int64_t)n * n * n;
-  if (nelem > (int64_t)INT32_MAX / 8 || nelem * n3 > ((int64_t)1 << 40))
+  if (nelem > (int64_t)INT32_MAX / 8 || nelem * n3 >= (int64_t)INT32_MAX)
     return fail(c, SFEM_E_ARG, "mesh too large");
   HIPCHK(c, hipStreamSynchronize(c->stream));
   free_all(c);
@@ -566,6 +601,24 @@ sfem_status sfem_setup(sfem_ctx *c, int p, int q, int64_t nelem, const double *e
     std::memcpy(&ixyz[(size_t)s * 24], &xyz[(size_t)e * 24], 24 * sizeof(double));
   }
 
+  // ---- DoF -> E-vector slots in internal element order (essential DoFs get none)
+  std::vector<int32_t> coff_dof((size_t)ndof + 1, 0);
+  for (int64_t s = 0; s < nelem; ++s)
+    for (int64_t l = 0; l < n3; ++l) {
+      const int32_t gd = imap[(size_t)(s * n3 + l)];
+      if (gd >= 0) coff_dof[(gd & kDofMask) + 1]++;
+    }
+  for (int64_t gd = 0; gd < ndof; ++gd) coff_dof[gd + 1] += coff_dof[gd];
+  std::vector<int32_t> slots((size_t)coff_dof[ndof]);
+  {
+    std::vector<int32_t> pos(coff_dof.begin(), coff_dof.end() - 1);
+    for (int64_t s = 0; s < nelem; ++s)
+      for (int64_t l = 0; l < n3; ++l) {
+        const int32_t gd = imap[(size_t)(s * n3 + l)];
+        if (gd >= 0) slots[(size_t)pos[gd & kDofMask]++] = (int32_t)(s * n3 + l);
+      }
+  }
+
   // ---- rules
   if (!make_rules(p, q, c->rules)) return fail(c, SFEM_E_HIP, "1D rule construction failed");
   c->p = p;
@@ -583,8 +636,13 @@ sfem_status sfem_setup(sfem_ctx *c, int p, int q, int64_t nelem, const double *e
   if ((st = dalloc(c, &c->d_xyz, nelem * 24)) != SFEM_OK) return st;
   if ((st = dalloc(c, &c->d_qd, nelem * q3 * kQdSlots)) != SFEM_OK) return st;
   if ((st = dalloc(c, &c->d_qd32, nelem * q3 * kQdSlots)) != SFEM_OK) return st;
+  if ((st = dalloc(c, &c->d_off, ndof + 1)) != SFEM_OK) return st;
+  if ((st = dalloc(c, &c->d_slot, (int64_t)slots.size())) != SFEM_OK) return st;
   int *d_bad = nullptr;
   if ((st = dalloc(c, &d_bad, 1)) != SFEM_OK) return st;
+  HIPCHK(c, hipMemcpyAsync(c->d_off, coff_dof.data(), coff_dof.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  if (!slots.empty())
+    HIPCHK(c, hipMemcpyAsync(c->d_slot, slots.data(), slots.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
   if (nelem > 0) {
     HIPCHK(c, hipMemcpyAsync(c->d_map, imap.data(), imap.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->d_perm, perm.data(), perm.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
@@ -844,7 +902,7 @@ sfem_status sfem_get_info(const sfem_ctx *c, sfem_ctx_info *out) {
   out->ndof = c->ndof;
   out->ncolors = c->ncolors;
   out->nfields = c->nfield;
-  out->device_bytes = c->bytes + (int64_t)c->ws.bytes;
+  out->device_bytes = c->bytes + (int64_t)c->ws.bytes + (int64_t)c->evec.bytes;
   return SFEM_OK;
 }
 

@@ -14,11 +14,19 @@
 // between stages live in LDS, one buffer per element.  Several elements share a
 // workgroup (E = 256 / q^2).
 //
-// Scatter: the elements of one launch all have the same color, so no two of them
-// share a DoF.  Each map entry says whether this element is the first (in color
-// order) to write its DoF -- it then stores -- or accumulates onto what an earlier
-// color stored.  No atomics; the result is bitwise deterministic.  Essential DoFs
-// read as 0 in the gather and receive y = x from their first writer.
+// Assembly (no atomics, deterministic): the apply runs in two launches.  The element
+// kernel processes every element in one launch and writes its element vector to an
+// E-vector buffer Y[e][l] (contiguous, coalesced).  The assembly kernel then gives
+// each global DoF to one thread, which sums the E-vector entries of that DoF in a
+// fixed order through a DoF -> E-vector-slot table (owner computes).  Essential DoFs
+// read as 0 in the gather, have no slots, and receive y = x.  Workgroups are mapped
+// to elements so that each of the 8 XCDs works on one contiguous range of elements,
+// which keeps the x values shared by neighbouring elements in that XCD's L2.
+//
+// The diagonal and load vector (set-up time work) still use a colored scatter: the
+// elements of one launch have one color, so no two share a DoF; each map entry says
+// whether the element is the first (in color order) to write the DoF -- it then
+// stores -- or accumulates onto what an earlier color stored.
 //
 // LDS layouts inside an element buffer (a, b, c: quadrature indices along
 // xi_1..3; i, j, k: node indices):
@@ -273,14 +281,24 @@ __device__ __forceinline__ void scatter_e(const T *buf, int t, bool active, cons
   __syncthreads();
 }
 
-// OP: 0 mass, 1 diffusion, 2 helmholtz (matches sfem_op)
+// Element index of this workgroup's first element such that XCD k (workgroups are
+// dispatched round-robin over the 8 XCDs) gets one contiguous range of blocks.
+__device__ __forceinline__ int64_t xcd_block(int64_t nblk) {
+  const int64_t b = blockIdx.x;
+  const int64_t xcd = b & 7, k = b >> 3;
+  const int64_t q8 = nblk >> 3, r8 = nblk & 7;
+  return xcd * q8 + (xcd < r8 ? xcd : r8) + k;
+}
+
+// OP: 0 mass, 1 diffusion, 2 helmholtz (matches sfem_op).  Writes the element vectors
+// Y[m][e][l] of every non-essential local node.
 template <int P, typename T, int OP>
 __global__ void __launch_bounds__(Dims<P>::THREADS)
 apply_kernel(const Tab<P, T> tb, const int32_t *__restrict__ map, const T *__restrict__ qd,
-             int64_t qd_mstride, const T *__restrict__ nu, int64_t nu_mstride, int64_t e_begin,
-             int64_t e_end, int nbatch, int64_t ndof, const T *__restrict__ x, T *__restrict__ y) {
+             int64_t qd_mstride, const T *__restrict__ nu, int64_t nu_mstride, int64_t nelem,
+             int nbatch, int64_t ndof, const T *__restrict__ x, T *__restrict__ Y) {
   using D = Dims<P>;
-  constexpr int N = D::N, Q = D::Q, Q2 = D::Q2, Q3 = D::Q3;
+  constexpr int N = D::N, Q = D::Q, Q2 = D::Q2, Q3 = D::Q3, N3 = D::N3;
   constexpr int TPE = D::TPE, E = D::E;
   constexpr bool MASS = (OP == 0) || (OP == 2);
   constexpr bool DIFF = (OP == 1) || (OP == 2);
@@ -288,15 +306,15 @@ apply_kernel(const Tab<P, T> tb, const int32_t *__restrict__ map, const T *__res
   __shared__ T smem[E * D::BUF];
   const int le = threadIdx.x / TPE;
   const int t = threadIdx.x - le * TPE;
-  const int64_t e = e_begin + (int64_t)blockIdx.x * E + le;
-  const bool active = e < e_end;
-  const int64_t es = active ? e : e_begin;
+  const int64_t nblk = (nelem + E - 1) / E;
+  const int64_t e = xcd_block(nblk) * E + le;
+  const bool active = e < nelem;
+  const int64_t es = active ? e : 0;
   T *buf = smem + le * D::BUF;
-  const int32_t *emap = map + es * (int64_t)D::N3;
+  const int32_t *emap = map + es * (int64_t)N3;
 
   for (int m = 0; m < nbatch; ++m) {
     const T *xm = x + (int64_t)m * ndof;
-    T *ym = y + (int64_t)m * ndof;
 
     gather_e<P, T>(buf, t, active, emap, xm);
     fwd_x<P, T, DIFF>(buf, t, tb);
@@ -370,34 +388,37 @@ apply_kernel(const Tab<P, T> tb, const int32_t *__restrict__ map, const T *__res
 
     bwd_y<P, T, DIFF>(buf, t, tb);
     bwd_x<P, T, DIFF>(buf, t, tb);
-    scatter_e<P, T>(buf, t, active, emap, ym, [&](int64_t g) { return xm[g]; });
+    if (active) {
+      T *Ye = Y + ((int64_t)m * nelem + e) * N3;
+      for (int l = t; l < N3; l += TPE) Ye[l] = buf[l];
+    }
+    __syncthreads();
   }
 }
 
 template <int P, typename T>
-hipError_t launch_apply_pt(const ApplyArgs &a, int64_t e_begin, int64_t e_end, hipStream_t s) {
+hipError_t launch_apply_pt(const ApplyArgs &a, hipStream_t s) {
   using D = Dims<P>;
-  const int64_t ne = e_end - e_begin;
-  if (ne <= 0) return hipSuccess;
+  if (a.nelem <= 0 || a.nbatch <= 0) return hipSuccess;
   const Tab<P, T> tb = make_tab<P, T>(a.B, a.G);
-  dim3 grid((unsigned)((ne + D::E - 1) / D::E));
+  dim3 grid((unsigned)((a.nelem + D::E - 1) / D::E));
   dim3 block(D::THREADS);
   const T *qd = (const T *)a.qd;
   const T *nu = (const T *)a.nu;
   const T *x = (const T *)a.x;
-  T *y = (T *)a.y;
+  T *Y = (T *)a.evec;
   switch (a.op) {
     case SFEM_MASS:
       hipLaunchKernelGGL((apply_kernel<P, T, 0>), grid, block, 0, s, tb, a.map, qd, a.qd_mstride,
-                         nu, a.nu_mstride, e_begin, e_end, a.nbatch, a.ndof, x, y);
+                         nu, a.nu_mstride, a.nelem, a.nbatch, a.ndof, x, Y);
       break;
     case SFEM_DIFFUSION:
       hipLaunchKernelGGL((apply_kernel<P, T, 1>), grid, block, 0, s, tb, a.map, qd, a.qd_mstride,
-                         nu, a.nu_mstride, e_begin, e_end, a.nbatch, a.ndof, x, y);
+                         nu, a.nu_mstride, a.nelem, a.nbatch, a.ndof, x, Y);
       break;
     default:
       hipLaunchKernelGGL((apply_kernel<P, T, 2>), grid, block, 0, s, tb, a.map, qd, a.qd_mstride,
-                         nu, a.nu_mstride, e_begin, e_end, a.nbatch, a.ndof, x, y);
+                         nu, a.nu_mstride, a.nelem, a.nbatch, a.ndof, x, Y);
       break;
   }
   return hipGetLastError();

@@ -63,13 +63,21 @@ struct ApplyArgs {
   int64_t nu_mstride;
   int64_t ndof;
   int nbatch;
+  int64_t nelem;
   const void *x;
-  void *y;
+  void *evec;               // [nbatch][nelem][n^3] element vectors (output)
   const double *B, *G;
 };
-// Launch the apply over elements [e_begin, e_end) of one color.
-hipError_t launch_apply_f64(const ApplyArgs &a, int64_t e_begin, int64_t e_end, hipStream_t s);
-hipError_t launch_apply_f32(const ApplyArgs &a, int64_t e_begin, int64_t e_end, hipStream_t s);
+// Element phase of the apply over all elements (writes the E-vector).
+hipError_t launch_apply_f64(const ApplyArgs &a, hipStream_t s);
+hipError_t launch_apply_f32(const ApplyArgs &a, hipStream_t s);
+// Assembly phase: y[g] = sum of the E-vector entries of DoF g (slots off[g]..off[g+1]),
+// y[g] = x[g] for essential DoFs (no slots).  With part != null also the partial sums
+// of x . y (the p^T A p of CG) over nblk blocks.
+template <typename T>
+hipError_t launch_assemble(const int32_t *off, const int32_t *slot, const T *evec, int64_t estride,
+                           const T *x, T *y, int64_t n, int nb, double *part, int nblk,
+                           hipStream_t s);
 
 struct DiagArgs {
   int p;

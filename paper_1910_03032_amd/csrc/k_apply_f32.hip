@@ -3,8 +3,8 @@
 
 namespace sfem {
 
-hipError_t launch_apply_f32(const ApplyArgs &a, int64_t e_begin, int64_t e_end, hipStream_t s) {
-#define SFEM_CALL(P) launch_apply_pt<P, float>(a, e_begin, e_end, s)
+hipError_t launch_apply_f32(const ApplyArgs &a, hipStream_t s) {
+#define SFEM_CALL(P) launch_apply_pt<P, float>(a, s)
   SFEM_DISPATCH_P(a.p, SFEM_CALL)
 #undef SFEM_CALL
 }

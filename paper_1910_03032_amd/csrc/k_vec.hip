@@ -251,6 +251,32 @@ __global__ void ir_accum_kernel(double *__restrict__ x, const float *__restrict_
     x[off + i] += sc * (double)d[off + i];
 }
 
+// y[g] = sum of E-vector entries of DoF g in slot order; y[g] = x[g] for essential DoFs
+// (they have no slots).  DOT: also the partial sums of x . y.
+template <typename T, bool DOT>
+__global__ void assemble_kernel(const int32_t *__restrict__ off, const int32_t *__restrict__ slot,
+                                const T *__restrict__ Y, int64_t estride, const T *__restrict__ x,
+                                T *__restrict__ y, int64_t n, double *__restrict__ part, int nblk) {
+  const int m = blockIdx.y;
+  const T *Ym = Y + (int64_t)m * estride;
+  const T *xm = x + (int64_t)m * n;
+  T *ym = y + (int64_t)m * n;
+  double v[1] = {0.0};
+  for (int64_t g = (int64_t)blockIdx.x * VB + threadIdx.x; g < n; g += (int64_t)nblk * VB) {
+    const int32_t a = off[g], b = off[g + 1];
+    T s;
+    if (a == b) {
+      s = xm[g];
+    } else {
+      s = Ym[slot[a]];
+      for (int32_t k = a + 1; k < b; ++k) s += Ym[slot[k]];
+    }
+    ym[g] = s;
+    if constexpr (DOT) v[0] += (double)xm[g] * (double)s;
+  }
+  if constexpr (DOT) write_part<1>(v, part, nblk);
+}
+
 template <typename T>
 __global__ void fill_kernel(T *__restrict__ p, T v, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n;
@@ -326,6 +352,26 @@ hipError_t VecOps<T>::recip(const double *d, T *out, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL((recip_kernel<T>), dim3(grid_for(n)), dim3(VB), 0, s, d, out, n);
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_assemble(const int32_t *off, const int32_t *slot, const T *evec, int64_t estride,
+                           const T *x, T *y, int64_t n, int nb, double *part, int nblk,
+                           hipStream_t s) {
+  if (n <= 0 || nb <= 0) return hipSuccess;
+  if (part)
+    hipLaunchKernelGGL((assemble_kernel<T, true>), dim3(nblk, nb), dim3(VB), 0, s, off, slot, evec,
+                       estride, x, y, n, part, nblk);
+  else
+    hipLaunchKernelGGL((assemble_kernel<T, false>), dim3(vec_nblk(n), nb), dim3(VB), 0, s, off,
+                       slot, evec, estride, x, y, n, part, vec_nblk(n));
+  return hipGetLastError();
+}
+template hipError_t launch_assemble<double>(const int32_t *, const int32_t *, const double *,
+                                            int64_t, const double *, double *, int64_t, int,
+                                            double *, int, hipStream_t);
+template hipError_t launch_assemble<float>(const int32_t *, const int32_t *, const float *, int64_t,
+                                           const float *, float *, int64_t, int, double *, int,
+                                           hipStream_t);
 
 template struct VecOps<double>;
 template struct VecOps<float>;
