@@ -2,13 +2,18 @@
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 
-One timed step = one FP64 Helmholtz apply y = (alpha M + beta K(nu)) x over the whole
-workload (gather, three contractions, quadrature function, three transposed
-contractions, colored scatter).  `value` is the FP64 apply throughput in GDoF/s
-(global DoFs per second) with every input resident in HBM.  The same run also
-times the FP32 apply, the FP64 Jacobi-PCG solve and the FP32-inner iterative
-refinement solve to relative residual 1e-10, and the adjoint gradient kernel; the
-CPU oracle is timed on a bounded sample of the same workload.  Prints one JSON line.
+Default workload `helmholtz_p4_32e` (32^3 hexes, p = 4, q = 6, 2.1M DoFs, alpha = 1e3,
+beta = 1, nu(x) = 1 + 0.5 sin(2 pi x) cos(2 pi y)).  One timed step = one FP64 Helmholtz
+apply y = (alpha M + beta K(nu)) x over the whole workload (gather, three
+contractions, quadrature function, three transposed contractions, atomic-free
+assembly).  `value` is that apply's throughput in GDoF/s (global DoFs per second)
+with every input resident in HBM.  The same run times the FP32 apply, the FP64
+Jacobi-PCG solve and the FP32-inner iterative-refinement solve to relative residual
+1e-10, and the adjoint gradient kernel; the CPU oracle is timed on a bounded sample of
+the same workload.  Prints one JSON line.
+
+Other workloads (`--workload`): vector_helmholtz_p7_24e, adjoint_p5_20e, large_p8_40e,
+poisson_p2_4e, and `sweep` (FP64/FP32 apply for p = 4..8 on meshes of 15-33M DoFs).
 """
 from __future__ import annotations
 
@@ -18,13 +23,12 @@ import os
 import sys
 import time
 
-import numpy as np
-
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "GDoF/s of sum-factorized Helmholtz apply (FP64 vs FP32+IR); PCG time to 1e-10"
 HBM_PEAK_GBS = 8000.0
+SWEEP = [(4, 64), (5, 50), (6, 45), (7, 40), (8, 40)]  # (p, elements per direction)
 
 
 def parse():
@@ -37,6 +41,8 @@ def parse():
     ap.add_argument("--no-solves", action="store_true")
     ap.add_argument("--cpu-elements", type=int, default=8192,
                     help="elements of the workload the CPU oracle applies to (bounded sample)")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="only run a plain device copy of this many MB (hardware-counter calibration)")
     return ap.parse_args()
 
 
@@ -44,10 +50,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(nelem, p, ndof, s, nqd=7, nb=1):
-    """Bytes an apply must move: quadrature data once, x read and y written once, the map."""
+def algorithmic_bytes(nelem, p, ndof, s, nb=1, nqd=7, nb_qd=1):
+    """Bytes an apply must move: quadrature data once (per distinct field), x read and
+    y written once per member, the element->DoF map once."""
     q = p + 2
-    return nelem * q ** 3 * nqd * s + nb * 2 * ndof * s + nelem * (p + 1) ** 3 * 4
+    return nb_qd * nelem * q ** 3 * nqd * s + nb * 2 * ndof * s + nelem * (p + 1) ** 3 * 4
 
 
 def flops_helmholtz(nelem, p, nb=1):
@@ -55,135 +62,95 @@ def flops_helmholtz(nelem, p, nb=1):
     return nelem * nb * (2 * (4 * q * n ** 3 + 6 * q * q * n * n + 8 * q ** 3 * n) + 25 * q ** 3)
 
 
-def main():
-    a = parse()
-    if a.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of "
-                                   "this build (the sharding design is described in DESIGN.md)",
-                          "n_gpus": a.gpus}))
-        return 2
+def copy_calibration(mb, reps=5):
+    """A plain device-to-device copy of known size: reference for the HBM byte counters."""
     import torch
-    from paper_1910_03032_amd import Operator, HELMHOLTZ
-    from workloads import BoxMesh, WORKLOADS, nu_c2, normal, rhs_uniform
+    n = mb * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "reps": reps,
+                      "us": round(ms * 1e3, 1), "GBps": round(2 * n * 8 / (ms * 1e-3) / 1e9, 1)}),
+          flush=True)
+    return 0
 
-    wl = WORKLOADS[a.workload]
-    ne, p, alpha, beta = wl["ne"], wl["p"], wl["alpha"], wl["beta"]
-    q = p + 2
-    torch.cuda.set_device(0)
-    dev = torch.device("cuda", 0)
-    t0 = time.time()
-    m = BoxMesh(ne, p)
-    op = Operator(m.elem_xyz, m.elem_dofs, m.ndof, p, ess=m.ess)
-    xq = op.qpoint_coords()
-    nu = nu_c2(xq[0], xq[1], xq[2])
-    op.set_coeffs(alpha, beta, nu)
-    info = op.info()
-    log(f"[bench] setup {time.time() - t0:.1f}s: {a.workload} nelem={m.nelem} p={p} ndof={m.ndof} "
-        f"colors={info['ncolors']} device bytes={info['device_bytes'] / 1e9:.2f} GB")
-    N = m.ndof
-    x64 = torch.as_tensor(normal(N, seed=1), device=dev)
-    y64 = torch.empty_like(x64)
-    x32 = x64.float()
-    y32 = torch.empty_like(x32)
-    stream = torch.cuda.current_stream(dev)
 
-    def timed(fn, steps, warmup):
+class Bench:
+    def __init__(self, ne, p, alpha, beta, nu="c2"):
+        import torch
+        from paper_1910_03032_amd import Operator
+        from workloads import BoxMesh, nu_c2
+        self.torch = torch
+        self.dev = torch.device("cuda", 0)
+        t0 = time.time()
+        self.m = m = BoxMesh(ne, p)
+        self.ne, self.p, self.q, self.alpha, self.beta = ne, p, p + 2, alpha, beta
+        self.op = Operator(m.elem_xyz, m.elem_dofs, m.ndof, p, ess=m.ess)
+        if nu == "c2":
+            xq = self.op.qpoint_coords()
+            self.op.set_coeffs(alpha, beta, nu_c2(xq[0], xq[1], xq[2]))
+        else:
+            self.op.set_coeffs(alpha, beta, None)
+        self.info = self.op.info()
+        self.stream = torch.cuda.current_stream(self.dev)
+        log(f"[bench] setup {time.time() - t0:.1f}s: {ne}^3 p={p} ndof={m.ndof} "
+            f"device bytes={self.info['device_bytes'] / 1e9:.2f} GB")
+
+    def timed(self, fn, steps, warmup):
+        torch = self.torch
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
+        e0.record(self.stream)
         for _ in range(steps):
             fn()
-        e1.record(stream)
+        e1.record(self.stream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps  # ms
 
-    # ---- timed region: K FP64 applies
-    ms64 = timed(lambda: op.apply(x64, op=HELMHOLTZ, out=y64), a.steps, a.warmup)
-    gdofs64 = N / (ms64 * 1e-3) / 1e9
-    log(f"[bench] fp64 apply {ms64 * 1e3:.1f} us  {gdofs64:.2f} GDoF/s")
-    ms32 = timed(lambda: op.apply(x32, op=HELMHOLTZ, out=y32), a.steps, a.warmup)
-    gdofs32 = N / (ms32 * 1e-3) / 1e9
-    log(f"[bench] fp32 apply {ms32 * 1e3:.1f} us  {gdofs32:.2f} GDoF/s")
+    def apply_rate(self, dtype, nb=1, steps=50, warmup=10):
+        from paper_1910_03032_amd import HELMHOLTZ
+        from workloads import normal
+        torch = self.torch
+        N = self.m.ndof
+        x = torch.as_tensor(normal(nb * N, seed=1), device=self.dev)
+        x = (x.reshape(nb, N) if nb > 1 else x).to(dtype)
+        y = torch.empty_like(x)
+        ms = self.timed(lambda: self.op.apply(x, op=HELMHOLTZ, out=y), steps, warmup)
+        s = 8 if dtype == torch.float64 else 4
+        nbytes = algorithmic_bytes(self.m.nelem, self.p, N, s, nb=nb)
+        return {"us": round(ms * 1e3, 2), "GDoF/s": round(nb * N / (ms * 1e-3) / 1e9, 3),
+                "algorithmic_GBps": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "algorithmic_bytes": nbytes}
 
-    ncol = info["ncolors"]
-    bytes64 = algorithmic_bytes(m.nelem, p, N, 8)
-    bytes32 = algorithmic_bytes(m.nelem, p, N, 4)
-    # one apply = one launch of the apply kernel per element color
-    per_launch_us = ms64 * 1e3 / ncol
-    achieved = bytes64 / (ms64 * 1e-3) / 1e9
-    roofline = {
-        "bound": "hbm",
-        "kernel": f"apply_kernel<P={p}, double, helmholtz>",
-        "achieved": round(achieved, 1),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
-        "algorithmic_bytes_per_apply": bytes64,
-        "launches_per_apply": ncol,
-        "avg_launch_us": round(per_launch_us, 2),
-        "fp64_flop_rate_tflops": round(flops_helmholtz(m.nelem, p) / (ms64 * 1e-3) / 1e12, 2),
-    }
-    out = {
-        "metric": METRIC,
-        "value": round(gdofs64, 3),
-        "unit": "GDoF/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": round(ms64, 5),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic (seeded perturbed hex mesh, x ~ N(0,1))",
-        "config": {"workload": a.workload, "elements": f"{ne}^3", "p": p, "q": q, "ndof": N,
-                   "alpha": alpha, "beta": beta, "nu": "1+0.5 sin(2 pi x) cos(2 pi y) at quadrature points",
-                   "step": "one FP64 Helmholtz apply"},
-        "roofline": roofline,
-        "fp32_apply": {"value": round(gdofs32, 3), "unit": "GDoF/s", "us": round(ms32 * 1e3, 1),
-                       "algorithmic_GBps": round(bytes32 / (ms32 * 1e-3) / 1e9, 1),
-                       "note": "FP32 working set fits the 256 MB last-level cache"
-                       if bytes32 < 256e6 else ""},
-    }
-
-    if not a.no_solves:
-        b = torch.as_tensor(rhs_uniform(m, seed=1)[0], device=dev)
-        solves = {}
-        for name, mode in (("pcg_fp64", 0), ("pcg_fp32_ir", 1)):
-            best = None
-            for rep in range(3):
-                torch.cuda.synchronize()
-                t = time.perf_counter()
-                xs, res = op.pcg(b, rtol=1e-10, mode=mode, inner_rtol=1e-5, check_every=16)
-                torch.cuda.synchronize()
-                dt = time.perf_counter() - t
-                best = dt if best is None else min(best, dt)
-            solves[name] = {"ms": round(best * 1e3, 2), "iters": res.iters[0], "outer": res.outer[0],
-                            "true_rel_res": res.true_rel_res[0], "status": res.status}
-            log(f"[bench] {name}: {best * 1e3:.1f} ms {res}")
-        out["pcg_fp64"] = solves["pcg_fp64"]
-        out["pcg_fp32_ir"] = solves["pcg_fp32_ir"]
-        out["ir_speedup"] = round(solves["pcg_fp64"]["ms"] / solves["pcg_fp32_ir"]["ms"], 3)
-        # adjoint gradient kernel (u, lam from the solve)
-        lam = xs.clone()
-        msg = timed(lambda: op.grad_nu(xs, lam), 10, 2)
-        out["adjoint_grad"] = {"us": round(msg * 1e3, 1),
-                               "GBps": round((m.nelem * q ** 3 * 7 * 8 + 2 * N * 8 + m.nelem * q ** 3 * 8)
-                                             / (msg * 1e-3) / 1e9, 1)}
-
-    if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(m, p, alpha, beta, min(a.cpu_elements, m.nelem))
-    print(json.dumps(out), flush=True)
-    return 0
+    def solve(self, b, mode, reps=3, **kw):
+        torch = self.torch
+        best, res, xs = None, None, None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            xs, res = self.op.pcg(b, rtol=1e-10, mode=mode, inner_rtol=1e-5, check_every=16, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            best = dt if best is None else min(best, dt)
+        return xs, {"ms": round(best * 1e3, 2), "iters": res.iters, "outer": res.outer,
+                    "true_rel_res": res.true_rel_res, "status": res.status}
 
 
 def cpu_baseline(m, p, alpha, beta, sub):
     """The oracle's dense (non-sum-factorized) FP64 apply on the first `sub` elements."""
     from oracle import Discretization
+    from workloads import nu_c2, normal
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
@@ -191,7 +158,6 @@ def cpu_baseline(m, p, alpha, beta, sub):
         threads = os.cpu_count() or 1
     d = Discretization(m.elem_xyz[:sub], m.elem_dofs[:sub], m.ess, m.ndof, p, p + 2)
     xq = d.qpoint_coords()
-    from workloads import nu_c2, normal
     nu = nu_c2(xq[..., 0], xq[..., 1], xq[..., 2])
     x = normal(m.ndof, seed=1)
     t = time.perf_counter()
@@ -202,6 +168,192 @@ def cpu_baseline(m, p, alpha, beta, sub):
     return {"value": round(dofs / dt / 1e9, 7), "unit": "GDoF/s", "cores": threads, "kind": "oracle",
             "sample": f"dense element apply over {sub} of {m.nelem} elements "
                       f"({dt:.2f} s), scaled by the element fraction"}
+
+
+def run_main(a, wl):
+    """The metric's configuration: FP64 apply as the timed step, plus solves."""
+    from workloads import rhs_uniform
+    torch = __import__("torch")
+    B = Bench(wl["ne"], wl["p"], wl["alpha"], wl["beta"])
+    m, p, q, N = B.m, B.p, B.q, B.m.ndof
+    r64 = B.apply_rate(torch.float64, steps=a.steps, warmup=a.warmup)
+    log(f"[bench] fp64 apply {r64['us']} us  {r64['GDoF/s']} GDoF/s")
+    r32 = B.apply_rate(torch.float32, steps=a.steps, warmup=a.warmup)
+    log(f"[bench] fp32 apply {r32['us']} us  {r32['GDoF/s']} GDoF/s")
+    ms64 = r64["us"] * 1e-3
+    achieved = r64["algorithmic_bytes"] / (ms64 * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": r64["GDoF/s"],
+        "unit": "GDoF/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms64, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded perturbed hex mesh, x ~ N(0,1))",
+        "config": {"workload": a.workload, "elements": f"{B.ne}^3", "p": p, "q": q, "ndof": N,
+                   "alpha": B.alpha, "beta": B.beta,
+                   "nu": "1+0.5 sin(2 pi x) cos(2 pi y) at quadrature points",
+                   "step": "one FP64 Helmholtz apply"},
+        # one apply = the element kernel + the assembly kernel, on one stream
+        "roofline": {
+            "bound": "hbm",
+            "kernel": f"Helmholtz apply: apply_kernel<{p}, double, 2> + assemble_kernel<double>",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "algorithmic_bytes_per_apply": r64["algorithmic_bytes"],
+            "launches_per_apply": 2,
+            "apply_us": r64["us"],
+            "fp64_flop_rate_tflops": round(flops_helmholtz(m.nelem, p) / (ms64 * 1e-3) / 1e12, 2),
+        },
+        "fp32_apply": dict(r32, value=r32["GDoF/s"], unit="GDoF/s",
+                           note="FP32 working set fits the 256 MB last-level cache"
+                           if r32["algorithmic_bytes"] < 256e6 else ""),
+    }
+    if not a.no_solves:
+        b = torch.as_tensor(rhs_uniform(m, seed=1)[0], device=B.dev)
+        xs, s64 = B.solve(b, 0)
+        log(f"[bench] pcg fp64 {s64}")
+        _, sir = B.solve(b, 1)
+        log(f"[bench] pcg fp32+IR {sir}")
+        out["pcg_fp64"] = s64
+        out["pcg_fp32_ir"] = sir
+        out["ir_speedup"] = round(s64["ms"] / sir["ms"], 3)
+        lam = xs.clone()
+        msg = B.timed(lambda: B.op.grad_nu(xs, lam), 10, 2)
+        gbytes = m.nelem * q ** 3 * 6 * 8 + 2 * N * 8 + m.nelem * q ** 3 * 8 + m.nelem * (p + 1) ** 3 * 4
+        out["adjoint_grad_kernel"] = {"us": round(msg * 1e3, 1),
+                                      "algorithmic_GBps": round(gbytes / (msg * 1e-3) / 1e9, 1)}
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(m, p, B.alpha, B.beta, min(a.cpu_elements, m.nelem))
+    return out
+
+
+def run_vector(a, wl):
+    """3-component Helmholtz: batched apply and FP64 PCG vs FP32-inner IR to 1e-10."""
+    from workloads import rhs_uniform
+    torch = __import__("torch")
+    B = Bench(wl["ne"], wl["p"], wl["alpha"], wl["beta"])
+    nb = wl["nbatch"]
+    out = {"workload": a.workload, "p": B.p, "elements": f"{B.ne}^3", "ndof_per_component": B.m.ndof,
+           "components": nb,
+           "apply_fp64": B.apply_rate(torch.float64, nb=nb, steps=a.steps, warmup=a.warmup),
+           "apply_fp32": B.apply_rate(torch.float32, nb=nb, steps=a.steps, warmup=a.warmup)}
+    b = torch.as_tensor(rhs_uniform(B.m, seed=1, nbatch=nb), device=B.dev)
+    x64, out["pcg_fp64"] = B.solve(b, 0, reps=2)
+    xir, out["pcg_fp32_ir"] = B.solve(b, 1, reps=2)
+    out["ir_speedup"] = round(out["pcg_fp64"]["ms"] / out["pcg_fp32_ir"]["ms"], 3)
+    out["ir_vs_fp64_solution_rel_diff"] = float((xir - x64).norm() / x64.norm())
+    return out
+
+
+def run_adjoint(a, wl):
+    """Forward solve, adjoint solve and gradient kernel for nu ~ U(0.5, 2) per point."""
+    from workloads import rhs_uniform, nu_uniform
+    torch = __import__("torch")
+    B = Bench(wl["ne"], wl["p"], wl["alpha"], wl["beta"], nu=None)
+    m, op = B.m, B.op
+    nu = torch.as_tensor(nu_uniform(m.nelem, B.q, seed=2), device=B.dev)
+    nu_star = torch.as_tensor(nu_uniform(m.nelem, B.q, seed=3), device=B.dev)
+    b = torch.as_tensor(rhs_uniform(m, seed=1)[0], device=B.dev)
+    ess = torch.as_tensor(m.ess.astype(bool), device=B.dev)
+    op.set_coeffs(B.alpha, B.beta, nu_star)
+    u_t, _ = op.pcg(b, rtol=1e-12)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    op.set_coeffs(B.alpha, B.beta, nu)
+    u, r1 = op.pcg(b, rtol=1e-10, check_every=16)
+    lam, r2 = op.pcg(torch.where(ess, torch.zeros_like(u), u - u_t), rtol=1e-10, check_every=16)
+    g = op.grad_nu(u, lam)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    msg = B.timed(lambda: op.grad_nu(u, lam), 10, 2)
+    return {"workload": a.workload, "p": B.p, "elements": f"{B.ne}^3", "ndof": m.ndof,
+            "gradient_total_ms": round(dt * 1e3, 2), "forward_iters": r1.iters[0],
+            "adjoint_iters": r2.iters[0], "grad_kernel_us": round(msg * 1e3, 1),
+            "grad_norm": float(g.norm())}
+
+
+def run_large(a, wl):
+    """p = 8, 33M DoFs: FP32+IR vs FP64 PCG to 1e-10, and the 4-field batched gradient."""
+    from workloads import rhs_uniform, nu_uniform
+    torch = __import__("torch")
+    B = Bench(wl["ne"], wl["p"], wl["alpha"], wl["beta"])
+    m, op = B.m, B.op
+    out = {"workload": a.workload, "p": B.p, "elements": f"{B.ne}^3", "ndof": m.ndof,
+           "apply_fp64": B.apply_rate(torch.float64, steps=20, warmup=3),
+           "apply_fp32": B.apply_rate(torch.float32, steps=20, warmup=3)}
+    b = torch.as_tensor(rhs_uniform(m, seed=1)[0], device=B.dev)
+    _, out["pcg_fp64"] = B.solve(b, 0, reps=1)
+    _, out["pcg_fp32_ir"] = B.solve(b, 1, reps=1)
+    out["ir_speedup"] = round(out["pcg_fp64"]["ms"] / out["pcg_fp32_ir"]["ms"], 3)
+    log(f"[bench] large solves {out['pcg_fp64']} {out['pcg_fp32_ir']}")
+    nus = torch.stack([torch.as_tensor(nu_uniform(m.nelem, B.q, seed=200 + k).reshape(-1), device=B.dev)
+                       for k in range(4)])
+    ess = torch.as_tensor(m.ess.astype(bool), device=B.dev)
+    B4 = b.expand(4, -1).contiguous()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    op.set_coeffs(B.alpha, B.beta, nus)
+    U, r1 = op.pcg(B4, rtol=1e-10, mode=1, check_every=16)
+    L, r2 = op.pcg(torch.where(ess, torch.zeros_like(U), U), rtol=1e-10, mode=1, check_every=16)
+    G = op.grad_nu(U, L)
+    torch.cuda.synchronize()
+    out["batched_gradient_4_fields"] = {"ms": round((time.perf_counter() - t) * 1e3, 1),
+                                        "forward_inner_iters": r1.iters, "adjoint_inner_iters": r2.iters,
+                                        "grad_norms": [float(G[k].norm()) for k in range(4)]}
+    return out
+
+
+def run_sweep(a):
+    torch = __import__("torch")
+    rows = []
+    for p, ne in SWEEP:
+        B = Bench(ne, p, 1e3, 1.0)
+        r64 = B.apply_rate(torch.float64, steps=20, warmup=3)
+        r32 = B.apply_rate(torch.float32, steps=20, warmup=3)
+        rows.append({"p": p, "elements": f"{ne}^3", "ndof": B.m.ndof, "fp64": r64, "fp32": r32})
+        log(f"[bench] sweep p={p}: fp64 {r64['GDoF/s']} GDoF/s ({r64['hbm_frac']:.3f} of HBM), "
+            f"fp32 {r32['GDoF/s']} GDoF/s")
+        B.op.close()
+        del B
+        torch.cuda.empty_cache()
+    return {"workload": "sweep", "rows": rows}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of "
+                                   "this build (the sharding design is described in DESIGN.md)",
+                          "n_gpus": a.gpus}))
+        return 2
+    if a.copy_mb > 0:
+        return copy_calibration(a.copy_mb)
+    import torch
+    from workloads import WORKLOADS
+    torch.cuda.set_device(0)
+    if a.workload == "sweep":
+        out = run_sweep(a)
+    else:
+        wl = WORKLOADS[a.workload]
+        if a.workload == "vector_helmholtz_p7_24e":
+            out = run_vector(a, wl)
+        elif a.workload == "adjoint_p5_20e":
+            out = run_adjoint(a, wl)
+        elif a.workload == "large_p8_40e":
+            out = run_large(a, wl)
+        else:
+            out = run_main(a, wl)
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 if __name__ == "__main__":

@@ -103,9 +103,9 @@ const char *sfem_last_error(const sfem_ctx *ctx);
  *              values in [0, ndof), no DoF twice in one element, every DoF used
  *   ndof       number of global DoFs (< 2^30)
  *   ess_mask   [ndof] uint8, nonzero = essential DoF (device), or NULL (none)
- * Computes per quadrature point w|J| and w|J| J^{-1} J^{-T} (FP64), colors the
- * elements so that no two elements of one color share a DoF, and resets the
- * coefficients to alpha = 1, beta = 1, nu = 1.  Returns SFEM_E_MESH if some
+ * Computes per quadrature point w|J| and w|J| J^{-1} J^{-T} (FP64), classifies the
+ * DoFs (owned by one element, or shared and summed by an assembly pass without
+ * atomics), and resets the coefficients to alpha = 1, beta = 1, nu = 1.  Returns SFEM_E_MESH if some
  * det J <= 0 or the map is invalid.  May be called again to replace the mesh. */
 sfem_status sfem_setup(sfem_ctx *ctx, int p, int q, int64_t nelem, const double *elem_xyz,
                        const int32_t *elem_dofs, int64_t ndof, const uint8_t *ess_mask);
@@ -173,9 +173,10 @@ sfem_status sfem_grad_nu(sfem_ctx *ctx, int nbatch, const double *u, const doubl
 typedef struct {
   int p, q;
   int64_t nelem, ndof;
-  int ncolors;
+  int compact;            /* 1: only element-surface nodes pass through the E-vector */
   int nfields;            /* nu fields set by sfem_set_coeffs (1 when nu is NULL) */
   int64_t device_bytes;   /* device memory held by the context */
+  int64_t nassembled;     /* DoFs shared by several elements, plus essential DoFs */
 } sfem_ctx_info;
 
 /* Sizes and counters of a set-up context (host struct). */

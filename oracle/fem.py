@@ -101,6 +101,8 @@ class Discretization:
             per = self.nqp * self.nloc * 3 * 8
             chunk = max(1, int(64e6 // per))
         self.chunk = chunk
+        # geometry-only loops (J, det, coordinates: ~15 values per point)
+        self.gchunk = max(1, int(64e6 // (self.nqp * 15 * 8)))
 
     # ---------------- geometry ----------------
     def geometry(self, e0, e1):
@@ -113,17 +115,17 @@ class Discretization:
         return det, inv, xq
 
     def qpoint_coords(self):
+        """Physical quadrature points x(xi_Q) of the trilinear map: [NE, Q, 3]."""
         out = np.empty((self.nelem, self.nqp, 3))
-        for e0 in range(0, self.nelem, self.chunk):
-            e1 = min(self.nelem, e0 + self.chunk)
-            _, _, xq = self.geometry(e0, e1)
-            out[e0:e1] = xq
+        for e0 in range(0, self.nelem, self.gchunk):
+            e1 = min(self.nelem, e0 + self.gchunk)
+            out[e0:e1] = np.einsum("cvr,Qv->cQr", self.elem_xyz[e0:e1], self.Ntri)
         return out
 
     def min_detJ(self):
         m = np.inf
-        for e0 in range(0, self.nelem, self.chunk):
-            e1 = min(self.nelem, e0 + self.chunk)
+        for e0 in range(0, self.nelem, self.gchunk):
+            e1 = min(self.nelem, e0 + self.gchunk)
             det, _, _ = self.geometry(e0, e1)
             m = min(m, det.min())
         return m
@@ -194,6 +196,17 @@ class Discretization:
         y[..., self.ess] = x[..., self.ess]
         return y
 
+    def element_row(self, e, l, alpha, beta, nu=None):
+        """Row l of A_e: sum_Q w|J| (alpha phi_l phi_m + beta nu grad phi_l . grad phi_m) over m."""
+        det, inv, _ = self.geometry(e, e + 1)
+        nuc = self._nu_chunk(nu, e, e + 1)[0]
+        wd = self.Wq * det[0]
+        row = alpha * (wd * self.Phi[:, l]) @ self.Phi
+        if beta != 0.0:
+            gp = np.einsum("Qdr,Qmd->Qmr", inv[0], self.dPhi)  # physical gradients [Q, m, r]
+            row = row + beta * np.einsum("Q,Qr,Qmr->m", wd * nuc, gp[:, l, :], gp)
+        return row
+
     def apply_rows(self, rows, x, alpha, beta, nu=None):
         """(A_c x)[rows] for a few rows, summing the element rows that contain each DoF."""
         rows = np.asarray(rows, dtype=np.int64)
@@ -211,8 +224,7 @@ class Discretization:
             lo, hi = np.searchsorted(sflat, [g, g + 1])
             for pos in order[lo:hi]:
                 e, l = divmod(int(pos), self.nloc)
-                Ae = self.element_matrices(alpha, beta, nu, e, e + 1)[0]
-                out[t] += Ae[l] @ xf[self.elem_dofs[e]]
+                out[t] += self.element_row(e, l, alpha, beta, nu) @ xf[self.elem_dofs[e]]
         return out
 
     # ---------------- diagonal ----------------

@@ -37,7 +37,8 @@ class PcgInfo(C.Structure):
 
 class CtxInfo(C.Structure):
     _fields_ = [("p", C.c_int), ("q", C.c_int), ("nelem", C.c_int64), ("ndof", C.c_int64),
-                ("ncolors", C.c_int), ("nfields", C.c_int), ("device_bytes", C.c_int64)]
+                ("compact", C.c_int), ("nfields", C.c_int), ("device_bytes", C.c_int64),
+                ("nassembled", C.c_int64)]
 
 
 class SfemError(RuntimeError):

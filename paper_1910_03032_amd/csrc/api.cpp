@@ -1,6 +1,7 @@
-// C ABI of the sfem library: context, mesh setup (coloring, scatter flags, geometric
-// factors), operator apply / diagonal / load / adjoint gradient dispatch, and the
-// Jacobi-PCG and FP32-inner iterative-refinement drivers.
+// C ABI of the sfem library: context, mesh setup (map validation, sole/shared DoF
+// classification, assembly lists, geometric factors), operator apply / diagonal / load /
+// adjoint gradient dispatch, and the Jacobi-PCG and FP32-inner iterative-refinement
+// drivers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,16 +35,18 @@ struct sfem_ctx {
   bool ready = false;
   int p = 0, q = 0;
   int64_t nelem = 0, ndof = 0;
-  int ncolors = 0;
-  std::vector<int64_t> color_off;  // [ncolors + 1], internal element order
   Rules1D rules;
-  int32_t *d_map = nullptr;        // [nelem][n^3] flagged
-  int32_t *d_perm = nullptr;       // internal -> caller element id
-  double *d_xyz = nullptr;         // [nelem][8][3] internal order
+  int32_t *d_map = nullptr;        // [nelem][n^3] flagged (sole / essential bits)
+  double *d_xyz = nullptr;         // [nelem][8][3]
   double *d_qd = nullptr;          // [nelem][7][q^3]
   float *d_qd32 = nullptr;
-  int32_t *d_off = nullptr;        // [ndof + 1] DoF -> E-vector slots (CSR), empty for essential
-  int32_t *d_slot = nullptr;       // E-vector slot (internal element * n^3 + local node)
+  // assembly of the shared and essential DoFs
+  int compact = 0;                 // E-vector over surface nodes only
+  int64_t epe = 0;                 // E-vector entries per element (surface nodes or n^3)
+  int64_t na = 0;                  // number of DoFs the assembly kernel writes
+  int32_t *d_alist = nullptr;      // [na] those DoFs, ascending
+  int32_t *d_aoff = nullptr;       // [na + 1] CSR offsets into d_slot
+  int32_t *d_slot = nullptr;       // E-vector slot of each contribution
 
   // ---- coefficients
   double alpha = 1.0, beta = 1.0;
@@ -150,12 +153,13 @@ void free_all(sfem_ctx *c) {
   c->owned.clear();
   c->bytes = 0;
   c->d_map = nullptr;
-  c->d_perm = nullptr;
   c->d_xyz = nullptr;
   c->d_qd = nullptr;
   c->d_qd32 = nullptr;
-  c->d_off = nullptr;
+  c->d_alist = nullptr;
+  c->d_aoff = nullptr;
   c->d_slot = nullptr;
+  c->na = 0;
   c->d_fold64 = nullptr;
   c->d_fold32 = nullptr;
   c->d_nu64 = nullptr;
@@ -190,58 +194,8 @@ sfem_status fold_coeffs(sfem_ctx *c, const double *nu_user, int nfield, double a
   if ((st = dalloc(c, &c->d_fold32, nq * kQdSlots * nfield)) != SFEM_OK) return st;
   if ((st = dalloc(c, &c->d_nu64, nq * nfield)) != SFEM_OK) return st;
   if ((st = dalloc(c, &c->d_nu32, nq * nfield)) != SFEM_OK) return st;
-  HIPCHK(c, launch_fold(c->q, c->d_qd, nu_user, c->d_perm, c->nelem, nfield, alpha, beta,
-                        c->d_fold64, c->d_fold32, c->d_nu64, c->d_nu32, c->stream));
-  return SFEM_OK;
-}
-
-// Compute (lazily) the diagonal of operator kind op for every field.
-sfem_status ensure_diag(sfem_ctx *c, int op) {
-  if (c->diag_ok[op]) return SFEM_OK;
-  const int nf = nfields_of(c, op);
-  const int64_t n = c->ndof * nf;
-  sfem_status st;
-  if (!c->d_diag[op]) {
-    if ((st = dalloc(c, &c->d_diag[op], n)) != SFEM_OK) return st;
-    if ((st = dalloc(c, &c->d_dinv[op], n)) != SFEM_OK) return st;
-    if ((st = dalloc(c, &c->d_diag32[op], n)) != SFEM_OK) return st;
-    if ((st = dalloc(c, &c->d_dinv32[op], n)) != SFEM_OK) return st;
-  }
-  double a = 1.0, b = 0.0;
-  if (op == SFEM_DIFFUSION) {
-    a = 0.0;
-    b = 1.0;
-  } else if (op == SFEM_HELMHOLTZ) {
-    a = c->alpha;
-    b = c->beta;
-  }
-  for (int f = 0; f < nf; ++f) {
-    DiagArgs da;
-    da.p = c->p;
-    da.map = c->d_map;
-    da.qd = c->d_qd;
-    da.nu = (op != SFEM_MASS && c->has_nu) ? c->d_nu64 + (int64_t)f * c->nelem * q3_of(c) : nullptr;
-    da.alpha = a;
-    da.beta = b;
-    da.diag = c->d_diag[op] + (int64_t)f * c->ndof;
-    da.B = c->rules.B.data();
-    da.G = c->rules.G.data();
-    for (int col = 0; col < c->ncolors; ++col)
-      HIPCHK(c, launch_diag(da, c->color_off[col], c->color_off[col + 1], c->stream));
-  }
-  HIPCHK(c, VecOps<double>::recip(c->d_diag[op], c->d_dinv[op], n, c->stream));
-  HIPCHK(c, VecOps<float>::recip(c->d_diag[op], c->d_dinv32[op], n, c->stream));
-  HIPCHK(c, launch_cast_f32(c->d_diag[op], c->d_diag32[op], n, c->stream));
-  c->diag_ok[op] = true;
-  return SFEM_OK;
-}
-
-sfem_status check_op_batch(sfem_ctx *c, int op, int nbatch) {
-  if (op < 0 || op > 2) return fail(c, SFEM_E_ARG, "op must be SFEM_MASS, SFEM_DIFFUSION or SFEM_HELMHOLTZ");
-  if (nbatch < 0) return fail(c, SFEM_E_ARG, "nbatch must be >= 0");
-  if (op != SFEM_MASS && c->nfield > 1 && nbatch != c->nfield && nbatch != 0)
-    return fail(c, SFEM_E_ARG, "with " + std::to_string(c->nfield) +
-                                   " nu fields, nbatch must equal the number of fields");
+  HIPCHK(c, launch_fold(c->q, c->d_qd, nu_user, c->nelem, nfield, alpha, beta, c->d_fold64,
+                        c->d_fold32, c->d_nu64, c->d_nu32, c->stream));
   return SFEM_OK;
 }
 
@@ -262,16 +216,80 @@ sfem_status ensure_evec(sfem_ctx *c, size_t bytes) {
   return SFEM_OK;
 }
 
+// Compute (lazily) the diagonal of operator kind op for every field.
+sfem_status ensure_diag(sfem_ctx *c, int op) {
+  if (c->diag_ok[op]) return SFEM_OK;
+  const int nf = nfields_of(c, op);
+  const int64_t n = c->ndof * nf;
+  sfem_status st;
+  if (!c->d_diag[op]) {
+    if ((st = dalloc(c, &c->d_diag[op], n)) != SFEM_OK) return st;
+    if ((st = dalloc(c, &c->d_dinv[op], n)) != SFEM_OK) return st;
+    if ((st = dalloc(c, &c->d_diag32[op], n)) != SFEM_OK) return st;
+    if ((st = dalloc(c, &c->d_dinv32[op], n)) != SFEM_OK) return st;
+  }
+  if ((st = ensure_evec(c, (size_t)(c->nelem * c->epe) * sizeof(double))) != SFEM_OK) return st;
+  double a = 1.0, b = 0.0;
+  if (op == SFEM_DIFFUSION) {
+    a = 0.0;
+    b = 1.0;
+  } else if (op == SFEM_HELMHOLTZ) {
+    a = c->alpha;
+    b = c->beta;
+  }
+  for (int f = 0; f < nf; ++f) {
+    DiagArgs da;
+    da.p = c->p;
+    da.map = c->d_map;
+    da.qd = c->d_qd;
+    da.nu = (op != SFEM_MASS && c->has_nu) ? c->d_nu64 + (int64_t)f * c->nelem * q3_of(c) : nullptr;
+    da.alpha = a;
+    da.beta = b;
+    da.nelem = c->nelem;
+    da.diag = c->d_diag[op] + (int64_t)f * c->ndof;
+    da.evec = (double *)c->evec.p;
+    da.compact = c->compact;
+    HIPCHK(c, launch_diag(da, c->stream));
+    HIPCHK(c, launch_assemble<double>(c->d_alist, c->d_aoff, c->d_slot, c->na, (const double *)c->evec.p,
+                                      0, nullptr, da.diag, c->ndof, 1, kEssOne, nullptr, 0, c->stream));
+  }
+  HIPCHK(c, VecOps<double>::recip(c->d_diag[op], c->d_dinv[op], n, c->stream));
+  HIPCHK(c, VecOps<float>::recip(c->d_diag[op], c->d_dinv32[op], n, c->stream));
+  HIPCHK(c, launch_cast_f32(c->d_diag[op], c->d_diag32[op], n, c->stream));
+  c->diag_ok[op] = true;
+  return SFEM_OK;
+}
+
+sfem_status check_op_batch(sfem_ctx *c, int op, int nbatch) {
+  if (op < 0 || op > 2) return fail(c, SFEM_E_ARG, "op must be SFEM_MASS, SFEM_DIFFUSION or SFEM_HELMHOLTZ");
+  if (nbatch < 0) return fail(c, SFEM_E_ARG, "nbatch must be >= 0");
+  if (op != SFEM_MASS && c->nfield > 1 && nbatch != c->nfield && nbatch != 0)
+    return fail(c, SFEM_E_ARG, "with " + std::to_string(c->nfield) +
+                                   " nu fields, nbatch must equal the number of fields");
+  return SFEM_OK;
+}
+
+// Number of per-block dot partials one apply leaves per member (element kernel blocks
+// followed by assembly blocks).
+int apply_nparts(const sfem_ctx *c) {
+  const int n = c->p + 1, q = c->p + 2;
+  int e = 256 / (q * q);
+  if (e < 1) e = 1;
+  (void)n;
+  return (int)((c->nelem + e - 1) / e) + (c->na > 0 ? assemble_nblk(c->na) : 0);
+}
+
 // Enqueue y = A x on the context stream (no argument checks).  With part != null the
-// assembly also leaves the partial sums of x . y (nblk blocks per member) in part.
+// two launches also leave the per-block partial sums of x . y in part[m][0..nparts).
 sfem_status do_apply(sfem_ctx *c, int op, bool f32, int nbatch, const void *x, void *y,
-                     double *part = nullptr, int nblk = 0) {
+                     double *part = nullptr) {
   if (nbatch == 0 || c->ndof == 0) return SFEM_OK;
-  const int64_t n3 = (int64_t)(c->p + 1) * (c->p + 1) * (c->p + 1);
-  const int64_t estride = c->nelem * n3;
+  const int64_t estride = c->nelem * c->epe;
   const size_t esz = f32 ? sizeof(float) : sizeof(double);
   sfem_status st;
   if ((st = ensure_evec(c, (size_t)estride * nbatch * esz)) != SFEM_OK) return st;
+  const int nparts = apply_nparts(c);
+  const int nblk_a = c->na > 0 ? assemble_nblk(c->na) : 0;
   ApplyArgs a;
   a.p = c->p;
   a.op = op;
@@ -280,9 +298,12 @@ sfem_status do_apply(sfem_ctx *c, int op, bool f32, int nbatch, const void *x, v
   a.nbatch = nbatch;
   a.nelem = c->nelem;
   a.x = x;
+  a.y = y;
   a.evec = c->evec.p;
-  a.B = c->rules.B.data();
-  a.G = c->rules.G.data();
+  a.estride = estride;
+  a.compact = c->compact;
+  a.part = part;
+  a.part_mstride = nparts;
   a.nu = nullptr;
   a.qd_mstride = 0;
   a.nu_mstride = 0;
@@ -300,12 +321,15 @@ sfem_status do_apply(sfem_ctx *c, int op, bool f32, int nbatch, const void *x, v
   }
   hipError_t e = f32 ? launch_apply_f32(a, c->stream) : launch_apply_f64(a, c->stream);
   if (e != hipSuccess) return fail(c, SFEM_E_HIP, std::string("apply launch: ") + hipGetErrorString(e));
+  double *pa = part ? part + (nparts - nblk_a) : nullptr;
   if (f32)
-    e = launch_assemble<float>(c->d_off, c->d_slot, (const float *)c->evec.p, estride,
-                               (const float *)x, (float *)y, c->ndof, nbatch, part, nblk, c->stream);
+    e = launch_assemble<float>(c->d_alist, c->d_aoff, c->d_slot, c->na, (const float *)c->evec.p,
+                               estride, (const float *)x, (float *)y, c->ndof, nbatch, kEssCopyX, pa,
+                               nparts, c->stream);
   else
-    e = launch_assemble<double>(c->d_off, c->d_slot, (const double *)c->evec.p, estride,
-                                (const double *)x, (double *)y, c->ndof, nbatch, part, nblk, c->stream);
+    e = launch_assemble<double>(c->d_alist, c->d_aoff, c->d_slot, c->na, (const double *)c->evec.p,
+                                estride, (const double *)x, (double *)y, c->ndof, nbatch, kEssCopyX,
+                                pa, nparts, c->stream);
   if (e != hipSuccess) return fail(c, SFEM_E_HIP, std::string("assembly launch: ") + hipGetErrorString(e));
   return SFEM_OK;
 }
@@ -354,26 +378,30 @@ struct Carver {
 template <typename T>
 struct PcgWork {
   T *r, *p, *w;
-  double *part;
+  double *part;   // vector-kernel partials [nb][3][nblk]
+  double *dpart;  // p^T A p partials of the apply [nb][nparts]
   PcgScalars *sc;
-  int nblk;
+  int nblk, nparts;
 };
 
 template <typename T>
-size_t pcg_work_bytes(int64_t n, int nb) {
+size_t pcg_work_bytes(const sfem_ctx *c, int64_t n, int nb) {
   const int nblk = vec_nblk(n);
   return 3 * align_up((size_t)n * nb * sizeof(T)) + align_up((size_t)nb * 3 * nblk * sizeof(double)) +
+         align_up((size_t)nb * apply_nparts(c) * sizeof(double)) +
          align_up((size_t)nb * sizeof(PcgScalars));
 }
 
 template <typename T>
-PcgWork<T> carve_pcg(Carver &cv, int64_t n, int nb) {
+PcgWork<T> carve_pcg(const sfem_ctx *c, Carver &cv, int64_t n, int nb) {
   PcgWork<T> w;
   w.nblk = vec_nblk(n);
+  w.nparts = apply_nparts(c);
   w.r = cv.take<T>(n * nb);
   w.p = cv.take<T>(n * nb);
   w.w = cv.take<T>(n * nb);
   w.part = cv.take<double>((int64_t)nb * 3 * w.nblk);
+  w.dpart = cv.take<double>((int64_t)nb * w.nparts);
   w.sc = cv.take<PcgScalars>(nb);
   return w;
 }
@@ -409,8 +437,8 @@ sfem_status run_pcg(sfem_ctx *c, int op, int nb, const T *b, T *x, bool x0_zero,
   };
   if (!any_active()) return SFEM_OK;
   for (int it = 0; it < maxit; ++it) {
-    if ((st = do_apply(c, op, f32, nb, w.p, w.w, w.part, w.nblk)) != SFEM_OK) return st;
-    HIPCHK(c, launch_pcg_alpha(w.part, w.nblk, nb, w.sc, s));
+    if ((st = do_apply(c, op, f32, nb, w.p, w.w, w.dpart)) != SFEM_OK) return st;
+    HIPCHK(c, launch_pcg_alpha(w.dpart, w.nparts, nb, w.sc, s));
     HIPCHK(c, VecOps<T>::update(x, w.p, w.r, w.w, dinv, dms, w.sc, w.part, w.nblk, n, nb, s));
     HIPCHK(c, launch_pcg_beta(w.part, w.nblk, nb, w.sc, s));
     HIPCHK(c, VecOps<T>::newdir(w.r, dinv, dms, w.p, w.sc, n, nb, s));
@@ -544,78 +572,68 @@ sfem_status sfem_setup(sfem_ctx *c, int p, int q, int64_t nelem, const double *e
       if (deg[gd] == 0)
         return fail(c, SFEM_E_MESH, "DoF " + std::to_string(gd) + " belongs to no element");
   }
-  // ---- DoF -> element incidence (CSR)
-  std::vector<int64_t> off((size_t)ndof + 1, 0);
-  for (int64_t gd = 0; gd < ndof; ++gd) off[gd + 1] = off[gd] + deg[gd];
-  std::vector<int32_t> inc((size_t)off[ndof]);
-  {
-    std::vector<int64_t> pos(off.begin(), off.end() - 1);
-    for (int64_t e = 0; e < nelem; ++e)
-      for (int64_t l = 0; l < n3; ++l) inc[(size_t)pos[dofs[(size_t)(e * n3 + l)]]++] = (int32_t)e;
-  }
-  // ---- greedy coloring in element order: no two elements sharing a DoF get one color
-  constexpr int kMaxColors = 64;
-  std::vector<int> color((size_t)nelem, -1);
-  int ncolors = 0;
-  {
-    std::vector<int64_t> used(kMaxColors, -1);
-    for (int64_t e = 0; e < nelem; ++e) {
-      for (int64_t l = 0; l < n3; ++l) {
-        const int32_t gd = dofs[(size_t)(e * n3 + l)];
-        for (int64_t k = off[gd]; k < off[gd + 1]; ++k) {
-          const int32_t e2 = inc[(size_t)k];
-          if (e2 < e) used[color[e2]] = e;
-        }
+  // ---- a DoF referenced by one element only is written directly by that element
+  // ("sole"); the others, and the essential DoFs, are written by the assembly kernel
+  // from the E-vector.  Compact E-vector: only the element's surface nodes get slots,
+  // valid when every element-interior local node is sole or essential.
+  const int64_t S = (p == 1) ? 8 : (int64_t)(2 * n * n + (n - 2) * 4 * p);
+  auto is_surface = [&](int64_t l) {
+    const int64_t i = l % n, j = (l / n) % n, k = l / ((int64_t)n * n);
+    return i == 0 || i == p || j == 0 || j == p || k == 0 || k == p;
+  };
+  auto surf_rank = [&](int64_t l) -> int64_t {
+    const int64_t i = l % n, j = (l / n) % n, k = l / ((int64_t)n * n);
+    if (k == 0) return i + (int64_t)n * j;
+    if (k == p) return (int64_t)n * n + i + (int64_t)n * j;
+    const int64_t base = 2 * (int64_t)n * n + (k - 1) * 4 * p;
+    if (j == 0) return base + i;
+    if (j == p) return base + n + i;
+    return base + 2 * n + 2 * (j - 1) + (i == 0 ? 0 : 1);
+  };
+  bool compact = true;
+  for (int64_t e = 0; e < nelem && compact; ++e)
+    for (int64_t l = 0; l < n3; ++l) {
+      const int32_t gd = dofs[(size_t)(e * n3 + l)];
+      if (!is_surface(l) && !(deg[gd] == 1 || ess[gd])) {
+        compact = false;
+        break;
       }
-      int col = 0;
-      while (col < kMaxColors && used[col] == e) ++col;
-      if (col == kMaxColors) return fail(c, SFEM_E_MESH, "element coloring needs more than 64 colors");
-      color[e] = col;
-      ncolors = std::max(ncolors, col + 1);
     }
-  }
-  // ---- internal order: by color, stable in caller order
-  std::vector<int64_t> coff((size_t)ncolors + 1, 0);
-  for (int64_t e = 0; e < nelem; ++e) coff[color[e] + 1]++;
-  for (int col = 0; col < ncolors; ++col) coff[col + 1] += coff[col];
-  std::vector<int32_t> perm((size_t)nelem);
-  {
-    std::vector<int64_t> pos(coff.begin(), coff.end() - 1);
-    for (int64_t e = 0; e < nelem; ++e) perm[(size_t)pos[color[e]]++] = (int32_t)e;
-  }
-  // ---- first writer of each DoF = the (unique) element of the smallest color touching it
-  std::vector<int> firstc((size_t)ndof, kMaxColors);
-  for (int64_t gd = 0; gd < ndof; ++gd)
-    for (int64_t k = off[gd]; k < off[gd + 1]; ++k) firstc[gd] = std::min(firstc[gd], color[inc[(size_t)k]]);
+  const int64_t epe = compact ? S : n3;
+  if (nelem * epe >= (int64_t)INT32_MAX) return fail(c, SFEM_E_ARG, "mesh too large");
   std::vector<int32_t> imap((size_t)(nelem * n3));
-  std::vector<double> ixyz((size_t)nelem * 24);
-  for (int64_t s = 0; s < nelem; ++s) {
-    const int64_t e = perm[(size_t)s];
+  for (int64_t e = 0; e < nelem; ++e)
     for (int64_t l = 0; l < n3; ++l) {
       const int32_t gd = dofs[(size_t)(e * n3 + l)];
       int32_t v = gd;
-      if (color[e] == firstc[gd]) v |= kFirstBit;
-      if (ess[gd]) v |= (int32_t)0x80000000u;
-      imap[(size_t)(s * n3 + l)] = v;
+      if (ess[gd])
+        v |= (int32_t)0x80000000u;
+      else if (deg[gd] == 1)
+        v |= kSoleBit;
+      imap[(size_t)(e * n3 + l)] = v;
     }
-    std::memcpy(&ixyz[(size_t)s * 24], &xyz[(size_t)e * 24], 24 * sizeof(double));
-  }
-
-  // ---- DoF -> E-vector slots in internal element order (essential DoFs get none)
-  std::vector<int32_t> coff_dof((size_t)ndof + 1, 0);
-  for (int64_t s = 0; s < nelem; ++s)
-    for (int64_t l = 0; l < n3; ++l) {
-      const int32_t gd = imap[(size_t)(s * n3 + l)];
-      if (gd >= 0) coff_dof[(gd & kDofMask) + 1]++;
+  // assembled DoFs (shared or essential), ascending, and their E-vector slots in
+  // element order
+  std::vector<int32_t> apos((size_t)ndof, -1);
+  std::vector<int32_t> alist;
+  for (int64_t gd = 0; gd < ndof; ++gd)
+    if (ess[gd] || deg[gd] > 1) {
+      apos[gd] = (int32_t)alist.size();
+      alist.push_back((int32_t)gd);
     }
-  for (int64_t gd = 0; gd < ndof; ++gd) coff_dof[gd + 1] += coff_dof[gd];
-  std::vector<int32_t> slots((size_t)coff_dof[ndof]);
+  const int64_t na = (int64_t)alist.size();
+  std::vector<int32_t> aoff((size_t)na + 1, 0);
+  for (int64_t gd = 0; gd < ndof; ++gd)
+    if (apos[gd] >= 0 && !ess[gd]) aoff[apos[gd] + 1] = (int32_t)deg[gd];
+  for (int64_t i = 0; i < na; ++i) aoff[i + 1] += aoff[i];
+  std::vector<int32_t> slots((size_t)aoff[na]);
   {
-    std::vector<int32_t> pos(coff_dof.begin(), coff_dof.end() - 1);
-    for (int64_t s = 0; s < nelem; ++s)
+    std::vector<int32_t> pos(aoff.begin(), aoff.end() - 1);
+    for (int64_t e = 0; e < nelem; ++e)
       for (int64_t l = 0; l < n3; ++l) {
-        const int32_t gd = imap[(size_t)(s * n3 + l)];
-        if (gd >= 0) slots[(size_t)pos[gd & kDofMask]++] = (int32_t)(s * n3 + l);
+        const int32_t gd = dofs[(size_t)(e * n3 + l)];
+        if (ess[gd] || deg[gd] == 1) continue;
+        slots[(size_t)pos[apos[gd]]++] = (int32_t)(e * epe + (compact ? surf_rank(l) : l));
       }
   }
 
@@ -625,28 +643,31 @@ sfem_status sfem_setup(sfem_ctx *c, int p, int q, int64_t nelem, const double *e
   c->q = q;
   c->nelem = nelem;
   c->ndof = ndof;
-  c->ncolors = ncolors;
-  c->color_off = coff;
+  c->compact = compact ? 1 : 0;
+  c->epe = epe;
+  c->na = na;
 
   // ---- upload + geometric factors
   sfem_status st;
   const int64_t q3 = (int64_t)q * q * q;
   if ((st = dalloc(c, &c->d_map, nelem * n3)) != SFEM_OK) return st;
-  if ((st = dalloc(c, &c->d_perm, nelem)) != SFEM_OK) return st;
   if ((st = dalloc(c, &c->d_xyz, nelem * 24)) != SFEM_OK) return st;
   if ((st = dalloc(c, &c->d_qd, nelem * q3 * kQdSlots)) != SFEM_OK) return st;
   if ((st = dalloc(c, &c->d_qd32, nelem * q3 * kQdSlots)) != SFEM_OK) return st;
-  if ((st = dalloc(c, &c->d_off, ndof + 1)) != SFEM_OK) return st;
+  if ((st = dalloc(c, &c->d_alist, na)) != SFEM_OK) return st;
+  if ((st = dalloc(c, &c->d_aoff, na + 1)) != SFEM_OK) return st;
   if ((st = dalloc(c, &c->d_slot, (int64_t)slots.size())) != SFEM_OK) return st;
   int *d_bad = nullptr;
   if ((st = dalloc(c, &d_bad, 1)) != SFEM_OK) return st;
-  HIPCHK(c, hipMemcpyAsync(c->d_off, coff_dof.data(), coff_dof.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  if (na > 0) {
+    HIPCHK(c, hipMemcpyAsync(c->d_alist, alist.data(), alist.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_aoff, aoff.data(), aoff.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  }
   if (!slots.empty())
     HIPCHK(c, hipMemcpyAsync(c->d_slot, slots.data(), slots.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
   if (nelem > 0) {
     HIPCHK(c, hipMemcpyAsync(c->d_map, imap.data(), imap.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->d_perm, perm.data(), perm.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->d_xyz, ixyz.data(), ixyz.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_xyz, xyz.data(), xyz.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
   }
   int h_bad = 0;
   if (d_bad) {
@@ -673,7 +694,7 @@ sfem_status sfem_qpoint_coords(sfem_ctx *c, double *xq) {
   if (c->nelem > 0 && !xq) return fail(c, SFEM_E_ARG, "xq must not be NULL");
   DeviceGuard g(c->device);
   HIPCHK(c, launch_qpoint_coords(c->q, c->rules.gauss_x.data(), c->rules.gauss_w.data(), c->d_xyz,
-                                 c->d_perm, c->nelem, xq, c->stream));
+                                 c->nelem, xq, c->stream));
   return SFEM_OK;
 }
 
@@ -724,20 +745,24 @@ sfem_status sfem_load(sfem_ctx *c, int nbatch, const double *f_q, double *b) {
   if (nbatch == 0 || c->ndof == 0) return SFEM_OK;
   if (!f_q || !b) return fail(c, SFEM_E_ARG, "f_q and b must not be NULL");
   DeviceGuard g(c->device);
+  const int64_t estride = c->nelem * c->epe;
+  if ((st = ensure_evec(c, (size_t)estride * nbatch * sizeof(double))) != SFEM_OK) return st;
   LoadArgs a;
   a.p = c->p;
   a.map = c->d_map;
-  a.perm = c->d_perm;
   a.qd = c->d_qd;
   a.ndof = c->ndof;
   a.nei = c->nelem;
   a.nbatch = nbatch;
   a.f = f_q;
   a.b = b;
-  a.B = c->rules.B.data();
-  a.G = c->rules.G.data();
-  for (int col = 0; col < c->ncolors; ++col)
-    HIPCHK(c, launch_load(a, c->color_off[col], c->color_off[col + 1], c->stream));
+  a.evec = (double *)c->evec.p;
+  a.estride = estride;
+  a.compact = c->compact;
+  HIPCHK(c, launch_load(a, c->stream));
+  HIPCHK(c, launch_assemble<double>(c->d_alist, c->d_aoff, c->d_slot, c->na, (const double *)c->evec.p,
+                                    estride, nullptr, b, c->ndof, nbatch, kEssZero, nullptr, 0,
+                                    c->stream));
   return SFEM_OK;
 }
 
@@ -751,7 +776,6 @@ sfem_status sfem_grad_nu(sfem_ctx *c, int nbatch, const double *u, const double 
   GradArgs a;
   a.p = c->p;
   a.map = c->d_map;
-  a.perm = c->d_perm;
   a.qd = c->d_qd;
   a.beta = c->beta;
   a.ndof = c->ndof;
@@ -760,8 +784,6 @@ sfem_status sfem_grad_nu(sfem_ctx *c, int nbatch, const double *u, const double 
   a.u = u;
   a.lam = lam;
   a.g = gq;
-  a.B = c->rules.B.data();
-  a.G = c->rules.G.data();
   HIPCHK(c, launch_grad(a, c->stream));
   return SFEM_OK;
 }
@@ -797,11 +819,11 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
   int outer = 0;
 
   if (opts->mode == 0) {
-    const size_t bytes = pcg_work_bytes<double>(n, nb) + align_up((size_t)nb * sizeof(double));
+    const size_t bytes = pcg_work_bytes<double>(c, n, nb) + align_up((size_t)nb * sizeof(double));
     if ((st = ensure_ws(c, bytes)) != SFEM_OK) return st;
     if ((st = ensure_pinned(c, std::max(sizeof(PcgScalars), sizeof(double)) * nb)) != SFEM_OK) return st;
     Carver cv{(char *)c->ws.p};
-    PcgWork<double> w = carve_pcg<double>(cv, n, nb);
+    PcgWork<double> w = carve_pcg<double>(c, cv, n, nb);
     double *d_out = cv.take<double>(nb);
     PcgScalars *hs = (PcgScalars *)c->h_pinned;
     if ((st = run_pcg<double>(c, op, nb, b, x, opts->x0_zero != 0, opts->rtol, opts->maxit,
@@ -825,14 +847,14 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
     }
   } else {
     // FP64 iterative refinement around an FP32 Jacobi-PCG
-    const size_t bytes = pcg_work_bytes<float>(n, nb) + 2 * align_up((size_t)n * nb * sizeof(double)) +
+    const size_t bytes = pcg_work_bytes<float>(c, n, nb) + 2 * align_up((size_t)n * nb * sizeof(double)) +
                          2 * align_up((size_t)n * nb * sizeof(float)) +
                          align_up((size_t)nb * 3 * sizeof(double)) +
                          align_up((size_t)nb * nblk * sizeof(double));
     if ((st = ensure_ws(c, bytes)) != SFEM_OK) return st;
     if ((st = ensure_pinned(c, std::max(sizeof(PcgScalars), 3 * sizeof(double)) * nb)) != SFEM_OK) return st;
     Carver cv{(char *)c->ws.p};
-    PcgWork<float> w = carve_pcg<float>(cv, n, nb);
+    PcgWork<float> w = carve_pcg<float>(c, cv, n, nb);
     double *r64 = cv.take<double>(n * nb);
     double *w64 = cv.take<double>(n * nb);
     float *r32 = cv.take<float>(n * nb);
@@ -866,8 +888,21 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
       }
       if (all || outer >= opts->max_outer || total_inner >= opts->maxit) break;
       HIPCHK(c, launch_ir_cast(r64, ir, r32, n, nb, s));
+      // Inner tolerance: a standard refinement step reduces the residual by inner_rtol;
+      // when the reduction still needed to reach rtol is within reach of one FP32
+      // solve (>= inner_rtol / 10), solve just far enough to finish in this step.
+      double need = 0.0;
+      for (int m = 0; m < nb; ++m) {
+        if (conv[m]) continue;
+        const double rn = std::sqrt(hir[3 * m]), bn = std::sqrt(hir[3 * m + 1]);
+        const double f = rn > 0 ? opts->rtol * bn / rn : 1.0;
+        need = (need == 0.0) ? f : std::min(need, f);
+      }
+      double itol = opts->inner_rtol;
+      if (need >= 0.1 * opts->inner_rtol) itol = std::min(opts->inner_rtol, 0.5 * need);
+      if (need >= opts->inner_rtol) itol = 0.5 * need;
       PcgScalars *hs = (PcgScalars *)c->h_pinned;
-      if ((st = run_pcg<float>(c, op, nb, r32, d32, true, opts->inner_rtol,
+      if ((st = run_pcg<float>(c, op, nb, r32, d32, true, itol,
                                opts->maxit - total_inner, opts->check_every, c->d_dinv32[op], dms,
                                w, hs)) != SFEM_OK)
         return st;
@@ -900,7 +935,8 @@ sfem_status sfem_get_info(const sfem_ctx *c, sfem_ctx_info *out) {
   out->q = c->q;
   out->nelem = c->nelem;
   out->ndof = c->ndof;
-  out->ncolors = c->ncolors;
+  out->compact = c->compact;
+  out->nassembled = c->na;
   out->nfields = c->nfield;
   out->device_bytes = c->bytes + (int64_t)c->ws.bytes + (int64_t)c->evec.bytes;
   return SFEM_OK;

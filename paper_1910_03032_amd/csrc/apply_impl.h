@@ -14,19 +14,15 @@
 // between stages live in LDS, one buffer per element.  Several elements share a
 // workgroup (E = 256 / q^2).
 //
-// Assembly (no atomics, deterministic): the apply runs in two launches.  The element
-// kernel processes every element in one launch and writes its element vector to an
-// E-vector buffer Y[e][l] (contiguous, coalesced).  The assembly kernel then gives
-// each global DoF to one thread, which sums the E-vector entries of that DoF in a
-// fixed order through a DoF -> E-vector-slot table (owner computes).  Essential DoFs
-// read as 0 in the gather, have no slots, and receive y = x.  Workgroups are mapped
-// to elements so that each of the 8 XCDs works on one contiguous range of elements,
-// which keeps the x values shared by neighbouring elements in that XCD's L2.
-//
-// The diagonal and load vector (set-up time work) still use a colored scatter: the
-// elements of one launch have one color, so no two share a DoF; each map entry says
-// whether the element is the first (in color order) to write the DoF -- it then
-// stores -- or accumulates onto what an earlier color stored.
+// Assembly (no atomics, deterministic): one launch of the element kernel covers every
+// element.  A DoF that belongs to this element only (the element-interior nodes of a
+// conforming mesh) is written straight to y.  The values of shared nodes (element
+// surface) go to a compact E-vector, Y[e][rank(l)] over the element's surface nodes;
+// an assembly kernel then gives each shared DoF to one thread, which sums its
+// E-vector entries in a fixed order (owner computes) -- and sets the essential DoFs.
+// Workgroups are mapped to elements so that each of the 8 XCDs works on one
+// contiguous range of elements, which keeps the x values shared by neighbouring
+// elements in that XCD's L2.
 //
 // LDS layouts inside an element buffer (a, b, c: quadrature indices along
 // xi_1..3; i, j, k: node indices):
@@ -39,6 +35,7 @@
 #include <stdint.h>
 
 #include "internal.h"
+#include "rules.h"
 
 namespace sfem {
 
@@ -54,22 +51,14 @@ struct Dims {
   static constexpr int THREADS = E * TPE;
 };
 
+// The 1D tables as compile-time constants of the order P (q = P + 2): after loop
+// unrolling every table entry is a literal, so no table lives in registers or memory.
 template <int P, typename T>
 struct Tab {
-  T B[P + 2][P + 1];
-  T G[P + 2][P + 1];
+  static constexpr rules::Tables<P, P + 2> c = rules::tables<P, P + 2>();
+  __host__ __device__ static constexpr T B(int a, int i) { return (T)c.B[a][i]; }
+  __host__ __device__ static constexpr T G(int a, int i) { return (T)c.G[a][i]; }
 };
-
-template <int P, typename T>
-inline Tab<P, T> make_tab(const double *B, const double *G) {
-  Tab<P, T> t;
-  for (int a = 0; a < P + 2; ++a)
-    for (int i = 0; i < P + 1; ++i) {
-      t.B[a][i] = (T)B[a * (P + 1) + i];
-      t.G[a][i] = (T)G[a * (P + 1) + i];
-    }
-  return t;
-}
 
 // Gather the element's nodal values (essential DoFs as 0) into buf[k][j][i].
 template <int P, typename T>
@@ -85,10 +74,71 @@ __device__ __forceinline__ void gather_e(T *buf, int t, bool active, const int32
   __syncthreads();
 }
 
+// Rank of local node l among the element's surface nodes (a node with i, j or k in
+// {0, p}): face k = 0, face k = p, then for each interior k the ring of the (i, j)
+// square.  Interior nodes have no rank.
+template <int P>
+__host__ __device__ constexpr int surf_rank(int l) {
+  constexpr int N = P + 1;
+  const int i = l % N, j = (l / N) % N, k = l / (N * N);
+  if (k == 0) return i + N * j;
+  if (k == P) return N * N + i + N * j;
+  const int base = 2 * N * N + (k - 1) * 4 * P;
+  if (j == 0) return base + i;
+  if (j == P) return base + N + i;
+  return base + 2 * N + 2 * (j - 1) + (i == 0 ? 0 : 1);
+}
+template <int P>
+__host__ __device__ constexpr int surf_count() {
+  return 2 * (P + 1) * (P + 1) + (P - 1) * 4 * P;
+}
+
+// Output of the element vector buf[l] of element e: sole DoFs -> y, shared nodes ->
+// E-vector slot e * S + rank (compact) or e * n^3 + l (general), essential -> nothing.
+// The map entries are read again (they are in L2 from the gather).  With DOT, returns
+// this thread's part of sum x_g y_g over the sole DoFs.
+template <int P, typename T, bool DOT>
+__device__ __forceinline__ double emit_e(const T *buf, int t, bool active, const int32_t *emap,
+                                         int64_t e, bool compact, const T *__restrict__ xm,
+                                         T *__restrict__ Y, T *__restrict__ y) {
+  using D = Dims<P>;
+  double dot = 0.0;
+  if (!active) return dot;
+  for (int l = t; l < D::N3; l += D::TPE) {
+    const int32_t c = emap[l];
+    if (c < 0) continue;
+    const T v = buf[l];
+    if (c & kSoleBit) {
+      y[c & kDofMask] = v;
+      if constexpr (DOT) dot += (double)xm[c & kDofMask] * (double)v;
+    } else if (compact) {
+      Y[e * surf_count<P>() + surf_rank<P>(l)] = v;
+    } else {
+      Y[e * D::N3 + l] = v;
+    }
+  }
+  return dot;
+}
+
+// Deterministic block sum (wave64 butterfly, then the waves in order); result on thread 0.
+__device__ __forceinline__ double block_sum_d(double v, double *sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < nw; ++i) s += sh[i];
+  return s;
+}
+
 // xi_1 contraction: [k][j][i] -> [k][j][a] with B (field 0) and, if DIFF, G (field 1).
 template <int P, typename T, bool DIFF>
-__device__ __forceinline__ void fwd_x(T *buf, int t, const Tab<P, T> &tb) {
+__device__ __forceinline__ void fwd_x(T *buf, int t) {
   using D = Dims<P>;
+  using TB = Tab<P, T>;
   constexpr int N = D::N, Q = D::Q;
   const bool w = t < D::N2;
   const int j = t % N, k = t / N;
@@ -102,8 +152,8 @@ __device__ __forceinline__ void fwd_x(T *buf, int t, const Tab<P, T> &tb) {
       T sb = 0, sg = 0;
 #pragma unroll
       for (int i = 0; i < N; ++i) {
-        sb += tb.B[a][i] * in[i];
-        if constexpr (DIFF) sg += tb.G[a][i] * in[i];
+        sb += TB::B(a, i) * in[i];
+        if constexpr (DIFF) sg += TB::G(a, i) * in[i];
       }
       ob[a] = sb;
       og[a] = sg;
@@ -123,8 +173,9 @@ __device__ __forceinline__ void fwd_x(T *buf, int t, const Tab<P, T> &tb) {
 // xi_2 contraction: [k][j][a] -> [k][b][a]: field 0 = B(B x), and if DIFF
 // field 1 = G_y(B_x x) (for d/dxi_2), field 2 = B_y(G_x x) (for d/dxi_1).
 template <int P, typename T, bool DIFF>
-__device__ __forceinline__ void fwd_y(T *buf, int t, const Tab<P, T> &tb) {
+__device__ __forceinline__ void fwd_y(T *buf, int t) {
   using D = Dims<P>;
+  using TB = Tab<P, T>;
   constexpr int N = D::N, Q = D::Q;
   const bool w = t < Q * N;
   const int a = t % Q, k = t / Q;
@@ -141,10 +192,10 @@ __device__ __forceinline__ void fwd_y(T *buf, int t, const Tab<P, T> &tb) {
       T s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        s0 += tb.B[b][j] * ib[j];
+        s0 += TB::B(b, j) * ib[j];
         if constexpr (DIFF) {
-          s1 += tb.G[b][j] * ib[j];
-          s2 += tb.B[b][j] * ig[j];
+          s1 += TB::G(b, j) * ib[j];
+          s2 += TB::B(b, j) * ig[j];
         }
       }
       obb[b] = s0;
@@ -171,6 +222,7 @@ template <int P, typename T, bool DIFF>
 __device__ __forceinline__ void load_z(const T *buf, int t, T (&zbb)[P + 1], T (&zgb)[P + 1],
                                        T (&zbg)[P + 1]) {
   using D = Dims<P>;
+  using TB = Tab<P, T>;
 #pragma unroll
   for (int k = 0; k < D::N; ++k) {
     zbb[k] = buf[k * D::Q2 + t];
@@ -184,8 +236,9 @@ __device__ __forceinline__ void load_z(const T *buf, int t, T (&zbb)[P + 1], T (
 // Transposed xi_2: [k][b][a] (fields p1, p2, p3) -> [k][j][a] (fields r1, r2) with
 // r1 = B^T p1 + G^T p2 and r2 = B^T p3.
 template <int P, typename T, bool DIFF>
-__device__ __forceinline__ void bwd_y(T *buf, int t, const Tab<P, T> &tb) {
+__device__ __forceinline__ void bwd_y(T *buf, int t) {
   using D = Dims<P>;
+  using TB = Tab<P, T>;
   constexpr int N = D::N, Q = D::Q;
   const bool w = t < Q * N;
   const int a = t % Q, k = t / Q;
@@ -205,10 +258,10 @@ __device__ __forceinline__ void bwd_y(T *buf, int t, const Tab<P, T> &tb) {
       T s1 = 0, s2 = 0;
 #pragma unroll
       for (int b = 0; b < Q; ++b) {
-        s1 += tb.B[b][j] * i1[b];
+        s1 += TB::B(b, j) * i1[b];
         if constexpr (DIFF) {
-          s1 += tb.G[b][j] * i2[b];
-          s2 += tb.B[b][j] * i3[b];
+          s1 += TB::G(b, j) * i2[b];
+          s2 += TB::B(b, j) * i3[b];
         }
       }
       r1[j] = s1;
@@ -228,8 +281,9 @@ __device__ __forceinline__ void bwd_y(T *buf, int t, const Tab<P, T> &tb) {
 
 // Transposed xi_1: [k][j][a] (r1, r2) -> nodal [k][j][i] = B^T r1 + G^T r2.
 template <int P, typename T, bool DIFF>
-__device__ __forceinline__ void bwd_x(T *buf, int t, const Tab<P, T> &tb) {
+__device__ __forceinline__ void bwd_x(T *buf, int t) {
   using D = Dims<P>;
+  using TB = Tab<P, T>;
   constexpr int N = D::N, Q = D::Q;
   const bool w = t < D::N2;
   const int j = t % N, k = t / N;
@@ -246,8 +300,8 @@ __device__ __forceinline__ void bwd_x(T *buf, int t, const Tab<P, T> &tb) {
       T s = 0;
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
-        s += tb.B[a][i] * i1[a];
-        if constexpr (DIFF) s += tb.G[a][i] * i2[a];
+        s += TB::B(a, i) * i1[a];
+        if constexpr (DIFF) s += TB::G(a, i) * i2[a];
       }
       yo[i] = s;
     }
@@ -256,27 +310,6 @@ __device__ __forceinline__ void bwd_x(T *buf, int t, const Tab<P, T> &tb) {
   if (w) {
 #pragma unroll
     for (int i = 0; i < N; ++i) buf[(k * N + j) * N + i] = yo[i];
-  }
-  __syncthreads();
-}
-
-// Colored scatter of buf[l] into ym; essential DoFs get ess_val(g) from their first writer.
-template <int P, typename T, typename EssVal>
-__device__ __forceinline__ void scatter_e(const T *buf, int t, bool active, const int32_t *emap,
-                                          T *__restrict__ ym, EssVal ess_val) {
-  using D = Dims<P>;
-  if (active) {
-    for (int l = t; l < D::N3; l += D::TPE) {
-      const int32_t c = emap[l];
-      const int64_t g = c & kDofMask;
-      if (c < 0) {
-        if (c & kFirstBit) ym[g] = ess_val(g);
-      } else if (c & kFirstBit) {
-        ym[g] = buf[l];
-      } else {
-        ym[g] += buf[l];
-      }
-    }
   }
   __syncthreads();
 }
@@ -290,20 +323,25 @@ __device__ __forceinline__ int64_t xcd_block(int64_t nblk) {
   return xcd * q8 + (xcd < r8 ? xcd : r8) + k;
 }
 
-// OP: 0 mass, 1 diffusion, 2 helmholtz (matches sfem_op).  Writes the element vectors
-// Y[m][e][l] of every non-essential local node.
+// OP: 0 mass, 1 diffusion, 2 helmholtz (matches sfem_op).  Writes y at the sole DoFs
+// and the E-vector Y[m] at the shared nodes; with part != null also the per-block sums
+// of x_g y_g over the sole DoFs (part[m * part_mstride + block]).
 template <int P, typename T, int OP>
 __global__ void __launch_bounds__(Dims<P>::THREADS)
-apply_kernel(const Tab<P, T> tb, const int32_t *__restrict__ map, const T *__restrict__ qd,
+apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
              int64_t qd_mstride, const T *__restrict__ nu, int64_t nu_mstride, int64_t nelem,
-             int nbatch, int64_t ndof, const T *__restrict__ x, T *__restrict__ Y) {
+             int nbatch, int64_t ndof, const T *__restrict__ x, T *__restrict__ Y,
+             int64_t estride, int compact, T *__restrict__ y, double *__restrict__ part,
+             int64_t part_mstride) {
   using D = Dims<P>;
+  using TB = Tab<P, T>;
   constexpr int N = D::N, Q = D::Q, Q2 = D::Q2, Q3 = D::Q3, N3 = D::N3;
   constexpr int TPE = D::TPE, E = D::E;
   constexpr bool MASS = (OP == 0) || (OP == 2);
   constexpr bool DIFF = (OP == 1) || (OP == 2);
 
   __shared__ T smem[E * D::BUF];
+  __shared__ double red[8];
   const int le = threadIdx.x / TPE;
   const int t = threadIdx.x - le * TPE;
   const int64_t nblk = (nelem + E - 1) / E;
@@ -317,8 +355,8 @@ apply_kernel(const Tab<P, T> tb, const int32_t *__restrict__ map, const T *__res
     const T *xm = x + (int64_t)m * ndof;
 
     gather_e<P, T>(buf, t, active, emap, xm);
-    fwd_x<P, T, DIFF>(buf, t, tb);
-    fwd_y<P, T, DIFF>(buf, t, tb);
+    fwd_x<P, T, DIFF>(buf, t);
+    fwd_y<P, T, DIFF>(buf, t);
 
     // xi_3 contraction, quadrature function, transposed xi_3: thread = line (a, b)
     {
@@ -338,11 +376,11 @@ apply_kernel(const Tab<P, T> tb, const int32_t *__restrict__ map, const T *__res
         T u = 0, dx = 0, dy = 0, dz = 0;
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-          if constexpr (MASS) u += tb.B[c][k] * zbb[k];
+          if constexpr (MASS) u += TB::B(c, k) * zbb[k];
           if constexpr (DIFF) {
-            dz += tb.G[c][k] * zbb[k];
-            dy += tb.B[c][k] * zgb[k];
-            dx += tb.B[c][k] * zbg[k];
+            dz += TB::G(c, k) * zbb[k];
+            dy += TB::B(c, k) * zgb[k];
+            dx += TB::B(c, k) * zbg[k];
           }
         }
         T v = 0, g1 = 0, g2 = 0, g3 = 0;
@@ -366,11 +404,11 @@ apply_kernel(const Tab<P, T> tb, const int32_t *__restrict__ map, const T *__res
         }
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-          if constexpr (MASS) p1[k] += tb.B[c][k] * v;
+          if constexpr (MASS) p1[k] += TB::B(c, k) * v;
           if constexpr (DIFF) {
-            p1[k] += tb.G[c][k] * g3;
-            p2[k] += tb.B[c][k] * g2;
-            p3[k] += tb.B[c][k] * g1;
+            p1[k] += TB::G(c, k) * g3;
+            p2[k] += TB::B(c, k) * g2;
+            p3[k] += TB::B(c, k) * g1;
           }
         }
       }
@@ -386,11 +424,16 @@ apply_kernel(const Tab<P, T> tb, const int32_t *__restrict__ map, const T *__res
       __syncthreads();
     }
 
-    bwd_y<P, T, DIFF>(buf, t, tb);
-    bwd_x<P, T, DIFF>(buf, t, tb);
-    if (active) {
-      T *Ye = Y + ((int64_t)m * nelem + e) * N3;
-      for (int l = t; l < N3; l += TPE) Ye[l] = buf[l];
+    bwd_y<P, T, DIFF>(buf, t);
+    bwd_x<P, T, DIFF>(buf, t);
+    if (part) {
+      const double dot = emit_e<P, T, true>(buf, t, active, emap, es, compact != 0, xm,
+                                            Y + (int64_t)m * estride, y + (int64_t)m * ndof);
+      const double sum = block_sum_d(dot, red);
+      if (threadIdx.x == 0) part[(int64_t)m * part_mstride + blockIdx.x] = sum;
+    } else {
+      emit_e<P, T, false>(buf, t, active, emap, es, compact != 0, xm, Y + (int64_t)m * estride,
+                          y + (int64_t)m * ndof);
     }
     __syncthreads();
   }
@@ -399,28 +442,30 @@ apply_kernel(const Tab<P, T> tb, const int32_t *__restrict__ map, const T *__res
 template <int P, typename T>
 hipError_t launch_apply_pt(const ApplyArgs &a, hipStream_t s) {
   using D = Dims<P>;
+  using TB = Tab<P, T>;
   if (a.nelem <= 0 || a.nbatch <= 0) return hipSuccess;
-  const Tab<P, T> tb = make_tab<P, T>(a.B, a.G);
   dim3 grid((unsigned)((a.nelem + D::E - 1) / D::E));
   dim3 block(D::THREADS);
   const T *qd = (const T *)a.qd;
   const T *nu = (const T *)a.nu;
   const T *x = (const T *)a.x;
   T *Y = (T *)a.evec;
+  T *y = (T *)a.y;
+#define SFEM_APPLY_ARGS                                                                    \
+  a.map, qd, a.qd_mstride, nu, a.nu_mstride, a.nelem, a.nbatch, a.ndof, x, Y, a.estride, \
+      a.compact, y, a.part, a.part_mstride
   switch (a.op) {
     case SFEM_MASS:
-      hipLaunchKernelGGL((apply_kernel<P, T, 0>), grid, block, 0, s, tb, a.map, qd, a.qd_mstride,
-                         nu, a.nu_mstride, a.nelem, a.nbatch, a.ndof, x, Y);
+      hipLaunchKernelGGL((apply_kernel<P, T, 0>), grid, block, 0, s, SFEM_APPLY_ARGS);
       break;
     case SFEM_DIFFUSION:
-      hipLaunchKernelGGL((apply_kernel<P, T, 1>), grid, block, 0, s, tb, a.map, qd, a.qd_mstride,
-                         nu, a.nu_mstride, a.nelem, a.nbatch, a.ndof, x, Y);
+      hipLaunchKernelGGL((apply_kernel<P, T, 1>), grid, block, 0, s, SFEM_APPLY_ARGS);
       break;
     default:
-      hipLaunchKernelGGL((apply_kernel<P, T, 2>), grid, block, 0, s, tb, a.map, qd, a.qd_mstride,
-                         nu, a.nu_mstride, a.nelem, a.nbatch, a.ndof, x, Y);
+      hipLaunchKernelGGL((apply_kernel<P, T, 2>), grid, block, 0, s, SFEM_APPLY_ARGS);
       break;
   }
+#undef SFEM_APPLY_ARGS
   return hipGetLastError();
 }
 

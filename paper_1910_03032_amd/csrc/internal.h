@@ -13,11 +13,13 @@ namespace sfem {
 
 // Encoding of the library-owned element->DoF map entries (int32):
 //   bits 0..29  global DoF
-//   bit 30      "first touch": this (element, local node) is the first writer of
-//               the DoF in color order, so it stores instead of accumulating
+//   bit 30      "sole": the DoF belongs to this element only (written directly)
 //   bit 31      essential DoF (entry is negative)
 constexpr int32_t kDofMask = 0x3fffffff;
-constexpr int32_t kFirstBit = 0x40000000;
+constexpr int32_t kSoleBit = 0x40000000;
+
+// How the assembly sets essential DoFs: copy x (operator apply), 1 (diagonal), 0 (load)
+enum EssKind { kEssCopyX = 0, kEssOne = 1, kEssZero = 2 };
 
 // Quadrature-data slots per point, layout [elem][kQdSlots][q^3]:
 //   0: w|J|      1..6: w|J| (J^-1 J^-T) as (11, 22, 33, 12, 13, 23)
@@ -50,8 +52,8 @@ struct PcgScalars {
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (implemented in the .hip files).  Every launcher enqueues on
-// `s` and returns the hipError_t of the launch.  B, G are HOST pointers to the
-// row-major [q][n] FP64 tables; they are passed to the kernels by value.
+// `s` and returns the hipError_t of the launch.  The 1D tables are compile-time
+// constants of the kernels (rules.h).
 // ---------------------------------------------------------------------------
 struct ApplyArgs {
   int p;
@@ -65,66 +67,74 @@ struct ApplyArgs {
   int nbatch;
   int64_t nelem;
   const void *x;
-  void *evec;               // [nbatch][nelem][n^3] element vectors (output)
-  const double *B, *G;
+  void *y;                  // output at the sole DoFs
+  void *evec;               // E-vector of the shared nodes, [nbatch][estride]
+  int64_t estride;          // nelem * S (S = surface nodes, or n^3 when not compact)
+  int compact;
+  double *part;             // per-block dot partials (or null)
+  int64_t part_mstride;
 };
 // Element phase of the apply over all elements (writes the E-vector).
 hipError_t launch_apply_f64(const ApplyArgs &a, hipStream_t s);
 hipError_t launch_apply_f32(const ApplyArgs &a, hipStream_t s);
-// Assembly phase: y[g] = sum of the E-vector entries of DoF g (slots off[g]..off[g+1]),
-// y[g] = x[g] for essential DoFs (no slots).  With part != null also the partial sums
-// of x . y (the p^T A p of CG) over nblk blocks.
+// Assembly phase over the na DoFs of alist (shared or essential): y[g] = sum of the
+// E-vector entries slot[aoff[i]..aoff[i+1]) in order; essential DoFs (no slots) get
+// x[g], 1 or 0 per ess_kind.  With part != null also the per-block sums of x_g y_g
+// (part[m * part_mstride + block], nblk blocks).
+int assemble_nblk(int64_t na);
 template <typename T>
-hipError_t launch_assemble(const int32_t *off, const int32_t *slot, const T *evec, int64_t estride,
-                           const T *x, T *y, int64_t n, int nb, double *part, int nblk,
+hipError_t launch_assemble(const int32_t *alist, const int32_t *aoff, const int32_t *slot,
+                           int64_t na, const T *evec, int64_t estride, const T *x, T *y,
+                           int64_t n, int nb, int ess_kind, double *part, int64_t part_mstride,
                            hipStream_t s);
 
 struct DiagArgs {
   int p;
   const int32_t *map;
   const double *qd;         // base quadrature data (FP64)
-  const double *nu;         // [nei][q^3] or null
+  const double *nu;         // [nelem][q^3] or null
   double alpha, beta;       // coefficients of the mass and diffusion terms
-  double *diag;             // [ndof]
-  const double *B, *G;
+  int64_t nelem;
+  double *diag;             // [ndof], written at the sole DoFs
+  double *evec;             // E-vector of the shared nodes
+  int compact;
 };
-hipError_t launch_diag(const DiagArgs &a, int64_t e_begin, int64_t e_end, hipStream_t s);
+hipError_t launch_diag(const DiagArgs &a, hipStream_t s);
 
 hipError_t launch_qdata_setup(int q, const double *gx, const double *gw, const double *xyz,
                               int64_t nei, double *qd, int *bad, hipStream_t s);
 hipError_t launch_qpoint_coords(int q, const double *gx, const double *gw, const double *xyz,
-                                const int32_t *perm, int64_t nei, double *xq, hipStream_t s);
-hipError_t launch_fold(int q, const double *qd, const double *nu_user, const int32_t *perm,
-                       int64_t nei, int nfield, double alpha, double beta, double *fold64,
-                       float *fold32, double *nu64, float *nu32, hipStream_t s);
+                                int64_t nei, double *xq, hipStream_t s);
+hipError_t launch_fold(int q, const double *qd, const double *nu_user, int64_t nei, int nfield,
+                       double alpha, double beta, double *fold64, float *fold32, double *nu64,
+                       float *nu32, hipStream_t s);
 hipError_t launch_cast_f32(const double *src, float *dst, int64_t n, hipStream_t s);
 
 struct GradArgs {
   int p;
   const int32_t *map;
-  const int32_t *perm;
   const double *qd;
   double beta;
   int64_t ndof, nei;
   int nbatch;
   const double *u, *lam;
   double *g;                // [nbatch][nelem][q^3] caller order
-  const double *B, *G;
 };
 hipError_t launch_grad(const GradArgs &a, hipStream_t s);
 
 struct LoadArgs {
   int p;
   const int32_t *map;
-  const int32_t *perm;
   const double *qd;
   int64_t ndof, nei;
   int nbatch;
-  const double *f;          // [nbatch][nelem][q^3] caller order
-  double *b;
-  const double *B, *G;
+  const double *f;          // [nbatch][nelem][q^3]
+  double *b;                // written at the sole DoFs
+  double *evec;             // E-vector of the shared nodes, [nbatch][estride]
+  int64_t estride;
+  int compact;
 };
-hipError_t launch_load(const LoadArgs &a, int64_t e_begin, int64_t e_end, hipStream_t s);
+hipError_t launch_load(const LoadArgs &a, hipStream_t s);
 
 // Vector kernels of the PCG (T = double or float).  Partial-sum buffers hold
 // [nb][nv][nblk] doubles.  dinv may be shared by all members (dms = 0) or per member

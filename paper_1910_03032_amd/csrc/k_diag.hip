@@ -9,8 +9,8 @@
 // of the 7 distinct (r, s) products factors per direction into a Hadamard product
 // of 1D tables: B2 = B.B, G2 = G.G, BG = B.G, with the off-diagonal pairs doubled.
 // Every term is then a three-stage contraction q^3 -> n^3.  The element
-// contributions are added with the same colored, atomic-free scatter as the apply;
-// essential rows are set to 1.
+// contributions are assembled like the apply's (sole DoFs directly, shared nodes via
+// the E-vector and the assembly kernel, which sets the essential rows to 1).
 #include <hip/hip_runtime.h>
 
 #include "apply_impl.h"
@@ -18,10 +18,13 @@
 namespace sfem {
 namespace {
 
+// Hadamard products of the compile-time 1D tables: 0: B.B, 1: G.G, 2: B.G
 template <int P>
-struct DiagTab {
-  double T[3][P + 2][P + 1];  // 0: B2, 1: G2, 2: BG
-};
+__device__ __forceinline__ constexpr double dtab(int which, int a, int i) {
+  using TB = Tab<P, double>;
+  return which == 0 ? TB::B(a, i) * TB::B(a, i)
+                    : (which == 1 ? TB::G(a, i) * TB::G(a, i) : TB::B(a, i) * TB::G(a, i));
+}
 
 // (x, y, z) table of each term; term 0 = mass, 1..6 = G11, G22, G33, G12, G13, G23
 __device__ constexpr int kTermTab[7][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1},
@@ -29,9 +32,9 @@ __device__ constexpr int kTermTab[7][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 
 
 template <int P>
 __global__ void __launch_bounds__(Dims<P>::Q2 < 64 ? 64 : Dims<P>::Q2)
-diag_kernel(const DiagTab<P> tb, const int32_t *__restrict__ map, const double *__restrict__ qd,
-            const double *__restrict__ nu, double alpha, double beta, int64_t e_begin,
-            int64_t e_end, double *__restrict__ diag) {
+diag_kernel(const int32_t *__restrict__ map, const double *__restrict__ qd,
+            const double *__restrict__ nu, double alpha, double beta, int64_t nelem,
+            double *__restrict__ diag, double *__restrict__ Y, int compact) {
   using D = Dims<P>;
   constexpr int N = D::N, Q = D::Q, N2 = D::N2, N3 = D::N3, Q2 = D::Q2, Q3 = D::Q3;
   __shared__ double s0[Q3];
@@ -39,8 +42,8 @@ diag_kernel(const DiagTab<P> tb, const int32_t *__restrict__ map, const double *
   __shared__ double s2[Q * N2];
   const int t = threadIdx.x;
   const int nt = blockDim.x;
-  const int64_t e = e_begin + blockIdx.x;
-  if (e >= e_end) return;  // whole block exits together (one element per block)
+  const int64_t e = blockIdx.x;
+  if (e >= nelem) return;  // whole block exits together (one element per block)
   const double *qe = qd + e * (int64_t)(kQdSlots * Q3);
   const double *ne = nu ? nu + e * (int64_t)Q3 : nullptr;
   double acc[N];
@@ -67,7 +70,7 @@ diag_kernel(const DiagTab<P> tb, const int32_t *__restrict__ map, const double *
       for (int i = 0; i < N; ++i) {
         double s = 0.0;
 #pragma unroll
-        for (int a = 0; a < Q; ++a) s += tb.T[tx][a][i] * in[a];
+        for (int a = 0; a < Q; ++a) s += dtab<P>(tx, a, i) * in[a];
         s1[(c * Q + b) * N + i] = s;
       }
     }
@@ -81,7 +84,7 @@ diag_kernel(const DiagTab<P> tb, const int32_t *__restrict__ map, const double *
       for (int j = 0; j < N; ++j) {
         double s = 0.0;
 #pragma unroll
-        for (int b = 0; b < Q; ++b) s += tb.T[ty][b][j] * in[b];
+        for (int b = 0; b < Q; ++b) s += dtab<P>(ty, b, j) * in[b];
         s2[(c * N + j) * N + i] = s;
       }
     }
@@ -95,7 +98,7 @@ diag_kernel(const DiagTab<P> tb, const int32_t *__restrict__ map, const double *
       for (int k = 0; k < N; ++k) {
         double s = 0.0;
 #pragma unroll
-        for (int c = 0; c < Q; ++c) s += tb.T[tz][c][k] * in[c];
+        for (int c = 0; c < Q; ++c) s += dtab<P>(tz, c, k) * in[c];
         acc[k] += s;
       }
     }
@@ -111,40 +114,31 @@ diag_kernel(const DiagTab<P> tb, const int32_t *__restrict__ map, const double *
   const int32_t *emap = map + e * (int64_t)N3;
   for (int l = t; l < N3; l += nt) {
     const int32_t c = emap[l];
-    const int64_t g = c & kDofMask;
-    if (c < 0) {
-      if (c & kFirstBit) diag[g] = 1.0;
-    } else if (c & kFirstBit) {
-      diag[g] = s0[l];
-    } else {
-      diag[g] += s0[l];
-    }
+    if (c < 0) continue;
+    if (c & kSoleBit)
+      diag[c & kDofMask] = s0[l];
+    else if (compact)
+      Y[e * surf_count<P>() + surf_rank<P>(l)] = s0[l];
+    else
+      Y[e * N3 + l] = s0[l];
   }
 }
 
 template <int P>
-hipError_t launch_diag_p(const DiagArgs &a, int64_t e_begin, int64_t e_end, hipStream_t s) {
+hipError_t launch_diag_p(const DiagArgs &a, hipStream_t s) {
   using D = Dims<P>;
-  const int64_t ne = e_end - e_begin;
+  const int64_t ne = a.nelem;
   if (ne <= 0) return hipSuccess;
-  DiagTab<P> tb;
-  for (int x = 0; x < P + 2; ++x)
-    for (int i = 0; i < P + 1; ++i) {
-      const double b = a.B[x * (P + 1) + i], g = a.G[x * (P + 1) + i];
-      tb.T[0][x][i] = b * b;
-      tb.T[1][x][i] = g * g;
-      tb.T[2][x][i] = b * g;
-    }
   const int threads = D::Q2 < 64 ? 64 : D::Q2;
-  hipLaunchKernelGGL((diag_kernel<P>), dim3((unsigned)ne), dim3(threads), 0, s, tb, a.map, a.qd,
-                     a.nu, a.alpha, a.beta, e_begin, e_end, a.diag);
+  hipLaunchKernelGGL((diag_kernel<P>), dim3((unsigned)ne), dim3(threads), 0, s, a.map, a.qd,
+                     a.nu, a.alpha, a.beta, a.nelem, a.diag, a.evec, a.compact);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_diag(const DiagArgs &a, int64_t e_begin, int64_t e_end, hipStream_t s) {
-#define SFEM_CALL(P) launch_diag_p<P>(a, e_begin, e_end, s)
+hipError_t launch_diag(const DiagArgs &a, hipStream_t s) {
+#define SFEM_CALL(P) launch_diag_p<P>(a, s)
   SFEM_DISPATCH_P(a.p, SFEM_CALL)
 #undef SFEM_CALL
 }

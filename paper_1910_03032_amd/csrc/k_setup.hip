@@ -83,8 +83,7 @@ __global__ void qdata_setup_kernel(GaussArg g, int q, const double *__restrict__
 }
 
 __global__ void qpoint_coords_kernel(GaussArg g, int q, const double *__restrict__ xyz,
-                                     const int32_t *__restrict__ perm, int64_t nei,
-                                     double *__restrict__ xq) {
+                                     int64_t nei, double *__restrict__ xq) {
   const int64_t q3 = (int64_t)q * q * q;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= nei * q3) return;
@@ -94,7 +93,7 @@ __global__ void qpoint_coords_kernel(GaussArg g, int q, const double *__restrict
   const double xi[3] = {g.x[a], g.x[b], g.x[c]};
   double pos[3], J[3][3];
   trilinear(xyz + e * 24, xi, pos, J);
-  const int64_t o = (int64_t)perm[e] * q3 + qi;
+  const int64_t o = e * q3 + qi;
   const int64_t plane = nei * q3;
   xq[o] = pos[0];
   xq[plane + o] = pos[1];
@@ -103,8 +102,8 @@ __global__ void qpoint_coords_kernel(GaussArg g, int q, const double *__restrict
 
 // fold[f][e][s][qi]: s = 0: alpha w|J|; s = 1..6: beta nu_f w|J| J^-1 J^-T
 __global__ void fold_kernel(int q3, const double *__restrict__ qd,
-                            const double *__restrict__ nu_user, const int32_t *__restrict__ perm,
-                            int64_t nei, int nfield, double alpha, double beta,
+                            const double *__restrict__ nu_user, int64_t nei, int nfield,
+                            double alpha, double beta,
                             double *__restrict__ fold64, float *__restrict__ fold32,
                             double *__restrict__ nu64, float *__restrict__ nu32) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -114,7 +113,7 @@ __global__ void fold_kernel(int q3, const double *__restrict__ qd,
   const int64_t r = gid - f * per_field;
   const int64_t e = r / q3;
   const int qi = (int)(r - e * q3);
-  const double nv = nu_user ? nu_user[f * per_field + (int64_t)perm[e] * q3 + qi] : 1.0;
+  const double nv = nu_user ? nu_user[f * per_field + r] : 1.0;
   const double *src = qd + e * (int64_t)(kQdSlots * q3) + qi;
   const int64_t o = (f * nei + e) * (int64_t)(kQdSlots * q3) + qi;
   for (int s = 0; s < kQdSlots; ++s) {
@@ -155,21 +154,21 @@ hipError_t launch_qdata_setup(int q, const double *gx, const double *gw, const d
 }
 
 hipError_t launch_qpoint_coords(int q, const double *gx, const double *gw, const double *xyz,
-                                const int32_t *perm, int64_t nei, double *xq, hipStream_t s) {
+                                int64_t nei, double *xq, hipStream_t s) {
   const int64_t n = nei * (int64_t)q * q * q;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(qpoint_coords_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s,
-                     gauss_arg(gx, gw, q), q, xyz, perm, nei, xq);
+                     gauss_arg(gx, gw, q), q, xyz, nei, xq);
   return hipGetLastError();
 }
 
-hipError_t launch_fold(int q, const double *qd, const double *nu_user, const int32_t *perm,
-                       int64_t nei, int nfield, double alpha, double beta, double *fold64,
-                       float *fold32, double *nu64, float *nu32, hipStream_t s) {
+hipError_t launch_fold(int q, const double *qd, const double *nu_user, int64_t nei, int nfield,
+                       double alpha, double beta, double *fold64, float *fold32, double *nu64,
+                       float *nu32, hipStream_t s) {
   const int q3 = q * q * q;
   const int64_t n = nei * (int64_t)q3 * nfield;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(fold_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s, q3, qd, nu_user, perm,
+  hipLaunchKernelGGL(fold_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s, q3, qd, nu_user,
                      nei, nfield, alpha, beta, fold64, fold32, nu64, nu32);
   return hipGetLastError();
 }

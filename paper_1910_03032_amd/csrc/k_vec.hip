@@ -251,30 +251,64 @@ __global__ void ir_accum_kernel(double *__restrict__ x, const float *__restrict_
     x[off + i] += sc * (double)d[off + i];
 }
 
-// y[g] = sum of E-vector entries of DoF g in slot order; y[g] = x[g] for essential DoFs
-// (they have no slots).  DOT: also the partial sums of x . y.
+// Assembly over the list of shared and essential DoFs: y[g] = sum of the E-vector
+// entries of g in slot order; essential DoFs (no slots) get x[g], 1 or 0.  DOT: also the
+// per-block sums of x_g y_g.  Each thread takes AU list entries per pass (stride VB);
+// for each it loads the first KS slot indices together, then the E-vector values
+// together, so a DoF shared by up to KS elements (8 on a hex mesh) costs three
+// dependent memory round trips; longer slot lists fall back to a loop.
+constexpr int AU = 2;
+constexpr int KS = 8;
 template <typename T, bool DOT>
-__global__ void assemble_kernel(const int32_t *__restrict__ off, const int32_t *__restrict__ slot,
-                                const T *__restrict__ Y, int64_t estride, const T *__restrict__ x,
-                                T *__restrict__ y, int64_t n, double *__restrict__ part, int nblk) {
+__global__ void __launch_bounds__(VB)
+assemble_kernel(const int32_t *__restrict__ alist, const int32_t *__restrict__ aoff,
+                const int32_t *__restrict__ slot, int64_t na, const T *__restrict__ Y,
+                int64_t estride, const T *__restrict__ x, T *__restrict__ y, int64_t n,
+                int ess_kind, double *__restrict__ part, int64_t part_mstride, int nblk) {
   const int m = blockIdx.y;
   const T *Ym = Y + (int64_t)m * estride;
-  const T *xm = x + (int64_t)m * n;
+  const T *xm = x ? x + (int64_t)m * n : nullptr;
   T *ym = y + (int64_t)m * n;
   double v[1] = {0.0};
-  for (int64_t g = (int64_t)blockIdx.x * VB + threadIdx.x; g < n; g += (int64_t)nblk * VB) {
-    const int32_t a = off[g], b = off[g + 1];
-    T s;
-    if (a == b) {
-      s = xm[g];
-    } else {
-      s = Ym[slot[a]];
-      for (int32_t k = a + 1; k < b; ++k) s += Ym[slot[k]];
+  for (int64_t base = (int64_t)blockIdx.x * (VB * AU) + threadIdx.x; base < na;
+       base += (int64_t)nblk * (VB * AU)) {
+    int32_t g[AU], a[AU], d[AU];
+#pragma unroll
+    for (int k = 0; k < AU; ++k) {
+      const int64_t i = base + (int64_t)k * VB;
+      const bool in = i < na;
+      g[k] = in ? alist[i] : 0;
+      a[k] = in ? aoff[i] : 0;
+      d[k] = in ? aoff[i + 1] - a[k] : -1;
     }
-    ym[g] = s;
-    if constexpr (DOT) v[0] += (double)xm[g] * (double)s;
+    int32_t sl[AU][KS];
+#pragma unroll
+    for (int k = 0; k < AU; ++k)
+#pragma unroll
+      for (int j = 0; j < KS; ++j) sl[k][j] = (j < d[k]) ? slot[a[k] + j] : 0;
+    T val[AU][KS];
+#pragma unroll
+    for (int k = 0; k < AU; ++k)
+#pragma unroll
+      for (int j = 0; j < KS; ++j) val[k][j] = (j < d[k]) ? Ym[sl[k][j]] : T(0);
+#pragma unroll
+    for (int k = 0; k < AU; ++k) {
+      if (d[k] < 0) continue;
+      T acc = val[k][0];
+#pragma unroll
+      for (int j = 1; j < KS; ++j)
+        if (j < d[k]) acc += val[k][j];
+      for (int32_t j = KS; j < d[k]; ++j) acc += Ym[slot[a[k] + j]];
+      const T xg = (DOT || (d[k] == 0 && ess_kind == kEssCopyX)) ? xm[g[k]] : T(0);
+      if (d[k] == 0) acc = (ess_kind == kEssCopyX) ? xg : (ess_kind == kEssOne ? T(1) : T(0));
+      ym[g[k]] = acc;
+      if constexpr (DOT) v[0] += (double)xg * (double)acc;
+    }
   }
-  if constexpr (DOT) write_part<1>(v, part, nblk);
+  if constexpr (DOT) {
+    block_sum<1>(v);
+    if (threadIdx.x == 0) part[(int64_t)m * part_mstride + blockIdx.x] = v[0];
+  }
 }
 
 template <typename T>
@@ -301,9 +335,9 @@ unsigned grid_for(int64_t n) {
 }  // namespace
 
 int vec_nblk(int64_t n) {
-  int64_t b = (n + VB * 8 - 1) / (VB * 8);
+  int64_t b = (n + VB * 2 - 1) / (VB * 2);
   if (b < 1) b = 1;
-  if (b > 1024) b = 1024;
+  if (b > 8192) b = 8192;
   return (int)b;
 }
 
@@ -353,25 +387,35 @@ hipError_t VecOps<T>::recip(const double *d, T *out, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+int assemble_nblk(int64_t na) {
+  int64_t b = (na + VB * AU - 1) / (VB * AU);
+  if (b < 1) b = 1;
+  if (b > 8192) b = 8192;
+  return (int)b;
+}
+
 template <typename T>
-hipError_t launch_assemble(const int32_t *off, const int32_t *slot, const T *evec, int64_t estride,
-                           const T *x, T *y, int64_t n, int nb, double *part, int nblk,
+hipError_t launch_assemble(const int32_t *alist, const int32_t *aoff, const int32_t *slot,
+                           int64_t na, const T *evec, int64_t estride, const T *x, T *y,
+                           int64_t n, int nb, int ess_kind, double *part, int64_t part_mstride,
                            hipStream_t s) {
-  if (n <= 0 || nb <= 0) return hipSuccess;
+  if (na <= 0 || nb <= 0) return hipSuccess;
+  const int nblk = assemble_nblk(na);
   if (part)
-    hipLaunchKernelGGL((assemble_kernel<T, true>), dim3(nblk, nb), dim3(VB), 0, s, off, slot, evec,
-                       estride, x, y, n, part, nblk);
+    hipLaunchKernelGGL((assemble_kernel<T, true>), dim3(nblk, nb), dim3(VB), 0, s, alist, aoff, slot,
+                       na, evec, estride, x, y, n, ess_kind, part, part_mstride, nblk);
   else
-    hipLaunchKernelGGL((assemble_kernel<T, false>), dim3(vec_nblk(n), nb), dim3(VB), 0, s, off,
-                       slot, evec, estride, x, y, n, part, vec_nblk(n));
+    hipLaunchKernelGGL((assemble_kernel<T, false>), dim3(nblk, nb), dim3(VB), 0, s, alist, aoff,
+                       slot, na, evec, estride, x, y, n, ess_kind, part, part_mstride, nblk);
   return hipGetLastError();
 }
-template hipError_t launch_assemble<double>(const int32_t *, const int32_t *, const double *,
-                                            int64_t, const double *, double *, int64_t, int,
-                                            double *, int, hipStream_t);
-template hipError_t launch_assemble<float>(const int32_t *, const int32_t *, const float *, int64_t,
-                                           const float *, float *, int64_t, int, double *, int,
-                                           hipStream_t);
+template hipError_t launch_assemble<double>(const int32_t *, const int32_t *, const int32_t *,
+                                            int64_t, const double *, int64_t, const double *,
+                                            double *, int64_t, int, int, double *, int64_t,
+                                            hipStream_t);
+template hipError_t launch_assemble<float>(const int32_t *, const int32_t *, const int32_t *,
+                                           int64_t, const float *, int64_t, const float *, float *,
+                                           int64_t, int, int, double *, int64_t, hipStream_t);
 
 template struct VecOps<double>;
 template struct VecOps<float>;

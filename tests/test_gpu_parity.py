@@ -2,9 +2,9 @@
 
 Tolerances (relative 2-norm over all DoFs): FP64 apply / diagonal / load <= 1e-12,
 FP32 apply <= 1e-5 against the FP64 oracle, geometric quantities <= 1e-13.
-Sizes span several workgroups, every color and ragged tails (3^3 and 5^3 element
-meshes give colors of unequal sizes that are not multiples of the elements per
-workgroup).
+Sizes span several workgroups and ragged tails (3^3 and 5^3 element meshes are not
+multiples of the elements per workgroup, and the interior/shared/essential DoF
+classes all occur).
 """
 import numpy as np
 import pytest
@@ -166,3 +166,39 @@ def test_helmholtz_workload_p4_32e_sampled_rows():
     # fp32 on the same rows
     y32 = host(op.apply(gpu(x, torch.float32), op=2))
     assert np.abs(y32[rows] - yo).max() / np.abs(yo).max() <= 1e-5
+
+
+def _shared_interior_mesh():
+    """A 2^3, p = 2 mesh whose element 1 reuses element 0's interior node: the
+    element-interior node is then shared, which switches the library to its general
+    (non-compact) E-vector layout."""
+    from workloads import BoxMesh
+    m = BoxMesh(2, 2)
+    dofs = m.elem_dofs.copy()
+    center = 13  # local (1, 1, 1)
+    d0, d1 = dofs[0, center], dofs[1, center]
+    dofs[1, center] = d0
+    last = m.ndof - 1
+    dofs[dofs == last] = d1  # relabel the last DoF into the freed index
+    ess = m.ess.copy()
+    ess[d1] = ess[last]
+    return m, dofs, ess[:last], last
+
+
+def test_general_layout_when_interior_nodes_are_shared():
+    from oracle import Discretization
+    from paper_1910_03032_amd import Operator
+    m, dofs, ess, ndof = _shared_interior_mesh()
+    d = Discretization(m.elem_xyz, dofs, ess, ndof, 2, 4)
+    op = Operator(m.elem_xyz, dofs, ndof, 2, ess=ess)
+    assert op.info()["compact"] == 0
+    x = uniform(ndof, seed=1)
+    nu = nu_uniform(m.nelem, 4, seed=2)
+    op.set_coeffs(1e3, 1.0, gpu(nu))
+    assert rel(host(op.apply(gpu(x), op=2)), d.apply(x, 1e3, 1.0, nu)) <= 1e-12
+    assert rel(host(op.diagonal(op=2)), d.diagonal(1e3, 1.0, nu)) <= 1e-12
+    f = uniform(m.nelem * 64, seed=5)
+    assert rel(host(op.load(gpu(f))), d.load(f.reshape(m.nelem, 64))) <= 1e-12
+    # the standard box mesh uses the compact layout
+    _, _, op2 = case(2, 2)
+    assert op2.info()["compact"] == 1

@@ -134,6 +134,9 @@ def test_apply_equals_assembled_matrix():
     assert np.array_equal(y[ess], x[ess])
     rows = np.array([0, 5, 40, 100, m.ndof // 2, m.ndof - 1])
     assert np.allclose(d.apply_rows(rows, x, 1e3, 1.0, nu), y[rows], rtol=1e-13, atol=0)
+    # a single row of an element matrix equals that row of the full element matrix
+    Ae = d.element_matrices(1e3, 1.0, nu, 5, 6)[0]
+    assert np.allclose(d.element_row(5, 7, 1e3, 1.0, nu), Ae[7], rtol=1e-13, atol=1e-13 * np.abs(Ae).max())
 
 
 def test_diagonal_brute_force():
