@@ -39,8 +39,10 @@ def parse():
     ap.add_argument("--workload", default="helmholtz_p4_32e")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solves", action="store_true")
-    ap.add_argument("--cpu-elements", type=int, default=8192,
-                    help="elements of the workload the CPU oracle applies to (bounded sample)")
+    ap.add_argument("--sets", type=int, default=4,
+                    help="independent operator/vector copies cycled by the timed applies")
+    ap.add_argument("--cpu-elements", type=int, default=32768,
+                    help="upper bound on the elements the CPU oracle applies (sample sized to ~15 s)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MB (hardware-counter calibration)")
     return ap.parse_args()
@@ -48,6 +50,23 @@ def parse():
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+# HBM bytes of one FP64 Helmholtz apply on the metric's workload (element kernel +
+# assembly dispatch), from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a plain
+# copy's readings; valid only for the kernel sources they were taken with (keyed by
+# the hash of those sources), otherwise the roofline reports traffic = null.
+KERNEL_SOURCES = ["apply_impl.h", "eo.h", "rules.h", "internal.h", "k_apply_f64.hip", "k_vec.hip"]
+MEASURED_TRAFFIC = {}
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1910_03032_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def algorithmic_bytes(nelem, p, ndof, s, nb=1, nqd=7, nb_qd=1):
@@ -83,7 +102,11 @@ def copy_calibration(mb, reps=5):
 
 
 class Bench:
-    def __init__(self, ne, p, alpha, beta, nu="c2"):
+    """One workload on the GPU.  `nsets` independent copies of the operator (quadrature
+    data, map, E-vector) and of x, y are applied in turn, so that a working set smaller
+    than the 256 MB last-level cache is not served from that cache on repeats."""
+
+    def __init__(self, ne, p, alpha, beta, nu="c2", nsets=1):
         import torch
         from paper_1910_03032_amd import Operator
         from workloads import BoxMesh, nu_c2
@@ -92,16 +115,26 @@ class Bench:
         t0 = time.time()
         self.m = m = BoxMesh(ne, p)
         self.ne, self.p, self.q, self.alpha, self.beta = ne, p, p + 2, alpha, beta
-        self.op = Operator(m.elem_xyz, m.elem_dofs, m.ndof, p, ess=m.ess)
-        if nu == "c2":
-            xq = self.op.qpoint_coords()
-            self.op.set_coeffs(alpha, beta, nu_c2(xq[0], xq[1], xq[2]))
-        else:
-            self.op.set_coeffs(alpha, beta, None)
+        self.ops = []
+        for _ in range(max(1, nsets)):
+            op = Operator(m.elem_xyz, m.elem_dofs, m.ndof, p, ess=m.ess)
+            if nu == "c2":
+                xq = op.qpoint_coords()
+                op.set_coeffs(alpha, beta, nu_c2(xq[0], xq[1], xq[2]))
+                del xq
+            else:
+                op.set_coeffs(alpha, beta, None)
+            self.ops.append(op)
+        self.op = self.ops[0]
         self.info = self.op.info()
         self.stream = torch.cuda.current_stream(self.dev)
         log(f"[bench] setup {time.time() - t0:.1f}s: {ne}^3 p={p} ndof={m.ndof} "
-            f"device bytes={self.info['device_bytes'] / 1e9:.2f} GB")
+            f"device bytes={self.info['device_bytes'] / 1e9:.2f} GB x {len(self.ops)} set(s)")
+
+    def close(self):
+        for op in self.ops:
+            op.close()
+        self.ops = []
 
     def timed(self, fn, steps, warmup):
         torch = self.torch
@@ -118,20 +151,32 @@ class Bench:
         return e0.elapsed_time(e1) / steps  # ms
 
     def apply_rate(self, dtype, nb=1, steps=50, warmup=10):
+        """Time `steps` applies, cycling over the operator copies; inputs are resident."""
         from paper_1910_03032_amd import HELMHOLTZ
         from workloads import normal
         torch = self.torch
         N = self.m.ndof
-        x = torch.as_tensor(normal(nb * N, seed=1), device=self.dev)
-        x = (x.reshape(nb, N) if nb > 1 else x).to(dtype)
-        y = torch.empty_like(x)
-        ms = self.timed(lambda: self.op.apply(x, op=HELMHOLTZ, out=y), steps, warmup)
+        k = len(self.ops)
+        xs, ys = [], []
+        for i in range(k):
+            x = torch.as_tensor(normal(nb * N, seed=1 + i), device=self.dev)
+            x = (x.reshape(nb, N) if nb > 1 else x).to(dtype)
+            xs.append(x)
+            ys.append(torch.empty_like(x))
+        it = [0]
+
+        def step():
+            i = it[0] % k
+            self.ops[i].apply(xs[i], op=HELMHOLTZ, out=ys[i])
+            it[0] += 1
+
+        ms = self.timed(step, steps, warmup)
         s = 8 if dtype == torch.float64 else 4
         nbytes = algorithmic_bytes(self.m.nelem, self.p, N, s, nb=nb)
         return {"us": round(ms * 1e3, 2), "GDoF/s": round(nb * N / (ms * 1e-3) / 1e9, 3),
                 "algorithmic_GBps": round(nbytes / (ms * 1e-3) / 1e9, 1),
                 "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                "algorithmic_bytes": nbytes}
+                "algorithmic_bytes": nbytes, "buffer_sets": k}
 
     def solve(self, b, mode, reps=3, **kw):
         torch = self.torch
@@ -147,8 +192,9 @@ class Bench:
                     "true_rel_res": res.true_rel_res, "status": res.status}
 
 
-def cpu_baseline(m, p, alpha, beta, sub):
-    """The oracle's dense (non-sum-factorized) FP64 apply on the first `sub` elements."""
+def cpu_baseline(m, p, alpha, beta, max_elements, target_s=15.0):
+    """The oracle's dense (non-sum-factorized) FP64 apply on the first elements of the
+    workload: a 1024-element probe sizes the sample to about `target_s` seconds."""
     from oracle import Discretization
     from workloads import nu_c2, normal
     try:
@@ -156,25 +202,33 @@ def cpu_baseline(m, p, alpha, beta, sub):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         threads = os.cpu_count() or 1
-    d = Discretization(m.elem_xyz[:sub], m.elem_dofs[:sub], m.ess, m.ndof, p, p + 2)
-    xq = d.qpoint_coords()
-    nu = nu_c2(xq[..., 0], xq[..., 1], xq[..., 2])
     x = normal(m.ndof, seed=1)
-    t = time.perf_counter()
-    d.apply_unconstrained(x, alpha, beta, nu)
-    dt = time.perf_counter() - t
+
+    def run(sub):
+        d = Discretization(m.elem_xyz[:sub], m.elem_dofs[:sub], m.ess, m.ndof, p, p + 2)
+        xq = d.qpoint_coords()
+        nu = nu_c2(xq[..., 0], xq[..., 1], xq[..., 2])
+        t = time.perf_counter()
+        d.apply_unconstrained(x, alpha, beta, nu)
+        return time.perf_counter() - t
+
+    probe = min(1024, m.nelem, max_elements)
+    dt = run(probe)
+    sub = int(min(max_elements, m.nelem, max(probe, probe * target_s / max(dt, 1e-3))))
+    if sub > probe:
+        dt = run(sub)
     dofs = m.ndof * sub / m.nelem
     log(f"[bench] cpu oracle: {sub} elements in {dt:.2f}s")
     return {"value": round(dofs / dt / 1e9, 7), "unit": "GDoF/s", "cores": threads, "kind": "oracle",
-            "sample": f"dense element apply over {sub} of {m.nelem} elements "
-                      f"({dt:.2f} s), scaled by the element fraction"}
+            "sample": f"dense FP64 element apply over {sub} of {m.nelem} elements "
+                      f"({dt:.2f} s), DoFs scaled by the element fraction"}
 
 
 def run_main(a, wl):
     """The metric's configuration: FP64 apply as the timed step, plus solves."""
     from workloads import rhs_uniform
     torch = __import__("torch")
-    B = Bench(wl["ne"], wl["p"], wl["alpha"], wl["beta"])
+    B = Bench(wl["ne"], wl["p"], wl["alpha"], wl["beta"], nsets=a.sets)
     m, p, q, N = B.m, B.p, B.q, B.m.ndof
     r64 = B.apply_rate(torch.float64, steps=a.steps, warmup=a.warmup)
     log(f"[bench] fp64 apply {r64['us']} us  {r64['GDoF/s']} GDoF/s")
@@ -207,7 +261,9 @@ def run_main(a, wl):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": MEASURED_TRAFFIC.get((kernel_source_hash(), a.workload)),
+            "traffic_unit": "HBM bytes per apply (both dispatches)",
+            "kernel_source_hash": kernel_source_hash(),
             "algorithmic_bytes_per_apply": r64["algorithmic_bytes"],
             "launches_per_apply": 2,
             "apply_us": r64["us"],
@@ -232,7 +288,7 @@ def run_main(a, wl):
         out["adjoint_grad_kernel"] = {"us": round(msg * 1e3, 1),
                                       "algorithmic_GBps": round(gbytes / (msg * 1e-3) / 1e9, 1)}
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(m, p, B.alpha, B.beta, min(a.cpu_elements, m.nelem))
+        out["cpu_baseline"] = cpu_baseline(m, p, B.alpha, B.beta, a.cpu_elements)
     return out
 
 
@@ -240,7 +296,7 @@ def run_vector(a, wl):
     """3-component Helmholtz: batched apply and FP64 PCG vs FP32-inner IR to 1e-10."""
     from workloads import rhs_uniform
     torch = __import__("torch")
-    B = Bench(wl["ne"], wl["p"], wl["alpha"], wl["beta"])
+    B = Bench(wl["ne"], wl["p"], wl["alpha"], wl["beta"], nsets=2)
     nb = wl["nbatch"]
     out = {"workload": a.workload, "p": B.p, "elements": f"{B.ne}^3", "ndof_per_component": B.m.ndof,
            "components": nb,
@@ -322,7 +378,7 @@ def run_sweep(a):
         rows.append({"p": p, "elements": f"{ne}^3", "ndof": B.m.ndof, "fp64": r64, "fp32": r32})
         log(f"[bench] sweep p={p}: fp64 {r64['GDoF/s']} GDoF/s ({r64['hbm_frac']:.3f} of HBM), "
             f"fp32 {r32['GDoF/s']} GDoF/s")
-        B.op.close()
+        B.close()
         del B
         torch.cuda.empty_cache()
     return {"workload": "sweep", "rows": rows}

@@ -202,3 +202,36 @@ def test_general_layout_when_interior_nodes_are_shared():
     # the standard box mesh uses the compact layout
     _, _, op2 = case(2, 2)
     assert op2.info()["compact"] == 1
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_fan_mesh_multiplicities_3_and_6(p):
+    """Unstructured fan mesh (3 kite columns x 2 layers around an axis): axis DoFs are
+    shared by 3 or 6 elements, so the assembly plan pads classes 4 and 8.  Every
+    operator, the diagonal, the load vector and a solve match the oracle."""
+    from oracle import Discretization
+    from paper_1910_03032_amd import Operator
+    from workloads import FanMesh
+    m = FanMesh(p)
+    q = p + 2
+    say(f"[case] fan mesh p={p} nelem={m.nelem} ndof={m.ndof}")
+    d = Discretization(m.elem_xyz, m.elem_dofs, m.ess, m.ndof, p, q)
+    op = Operator(m.elem_xyz, m.elem_dofs, m.ndof, p, ess=m.ess)
+    assert op.info()["compact"] == 1
+    nu = nu_uniform(m.nelem, q, seed=2)
+    op.set_coeffs(3.0, 0.7, gpu(nu))
+    x = uniform(m.ndof, seed=1)
+    for opk, (a, b) in ((0, (3.0, 0.0)), (1, (0.0, 0.7)), (2, (3.0, 0.7))):
+        yo = d.apply(x, a, b, nu if opk else None)
+        assert rel(host(op.apply(gpu(x), op=opk)), yo) <= 1e-12, opk
+        assert rel(host(op.apply(gpu(x, torch.float32), op=opk)), yo) <= 1e-5, opk
+        assert rel(host(op.diagonal(op=opk)), d.diagonal(a, b, nu if opk else None)) <= 1e-12, opk
+    f = uniform(m.nelem * q ** 3, seed=5)
+    assert rel(host(op.load(gpu(f))), d.load(f.reshape(m.nelem, q ** 3))) <= 1e-12
+    bvec = uniform(m.ndof, seed=3)
+    bvec[m.ess.astype(bool)] = 0
+    xs, res = op.pcg(gpu(bvec), rtol=1e-12)
+    assert res.converged
+    import scipy.sparse.linalg as spla
+    xd = spla.spsolve(d.assemble(3.0, 0.7, nu).tocsc(), bvec)
+    assert rel(host(xs), xd) <= 1e-9

@@ -122,6 +122,41 @@ def test_autograd_vs_central_differences(alpha):
         assert abs(fd - ad) <= 1e-5 * abs(ad)
 
 
+def test_autograd_gradcheck_tiny():
+    """torch.autograd.gradcheck of the solve's nu-gradient on 2^3, p = 1 (every one of the
+    216 per-point coefficients perturbed), FP64, solves to 1e-14."""
+    from paper_1910_03032_amd.autograd import helmholtz_solve
+    m, d, op = case(2, 1)
+    b = gpu(rhs_uniform(m, seed=1)[0])
+    w = gpu(np.random.default_rng(7).uniform(-1, 1, m.ndof))
+    nu = gpu(nu_uniform(m.nelem, d.q, seed=2)).requires_grad_(True)
+
+    def f(nu_):
+        u = helmholtz_solve(nu_, b, op, alpha=10.0, beta=1.0, rtol=1e-14)
+        return (w * u).sum()
+
+    assert torch.autograd.gradcheck(f, (nu,), eps=1e-6, atol=1e-7, rtol=1e-4)
+
+
+def test_manufactured_poisson_rate_on_gpu():
+    """-Laplace u = 3 pi^2 sin sin sin, u = 0 on the boundary: load vector and PCG on the
+    GPU, L2 error measured by the oracle; the rate on 2^3 -> 4^3 -> 8^3 is >= p + 1 - 0.3."""
+    from workloads import f_manufactured, u_manufactured
+    for p in (2, 3):
+        errs = []
+        for ne in (2, 4, 8):
+            m, d, op = case(ne, p)
+            op.set_coeffs(0.0, 1.0, None)
+            xq = op.qpoint_coords()
+            bq = op.load(f_manufactured(xq[0], xq[1], xq[2]))
+            u, res = op.pcg(bq, op=1, rtol=1e-13)
+            assert res.converged
+            errs.append(d.l2_error(host(u), u_manufactured))
+        rates = np.diff(np.log(errs)) / np.log(0.5)
+        say(f"  p={p}: L2 errors {errs}, rates {rates}")
+        assert rates[-1] >= p + 1 - 0.3
+
+
 def test_gradient_homogeneity_identity_p5_20e():
     """Full 20^3, p = 5 adjoint workload: sum nu dJ/dnu = -beta lam^T K(nu) u (K linear in nu)."""
     m, d, op = case(20, 5)

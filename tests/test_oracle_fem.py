@@ -210,3 +210,40 @@ def test_planted_swapped_derivative_directions_fail_energy():
     K = d.assemble(0.0, 1.0, constrained=False)
     u, v = nodal(m, lin(A_VEC, C0)), nodal(m, lin(B_VEC, D0))
     assert abs(u @ (K @ v) - A_VEC @ B_VEC) > 1e-6
+
+
+def test_fan_mesh_volume_constants_and_linear_patch():
+    """Unstructured fan mesh (3 kite columns x 2 layers): 1^T M 1 equals the exact volume
+    3 sin(60 deg), K 1 = 0, and K annihilates the nodal values of a linear field at the
+    DoFs off the boundary (patch test)."""
+    from oracle.quadrature import gll
+    from workloads import FanMesh
+    p = 3
+    m = FanMesh(p)
+    d = Discretization(m.elem_xyz, m.elem_dofs, m.ess, m.ndof, p, p + 2)
+    one = np.ones(m.ndof)
+    assert abs(d.apply_unconstrained(one, 1.0, 0.0).sum() - 3 * np.sin(np.pi / 3)) <= 1e-13
+    assert np.abs(d.apply_unconstrained(one, 0.0, 1.0)).max() <= 1e-13
+    # physical GLL node positions through each element's trilinear map
+    t = (np.asarray(gll(p)[0]) + 1) / 2
+    n = p + 1
+    X = np.zeros((m.ndof, 3))
+    for e in range(m.nelem):
+        for l in range(n ** 3):
+            a, b, c = t[l % n], t[(l // n) % n], t[l // (n * n)]
+            w = np.array([(1 - a) * (1 - b) * (1 - c), a * (1 - b) * (1 - c), (1 - a) * b * (1 - c),
+                          a * b * (1 - c), (1 - a) * (1 - b) * c, a * (1 - b) * c, (1 - a) * b * c, a * b * c])
+            X[m.elem_dofs[e, l]] = w @ m.elem_xyz[e]
+    xl = X @ np.array([0.3, -1.2, 0.7]) + 0.4
+    r = d.apply_unconstrained(xl, 0.0, 1.0)
+    outer = np.zeros(m.ndof, dtype=bool)
+    for e in range(m.nelem):
+        loc = m.elem_dofs[e].reshape(n, n, n)  # [k][j][i]
+        outer[loc[:, -1, :].ravel()] = True    # j = p: the face R(theta_{s+1}) - corner
+        outer[loc[:, :, -1].ravel()] = True    # i = p: the face R(theta_s) - corner
+        outer[loc[0].ravel()] = outer[loc[-1].ravel()] = True  # bottom and top layers' caps
+    on_cap = (np.abs(X[:, 2]) < 1e-12) | (np.abs(X[:, 2] - 1) < 1e-12)
+    interior = ~outer | (~on_cap & (np.linalg.norm(X[:, :2], axis=1) < 1e-12))
+    interior &= ~on_cap
+    assert interior.sum() >= 2 * (p - 1) ** 3
+    assert np.abs(r[interior]).max() <= 1e-12

@@ -100,6 +100,67 @@ class BoxMesh:
         return g % self.n1, (g // self.n1) % self.n1, g // (self.n1 * self.n1)
 
 
+class FanMesh:
+    """An unstructured hex mesh: ``nsect`` kite-shaped columns around the z axis, each
+    split into ``nlayer`` layers on z in [0, 1], so that the nodes on the axis are
+    shared by nsect (inside a layer) or 2 nsect (on a layer interface) elements -- DoF
+    multiplicities a structured box mesh does not have.  Section s spans the angles
+    [2 pi s / nsect, 2 pi (s + 1) / nsect]; its cross-section has the vertices O (the
+    axis), R(theta_s), R(theta_{s+1}) (radius 1) and the outer corner at the middle
+    angle (radius ``rc``); vertex v = i + 2j + 4k with i along O -> R(theta_s) and j
+    along O -> R(theta_{s+1}), which keeps the map orientation positive for nsect >= 3.
+
+    DoFs are numbered by deduplicating the images of the equispaced lattice
+    (i/p, j/p, k/p) under each element's trilinear map (a conforming neighbour sees a
+    shared face through a symmetry of the square, so shared nodes coincide).
+    Essential DoFs: the nodes on the bottom face z = 0.
+    """
+
+    def __init__(self, p: int, nsect: int = 3, nlayer: int = 2, rc: float = 1.0):
+        if nsect < 3 or nlayer < 1 or p < 1:
+            raise ValueError("need nsect >= 3, nlayer >= 1, p >= 1")
+        self.p, self.n = p, p + 1
+        n = p + 1
+        self.nelem = nsect * nlayer
+        xyz = np.empty((self.nelem, 8, 3))
+        e = 0
+        for layer in range(nlayer):
+            for sct in range(nsect):
+                t0 = 2 * np.pi * sct / nsect
+                t1 = 2 * np.pi * (sct + 1) / nsect
+                tm = 0.5 * (t0 + t1)
+                quad = {(0, 0): (0.0, 0.0), (1, 0): (np.cos(t0), np.sin(t0)),
+                        (0, 1): (np.cos(t1), np.sin(t1)), (1, 1): (rc * np.cos(tm), rc * np.sin(tm))}
+                for v in range(8):
+                    i, j, k = v & 1, (v >> 1) & 1, (v >> 2) & 1
+                    xyz[e, v, :2] = quad[(i, j)]
+                    xyz[e, v, 2] = (layer + k) / nlayer
+                e += 1
+        self.elem_xyz = xyz
+        s = np.arange(n) / p
+        S1, S2, S3 = np.meshgrid(s, s, s, indexing="ij")  # [i, j, k]
+        # lattice point of local l = i + n (j + n k)
+        lat = np.stack([S1, S2, S3], -1).transpose(2, 1, 0, 3).reshape(-1, 3)
+        keys = {}
+        dofs = np.empty((self.nelem, n ** 3), dtype=np.int32)
+        coords = []
+        for e in range(self.nelem):
+            for l in range(n ** 3):
+                a, b, c = lat[l]
+                w = np.array([(1 - a) * (1 - b) * (1 - c), a * (1 - b) * (1 - c), (1 - a) * b * (1 - c),
+                              a * b * (1 - c), (1 - a) * (1 - b) * c, a * (1 - b) * c, (1 - a) * b * c, a * b * c])
+                x = w @ xyz[e]
+                key = tuple(np.round(x * 1e9).astype(np.int64))
+                if key not in keys:
+                    keys[key] = len(coords)
+                    coords.append(x)
+                dofs[e, l] = keys[key]
+        self.elem_dofs = dofs
+        self.ndof = len(coords)
+        self.node_xyz = np.array(coords)
+        self.ess = (np.abs(self.node_xyz[:, 2]) < 1e-12).astype(np.uint8)
+
+
 def uniform(n, seed: int = SEED_X, lo: float = -1.0, hi: float = 1.0, shape=None) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return rng.uniform(lo, hi, size=shape if shape is not None else n)
