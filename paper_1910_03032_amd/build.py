@@ -29,6 +29,7 @@ SOURCES = [
     "k_setup.hip",
     "k_vec.hip",
     "rules.cpp",
+    "plan.cpp",
     "api.cpp",
 ]
 

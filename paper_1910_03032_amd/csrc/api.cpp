@@ -47,6 +47,7 @@ struct sfem_ctx {
   int32_t *d_alist = nullptr;      // [na] those DoFs, ascending
   int32_t *d_aoff = nullptr;       // [na + 1] CSR offsets into d_slot
   int32_t *d_slot = nullptr;       // E-vector slot of each contribution
+  AsmPlan plan{};                  // the three arrays above, for the assembly kernel
 
   // ---- coefficients
   double alpha = 1.0, beta = 1.0;
@@ -159,6 +160,7 @@ void free_all(sfem_ctx *c) {
   c->d_alist = nullptr;
   c->d_aoff = nullptr;
   c->d_slot = nullptr;
+  c->plan = AsmPlan{};
   c->na = 0;
   c->d_fold64 = nullptr;
   c->d_fold32 = nullptr;
@@ -250,8 +252,8 @@ sfem_status ensure_diag(sfem_ctx *c, int op) {
     da.evec = (double *)c->evec.p;
     da.compact = c->compact;
     HIPCHK(c, launch_diag(da, c->stream));
-    HIPCHK(c, launch_assemble<double>(c->d_alist, c->d_aoff, c->d_slot, c->na, (const double *)c->evec.p,
-                                      0, nullptr, da.diag, c->ndof, 1, kEssOne, nullptr, 0, c->stream));
+    HIPCHK(c, launch_assemble<double>(c->plan, (const double *)c->evec.p, 0, nullptr, da.diag, c->ndof,
+                                      1, kEssOne, nullptr, 0, c->stream));
   }
   HIPCHK(c, VecOps<double>::recip(c->d_diag[op], c->d_dinv[op], n, c->stream));
   HIPCHK(c, VecOps<float>::recip(c->d_diag[op], c->d_dinv32[op], n, c->stream));
@@ -314,7 +316,7 @@ sfem_status do_apply(sfem_ctx *c, int op, bool f32, int nbatch, const void *x, v
     a.qd_mstride = per_member ? nq * kQdSlots : 0;
   } else {
     a.qd = f32 ? (const void *)c->d_qd32 : (const void *)c->d_qd;
-    if (op == SFEM_DIFFUSION && c->has_nu) {
+    if (op == SFEM_DIFFUSION) {  // nu = 1 is stored when no field was given
       a.nu = f32 ? (const void *)c->d_nu32 : (const void *)c->d_nu64;
       a.nu_mstride = per_member ? nq : 0;
     }
@@ -323,13 +325,11 @@ sfem_status do_apply(sfem_ctx *c, int op, bool f32, int nbatch, const void *x, v
   if (e != hipSuccess) return fail(c, SFEM_E_HIP, std::string("apply launch: ") + hipGetErrorString(e));
   double *pa = part ? part + (nparts - nblk_a) : nullptr;
   if (f32)
-    e = launch_assemble<float>(c->d_alist, c->d_aoff, c->d_slot, c->na, (const float *)c->evec.p,
-                               estride, (const float *)x, (float *)y, c->ndof, nbatch, kEssCopyX, pa,
-                               nparts, c->stream);
+    e = launch_assemble<float>(c->plan, (const float *)c->evec.p, estride, (const float *)x, (float *)y,
+                               c->ndof, nbatch, kEssCopyX, pa, nparts, c->stream);
   else
-    e = launch_assemble<double>(c->d_alist, c->d_aoff, c->d_slot, c->na, (const double *)c->evec.p,
-                                estride, (const double *)x, (double *)y, c->ndof, nbatch, kEssCopyX,
-                                pa, nparts, c->stream);
+    e = launch_assemble<double>(c->plan, (const double *)c->evec.p, estride, (const double *)x,
+                                (double *)y, c->ndof, nbatch, kEssCopyX, pa, nparts, c->stream);
   if (e != hipSuccess) return fail(c, SFEM_E_HIP, std::string("assembly launch: ") + hipGetErrorString(e));
   return SFEM_OK;
 }
@@ -551,91 +551,21 @@ sfem_status sfem_setup(sfem_ctx *c, int p, int q, int64_t nelem, const double *e
     HIPCHK(c, hipMemcpyAsync(ess.data(), ess_mask, (size_t)ndof, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
 
-  // ---- validate the map: range, no repeated DoF inside an element, every DoF used
-  std::vector<int64_t> deg((size_t)ndof + 1, 0);
+  // ---- validate the map, encode it, and build the assembly plan (host)
+  HostPlan hp;
   {
-    std::vector<int64_t> stamp((size_t)ndof, -1);
-    for (int64_t e = 0; e < nelem; ++e) {
-      for (int64_t l = 0; l < n3; ++l) {
-        const int32_t gd = dofs[(size_t)(e * n3 + l)];
-        if (gd < 0 || gd >= ndof)
-          return fail(c, SFEM_E_MESH, "elem_dofs[" + std::to_string(e) + "][" + std::to_string(l) +
-                                          "] = " + std::to_string(gd) + " is outside [0, ndof)");
-        if (stamp[gd] == e)
-          return fail(c, SFEM_E_MESH, "element " + std::to_string(e) + " references DoF " +
-                                          std::to_string(gd) + " twice");
-        stamp[gd] = e;
-        deg[gd]++;
-      }
-    }
-    for (int64_t gd = 0; gd < ndof; ++gd)
-      if (deg[gd] == 0)
-        return fail(c, SFEM_E_MESH, "DoF " + std::to_string(gd) + " belongs to no element");
+    std::string err;
+    const int rc = build_host_plan(p, nelem, dofs.data(), ndof, ess.data(), hp, err);
+    if (rc != 0) return fail(c, (sfem_status)rc, err);
   }
-  // ---- a DoF referenced by one element only is written directly by that element
-  // ("sole"); the others, and the essential DoFs, are written by the assembly kernel
-  // from the E-vector.  Compact E-vector: only the element's surface nodes get slots,
-  // valid when every element-interior local node is sole or essential.
-  const int64_t S = (p == 1) ? 8 : (int64_t)(2 * n * n + (n - 2) * 4 * p);
-  auto is_surface = [&](int64_t l) {
-    const int64_t i = l % n, j = (l / n) % n, k = l / ((int64_t)n * n);
-    return i == 0 || i == p || j == 0 || j == p || k == 0 || k == p;
-  };
-  auto surf_rank = [&](int64_t l) -> int64_t {
-    const int64_t i = l % n, j = (l / n) % n, k = l / ((int64_t)n * n);
-    if (k == 0) return i + (int64_t)n * j;
-    if (k == p) return (int64_t)n * n + i + (int64_t)n * j;
-    const int64_t base = 2 * (int64_t)n * n + (k - 1) * 4 * p;
-    if (j == 0) return base + i;
-    if (j == p) return base + n + i;
-    return base + 2 * n + 2 * (j - 1) + (i == 0 ? 0 : 1);
-  };
-  bool compact = true;
-  for (int64_t e = 0; e < nelem && compact; ++e)
-    for (int64_t l = 0; l < n3; ++l) {
-      const int32_t gd = dofs[(size_t)(e * n3 + l)];
-      if (!is_surface(l) && !(deg[gd] == 1 || ess[gd])) {
-        compact = false;
-        break;
-      }
-    }
-  const int64_t epe = compact ? S : n3;
-  if (nelem * epe >= (int64_t)INT32_MAX) return fail(c, SFEM_E_ARG, "mesh too large");
-  std::vector<int32_t> imap((size_t)(nelem * n3));
-  for (int64_t e = 0; e < nelem; ++e)
-    for (int64_t l = 0; l < n3; ++l) {
-      const int32_t gd = dofs[(size_t)(e * n3 + l)];
-      int32_t v = gd;
-      if (ess[gd])
-        v |= (int32_t)0x80000000u;
-      else if (deg[gd] == 1)
-        v |= kSoleBit;
-      imap[(size_t)(e * n3 + l)] = v;
-    }
-  // assembled DoFs (shared or essential), ascending, and their E-vector slots in
-  // element order
-  std::vector<int32_t> apos((size_t)ndof, -1);
-  std::vector<int32_t> alist;
-  for (int64_t gd = 0; gd < ndof; ++gd)
-    if (ess[gd] || deg[gd] > 1) {
-      apos[gd] = (int32_t)alist.size();
-      alist.push_back((int32_t)gd);
-    }
-  const int64_t na = (int64_t)alist.size();
-  std::vector<int32_t> aoff((size_t)na + 1, 0);
-  for (int64_t gd = 0; gd < ndof; ++gd)
-    if (apos[gd] >= 0 && !ess[gd]) aoff[apos[gd] + 1] = (int32_t)deg[gd];
-  for (int64_t i = 0; i < na; ++i) aoff[i + 1] += aoff[i];
-  std::vector<int32_t> slots((size_t)aoff[na]);
-  {
-    std::vector<int32_t> pos(aoff.begin(), aoff.end() - 1);
-    for (int64_t e = 0; e < nelem; ++e)
-      for (int64_t l = 0; l < n3; ++l) {
-        const int32_t gd = dofs[(size_t)(e * n3 + l)];
-        if (ess[gd] || deg[gd] == 1) continue;
-        slots[(size_t)pos[apos[gd]]++] = (int32_t)(e * epe + (compact ? surf_rank(l) : l));
-      }
-  }
+  const bool compact = hp.compact;
+  const int64_t epe = hp.epe;
+  const int64_t na = hp.na;
+  const std::vector<int32_t> &imap = hp.imap;
+  const std::vector<int32_t> &alist = hp.alist;
+  const std::vector<int32_t> &aoff = hp.aoff;
+  const std::vector<int32_t> &slots = hp.slots;
+  if ((int64_t)slots.size() >= (int64_t)INT32_MAX) return fail(c, SFEM_E_ARG, "mesh too large");
 
   // ---- rules
   if (!make_rules(p, q, c->rules)) return fail(c, SFEM_E_HIP, "1D rule construction failed");
@@ -665,6 +595,10 @@ sfem_status sfem_setup(sfem_ctx *c, int p, int q, int64_t nelem, const double *e
   }
   if (!slots.empty())
     HIPCHK(c, hipMemcpyAsync(c->d_slot, slots.data(), slots.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  c->plan.alist = c->d_alist;
+  c->plan.aoff = c->d_aoff;
+  c->plan.slot = c->d_slot;
+  c->plan.na = na;
   if (nelem > 0) {
     HIPCHK(c, hipMemcpyAsync(c->d_map, imap.data(), imap.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->d_xyz, xyz.data(), xyz.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
@@ -760,9 +694,8 @@ sfem_status sfem_load(sfem_ctx *c, int nbatch, const double *f_q, double *b) {
   a.estride = estride;
   a.compact = c->compact;
   HIPCHK(c, launch_load(a, c->stream));
-  HIPCHK(c, launch_assemble<double>(c->d_alist, c->d_aoff, c->d_slot, c->na, (const double *)c->evec.p,
-                                    estride, nullptr, b, c->ndof, nbatch, kEssZero, nullptr, 0,
-                                    c->stream));
+  HIPCHK(c, launch_assemble<double>(c->plan, (const double *)c->evec.p, estride, nullptr, b, c->ndof,
+                                    nbatch, kEssZero, nullptr, 0, c->stream));
   return SFEM_OK;
 }
 

@@ -9,10 +9,12 @@
 // Work decomposition: one element is owned by q^2 threads; in every stage a thread
 // owns one 1D line of the tensor along the direction being contracted, holds the
 // n (or q) inputs of that line in registers and produces the whole output line, so
-// LDS is read once per input value and the 1D tables (compile-time sized, passed
-// in the kernel argument segment) are wave-uniform operands.  Intermediates
-// between stages live in LDS, one buffer per element.  Several elements share a
-// workgroup (E = 256 / q^2).
+// LDS is read once per input value.  The 1D tables are compile-time constants and
+// every contraction uses their symmetry (even-odd form: the nodes and the Gauss
+// points are symmetric about 0, so B is centro-symmetric and G centro-antisymmetric),
+// which halves the multiply-adds; the xi_3 stage walks the quadrature slices in
+// symmetric pairs (c, q-1-c).  Intermediates between stages live in LDS, one buffer
+// per element.  Several elements share a workgroup (E = 256 / q^2).
 //
 // Assembly (no atomics, deterministic): one launch of the element kernel covers every
 // element.  A DoF that belongs to this element only (the element-interior nodes of a
@@ -34,6 +36,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "eo.h"
 #include "internal.h"
 #include "rules.h"
 
@@ -49,6 +52,9 @@ struct Dims {
   static constexpr int mx(int a, int b) { return a > b ? a : b; }
   static constexpr int BUF = mx(N3, mx(2 * Q * N2, 3 * Q2 * N));
   static constexpr int THREADS = E * TPE;
+  // minimum waves per SIMD the element kernels are compiled for: the largest that
+  // the Helmholtz kernels reach without spilling registers (p = 8 spills slightly)
+  static constexpr int OCC = P <= 2 ? 4 : (P <= 4 ? 3 : 2);
 };
 
 // The 1D tables as compile-time constants of the order P (q = P + 2): after loop
@@ -60,15 +66,39 @@ struct Tab {
   __host__ __device__ static constexpr T G(int a, int i) { return (T)c.G[a][i]; }
 };
 
-// Gather the element's nodal values (essential DoFs as 0) into buf[k][j][i].
+// Local nodes one thread handles in the gather and output loops (l = t + k TPE).
+template <int P>
+struct Per {
+  static constexpr int NL = (Dims<P>::N3 + Dims<P>::TPE - 1) / Dims<P>::TPE;
+};
+
+// Gather the element's nodal values (essential DoFs as 0) into buf[k][j][i].  All map
+// loads of the thread are issued together, then all value loads.  Loads are
+// unconditional (an inactive slot reads a valid element's entries and discards them)
+// so that the compiler can batch them.  If smap / sx are given (LDS), the map entries
+// and the raw x values are kept there for the output step.
 template <int P, typename T>
 __device__ __forceinline__ void gather_e(T *buf, int t, bool active, const int32_t *emap,
-                                         const T *__restrict__ xm) {
+                                         const T *__restrict__ xm, int32_t *smap = nullptr,
+                                         T *sx = nullptr) {
   using D = Dims<P>;
-  if (active) {
-    for (int l = t; l < D::N3; l += D::TPE) {
-      const int32_t c = emap[l];
-      buf[l] = (c < 0) ? T(0) : xm[c & kDofMask];
+  constexpr int NL = Per<P>::NL;
+  int32_t c[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int l = t + k * D::TPE;
+    c[k] = emap[l < D::N3 ? l : D::N3 - 1];
+  }
+  T v[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) v[k] = xm[c[k] & kDofMask];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int l = t + k * D::TPE;
+    if (l < D::N3) {
+      buf[l] = (active && c[k] >= 0) ? v[k] : T(0);
+      if (smap) smap[l] = c[k];
+      if (sx) sx[l] = v[k];
     }
   }
   __syncthreads();
@@ -95,22 +125,25 @@ __host__ __device__ constexpr int surf_count() {
 
 // Output of the element vector buf[l] of element e: sole DoFs -> y, shared nodes ->
 // E-vector slot e * S + rank (compact) or e * n^3 + l (general), essential -> nothing.
-// The map entries are read again (they are in L2 from the gather).  With DOT, returns
-// this thread's part of sum x_g y_g over the sole DoFs.
+// The map entries (and, with DOT, the x values) come from LDS, kept by the gather.
+// With DOT, returns this thread's part of sum x_g y_g over the sole DoFs.
 template <int P, typename T, bool DOT>
-__device__ __forceinline__ double emit_e(const T *buf, int t, bool active, const int32_t *emap,
-                                         int64_t e, bool compact, const T *__restrict__ xm,
+__device__ __forceinline__ double emit_e(const T *buf, int t, bool active, const int32_t *smap,
+                                         const T *sx, int64_t e, bool compact,
                                          T *__restrict__ Y, T *__restrict__ y) {
   using D = Dims<P>;
+  constexpr int NL = Per<P>::NL;
   double dot = 0.0;
-  if (!active) return dot;
-  for (int l = t; l < D::N3; l += D::TPE) {
-    const int32_t c = emap[l];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int l = t + k * D::TPE;
+    if (!active || l >= D::N3) continue;
+    const int32_t c = smap[l];
     if (c < 0) continue;
     const T v = buf[l];
     if (c & kSoleBit) {
       y[c & kDofMask] = v;
-      if constexpr (DOT) dot += (double)xm[c & kDofMask] * (double)v;
+      if constexpr (DOT) dot += (double)sx[l] * (double)v;
     } else if (compact) {
       Y[e * surf_count<P>() + surf_rank<P>(l)] = v;
     } else {
@@ -138,7 +171,6 @@ __device__ __forceinline__ double block_sum_d(double v, double *sh) {
 template <int P, typename T, bool DIFF>
 __device__ __forceinline__ void fwd_x(T *buf, int t) {
   using D = Dims<P>;
-  using TB = Tab<P, T>;
   constexpr int N = D::N, Q = D::Q;
   const bool w = t < D::N2;
   const int j = t % N, k = t / N;
@@ -147,17 +179,9 @@ __device__ __forceinline__ void fwd_x(T *buf, int t) {
     T in[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) in[i] = buf[(k * N + j) * N + i];
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      T sb = 0, sg = 0;
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        sb += TB::B(a, i) * in[i];
-        if constexpr (DIFF) sg += TB::G(a, i) * in[i];
-      }
-      ob[a] = sb;
-      og[a] = sg;
-    }
+    const auto sp = eo::split(in);
+    eo::apply<eo::Tab1<P, 0>>(sp, ob);
+    if constexpr (DIFF) eo::apply<eo::Tab1<P, 1>>(sp, og);
   }
   __syncthreads();
   if (w) {
@@ -175,7 +199,6 @@ __device__ __forceinline__ void fwd_x(T *buf, int t) {
 template <int P, typename T, bool DIFF>
 __device__ __forceinline__ void fwd_y(T *buf, int t) {
   using D = Dims<P>;
-  using TB = Tab<P, T>;
   constexpr int N = D::N, Q = D::Q;
   const bool w = t < Q * N;
   const int a = t % Q, k = t / Q;
@@ -187,20 +210,11 @@ __device__ __forceinline__ void fwd_y(T *buf, int t) {
       ib[j] = buf[(k * N + j) * Q + a];
       if constexpr (DIFF) ig[j] = buf[D::QN2 + (k * N + j) * Q + a];
     }
-#pragma unroll
-    for (int b = 0; b < Q; ++b) {
-      T s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        s0 += TB::B(b, j) * ib[j];
-        if constexpr (DIFF) {
-          s1 += TB::G(b, j) * ib[j];
-          s2 += TB::B(b, j) * ig[j];
-        }
-      }
-      obb[b] = s0;
-      ogb[b] = s1;
-      obg[b] = s2;
+    const auto sb = eo::split(ib);
+    eo::apply<eo::Tab1<P, 0>>(sb, obb);
+    if constexpr (DIFF) {
+      eo::apply<eo::Tab1<P, 1>>(sb, ogb);
+      eo::apply<eo::Tab1<P, 0>>(eo::split(ig), obg);
     }
   }
   __syncthreads();
@@ -222,7 +236,6 @@ template <int P, typename T, bool DIFF>
 __device__ __forceinline__ void load_z(const T *buf, int t, T (&zbb)[P + 1], T (&zgb)[P + 1],
                                        T (&zbg)[P + 1]) {
   using D = Dims<P>;
-  using TB = Tab<P, T>;
 #pragma unroll
   for (int k = 0; k < D::N; ++k) {
     zbb[k] = buf[k * D::Q2 + t];
@@ -238,7 +251,8 @@ __device__ __forceinline__ void load_z(const T *buf, int t, T (&zbb)[P + 1], T (
 template <int P, typename T, bool DIFF>
 __device__ __forceinline__ void bwd_y(T *buf, int t) {
   using D = Dims<P>;
-  using TB = Tab<P, T>;
+  using BT = eo::Tab1<P, 0>;
+  using GT = eo::Tab1<P, 1>;
   constexpr int N = D::N, Q = D::Q;
   const bool w = t < Q * N;
   const int a = t % Q, k = t / Q;
@@ -253,20 +267,26 @@ __device__ __forceinline__ void bwd_y(T *buf, int t) {
         i3[b] = buf[2 * D::NQ2 + (k * Q + b) * Q + a];
       }
     }
+    eo::Acc<N, T> A1, A2;
+    A1.zero();
+    A2.zero();
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-      T s1 = 0, s2 = 0;
-#pragma unroll
-      for (int b = 0; b < Q; ++b) {
-        s1 += TB::B(b, j) * i1[b];
-        if constexpr (DIFF) {
-          s1 += TB::G(b, j) * i2[b];
-          s2 += TB::B(b, j) * i3[b];
-        }
+    for (int b = 0; b < Q / 2; ++b) {
+      A1.template add_pair<BT>(b, i1[b], i1[Q - 1 - b]);
+      if constexpr (DIFF) {
+        A1.template add_pair<GT>(b, i2[b], i2[Q - 1 - b]);
+        A2.template add_pair<BT>(b, i3[b], i3[Q - 1 - b]);
       }
-      r1[j] = s1;
-      r2[j] = s2;
     }
+    if constexpr (Q % 2 == 1) {
+      A1.template add_mid<BT>(i1[Q / 2]);
+      if constexpr (DIFF) {
+        A1.template add_mid<GT>(i2[Q / 2]);
+        A2.template add_mid<BT>(i3[Q / 2]);
+      }
+    }
+    A1.finish(r1);
+    if constexpr (DIFF) A2.finish(r2);
   }
   __syncthreads();
   if (w) {
@@ -283,7 +303,8 @@ __device__ __forceinline__ void bwd_y(T *buf, int t) {
 template <int P, typename T, bool DIFF>
 __device__ __forceinline__ void bwd_x(T *buf, int t) {
   using D = Dims<P>;
-  using TB = Tab<P, T>;
+  using BT = eo::Tab1<P, 0>;
+  using GT = eo::Tab1<P, 1>;
   constexpr int N = D::N, Q = D::Q;
   const bool w = t < D::N2;
   const int j = t % N, k = t / N;
@@ -295,16 +316,18 @@ __device__ __forceinline__ void bwd_x(T *buf, int t) {
       i1[a] = buf[(k * N + j) * Q + a];
       if constexpr (DIFF) i2[a] = buf[D::QN2 + (k * N + j) * Q + a];
     }
+    eo::Acc<N, T> A;
+    A.zero();
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      T s = 0;
-#pragma unroll
-      for (int a = 0; a < Q; ++a) {
-        s += TB::B(a, i) * i1[a];
-        if constexpr (DIFF) s += TB::G(a, i) * i2[a];
-      }
-      yo[i] = s;
+    for (int a = 0; a < Q / 2; ++a) {
+      A.template add_pair<BT>(a, i1[a], i1[Q - 1 - a]);
+      if constexpr (DIFF) A.template add_pair<GT>(a, i2[a], i2[Q - 1 - a]);
     }
+    if constexpr (Q % 2 == 1) {
+      A.template add_mid<BT>(i1[Q / 2]);
+      if constexpr (DIFF) A.template add_mid<GT>(i2[Q / 2]);
+    }
+    A.finish(yo);
   }
   __syncthreads();
   if (w) {
@@ -327,20 +350,21 @@ __device__ __forceinline__ int64_t xcd_block(int64_t nblk) {
 // and the E-vector Y[m] at the shared nodes; with part != null also the per-block sums
 // of x_g y_g over the sole DoFs (part[m * part_mstride + block]).
 template <int P, typename T, int OP>
-__global__ void __launch_bounds__(Dims<P>::THREADS)
+__global__ void __launch_bounds__(Dims<P>::THREADS, Dims<P>::OCC)
 apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
              int64_t qd_mstride, const T *__restrict__ nu, int64_t nu_mstride, int64_t nelem,
              int nbatch, int64_t ndof, const T *__restrict__ x, T *__restrict__ Y,
              int64_t estride, int compact, T *__restrict__ y, double *__restrict__ part,
              int64_t part_mstride) {
   using D = Dims<P>;
-  using TB = Tab<P, T>;
   constexpr int N = D::N, Q = D::Q, Q2 = D::Q2, Q3 = D::Q3, N3 = D::N3;
   constexpr int TPE = D::TPE, E = D::E;
   constexpr bool MASS = (OP == 0) || (OP == 2);
   constexpr bool DIFF = (OP == 1) || (OP == 2);
 
   __shared__ T smem[E * D::BUF];
+  __shared__ int32_t smap_all[E * N3];  // the elements' map entries, kept for the output
+  __shared__ T sx_all[E * N3];          // their x values (for the fused dot product)
   __shared__ double red[8];
   const int le = threadIdx.x / TPE;
   const int t = threadIdx.x - le * TPE;
@@ -351,66 +375,143 @@ apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
   T *buf = smem + le * D::BUF;
   const int32_t *emap = map + es * (int64_t)N3;
 
+  // Quadrature values one thread needs per slice c: w|J| (mass), the 6 entries of
+  // w|J| J^-1 J^-T (diffusion), and nu for the diffusion operator.
+  constexpr int NS = (OP == 0) ? 1 : (OP == 2 ? 7 : 7);
   for (int m = 0; m < nbatch; ++m) {
     const T *xm = x + (int64_t)m * ndof;
+    const T *qe = qd + (int64_t)m * qd_mstride + es * (int64_t)(kQdSlots * Q3);
+    const T *ne = nullptr;
+    if constexpr (OP == 1) ne = nu + (int64_t)m * nu_mstride + es * (int64_t)Q3;
+    // (inactive slots read element 0's data, which is discarded)
+    auto load_slice = [&](T (&dst)[NS], int c) {
+      const int qi = c * Q2 + t;
+      if constexpr (OP == 0) {
+        dst[0] = qe[qi];
+      } else if constexpr (OP == 2) {
+#pragma unroll
+        for (int s = 0; s < 7; ++s) dst[s] = qe[s * Q3 + qi];
+      } else {
+#pragma unroll
+        for (int s = 0; s < 6; ++s) dst[s] = qe[(s + 1) * Q3 + qi];
+        dst[6] = ne[qi];
+      }
+    };
 
-    gather_e<P, T>(buf, t, active, emap, xm);
+    int32_t *smap = smap_all + le * N3;
+    T *sx = sx_all + le * N3;
+    gather_e<P, T>(buf, t, active, emap, xm, smap, part ? sx : nullptr);
     fwd_x<P, T, DIFF>(buf, t);
+    T pre0[NS], pre1[NS];  // quadrature data of the first slice pair, loaded early
+    load_slice(pre0, 0);
+    load_slice(pre1, Q - 1);
     fwd_y<P, T, DIFF>(buf, t);
 
-    // xi_3 contraction, quadrature function, transposed xi_3: thread = line (a, b)
+    // xi_3 contraction, quadrature function, transposed xi_3: thread = line (a, b),
+    // processed by symmetric slice pairs (c, q-1-c).
     {
+      using BT = eo::Tab1<P, 0>;
+      using GT = eo::Tab1<P, 1>;
       T zbb[N], zgb[N], zbg[N];
       load_z<P, T, DIFF>(buf, t, zbb, zgb, zbg);
-      T p1[N], p2[N], p3[N];
-#pragma unroll
-      for (int k = 0; k < N; ++k) p1[k] = p2[k] = p3[k] = T(0);
-      const T *qe = qd + (int64_t)m * qd_mstride + es * (int64_t)(kQdSlots * Q3);
-      const T *ne = nullptr;
-      if constexpr (OP == 1) {
-        if (nu) ne = nu + (int64_t)m * nu_mstride + es * (int64_t)Q3;
+      const auto sbb = eo::split(zbb);
+      eo::Split<N, T> sgb{}, sbg{};
+      if constexpr (DIFF) {
+        sgb = eo::split(zgb);
+        sbg = eo::split(zbg);
       }
+      eo::Acc<N, T> A1, A2, A3;
+      A1.zero();
+      A2.zero();
+      A3.zero();
+      auto row_pair = [](auto tb, const eo::Split<N, T> &x, int c, T &lo, T &hi) {
+        using TT = decltype(tb);
+        T Ev = 0, Od = 0;
 #pragma unroll
-      for (int c = 0; c < Q; ++c) {
-        const int qi = c * Q2 + t;
+        for (int i = 0; i < N / 2; ++i) {
+          Ev += (T)TT::e(c, i) * x.e[i];
+          Od += (T)TT::o(c, i) * x.o[i];
+        }
+        if constexpr (N % 2 == 1) Ev += (T)TT::t(c, N / 2) * x.e[N / 2];
+        lo = Ev + Od;
+        hi = (TT::S > 0) ? (Ev - Od) : (Od - Ev);
+      };
+      auto row_mid = [](auto tb, const eo::Split<N, T> &x) -> T {
+        using TT = decltype(tb);
+        T M = 0;
+#pragma unroll
+        for (int i = 0; i < N / 2; ++i) M += (T)TT::t(Q / 2, i) * (TT::S > 0 ? x.e[i] : x.o[i]);
+        if constexpr (N % 2 == 1 && TT::S > 0) M += (T)TT::t(Q / 2, N / 2) * x.e[N / 2];
+        return M;
+      };
+      auto qfun = [&](int c, T u, T dx, T dy, T dz, T &v, T &g1, T &g2, T &g3) {
+        T cur[NS];
+        if (c == 0) {
+#pragma unroll
+          for (int z = 0; z < NS; ++z) cur[z] = pre0[z];
+        } else if (c == Q - 1) {
+#pragma unroll
+          for (int z = 0; z < NS; ++z) cur[z] = pre1[z];
+        } else {
+          load_slice(cur, c);
+        }
+        v = g1 = g2 = g3 = T(0);
+        if constexpr (MASS) v = cur[0] * u;
+        if constexpr (DIFF) {
+          constexpr int o = MASS ? 1 : 0;
+          const T G11 = cur[o + 0], G22 = cur[o + 1], G33 = cur[o + 2];
+          const T G12 = cur[o + 3], G13 = cur[o + 4], G23 = cur[o + 5];
+          g1 = G11 * dx + G12 * dy + G13 * dz;
+          g2 = G12 * dx + G22 * dy + G23 * dz;
+          g3 = G13 * dx + G23 * dy + G33 * dz;
+          if constexpr (OP == 1) {
+            g1 *= cur[NS - 1];
+            g2 *= cur[NS - 1];
+            g3 *= cur[NS - 1];
+          }
+        }
+      };
+#pragma unroll
+      for (int c = 0; c < Q / 2; ++c) {
+        T u0 = 0, u1 = 0, dx0 = 0, dx1 = 0, dy0 = 0, dy1 = 0, dz0 = 0, dz1 = 0;
+        if constexpr (MASS) row_pair(BT{}, sbb, c, u0, u1);
+        if constexpr (DIFF) {
+          row_pair(GT{}, sbb, c, dz0, dz1);
+          row_pair(BT{}, sgb, c, dy0, dy1);
+          row_pair(BT{}, sbg, c, dx0, dx1);
+        }
+        T v0, g10, g20, g30, v1, g11, g21, g31;
+        qfun(c, u0, dx0, dy0, dz0, v0, g10, g20, g30);
+        qfun(Q - 1 - c, u1, dx1, dy1, dz1, v1, g11, g21, g31);
+        if constexpr (MASS) A1.template add_pair<BT>(c, v0, v1);
+        if constexpr (DIFF) {
+          A1.template add_pair<GT>(c, g30, g31);
+          A2.template add_pair<BT>(c, g20, g21);
+          A3.template add_pair<BT>(c, g10, g11);
+        }
+      }
+      if constexpr (Q % 2 == 1) {
         T u = 0, dx = 0, dy = 0, dz = 0;
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-          if constexpr (MASS) u += TB::B(c, k) * zbb[k];
-          if constexpr (DIFF) {
-            dz += TB::G(c, k) * zbb[k];
-            dy += TB::B(c, k) * zgb[k];
-            dx += TB::B(c, k) * zbg[k];
-          }
+        if constexpr (MASS) u = row_mid(BT{}, sbb);
+        if constexpr (DIFF) {
+          dz = row_mid(GT{}, sbb);
+          dy = row_mid(BT{}, sgb);
+          dx = row_mid(BT{}, sbg);
         }
-        T v = 0, g1 = 0, g2 = 0, g3 = 0;
-        if (active) {
-          if constexpr (MASS) v = qe[qi] * u;
-          if constexpr (DIFF) {
-            const T G11 = qe[1 * Q3 + qi], G22 = qe[2 * Q3 + qi], G33 = qe[3 * Q3 + qi];
-            const T G12 = qe[4 * Q3 + qi], G13 = qe[5 * Q3 + qi], G23 = qe[6 * Q3 + qi];
-            g1 = G11 * dx + G12 * dy + G13 * dz;
-            g2 = G12 * dx + G22 * dy + G23 * dz;
-            g3 = G13 * dx + G23 * dy + G33 * dz;
-            if constexpr (OP == 1) {
-              if (ne) {
-                const T s = ne[qi];
-                g1 *= s;
-                g2 *= s;
-                g3 *= s;
-              }
-            }
-          }
+        T v, g1, g2, g3;
+        qfun(Q / 2, u, dx, dy, dz, v, g1, g2, g3);
+        if constexpr (MASS) A1.template add_mid<BT>(v);
+        if constexpr (DIFF) {
+          A1.template add_mid<GT>(g3);
+          A2.template add_mid<BT>(g2);
+          A3.template add_mid<BT>(g1);
         }
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-          if constexpr (MASS) p1[k] += TB::B(c, k) * v;
-          if constexpr (DIFF) {
-            p1[k] += TB::G(c, k) * g3;
-            p2[k] += TB::B(c, k) * g2;
-            p3[k] += TB::B(c, k) * g1;
-          }
-        }
+      }
+      T p1[N], p2[N], p3[N];
+      A1.finish(p1);
+      if constexpr (DIFF) {
+        A2.finish(p2);
+        A3.finish(p3);
       }
       __syncthreads();
 #pragma unroll
@@ -427,12 +528,12 @@ apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
     bwd_y<P, T, DIFF>(buf, t);
     bwd_x<P, T, DIFF>(buf, t);
     if (part) {
-      const double dot = emit_e<P, T, true>(buf, t, active, emap, es, compact != 0, xm,
+      const double dot = emit_e<P, T, true>(buf, t, active, smap, sx, es, compact != 0,
                                             Y + (int64_t)m * estride, y + (int64_t)m * ndof);
       const double sum = block_sum_d(dot, red);
       if (threadIdx.x == 0) part[(int64_t)m * part_mstride + blockIdx.x] = sum;
     } else {
-      emit_e<P, T, false>(buf, t, active, emap, es, compact != 0, xm, Y + (int64_t)m * estride,
+      emit_e<P, T, false>(buf, t, active, smap, sx, es, compact != 0, Y + (int64_t)m * estride,
                           y + (int64_t)m * ndof);
     }
     __syncthreads();
@@ -442,7 +543,6 @@ apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
 template <int P, typename T>
 hipError_t launch_apply_pt(const ApplyArgs &a, hipStream_t s) {
   using D = Dims<P>;
-  using TB = Tab<P, T>;
   if (a.nelem <= 0 || a.nbatch <= 0) return hipSuccess;
   dim3 grid((unsigned)((a.nelem + D::E - 1) / D::E));
   dim3 block(D::THREADS);

@@ -7,16 +7,10 @@
 #include <string>
 #include <vector>
 
+#include "plan.h"
 #include "sfem.h"
 
 namespace sfem {
-
-// Encoding of the library-owned element->DoF map entries (int32):
-//   bits 0..29  global DoF
-//   bit 30      "sole": the DoF belongs to this element only (written directly)
-//   bit 31      essential DoF (entry is negative)
-constexpr int32_t kDofMask = 0x3fffffff;
-constexpr int32_t kSoleBit = 0x40000000;
 
 // How the assembly sets essential DoFs: copy x (operator apply), 1 (diagonal), 0 (load)
 enum EssKind { kEssCopyX = 0, kEssOne = 1, kEssZero = 2 };
@@ -77,14 +71,20 @@ struct ApplyArgs {
 // Element phase of the apply over all elements (writes the E-vector).
 hipError_t launch_apply_f64(const ApplyArgs &a, hipStream_t s);
 hipError_t launch_apply_f32(const ApplyArgs &a, hipStream_t s);
-// Assembly phase over the na DoFs of alist (shared or essential): y[g] = sum of the
-// E-vector entries slot[aoff[i]..aoff[i+1]) in order; essential DoFs (no slots) get
-// x[g], 1 or 0 per ess_kind.  With part != null also the per-block sums of x_g y_g
-// (part[m * part_mstride + block], nblk blocks).
+// Assembly list on the device (see HostPlan): the assembled DoFs, ascending, CSR offsets
+// and the E-vector slots of their contributions in element order.
+struct AsmPlan {
+  const int32_t *alist;
+  const int32_t *aoff;
+  const int32_t *slot;
+  int64_t na;
+};
+// Assembly phase over the list: y[g] = sum of g's E-vector entries in element order;
+// essential DoFs get x[g], 1 or 0 per ess_kind.  With part != null also the per-block
+// sums of x_g y_g (part[m * part_mstride + block], assemble_nblk blocks).
 int assemble_nblk(int64_t na);
 template <typename T>
-hipError_t launch_assemble(const int32_t *alist, const int32_t *aoff, const int32_t *slot,
-                           int64_t na, const T *evec, int64_t estride, const T *x, T *y,
+hipError_t launch_assemble(const AsmPlan &pl, const T *evec, int64_t estride, const T *x, T *y,
                            int64_t n, int nb, int ess_kind, double *part, int64_t part_mstride,
                            hipStream_t s);
 

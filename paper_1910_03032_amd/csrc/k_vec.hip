@@ -45,17 +45,78 @@ __device__ __forceinline__ void write_part(double (&v)[NV], double *part, int nb
   }
 }
 
-// Sum of the nblk partials of quantity k of member blockIdx.x (one block per member).
-template <int NV>
-__device__ __forceinline__ void reduce_parts(const double *part, int nblk, double (&v)[NV]) {
-  const int m = blockIdx.x;
+// Sum of the nblk partials of quantity k (NV quantities per member, part[(m NV + k) nblk
+// + i]) of member m by a block of NT threads: each thread sums a fixed strided subset
+// (4 independent loads per step), then a wave64 butterfly and the waves in order.  The
+// order depends only on nblk and NT.  Result broadcast to all threads.
+template <int NV, int NT>
+__device__ __forceinline__ void reduce_parts_m(const double *part, int nblk, int m, double (&v)[NV]) {
+  __shared__ double sh[NV][NT / 64];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double *pk = part + ((int64_t)m * NV + k) * nblk;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int i = threadIdx.x;
+    for (; i + 3 * NT < nblk; i += 4 * NT) {
+      s0 += pk[i];
+      s1 += pk[i + NT];
+      s2 += pk[i + 2 * NT];
+      s3 += pk[i + 3 * NT];
+    }
+    for (; i < nblk; i += NT) s0 += pk[i];
+    double s = (s0 + s1) + (s2 + s3);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = s;
+  }
+  __syncthreads();
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += VB) s += part[((int64_t)m * NV + k) * nblk + i];
+    for (int w = 0; w < NT / 64; ++w) s += sh[k][w];
     v[k] = s;
   }
-  block_sum<NV>(v);
+}
+
+// One block of RB threads per member (blockIdx.x = member).
+constexpr int RB = 1024;
+template <int NV>
+__device__ __forceinline__ void reduce_parts(const double *part, int nblk, double (&v)[NV]) {
+  reduce_parts_m<NV, RB>(part, nblk, blockIdx.x, v);
+}
+
+// CG step length from p.Ap (or the failure state).
+__device__ __forceinline__ void set_alpha(PcgScalars &s, double pw) {
+  s.pw = pw;
+  s.alpha = 0.0;
+  if (s.active) {
+    if (!isfinite(pw)) {
+      s.status = SFEM_E_NAN;
+      s.active = 0;
+    } else if (!(pw > 0.0)) {
+      s.status = SFEM_E_BREAKDOWN;
+      s.active = 0;
+    } else {
+      s.alpha = s.rho / pw;
+    }
+  }
+}
+
+// New direction coefficient from r.z and r.r, and the stopping test.
+__device__ __forceinline__ void set_beta(PcgScalars &s, double rz, double rr) {
+  s.beta = 0.0;
+  if (s.active) {
+    s.iters += 1;
+    if (!isfinite(rz) || !isfinite(rr)) {
+      s.status = SFEM_E_NAN;
+      s.active = 0;
+    } else {
+      s.beta = rz / s.rho;
+      s.rho = rz;
+      s.rr = rr;
+      if (rr <= s.tol2) s.active = 0;
+    }
+  }
 }
 
 // r = b - w (w may be null: r = b); x = 0 if xzero; p = dinv r;
@@ -140,7 +201,7 @@ __global__ void sub_norm_kernel(const double *__restrict__ b, const double *__re
   write_part<1>(v, part, nblk);
 }
 
-__global__ void init_scalars_kernel(const double *__restrict__ part, int nblk, double rtol,
+__global__ void __launch_bounds__(RB) init_scalars_kernel(const double *__restrict__ part, int nblk, double rtol,
                                     PcgScalars *__restrict__ sc) {
   double v[3];
   reduce_parts<3>(part, nblk, v);
@@ -160,53 +221,23 @@ __global__ void init_scalars_kernel(const double *__restrict__ part, int nblk, d
   }
 }
 
-__global__ void alpha_kernel(const double *__restrict__ part, int nblk,
-                             PcgScalars *__restrict__ sc) {
+__global__ void __launch_bounds__(RB) alpha_kernel(const double *__restrict__ part, int nblk,
+                                                   PcgScalars *__restrict__ sc) {
   double v[1];
   reduce_parts<1>(part, nblk, v);
-  if (threadIdx.x == 0) {
-    PcgScalars &s = sc[blockIdx.x];
-    s.pw = v[0];
-    s.alpha = 0.0;
-    if (s.active) {
-      if (!isfinite(v[0])) {
-        s.status = SFEM_E_NAN;
-        s.active = 0;
-      } else if (!(v[0] > 0.0)) {
-        s.status = SFEM_E_BREAKDOWN;
-        s.active = 0;
-      } else {
-        s.alpha = s.rho / v[0];
-      }
-    }
-  }
+  if (threadIdx.x == 0) set_alpha(sc[blockIdx.x], v[0]);
 }
 
-__global__ void beta_kernel(const double *__restrict__ part, int nblk,
-                            PcgScalars *__restrict__ sc) {
+__global__ void __launch_bounds__(RB) beta_kernel(const double *__restrict__ part, int nblk,
+                                                  PcgScalars *__restrict__ sc) {
   double v[2];
   reduce_parts<2>(part, nblk, v);
-  if (threadIdx.x == 0) {
-    PcgScalars &s = sc[blockIdx.x];
-    s.beta = 0.0;
-    if (s.active) {
-      s.iters += 1;
-      if (!isfinite(v[0]) || !isfinite(v[1])) {
-        s.status = SFEM_E_NAN;
-        s.active = 0;
-      } else {
-        s.beta = v[0] / s.rho;
-        s.rho = v[0];
-        s.rr = v[1];
-        if (v[1] <= s.tol2) s.active = 0;
-      }
-    }
-  }
+  if (threadIdx.x == 0) set_beta(sc[blockIdx.x], v[0], v[1]);
 }
 
 // out[m * nv + k] = sum of partials
 template <int NV>
-__global__ void reduce_out_kernel(const double *__restrict__ part, int nblk,
+__global__ void __launch_bounds__(RB) reduce_out_kernel(const double *__restrict__ part, int nblk,
                                   double *__restrict__ out) {
   double v[NV];
   reduce_parts<NV>(part, nblk, v);
@@ -217,7 +248,7 @@ __global__ void reduce_out_kernel(const double *__restrict__ part, int nblk,
 }
 
 // IR state per member: [0] = ||r||^2, [1] = ||b||^2, [2] = scale (||r|| while refining, else 0)
-__global__ void ir_norm_kernel(const double *__restrict__ part, int nblk, int set_bb, double rtol,
+__global__ void __launch_bounds__(RB) ir_norm_kernel(const double *__restrict__ part, int nblk, int set_bb, double rtol,
                                double *__restrict__ ir) {
   double v[1];
   reduce_parts<1>(part, nblk, v);
@@ -252,40 +283,41 @@ __global__ void ir_accum_kernel(double *__restrict__ x, const float *__restrict_
 }
 
 // Assembly over the list of shared and essential DoFs: y[g] = sum of the E-vector
-// entries of g in slot order; essential DoFs (no slots) get x[g], 1 or 0.  DOT: also the
-// per-block sums of x_g y_g.  Each thread takes AU list entries per pass (stride VB);
+// entries of g in element order; essential DoFs (no slots) get x[g], 1 or 0.  DOT: also
+// the per-block sums of x_g y_g.  Each thread takes AU list entries per pass (stride VB);
 // for each it loads the first KS slot indices together, then the E-vector values
-// together, so a DoF shared by up to KS elements (8 on a hex mesh) costs three
-// dependent memory round trips; longer slot lists fall back to a loop.
+// together; longer slot lists fall back to a loop.  The list is in ascending DoF order,
+// so a wavefront's E-vector reads fall on the lines of a few neighbouring elements.
+// Index arithmetic is 32-bit (entries and slots are below 2^31, checked at set-up).
 constexpr int AU = 2;
 constexpr int KS = 8;
+
 template <typename T, bool DOT>
 __global__ void __launch_bounds__(VB)
-assemble_kernel(const int32_t *__restrict__ alist, const int32_t *__restrict__ aoff,
-                const int32_t *__restrict__ slot, int64_t na, const T *__restrict__ Y,
-                int64_t estride, const T *__restrict__ x, T *__restrict__ y, int64_t n,
-                int ess_kind, double *__restrict__ part, int64_t part_mstride, int nblk) {
-  const int m = blockIdx.y;
-  const T *Ym = Y + (int64_t)m * estride;
-  const T *xm = x ? x + (int64_t)m * n : nullptr;
-  T *ym = y + (int64_t)m * n;
+assemble_kernel(AsmPlan pl, const T *__restrict__ Y, int64_t estride, const T *__restrict__ x,
+                T *__restrict__ y, int64_t n, int ess_kind, double *__restrict__ part,
+                int64_t part_mstride, int nblk) {
+  const int mb = blockIdx.y;
+  const T *Ym = Y + (int64_t)mb * estride;
+  const T *xm = x ? x + (int64_t)mb * n : nullptr;
+  T *ym = y + (int64_t)mb * n;
+  const int na = (int)pl.na;
   double v[1] = {0.0};
-  for (int64_t base = (int64_t)blockIdx.x * (VB * AU) + threadIdx.x; base < na;
-       base += (int64_t)nblk * (VB * AU)) {
+  for (int base = (int)blockIdx.x * (VB * AU) + (int)threadIdx.x; base < na; base += nblk * (VB * AU)) {
     int32_t g[AU], a[AU], d[AU];
 #pragma unroll
     for (int k = 0; k < AU; ++k) {
-      const int64_t i = base + (int64_t)k * VB;
+      const int i = base + k * VB;
       const bool in = i < na;
-      g[k] = in ? alist[i] : 0;
-      a[k] = in ? aoff[i] : 0;
-      d[k] = in ? aoff[i + 1] - a[k] : -1;
+      g[k] = in ? pl.alist[i] : 0;
+      a[k] = in ? pl.aoff[i] : 0;
+      d[k] = in ? pl.aoff[i + 1] - a[k] : -1;
     }
     int32_t sl[AU][KS];
 #pragma unroll
     for (int k = 0; k < AU; ++k)
 #pragma unroll
-      for (int j = 0; j < KS; ++j) sl[k][j] = (j < d[k]) ? slot[a[k] + j] : 0;
+      for (int j = 0; j < KS; ++j) sl[k][j] = (j < d[k]) ? pl.slot[a[k] + j] : 0;
     T val[AU][KS];
 #pragma unroll
     for (int k = 0; k < AU; ++k)
@@ -298,7 +330,7 @@ assemble_kernel(const int32_t *__restrict__ alist, const int32_t *__restrict__ a
 #pragma unroll
       for (int j = 1; j < KS; ++j)
         if (j < d[k]) acc += val[k][j];
-      for (int32_t j = KS; j < d[k]; ++j) acc += Ym[slot[a[k] + j]];
+      for (int j = KS; j < d[k]; ++j) acc += Ym[pl.slot[a[k] + j]];
       const T xg = (DOT || (d[k] == 0 && ess_kind == kEssCopyX)) ? xm[g[k]] : T(0);
       if (d[k] == 0) acc = (ess_kind == kEssCopyX) ? xg : (ess_kind == kEssOne ? T(1) : T(0));
       ym[g[k]] = acc;
@@ -307,7 +339,7 @@ assemble_kernel(const int32_t *__restrict__ alist, const int32_t *__restrict__ a
   }
   if constexpr (DOT) {
     block_sum<1>(v);
-    if (threadIdx.x == 0) part[(int64_t)m * part_mstride + blockIdx.x] = v[0];
+    if (threadIdx.x == 0) part[(int64_t)mb * part_mstride + blockIdx.x] = v[0];
   }
 }
 
@@ -333,6 +365,14 @@ unsigned grid_for(int64_t n) {
 }
 
 }  // namespace
+
+int assemble_nblk(int64_t na) {
+  int64_t b = (na + VB * AU - 1) / (VB * AU);
+  if (b < 1) b = 1;
+  if (b > 8192) b = 8192;
+  return (int)b;
+}
+
 
 int vec_nblk(int64_t n) {
   int64_t b = (n + VB * 2 - 1) / (VB * 2);
@@ -387,35 +427,25 @@ hipError_t VecOps<T>::recip(const double *d, T *out, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-int assemble_nblk(int64_t na) {
-  int64_t b = (na + VB * AU - 1) / (VB * AU);
-  if (b < 1) b = 1;
-  if (b > 8192) b = 8192;
-  return (int)b;
-}
-
 template <typename T>
-hipError_t launch_assemble(const int32_t *alist, const int32_t *aoff, const int32_t *slot,
-                           int64_t na, const T *evec, int64_t estride, const T *x, T *y,
+hipError_t launch_assemble(const AsmPlan &pl, const T *evec, int64_t estride, const T *x, T *y,
                            int64_t n, int nb, int ess_kind, double *part, int64_t part_mstride,
                            hipStream_t s) {
-  if (na <= 0 || nb <= 0) return hipSuccess;
-  const int nblk = assemble_nblk(na);
+  if (pl.na <= 0 || nb <= 0) return hipSuccess;
+  const int nblk = assemble_nblk(pl.na);
   if (part)
-    hipLaunchKernelGGL((assemble_kernel<T, true>), dim3(nblk, nb), dim3(VB), 0, s, alist, aoff, slot,
-                       na, evec, estride, x, y, n, ess_kind, part, part_mstride, nblk);
+    hipLaunchKernelGGL((assemble_kernel<T, true>), dim3(nblk, nb), dim3(VB), 0, s, pl, evec, estride,
+                       x, y, n, ess_kind, part, part_mstride, nblk);
   else
-    hipLaunchKernelGGL((assemble_kernel<T, false>), dim3(nblk, nb), dim3(VB), 0, s, alist, aoff,
-                       slot, na, evec, estride, x, y, n, ess_kind, part, part_mstride, nblk);
+    hipLaunchKernelGGL((assemble_kernel<T, false>), dim3(nblk, nb), dim3(VB), 0, s, pl, evec, estride,
+                       x, y, n, ess_kind, part, part_mstride, nblk);
   return hipGetLastError();
 }
-template hipError_t launch_assemble<double>(const int32_t *, const int32_t *, const int32_t *,
-                                            int64_t, const double *, int64_t, const double *,
+template hipError_t launch_assemble<double>(const AsmPlan &, const double *, int64_t, const double *,
                                             double *, int64_t, int, int, double *, int64_t,
                                             hipStream_t);
-template hipError_t launch_assemble<float>(const int32_t *, const int32_t *, const int32_t *,
-                                           int64_t, const float *, int64_t, const float *, float *,
-                                           int64_t, int, int, double *, int64_t, hipStream_t);
+template hipError_t launch_assemble<float>(const AsmPlan &, const float *, int64_t, const float *,
+                                           float *, int64_t, int, int, double *, int64_t, hipStream_t);
 
 template struct VecOps<double>;
 template struct VecOps<float>;
@@ -428,28 +458,28 @@ hipError_t launch_sub_norm(const double *b, const double *w, double *r, double *
 
 hipError_t launch_pcg_init(const double *part, int nblk, int nb, double rtol, PcgScalars *sc,
                            hipStream_t s) {
-  hipLaunchKernelGGL(init_scalars_kernel, dim3(nb), dim3(VB), 0, s, part, nblk, rtol, sc);
+  hipLaunchKernelGGL(init_scalars_kernel, dim3(nb), dim3(RB), 0, s, part, nblk, rtol, sc);
   return hipGetLastError();
 }
 
 hipError_t launch_pcg_alpha(const double *part, int nblk, int nb, PcgScalars *sc, hipStream_t s) {
-  hipLaunchKernelGGL(alpha_kernel, dim3(nb), dim3(VB), 0, s, part, nblk, sc);
+  hipLaunchKernelGGL(alpha_kernel, dim3(nb), dim3(RB), 0, s, part, nblk, sc);
   return hipGetLastError();
 }
 
 hipError_t launch_pcg_beta(const double *part, int nblk, int nb, PcgScalars *sc, hipStream_t s) {
-  hipLaunchKernelGGL(beta_kernel, dim3(nb), dim3(VB), 0, s, part, nblk, sc);
+  hipLaunchKernelGGL(beta_kernel, dim3(nb), dim3(RB), 0, s, part, nblk, sc);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce1(const double *part, int nblk, int nb, double *out, hipStream_t s) {
-  hipLaunchKernelGGL((reduce_out_kernel<1>), dim3(nb), dim3(VB), 0, s, part, nblk, out);
+  hipLaunchKernelGGL((reduce_out_kernel<1>), dim3(nb), dim3(RB), 0, s, part, nblk, out);
   return hipGetLastError();
 }
 
 hipError_t launch_ir_norm(const double *part, int nblk, int nb, int set_bb, double rtol, double *ir,
                           hipStream_t s) {
-  hipLaunchKernelGGL(ir_norm_kernel, dim3(nb), dim3(VB), 0, s, part, nblk, set_bb, rtol, ir);
+  hipLaunchKernelGGL(ir_norm_kernel, dim3(nb), dim3(RB), 0, s, part, nblk, set_bb, rtol, ir);
   return hipGetLastError();
 }
 

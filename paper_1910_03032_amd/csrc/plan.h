@@ -1,0 +1,43 @@
+// Host-side preparation of an order-p mesh for the library (no HIP): validation of the
+// element->DoF map, the encoded map the element kernels read, and the assembly plan
+// (which DoFs the assembly kernel writes and where their element contributions are).
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace sfem {
+
+// Encoding of the library-owned element->DoF map entries (int32):
+//   bits 0..29  global DoF
+//   bit 30      "sole": the DoF belongs to this element only (written directly)
+//   bit 31      essential DoF (entry is negative)
+constexpr int32_t kDofMask = 0x3fffffff;
+constexpr int32_t kSoleBit = 0x40000000;
+
+struct HostPlan {
+  bool compact = true;         // E-vector holds the surface nodes only (S per element)
+  int64_t epe = 0;             // E-vector entries per element (S or n^3)
+  std::vector<int32_t> imap;   // [nelem][n^3] encoded map
+  // Assembly list: the DoFs the assembly kernel writes (shared or essential), ascending,
+  // with CSR offsets into slots, the E-vector slots of their contributions in element
+  // order (essential DoFs have none).
+  std::vector<int32_t> alist;  // [na]
+  std::vector<int32_t> aoff;   // [na + 1]
+  std::vector<int32_t> slots;  // [aoff[na]]
+  int64_t na = 0;
+};
+
+// Rank of local node l (l = i + n (j + n k), n = p + 1) among the element's surface nodes:
+// face k = 0, face k = p, then for each interior k the ring of the (i, j) square; -1 for
+// an interior node.
+int64_t surface_rank(int p, int64_t l);
+
+// Validates the map (range, no DoF twice in an element, every DoF used) and builds the
+// plan.  Returns 0, or a negative sfem_status with err describing the problem.
+int build_host_plan(int p, int64_t nelem, const int32_t *dofs, int64_t ndof, const uint8_t *ess,
+                    HostPlan &out, std::string &err);
+
+}  // namespace sfem

@@ -221,7 +221,8 @@ def test_fan_mesh_multiplicities_3_and_6(p):
     nu = nu_uniform(m.nelem, q, seed=2)
     op.set_coeffs(3.0, 0.7, gpu(nu))
     x = uniform(m.ndof, seed=1)
-    for opk, (a, b) in ((0, (3.0, 0.0)), (1, (0.0, 0.7)), (2, (3.0, 0.7))):
+    # SFEM_MASS is M, SFEM_DIFFUSION is K(nu), SFEM_HELMHOLTZ is alpha M + beta K(nu)
+    for opk, (a, b) in ((0, (1.0, 0.0)), (1, (0.0, 1.0)), (2, (3.0, 0.7))):
         yo = d.apply(x, a, b, nu if opk else None)
         assert rel(host(op.apply(gpu(x), op=opk)), yo) <= 1e-12, opk
         assert rel(host(op.apply(gpu(x, torch.float32), op=opk)), yo) <= 1e-5, opk
