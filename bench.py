@@ -56,8 +56,11 @@ def log(*a):
 # assembly dispatch), from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a plain
 # copy's readings; valid only for the kernel sources they were taken with (keyed by
 # the hash of those sources), otherwise the roofline reports traffic = null.
-KERNEL_SOURCES = ["apply_impl.h", "eo.h", "rules.h", "internal.h", "k_apply_f64.hip", "k_vec.hip"]
-MEASURED_TRAFFIC = {}
+KERNEL_SOURCES = ["apply_impl.h", "eo.h", "rules.h", "internal.h", "plan.h", "k_apply_f64.hip", "k_vec.hip"]
+MEASURED_TRAFFIC = {
+    # profiles/helmholtz_apply_p4_32e_hbm_bytes.md
+    ("96e0c2326b6117e7", "helmholtz_p4_32e"): 588672021,
+}
 
 
 def kernel_source_hash():

@@ -289,7 +289,7 @@ __global__ void ir_accum_kernel(double *__restrict__ x, const float *__restrict_
 // together; longer slot lists fall back to a loop.  The list is in ascending DoF order,
 // so a wavefront's E-vector reads fall on the lines of a few neighbouring elements.
 // Index arithmetic is 32-bit (entries and slots are below 2^31, checked at set-up).
-constexpr int AU = 2;
+constexpr int AU = 1;
 constexpr int KS = 8;
 
 template <typename T, bool DOT>
