@@ -45,8 +45,9 @@ struct sfem_ctx {
   int64_t epe = 0;                 // E-vector entries per element (surface nodes or n^3)
   int64_t na = 0;                  // number of DoFs the assembly kernel writes
   int32_t *d_alist = nullptr;      // [na] those DoFs, ascending
-  int32_t *d_aoff = nullptr;       // [na + 1] CSR offsets into d_slot
-  int32_t *d_slot = nullptr;       // E-vector slot of each contribution
+  int32_t *d_aoff = nullptr;       // [na + 1] CSR offsets of their E-vector entries
+  int32_t *d_pos = nullptr;        // [nelem][epe] E-vector entry of each element node
+  int64_t nentries = 0;            // E-vector entries per member
   AsmPlan plan{};                  // the three arrays above, for the assembly kernel
 
   // ---- coefficients
@@ -159,7 +160,8 @@ void free_all(sfem_ctx *c) {
   c->d_qd32 = nullptr;
   c->d_alist = nullptr;
   c->d_aoff = nullptr;
-  c->d_slot = nullptr;
+  c->d_pos = nullptr;
+  c->nentries = 0;
   c->plan = AsmPlan{};
   c->na = 0;
   c->d_fold64 = nullptr;
@@ -230,7 +232,7 @@ sfem_status ensure_diag(sfem_ctx *c, int op) {
     if ((st = dalloc(c, &c->d_diag32[op], n)) != SFEM_OK) return st;
     if ((st = dalloc(c, &c->d_dinv32[op], n)) != SFEM_OK) return st;
   }
-  if ((st = ensure_evec(c, (size_t)(c->nelem * c->epe) * sizeof(double))) != SFEM_OK) return st;
+  if ((st = ensure_evec(c, (size_t)c->nentries * sizeof(double))) != SFEM_OK) return st;
   double a = 1.0, b = 0.0;
   if (op == SFEM_DIFFUSION) {
     a = 0.0;
@@ -250,6 +252,7 @@ sfem_status ensure_diag(sfem_ctx *c, int op) {
     da.nelem = c->nelem;
     da.diag = c->d_diag[op] + (int64_t)f * c->ndof;
     da.evec = (double *)c->evec.p;
+    da.pos = c->d_pos;
     da.compact = c->compact;
     HIPCHK(c, launch_diag(da, c->stream));
     HIPCHK(c, launch_assemble<double>(c->plan, (const double *)c->evec.p, 0, nullptr, da.diag, c->ndof,
@@ -286,7 +289,7 @@ int apply_nparts(const sfem_ctx *c) {
 sfem_status do_apply(sfem_ctx *c, int op, bool f32, int nbatch, const void *x, void *y,
                      double *part = nullptr) {
   if (nbatch == 0 || c->ndof == 0) return SFEM_OK;
-  const int64_t estride = c->nelem * c->epe;
+  const int64_t estride = c->nentries;
   const size_t esz = f32 ? sizeof(float) : sizeof(double);
   sfem_status st;
   if ((st = ensure_evec(c, (size_t)estride * nbatch * esz)) != SFEM_OK) return st;
@@ -303,6 +306,7 @@ sfem_status do_apply(sfem_ctx *c, int op, bool f32, int nbatch, const void *x, v
   a.y = y;
   a.evec = c->evec.p;
   a.estride = estride;
+  a.pos = c->d_pos;
   a.compact = c->compact;
   a.part = part;
   a.part_mstride = nparts;
@@ -564,8 +568,8 @@ sfem_status sfem_setup(sfem_ctx *c, int p, int q, int64_t nelem, const double *e
   const std::vector<int32_t> &imap = hp.imap;
   const std::vector<int32_t> &alist = hp.alist;
   const std::vector<int32_t> &aoff = hp.aoff;
-  const std::vector<int32_t> &slots = hp.slots;
-  if ((int64_t)slots.size() >= (int64_t)INT32_MAX) return fail(c, SFEM_E_ARG, "mesh too large");
+  const std::vector<int32_t> &pos = hp.pos;
+  if (hp.nentries >= (int64_t)kDofMask) return fail(c, SFEM_E_ARG, "mesh too large");
 
   // ---- rules
   if (!make_rules(p, q, c->rules)) return fail(c, SFEM_E_HIP, "1D rule construction failed");
@@ -586,18 +590,18 @@ sfem_status sfem_setup(sfem_ctx *c, int p, int q, int64_t nelem, const double *e
   if ((st = dalloc(c, &c->d_qd32, nelem * q3 * kQdSlots)) != SFEM_OK) return st;
   if ((st = dalloc(c, &c->d_alist, na)) != SFEM_OK) return st;
   if ((st = dalloc(c, &c->d_aoff, na + 1)) != SFEM_OK) return st;
-  if ((st = dalloc(c, &c->d_slot, (int64_t)slots.size())) != SFEM_OK) return st;
+  if ((st = dalloc(c, &c->d_pos, (int64_t)pos.size())) != SFEM_OK) return st;
   int *d_bad = nullptr;
   if ((st = dalloc(c, &d_bad, 1)) != SFEM_OK) return st;
   if (na > 0) {
     HIPCHK(c, hipMemcpyAsync(c->d_alist, alist.data(), alist.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->d_aoff, aoff.data(), aoff.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
   }
-  if (!slots.empty())
-    HIPCHK(c, hipMemcpyAsync(c->d_slot, slots.data(), slots.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  if (!pos.empty())
+    HIPCHK(c, hipMemcpyAsync(c->d_pos, pos.data(), pos.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
   c->plan.alist = c->d_alist;
   c->plan.aoff = c->d_aoff;
-  c->plan.slot = c->d_slot;
+  c->nentries = hp.nentries;
   c->plan.na = na;
   if (nelem > 0) {
     HIPCHK(c, hipMemcpyAsync(c->d_map, imap.data(), imap.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
@@ -679,7 +683,7 @@ sfem_status sfem_load(sfem_ctx *c, int nbatch, const double *f_q, double *b) {
   if (nbatch == 0 || c->ndof == 0) return SFEM_OK;
   if (!f_q || !b) return fail(c, SFEM_E_ARG, "f_q and b must not be NULL");
   DeviceGuard g(c->device);
-  const int64_t estride = c->nelem * c->epe;
+  const int64_t estride = c->nentries;
   if ((st = ensure_evec(c, (size_t)estride * nbatch * sizeof(double))) != SFEM_OK) return st;
   LoadArgs a;
   a.p = c->p;
@@ -692,6 +696,7 @@ sfem_status sfem_load(sfem_ctx *c, int nbatch, const double *f_q, double *b) {
   a.b = b;
   a.evec = (double *)c->evec.p;
   a.estride = estride;
+  a.pos = c->d_pos;
   a.compact = c->compact;
   HIPCHK(c, launch_load(a, c->stream));
   HIPCHK(c, launch_assemble<double>(c->plan, (const double *)c->evec.p, estride, nullptr, b, c->ndof,

@@ -75,38 +75,19 @@ struct Per {
 // Gather the element's nodal values (essential DoFs as 0) into buf[k][j][i].  All map
 // loads of the thread are issued together, then all value loads.  Loads are
 // unconditional (an inactive slot reads a valid element's entries and discards them)
-// so that the compiler can batch them.  If smap / sx are given (LDS), the map entries
-// and the raw x values are kept there for the output step.
+// so that the compiler can batch them.  If smap is given (LDS), it receives for each
+// node the map entry of a sole or essential DoF, or the E-vector entry of a shared
+// node (epos: the element's row of the position table, read together with the map);
+// sx (LDS, optional) receives the raw x values.
 template <int P, typename T>
 __device__ __forceinline__ void gather_e(T *buf, int t, bool active, const int32_t *emap,
                                          const T *__restrict__ xm, int32_t *smap = nullptr,
-                                         T *sx = nullptr) {
-  using D = Dims<P>;
-  constexpr int NL = Per<P>::NL;
-  int32_t c[NL];
-#pragma unroll
-  for (int k = 0; k < NL; ++k) {
-    const int l = t + k * D::TPE;
-    c[k] = emap[l < D::N3 ? l : D::N3 - 1];
-  }
-  T v[NL];
-#pragma unroll
-  for (int k = 0; k < NL; ++k) v[k] = xm[c[k] & kDofMask];
-#pragma unroll
-  for (int k = 0; k < NL; ++k) {
-    const int l = t + k * D::TPE;
-    if (l < D::N3) {
-      buf[l] = (active && c[k] >= 0) ? v[k] : T(0);
-      if (smap) smap[l] = c[k];
-      if (sx) sx[l] = v[k];
-    }
-  }
-  __syncthreads();
-}
+                                         T *sx = nullptr, const int32_t *epos = nullptr,
+                                         bool compact = true);
 
 // Rank of local node l among the element's surface nodes (a node with i, j or k in
 // {0, p}): face k = 0, face k = p, then for each interior k the ring of the (i, j)
-// square.  Interior nodes have no rank.
+// square; -1 for an interior node.
 template <int P>
 __host__ __device__ constexpr int surf_rank(int l) {
   constexpr int N = P + 1;
@@ -116,21 +97,53 @@ __host__ __device__ constexpr int surf_rank(int l) {
   const int base = 2 * N * N + (k - 1) * 4 * P;
   if (j == 0) return base + i;
   if (j == P) return base + N + i;
-  return base + 2 * N + 2 * (j - 1) + (i == 0 ? 0 : 1);
+  if (i == 0 || i == P) return base + 2 * N + 2 * (j - 1) + (i == 0 ? 0 : 1);
+  return -1;
 }
 template <int P>
 __host__ __device__ constexpr int surf_count() {
   return 2 * (P + 1) * (P + 1) + (P - 1) * 4 * P;
 }
 
-// Output of the element vector buf[l] of element e: sole DoFs -> y, shared nodes ->
-// E-vector slot e * S + rank (compact) or e * n^3 + l (general), essential -> nothing.
-// The map entries (and, with DOT, the x values) come from LDS, kept by the gather.
-// With DOT, returns this thread's part of sum x_g y_g over the sole DoFs.
+template <int P, typename T>
+__device__ __forceinline__ void gather_e(T *buf, int t, bool active, const int32_t *emap,
+                                         const T *__restrict__ xm, int32_t *smap, T *sx,
+                                         const int32_t *epos, bool compact) {
+  using D = Dims<P>;
+  constexpr int NL = Per<P>::NL;
+  int32_t c[NL], q[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int l0 = t + k * D::TPE;
+    const int l = l0 < D::N3 ? l0 : D::N3 - 1;
+    c[k] = emap[l];
+    if (epos) {
+      const int r = compact ? surf_rank<P>(l) : l;
+      q[k] = epos[r >= 0 ? r : 0];
+    }
+  }
+  T v[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) v[k] = xm[c[k] & kDofMask];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int l = t + k * D::TPE;
+    if (l < D::N3) {
+      buf[l] = (active && c[k] >= 0) ? v[k] : T(0);
+      if (smap) smap[l] = (epos && c[k] >= 0 && !(c[k] & kSoleBit)) ? q[k] : c[k];
+      if (sx) sx[l] = v[k];
+    }
+  }
+  __syncthreads();
+}
+
+// Output of the element vector buf[l]: sole DoFs -> y, shared nodes -> their E-vector
+// entry, essential -> nothing.  The map entries / E-vector entries (and, with DOT, the
+// x values) come from LDS, kept by the gather.  With DOT, returns this thread's part of
+// sum x_g y_g over the sole DoFs.
 template <int P, typename T, bool DOT>
 __device__ __forceinline__ double emit_e(const T *buf, int t, bool active, const int32_t *smap,
-                                         const T *sx, int64_t e, bool compact,
-                                         T *__restrict__ Y, T *__restrict__ y) {
+                                         const T *sx, T *__restrict__ Y, T *__restrict__ y) {
   using D = Dims<P>;
   constexpr int NL = Per<P>::NL;
   double dot = 0.0;
@@ -144,26 +157,27 @@ __device__ __forceinline__ double emit_e(const T *buf, int t, bool active, const
     if (c & kSoleBit) {
       y[c & kDofMask] = v;
       if constexpr (DOT) dot += (double)sx[l] * (double)v;
-    } else if (compact) {
-      Y[e * surf_count<P>() + surf_rank<P>(l)] = v;
     } else {
-      Y[e * D::N3 + l] = v;
+      Y[c] = v;
     }
   }
   return dot;
 }
 
-// Deterministic block sum (wave64 butterfly, then the waves in order); result on thread 0.
+// Deterministic block sum, result on thread 0.  Every thread stores its value in LDS
+// (sh holds blockDim.x entries); the lanes of wave 0 each add a fixed strided subset,
+// then a wave64 butterfly.  Only values of existing threads are read, so a block whose
+// size is not a multiple of 64 needs no special case.
 __device__ __forceinline__ double block_sum_d(double v, double *sh) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  sh[threadIdx.x] = v;
   __syncthreads();
   double s = 0.0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < nw; ++i) s += sh[i];
+  if (threadIdx.x < 64) {
+    for (int i = threadIdx.x; i < (int)blockDim.x; i += 64) s += sh[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  }
   return s;
 }
 
@@ -354,7 +368,8 @@ __global__ void __launch_bounds__(Dims<P>::THREADS, Dims<P>::OCC)
 apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
              int64_t qd_mstride, const T *__restrict__ nu, int64_t nu_mstride, int64_t nelem,
              int nbatch, int64_t ndof, const T *__restrict__ x, T *__restrict__ Y,
-             int64_t estride, int compact, T *__restrict__ y, double *__restrict__ part,
+             int64_t estride, const int32_t *__restrict__ pos, int compact, T *__restrict__ y,
+             double *__restrict__ part,
              int64_t part_mstride) {
   using D = Dims<P>;
   constexpr int N = D::N, Q = D::Q, Q2 = D::Q2, Q3 = D::Q3, N3 = D::N3;
@@ -365,7 +380,7 @@ apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
   __shared__ T smem[E * D::BUF];
   __shared__ int32_t smap_all[E * N3];  // the elements' map entries, kept for the output
   __shared__ T sx_all[E * N3];          // their x values (for the fused dot product)
-  __shared__ double red[8];
+  __shared__ double red[Dims<P>::THREADS];  // block sum of the fused dot product
   const int le = threadIdx.x / TPE;
   const int t = threadIdx.x - le * TPE;
   const int64_t nblk = (nelem + E - 1) / E;
@@ -400,7 +415,8 @@ apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
 
     int32_t *smap = smap_all + le * N3;
     T *sx = sx_all + le * N3;
-    gather_e<P, T>(buf, t, active, emap, xm, smap, part ? sx : nullptr);
+    gather_e<P, T>(buf, t, active, emap, xm, smap, part ? sx : nullptr,
+                   pos + es * (int64_t)(compact ? surf_count<P>() : N3), compact != 0);
     fwd_x<P, T, DIFF>(buf, t);
     T pre0[NS], pre1[NS];  // quadrature data of the first slice pair, loaded early
     load_slice(pre0, 0);
@@ -528,12 +544,12 @@ apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
     bwd_y<P, T, DIFF>(buf, t);
     bwd_x<P, T, DIFF>(buf, t);
     if (part) {
-      const double dot = emit_e<P, T, true>(buf, t, active, smap, sx, es, compact != 0,
+      const double dot = emit_e<P, T, true>(buf, t, active, smap, sx,
                                             Y + (int64_t)m * estride, y + (int64_t)m * ndof);
       const double sum = block_sum_d(dot, red);
       if (threadIdx.x == 0) part[(int64_t)m * part_mstride + blockIdx.x] = sum;
     } else {
-      emit_e<P, T, false>(buf, t, active, smap, sx, es, compact != 0, Y + (int64_t)m * estride,
+      emit_e<P, T, false>(buf, t, active, smap, sx, Y + (int64_t)m * estride,
                           y + (int64_t)m * ndof);
     }
     __syncthreads();
@@ -553,7 +569,7 @@ hipError_t launch_apply_pt(const ApplyArgs &a, hipStream_t s) {
   T *y = (T *)a.y;
 #define SFEM_APPLY_ARGS                                                                    \
   a.map, qd, a.qd_mstride, nu, a.nu_mstride, a.nelem, a.nbatch, a.ndof, x, Y, a.estride, \
-      a.compact, y, a.part, a.part_mstride
+      a.pos, a.compact, y, a.part, a.part_mstride
   switch (a.op) {
     case SFEM_MASS:
       hipLaunchKernelGGL((apply_kernel<P, T, 0>), grid, block, 0, s, SFEM_APPLY_ARGS);

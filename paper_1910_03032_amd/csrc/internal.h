@@ -63,25 +63,25 @@ struct ApplyArgs {
   const void *x;
   void *y;                  // output at the sole DoFs
   void *evec;               // E-vector of the shared nodes, [nbatch][estride]
-  int64_t estride;          // nelem * S (S = surface nodes, or n^3 when not compact)
-  int compact;
+  int64_t estride;          // E-vector entries per member (contributions to shared DoFs)
+  const int32_t *pos;       // [nelem][S or n^3] E-vector entry of each element node
+  int compact;              // pos indexed by surface rank (1) or local node (0)
   double *part;             // per-block dot partials (or null)
   int64_t part_mstride;
 };
 // Element phase of the apply over all elements (writes the E-vector).
 hipError_t launch_apply_f64(const ApplyArgs &a, hipStream_t s);
 hipError_t launch_apply_f32(const ApplyArgs &a, hipStream_t s);
-// Assembly list on the device (see HostPlan): the assembled DoFs, ascending, CSR offsets
-// and the E-vector slots of their contributions in element order.
+// Assembly list on the device (see HostPlan): the assembled DoFs, ascending, and the CSR
+// offsets of their contributions in the E-vector.
 struct AsmPlan {
   const int32_t *alist;
   const int32_t *aoff;
-  const int32_t *slot;
   int64_t na;
 };
-// Assembly phase over the list: y[g] = sum of g's E-vector entries in element order;
-// essential DoFs get x[g], 1 or 0 per ess_kind.  With part != null also the per-block
-// sums of x_g y_g (part[m * part_mstride + block], assemble_nblk blocks).
+// Assembly phase over the list: y[g] = sum of g's E-vector entries (contiguous, in element
+// order); essential DoFs get x[g], 1 or 0 per ess_kind.  With part != null also the
+// per-block sums of x_g y_g (part[m * part_mstride + block], assemble_nblk blocks).
 int assemble_nblk(int64_t na);
 template <typename T>
 hipError_t launch_assemble(const AsmPlan &pl, const T *evec, int64_t estride, const T *x, T *y,
@@ -97,6 +97,7 @@ struct DiagArgs {
   int64_t nelem;
   double *diag;             // [ndof], written at the sole DoFs
   double *evec;             // E-vector of the shared nodes
+  const int32_t *pos;       // E-vector entry of each element node (see ApplyArgs)
   int compact;
 };
 hipError_t launch_diag(const DiagArgs &a, hipStream_t s);
@@ -132,6 +133,7 @@ struct LoadArgs {
   double *b;                // written at the sole DoFs
   double *evec;             // E-vector of the shared nodes, [nbatch][estride]
   int64_t estride;
+  const int32_t *pos;       // E-vector entry of each element node (see ApplyArgs)
   int compact;
 };
 hipError_t launch_load(const LoadArgs &a, hipStream_t s);

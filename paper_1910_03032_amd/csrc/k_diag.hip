@@ -34,7 +34,8 @@ template <int P>
 __global__ void __launch_bounds__(Dims<P>::Q2 < 64 ? 64 : Dims<P>::Q2)
 diag_kernel(const int32_t *__restrict__ map, const double *__restrict__ qd,
             const double *__restrict__ nu, double alpha, double beta, int64_t nelem,
-            double *__restrict__ diag, double *__restrict__ Y, int compact) {
+            double *__restrict__ diag, double *__restrict__ Y, const int32_t *__restrict__ pos,
+            int compact) {
   using D = Dims<P>;
   constexpr int N = D::N, Q = D::Q, N2 = D::N2, N3 = D::N3, Q2 = D::Q2, Q3 = D::Q3;
   __shared__ double s0[Q3];
@@ -118,9 +119,9 @@ diag_kernel(const int32_t *__restrict__ map, const double *__restrict__ qd,
     if (c & kSoleBit)
       diag[c & kDofMask] = s0[l];
     else if (compact)
-      Y[e * surf_count<P>() + surf_rank<P>(l)] = s0[l];
+      Y[pos[e * surf_count<P>() + surf_rank<P>(l)]] = s0[l];
     else
-      Y[e * N3 + l] = s0[l];
+      Y[pos[e * N3 + l]] = s0[l];
   }
 }
 
@@ -131,7 +132,7 @@ hipError_t launch_diag_p(const DiagArgs &a, hipStream_t s) {
   if (ne <= 0) return hipSuccess;
   const int threads = D::Q2 < 64 ? 64 : D::Q2;
   hipLaunchKernelGGL((diag_kernel<P>), dim3((unsigned)ne), dim3(threads), 0, s, a.map, a.qd,
-                     a.nu, a.alpha, a.beta, a.nelem, a.diag, a.evec, a.compact);
+                     a.nu, a.alpha, a.beta, a.nelem, a.diag, a.evec, a.pos, a.compact);
   return hipGetLastError();
 }
 

@@ -85,7 +85,7 @@ template <int P>
 __global__ void __launch_bounds__(Dims<P>::THREADS)
 load_kernel(const int32_t *__restrict__ map, const double *__restrict__ qd, int64_t nei,
             int nbatch, int64_t ndof, const double *__restrict__ f, double *__restrict__ b,
-            double *__restrict__ Y, int64_t estride, int compact) {
+            double *__restrict__ Y, int64_t estride, const int32_t *__restrict__ pos, int compact) {
   using D = Dims<P>;
   using TB = Tab<P, double>;
   constexpr int N = D::N, Q = D::Q, Q2 = D::Q2, Q3 = D::Q3, TPE = D::TPE, E = D::E;
@@ -126,9 +126,9 @@ load_kernel(const int32_t *__restrict__ map, const double *__restrict__ qd, int6
         if (c & kSoleBit)
           bm[c & kDofMask] = buf[l];
         else if (compact)
-          Ym[e * surf_count<P>() + surf_rank<P>(l)] = buf[l];
+          Ym[pos[e * surf_count<P>() + surf_rank<P>(l)]] = buf[l];
         else
-          Ym[e * D::N3 + l] = buf[l];
+          Ym[pos[e * D::N3 + l]] = buf[l];
       }
     }
     __syncthreads();
@@ -152,7 +152,7 @@ hipError_t launch_load_p(const LoadArgs &a, hipStream_t s) {
   if (ne <= 0 || a.nbatch <= 0) return hipSuccess;
   hipLaunchKernelGGL((load_kernel<P>), dim3((unsigned)((ne + D::E - 1) / D::E)), dim3(D::THREADS),
                      0, s, a.map, a.qd, a.nei, a.nbatch, a.ndof, a.f, a.b, a.evec, a.estride,
-                     a.compact);
+                     a.pos, a.compact);
   return hipGetLastError();
 }
 

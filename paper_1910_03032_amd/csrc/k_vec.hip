@@ -283,12 +283,12 @@ __global__ void ir_accum_kernel(double *__restrict__ x, const float *__restrict_
 }
 
 // Assembly over the list of shared and essential DoFs: y[g] = sum of the E-vector
-// entries of g in element order; essential DoFs (no slots) get x[g], 1 or 0.  DOT: also
-// the per-block sums of x_g y_g.  Each thread takes AU list entries per pass (stride VB);
-// for each it loads the first KS slot indices together, then the E-vector values
-// together; longer slot lists fall back to a loop.  The list is in ascending DoF order,
-// so a wavefront's E-vector reads fall on the lines of a few neighbouring elements.
-// Index arithmetic is 32-bit (entries and slots are below 2^31, checked at set-up).
+// entries [aoff[i], aoff[i+1]) of entry i (contiguous, in element order); essential DoFs
+// (no entries) get x[g], 1 or 0.  DOT: also the per-block sums of x_g y_g.  Each thread
+// takes AU list entries per pass (stride VB); the first KS entries of each are loaded
+// together, longer lists fall back to a loop.  Consecutive threads read consecutive
+// runs of the E-vector.  Index arithmetic is 32-bit (entries below 2^31, checked at
+// set-up).
 constexpr int AU = 1;
 constexpr int KS = 8;
 
@@ -313,16 +313,11 @@ assemble_kernel(AsmPlan pl, const T *__restrict__ Y, int64_t estride, const T *_
       a[k] = in ? pl.aoff[i] : 0;
       d[k] = in ? pl.aoff[i + 1] - a[k] : -1;
     }
-    int32_t sl[AU][KS];
-#pragma unroll
-    for (int k = 0; k < AU; ++k)
-#pragma unroll
-      for (int j = 0; j < KS; ++j) sl[k][j] = (j < d[k]) ? pl.slot[a[k] + j] : 0;
     T val[AU][KS];
 #pragma unroll
     for (int k = 0; k < AU; ++k)
 #pragma unroll
-      for (int j = 0; j < KS; ++j) val[k][j] = (j < d[k]) ? Ym[sl[k][j]] : T(0);
+      for (int j = 0; j < KS; ++j) val[k][j] = (j < d[k]) ? Ym[a[k] + j] : T(0);
 #pragma unroll
     for (int k = 0; k < AU; ++k) {
       if (d[k] < 0) continue;
@@ -330,7 +325,7 @@ assemble_kernel(AsmPlan pl, const T *__restrict__ Y, int64_t estride, const T *_
 #pragma unroll
       for (int j = 1; j < KS; ++j)
         if (j < d[k]) acc += val[k][j];
-      for (int j = KS; j < d[k]; ++j) acc += Ym[pl.slot[a[k] + j]];
+      for (int j = KS; j < d[k]; ++j) acc += Ym[a[k] + j];
       const T xg = (DOT || (d[k] == 0 && ess_kind == kEssCopyX)) ? xm[g[k]] : T(0);
       if (d[k] == 0) acc = (ess_kind == kEssCopyX) ? xg : (ess_kind == kEssOne ? T(1) : T(0));
       ym[g[k]] = acc;

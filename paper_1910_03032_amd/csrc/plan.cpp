@@ -99,14 +99,15 @@ int build_host_plan(int p, int64_t nelem, const int32_t *dofs_ptr, int64_t ndof,
   for (int64_t gd = 0; gd < ndof; ++gd)
     if (apos[gd] >= 0 && !ess[gd]) aoff[(size_t)apos[gd] + 1] = (int32_t)deg[gd];
   for (int64_t i = 0; i < na; ++i) aoff[(size_t)i + 1] += aoff[(size_t)i];
-  std::vector<int32_t> &slots = out.slots;
-  slots.assign((size_t)aoff[(size_t)na], -1);
-  std::vector<int32_t> pos(aoff.begin(), aoff.end() - 1);
+  out.nentries = aoff[(size_t)na];
+  std::vector<int32_t> &pos = out.pos;
+  pos.assign((size_t)(nelem * epe), -1);
+  std::vector<int32_t> next(aoff.begin(), aoff.end() - 1);
   for (int64_t e = 0; e < nelem; ++e)
     for (int64_t l = 0; l < n3; ++l) {
       const int32_t gd = dofs((size_t)(e * n3 + l));
       if (ess[gd] || deg[gd] == 1) continue;
-      slots[(size_t)pos[(size_t)apos[gd]]++] = (int32_t)(e * epe + (compact ? surface_rank(p, l) : l));
+      pos[(size_t)(e * epe + (compact ? surface_rank(p, l) : l))] = next[(size_t)apos[gd]]++;
     }
   return 0;
 }

@@ -22,12 +22,16 @@ struct HostPlan {
   int64_t epe = 0;             // E-vector entries per element (S or n^3)
   std::vector<int32_t> imap;   // [nelem][n^3] encoded map
   // Assembly list: the DoFs the assembly kernel writes (shared or essential), ascending,
-  // with CSR offsets into slots, the E-vector slots of their contributions in element
-  // order (essential DoFs have none).
+  // with CSR offsets: the contributions of alist[i] occupy E-vector entries
+  // [aoff[i], aoff[i+1]) in element order (essential DoFs have none), so the assembly
+  // reads them contiguously.  pos maps an element node to its E-vector entry: index
+  // e * epe + r, r the node's surface rank (compact) or its local index (general); -1
+  // for nodes without an entry (sole or essential DoFs).
   std::vector<int32_t> alist;  // [na]
   std::vector<int32_t> aoff;   // [na + 1]
-  std::vector<int32_t> slots;  // [aoff[na]]
+  std::vector<int32_t> pos;    // [nelem * epe]
   int64_t na = 0;
+  int64_t nentries = 0;        // E-vector entries per member = aoff[na]
 };
 
 // Rank of local node l (l = i + n (j + n k), n = p + 1) among the element's surface nodes:

@@ -64,20 +64,33 @@ static void replay(const char *name, int p, int64_t nelem, const std::vector<int
     CHECK(((v & kSoleBit) != 0) == (!ess[(size_t)g] && deg[(size_t)g] == 1), "%s: sole bit %lld",
           name, (long long)k);
   }
-  // integer element contributions: value of (e, l) = 1000 e + l + 1
-  std::vector<int64_t> Y((size_t)(nelem * hp.epe), 0), direct((size_t)ndof, 0);
+  // integer element contributions: value of (e, l) = 1000 e + l + 1, written to the
+  // E-vector entry pos[e * epe + r]; every entry is written exactly once
+  CHECK((int64_t)hp.aoff.size() == hp.na + 1 && hp.aoff[0] == 0, "%s: offsets", name);
+  CHECK(hp.nentries == hp.aoff[(size_t)hp.na], "%s: entry count", name);
+  CHECK((int64_t)hp.pos.size() == nelem * hp.epe, "%s: pos size", name);
+  std::vector<int64_t> Y((size_t)hp.nentries, 0), direct((size_t)ndof, 0);
+  std::vector<int> hits((size_t)hp.nentries, 0);
+  std::vector<int64_t> owner((size_t)hp.nentries, -1);
   for (int64_t e = 0; e < nelem; ++e)
     for (int64_t l = 0; l < n3; ++l) {
       const int32_t g = dofs[(size_t)(e * n3 + l)];
       const int64_t v = 1000 * e + l + 1;
       direct[(size_t)g] += v;
-      if (ess[(size_t)g] || deg[(size_t)g] == 1) continue;
-      const int64_t slot = e * hp.epe + (hp.compact ? surface_rank(p, l) : l);
-      CHECK(slot >= 0 && slot < (int64_t)Y.size(), "%s: slot range", name);
-      Y[(size_t)slot] = v;
+      const int64_t r = hp.compact ? surface_rank(p, l) : l;
+      const int32_t q = r >= 0 ? hp.pos[(size_t)(e * hp.epe + r)] : -1;
+      if (ess[(size_t)g] || deg[(size_t)g] == 1) {
+        CHECK(q < 0, "%s: node (%lld, %lld) of a sole/essential DoF has an entry", name, (long long)e,
+              (long long)l);
+        continue;
+      }
+      CHECK(q >= 0 && q < hp.nentries, "%s: entry range", name);
+      if (q < 0 || q >= hp.nentries) continue;
+      Y[(size_t)q] = v;
+      hits[(size_t)q]++;
+      owner[(size_t)q] = e;
     }
-  CHECK((int64_t)hp.aoff.size() == hp.na + 1 && hp.aoff[0] == 0, "%s: offsets", name);
-  CHECK((int64_t)hp.slots.size() == hp.aoff[(size_t)hp.na], "%s: slot count", name);
+  for (int64_t k = 0; k < hp.nentries; ++k) CHECK(hits[(size_t)k] == 1, "%s: entry %lld written %d times", name, (long long)k, hits[(size_t)k]);
   std::vector<char> seen((size_t)ndof, 0);
   int64_t nslot_used = 0;
   for (int64_t i = 0; i < hp.na; ++i) {
@@ -87,17 +100,16 @@ static void replay(const char *name, int p, int64_t nelem, const std::vector<int
     if (i > 0) CHECK(hp.alist[(size_t)i - 1] < g, "%s: list not ascending", name);
     const int64_t a = hp.aoff[(size_t)i], d = hp.aoff[(size_t)i + 1] - a;
     if (ess[(size_t)g]) {
-      CHECK(d == 0, "%s: essential DoF %d has %lld slots", name, g, (long long)d);
+      CHECK(d == 0, "%s: essential DoF %d has %lld entries", name, g, (long long)d);
       continue;
     }
-    CHECK(d == deg[(size_t)g], "%s: DoF %d has %lld slots, degree %lld", name, g, (long long)d,
+    CHECK(d == deg[(size_t)g], "%s: DoF %d has %lld entries, degree %lld", name, g, (long long)d,
           (long long)deg[(size_t)g]);
     int64_t sum = 0, last = -1;
     for (int64_t k = 0; k < d; ++k) {
-      const int32_t s = hp.slots[(size_t)(a + k)];
-      CHECK(s > last, "%s: contributions not in element order (DoF %d)", name, g);
-      last = s;
-      sum += Y[(size_t)s];
+      CHECK(owner[(size_t)(a + k)] > last, "%s: contributions not in element order (DoF %d)", name, g);
+      last = owner[(size_t)(a + k)];
+      sum += Y[(size_t)(a + k)];
     }
     nslot_used += d;
     CHECK(sum == direct[(size_t)g], "%s: DoF %d assembled %lld, direct %lld", name, g,
@@ -108,7 +120,7 @@ static void replay(const char *name, int p, int64_t nelem, const std::vector<int
     CHECK((seen[(size_t)g] != 0) == assembled, "%s: DoF %lld listed = %d", name, (long long)g,
           (int)seen[(size_t)g]);
   }
-  std::printf("%s: na %lld, slots %lld, compact %d\n", name, (long long)hp.na,
+  std::printf("%s: na %lld, entries %lld, compact %d\n", name, (long long)hp.na,
               (long long)nslot_used, (int)hp.compact);
 }
 

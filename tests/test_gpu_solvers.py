@@ -32,6 +32,23 @@ def test_poisson_p2_4e_pcg_vs_direct_and_oracle_pcg():
     assert abs(d.l2_error(host(x), u_manufactured) - d.l2_error(xd, u_manufactured)) < 1e-10
 
 
+@pytest.mark.parametrize("p", [1, 3, 4, 5, 7, 8])
+def test_pcg_iterations_match_oracle_partial_waves(p):
+    """Orders whose workgroups end in a partial wavefront (q^2 threads per element do not
+    fill whole waves): the fused p.Ap partial sums of the element kernel feed the step
+    length, so the iteration count must match the oracle's PCG (within 2)."""
+    m, d, op = case(3, p)
+    nu = nu_uniform(m.nelem, d.q, seed=2)
+    op.set_coeffs(10.0, 1.0, gpu(nu))
+    b = rhs_uniform(m, seed=1)[0]
+    x, res = op.pcg(gpu(b), rtol=1e-10, check_every=1)
+    assert res.converged
+    _, it_o, _ = oracle_pcg(lambda v: d.apply(v, 10.0, 1.0, nu), b, 1.0 / d.diagonal(10.0, 1.0, nu),
+                            rtol=1e-10)
+    say(f"  p={p}: iterations gpu {res.iters[0]} oracle {it_o}")
+    assert abs(res.iters[0] - it_o) <= 2
+
+
 def test_helmholtz_pcg_and_ir_reduced():
     m, d, op = case(4, 4)
     nu = nu_uniform(m.nelem, d.q, seed=2)
