@@ -8,13 +8,15 @@ library and its Python binding) never does, and shares no code with it.
 Contents:
   quadrature  Gauss-Legendre / Gauss-Lobatto-Legendre rules, Lagrange basis (Section 3.1)
   fem         dense element operators M, K(nu), alpha M + beta K(nu), their diagonal,
-              load vector, adjoint-gradient integrand (Section 3, Section 3.1)
-  solvers     Jacobi-PCG, FP32-inner iterative refinement, adjoint gradient
-              (Section 5, Section 5.3)
+              load vector, adjoint-gradient integrand (Section 3, Section 3.1), the
+              collocated (GLL-integrated) mass diagonal (Section 5.1)
+  solvers     diagonally preconditioned CG (optionally orthogonalized against the
+              constants), FP32-inner iterative refinement, adjoint gradient, pure-Neumann
+              Poisson with the mean-zero condition (Section 5, Section 5.3)
 
 Pins (tests/test_oracle_*.py) tie each part to closed forms and invariants;
 nothing here is "parity unpinned".
 """
 from .quadrature import gauss_legendre, gll, lagrange_values, lagrange_derivs, legendre_p  # noqa: F401
 from .fem import Discretization, OP_MASS, OP_DIFFUSION, OP_HELMHOLTZ, op_coeffs  # noqa: F401
-from .solvers import pcg, ir_pcg, adjoint_gradient, objective  # noqa: F401
+from .solvers import pcg, ir_pcg, adjoint_gradient, objective, neumann_poisson  # noqa: F401

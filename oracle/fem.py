@@ -245,6 +245,27 @@ class Discretization:
         return d
 
     # ---------------- assembled sparse matrix (small cases) ----------------
+    def collocated_mass_diagonal(self, constrained=True):
+        """Mass matrix integrated with the GLL rule at the nodes themselves (Section 5.1):
+        phi_l(xi_m) = delta_lm makes it diagonal, entry g = sum over the elements and their
+        local nodes l -> g of w_l |J_e(xi_l)| (w_l the tensor GLL weight).  Essential rows
+        are 1 when constrained (the preconditioner of the constrained operator)."""
+        nodes, wg = gll(self.p)
+        n = self.n
+        l = np.arange(self.nloc)
+        i, j, k = l % n, (l // n) % n, l // (n * n)
+        XI = np.stack([nodes[i], nodes[j], nodes[k]], axis=-1)
+        W = wg[i] * wg[j] * wg[k]
+        _, dN = trilinear_shape(XI)
+        out = np.zeros(self.ndof)
+        for e0 in range(0, self.nelem, self.gchunk):
+            e1 = min(self.nelem, e0 + self.gchunk)
+            J = np.einsum("cvr,lvd->clrd", self.elem_xyz[e0:e1], dN)
+            np.add.at(out, self.elem_dofs[e0:e1], W[None, :] * np.linalg.det(J))
+        if constrained:
+            out[self.ess] = 1.0
+        return out
+
     def assemble(self, alpha, beta, nu=None, constrained=True):
         rows, cols, vals = [], [], []
         for e0 in range(0, self.nelem, self.chunk):

@@ -19,8 +19,14 @@ from __future__ import annotations
 import numpy as np
 
 
-def pcg(apply, b, dinv, rtol=1e-10, maxit=10000, x0=None, dtype=np.float64, dot_dtype=np.float64):
-    """Jacobi-PCG.  Returns (x, iters, rel_res_recursive).  ``apply`` maps a vector to A v."""
+def pcg(apply, b, dinv, rtol=1e-10, maxit=10000, x0=None, dtype=np.float64, dot_dtype=np.float64,
+        nullspace=False):
+    """Diagonally preconditioned CG.  Returns (x, iters, rel_res_recursive).  ``apply`` maps
+    a vector to A v, ``dinv`` is the inverse of the diagonal preconditioner.
+
+    nullspace=True: the operator has the constant vectors as null space (pure Neumann
+    Poisson, Section 5.3); every application of the preconditioner is followed by the
+    orthogonalization z <- z - mean(z) 1 against that null space."""
     b = np.asarray(b, dtype=dtype)
     dinv = np.asarray(dinv, dtype=dtype)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=dtype, copy=True)
@@ -32,7 +38,14 @@ def pcg(apply, b, dinv, rtol=1e-10, maxit=10000, x0=None, dtype=np.float64, dot_
     if bnorm == 0.0:
         return np.zeros_like(b), 0, 0.0
     r = b - apply(x) if x0 is not None else b.copy()
-    z = (dinv * r).astype(dtype)
+
+    def precond(v):
+        z = (dinv * v).astype(dtype)
+        if nullspace:
+            z = (z - dtype(np.mean(z.astype(dot_dtype)))).astype(dtype)
+        return z
+
+    z = precond(r)
     p = z.copy()
     rho = dot(r, z)
     rr = dot(r, r)
@@ -45,7 +58,7 @@ def pcg(apply, b, dinv, rtol=1e-10, maxit=10000, x0=None, dtype=np.float64, dot_
         alpha = rho / pw
         x = (x + dtype(alpha) * p).astype(dtype)
         r = (r - dtype(alpha) * w).astype(dtype)
-        z = (dinv * r).astype(dtype)
+        z = precond(r)
         rho_new = dot(r, z)
         rr = dot(r, r)
         beta = rho_new / rho
@@ -112,3 +125,23 @@ def objective(disc, nu, b, u_target, alpha, beta, rtol=1e-13, direct=False):
     res = u - u_target
     res[disc.ess] = 0.0
     return 0.5 * float(res @ res)
+
+
+def neumann_poisson(d, b, nu=None, rtol=1e-10, dinv=None):
+    """Pure-Neumann Poisson K(nu) x = b closed by the mean-zero condition int x = 0
+    (Section 3, eq. meanZero; Section 5.3).  d: a Discretization without essential DoFs.
+
+    The right-hand side is made orthogonal to the null space (b <- b - mean(b) 1, since
+    K 1 = 0), the system is solved by CG with the Jacobi diagonal (or the given inverse
+    diagonal) followed by the orthogonalization step, and the constant is fixed by
+    int x = (M 1)^T x = 0.  Returns (x, iters, rel_res_recursive)."""
+    if d.ess.any():
+        raise ValueError("the pure Neumann problem has no essential DoFs")
+    b = np.asarray(b, dtype=np.float64)
+    b = b - b.mean()
+    if dinv is None:
+        dinv = 1.0 / d.diagonal(0.0, 1.0, nu)
+    x, it, rr = pcg(lambda v: d.apply(v, 0.0, 1.0, nu), b, dinv, rtol=rtol, nullspace=True)
+    m1 = d.apply(np.ones(d.ndof), 1.0, 0.0)
+    x = x - np.dot(m1, x) / m1.sum()
+    return x, it, rr

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
 
-from oracle import Discretization, pcg, ir_pcg, adjoint_gradient, objective
+from oracle import Discretization, pcg, ir_pcg, adjoint_gradient, objective, neumann_poisson
 from workloads import BoxMesh, f_manufactured, u_manufactured, rhs_uniform, nu_uniform
 
 
@@ -123,3 +123,110 @@ def test_planted_gradient_sign_and_scale_fail():
     for wrong in (-g, 2.0 * g, d.grad_nu(u, u, 1.0)):
         ad = float(np.sum(wrong * dirn))
         assert abs(fd - ad) > 1e-3 * abs(fd)
+
+
+# ---------------------------------------------------------------------------------------
+# Collocated mass preconditioner (Section 5.1) and the pure-Neumann Poisson problem closed
+# by the mean-zero condition (Section 3, eq. meanZero; Section 5.3)
+
+
+def _free_mesh(ne, p, amp=0.1):
+    from workloads import BoxMesh
+    m = BoxMesh(ne, p, amp=amp)
+    return m, Discretization(m.elem_xyz, m.elem_dofs, np.zeros(m.ndof, np.uint8), m.ndof, p, p + 2)
+
+
+@pytest.mark.parametrize("p", [2, 3, 4, 6])
+def test_collocated_mass_integrates_the_volume(p):
+    """1^T D 1 = |Omega| = 1: the GLL rule with p + 1 points is exact for |J| of a
+    trilinear map (degree <= 2 per variable <= 2p - 1)."""
+    _, d = _free_mesh(3, p)
+    assert abs(d.collocated_mass_diagonal(constrained=False).sum() - 1.0) <= 1e-13
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_collocated_mass_is_the_gll_integrated_mass(p):
+    """The mass matrix integrated with the (p+1)^3 GLL rule, built from generic Lagrange
+    evaluation at those points and the element Jacobians, is diagonal and its assembled
+    diagonal is D."""
+    from oracle.fem import trilinear_shape
+    from oracle.quadrature import gll, lagrange_values
+    m, d = _free_mesh(2, p)
+    nodes, w = gll(p)
+    B = lagrange_values(nodes, nodes)  # [point, node]
+    n = p + 1
+    Phi = np.einsum("ck,bj,ai->cbakji", B, B, B).reshape(n ** 3, n ** 3)
+    W = np.einsum("c,b,a->cba", w, w, w).reshape(-1)
+    X = np.stack(np.meshgrid(nodes, nodes, nodes, indexing="ij"), -1).transpose(2, 1, 0, 3).reshape(-1, 3)
+    _, dN = trilinear_shape(X)
+    M = np.zeros((m.ndof, m.ndof))
+    for e in range(m.nelem):
+        det = np.linalg.det(np.einsum("vr,Qvd->Qrd", m.elem_xyz[e], dN))
+        Me = np.einsum("Q,Ql,Qm->lm", W * det, Phi, Phi)
+        dofs = m.elem_dofs[e]
+        M[np.ix_(dofs, dofs)] += Me
+    assert np.abs(M - np.diag(np.diag(M))).max() <= 1e-14
+    assert np.abs(np.diag(M) - d.collocated_mass_diagonal(constrained=False)).max() <= 1e-14
+
+
+def test_collocated_mass_spectral_equivalence():
+    """Eigenvalues of D^-1 M (M Gauss-integrated) stay in [1/27, 1 + 1e-2] for p = 1..6 on
+    a perturbed mesh: bounds independent of h and p; on an affine mesh at p = 1 the lower
+    bound is attained (the 1D ratio of the linear lumped and consistent mass is in
+    [1/3, 1])."""
+    import scipy.linalg as sla
+    for p in range(1, 7):
+        _, d = _free_mesh(2, p)
+        M = d.assemble(1.0, 0.0, constrained=False).toarray()
+        ev = sla.eigh(M, np.diag(d.collocated_mass_diagonal(constrained=False)), eigvals_only=True)
+        assert ev.min() >= 1 / 27 - 1e-10 and ev.max() <= 1.01, (p, ev.min(), ev.max())
+    _, d = _free_mesh(3, 1, amp=0.0)
+    M = d.assemble(1.0, 0.0, constrained=False).toarray()
+    ev = sla.eigh(M, np.diag(d.collocated_mass_diagonal(constrained=False)), eigvals_only=True)
+    assert abs(ev.min() - 1 / 27) <= 1e-12 and abs(ev.max() - 1.0) <= 1e-12
+
+
+@pytest.mark.parametrize("p", [1, 3, 5])
+def test_mass_solve_with_collocated_preconditioner(p):
+    """M x = b by CG with the collocated diagonal: the solution is the sparse direct one,
+    and the iteration count stays below the CG bound 0.5 sqrt(kappa) ln(2 / rtol) for the
+    h- and p-independent condition number kappa <= 27.3 of the spectral-equivalence pin."""
+    m, d = _free_mesh(3, p)
+    b = np.random.default_rng(1).uniform(-1, 1, m.ndof)
+    x, it, _ = pcg(lambda v: d.apply(v, 1.0, 0.0), b, 1.0 / d.collocated_mass_diagonal(False), rtol=1e-12)
+    xd = spla.spsolve(d.assemble(1.0, 0.0, constrained=False).tocsc(), b)
+    assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
+    assert it <= int(np.ceil(0.5 * np.sqrt(27.3) * np.log(2 / 1e-12))), it
+
+
+@pytest.mark.parametrize("p", [1, 2, 4])
+def test_neumann_poisson_matches_bordered_solve(p):
+    """Pure-Neumann K(nu) x = b with int x = 0 against the bordered system
+    [[K, M1], [(M1)^T, 0]] [x; l] = [b - mean(b); 0] solved directly."""
+    import scipy.sparse as sp
+    m, d = _free_mesh(3, p)
+    nu = np.random.default_rng(2).uniform(0.5, 2.0, (m.nelem, d.nqp))
+    b = np.random.default_rng(1).uniform(-1, 1, m.ndof)
+    x, it, _ = neumann_poisson(d, b, nu, rtol=1e-12)
+    K = d.assemble(0.0, 1.0, nu, constrained=False).tocsc()
+    m1 = d.apply(np.ones(m.ndof), 1.0, 0.0)
+    A = sp.bmat([[K, sp.csc_matrix(m1[:, None])], [sp.csc_matrix(m1[None, :]), None]]).tocsc()
+    xd = spla.spsolve(A, np.concatenate([b - b.mean(), [0.0]]))[:-1]
+    assert np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd), (it, np.linalg.norm(x - xd))
+    assert abs(np.dot(m1, x)) <= 1e-12 * np.linalg.norm(x)
+
+
+def test_neumann_poisson_manufactured_rate():
+    """u = cos(pi x) cos(pi y) cos(pi z): zero normal derivative on the cube, mean zero,
+    -Laplace u = 3 pi^2 u; the L2 error decays at rate p + 1 (p = 2)."""
+    p = 2
+    errs = []
+    for ne in (2, 4, 8):
+        m, d = _free_mesh(ne, p)
+        xq = d.qpoint_coords()
+        u = lambda x, y, z: np.cos(np.pi * x) * np.cos(np.pi * y) * np.cos(np.pi * z)
+        b = d.load(3 * np.pi ** 2 * u(xq[..., 0], xq[..., 1], xq[..., 2]))
+        x, _, _ = neumann_poisson(d, b, rtol=1e-12)
+        errs.append(d.l2_error(x, u))
+    rates = np.diff(np.log(errs)) / np.log(0.5)
+    assert rates[-1] >= p + 1 - 0.3, (errs, rates)
