@@ -13,7 +13,8 @@ Jacobi-PCG solve and the FP32-inner iterative-refinement solve to relative resid
 the same workload.  Prints one JSON line.
 
 Other workloads (`--workload`): vector_helmholtz_p7_24e, adjoint_p5_20e, large_p8_40e,
-poisson_p2_4e, and `sweep` (FP64/FP32 apply for p = 4..8 on meshes of 15-33M DoFs).
+poisson_p2_4e, `sweep` (FP64/FP32 apply for p = 4..8 on meshes of 15-33M DoFs) and
+`mass_neumann` (collocated-mass-preconditioned mass solve and pure-Neumann Poisson solve).
 """
 from __future__ import annotations
 
@@ -371,6 +372,39 @@ def run_large(a, wl):
     return out
 
 
+def run_mass_neumann(a):
+    """The other two solves of a projection step at 32^3, p = 4 (no essential DoFs): the
+    mass solve with the collocated mass preconditioner, and the pure-Neumann pressure
+    Poisson solve (orthogonalized Jacobi-PCG, mean-zero solution), both to 1e-10."""
+    import torch
+    from paper_1910_03032_amd import Operator, MASS, DIFFUSION, PRECOND_COLLOCATED_MASS
+    from workloads import BoxMesh, uniform
+    m = BoxMesh(32, 4)
+    op = Operator(m.elem_xyz, m.elem_dofs, m.ndof, 4)
+    op.set_coeffs(0.0, 1.0, None)
+    b = torch.as_tensor(uniform(m.ndof, seed=1), device="cuda")  # U(-1, 1) at every DoF
+
+    def timed_solve(reps=3, **kw):
+        best, res = None, None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, res = op.pcg(b, rtol=1e-10, check_every=16, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            best = dt if best is None else min(best, dt)
+        return {"ms": round(best * 1e3, 2), "iters": res.iters, "outer": res.outer,
+                "true_rel_res": res.true_rel_res, "status": res.status}
+
+    out = {"workload": "mass_and_neumann_p4_32e", "p": 4, "elements": "32^3", "ndof": m.ndof,
+           "mass_fp64_collocated": timed_solve(op=MASS, precond=PRECOND_COLLOCATED_MASS),
+           "mass_fp32_ir_collocated": timed_solve(op=MASS, precond=PRECOND_COLLOCATED_MASS, mode=1),
+           "mass_fp64_jacobi": timed_solve(op=MASS),
+           "neumann_poisson_fp64": timed_solve(op=DIFFUSION, nullspace=True)}
+    op.close()
+    return out
+
+
 def run_sweep(a):
     torch = __import__("torch")
     rows = []
@@ -401,6 +435,8 @@ def main():
     torch.cuda.set_device(0)
     if a.workload == "sweep":
         out = run_sweep(a)
+    elif a.workload == "mass_neumann":
+        out = run_mass_neumann(a)
     else:
         wl = WORKLOADS[a.workload]
         if a.workload == "vector_helmholtz_p7_24e":

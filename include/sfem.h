@@ -16,6 +16,10 @@
  *   - Jacobi-PCG to a relative residual tolerance (Section 5, Section 5.3,
  *     the residual convention of Section 7.1), optionally with an FP32 inner
  *     solve inside FP64 iterative refinement;
+ *   - the collocated (GLL-integrated, diagonal) mass matrix as the preconditioner
+ *     of mass solves (Section 5.1), and the pure-Neumann Poisson problem closed by
+ *     the mean-zero condition (eq. meanZero), whose CG orthogonalizes every
+ *     preconditioner application against the constants (Section 5.3);
  *   - the adjoint gradient of an objective with respect to a per-quadrature-point
  *     coefficient nu (K depends linearly on nu through the factor W of Section 3.1).
  *
@@ -51,7 +55,7 @@
 extern "C" {
 #endif
 
-#define SFEM_ABI_VERSION 1
+#define SFEM_ABI_VERSION 2
 #define SFEM_MAX_P 8
 
 typedef struct sfem_ctx sfem_ctx;
@@ -138,6 +142,18 @@ sfem_status sfem_diagonal(sfem_ctx *ctx, int op, int prec, void *diag);
  * essential entries of b are set to 0. */
 sfem_status sfem_load(sfem_ctx *ctx, int nbatch, const double *f_q, double *b);
 
+/* Collocated mass diagonal (Section 5.1): the mass matrix integrated with the GLL rule
+ * at the element nodes is diagonal, entry g = sum over the elements and their nodes
+ * l -> g of w_l |J(xi_l)| (tensor GLL weight, Jacobian determinant at the node);
+ * spectrally equivalent to the Gauss-integrated mass with h- and p-independent
+ * constants.  diag: [ndof] float64 (device); essential entries are 1. */
+sfem_status sfem_collocated_mass(sfem_ctx *ctx, double *diag);
+
+typedef enum {
+  SFEM_PRECOND_JACOBI = 0,         /* exact diagonal of the (constrained) operator */
+  SFEM_PRECOND_COLLOCATED_MASS = 1 /* collocated mass diagonal (for mass solves, Section 5.1) */
+} sfem_precond;
+
 typedef struct {
   double rtol;       /* stop when ||r||_2 <= rtol ||b||_2, per batch member */
   int maxit;         /* iteration cap (mode 1: cap on the total inner iterations) */
@@ -146,6 +162,11 @@ typedef struct {
   int max_outer;     /* mode 1: cap on refinement steps */
   int check_every;   /* iterations between host convergence checks (>= 1) */
   int x0_zero;       /* nonzero: ignore x on entry and start from x = 0 */
+  int precond;       /* sfem_precond: diagonal preconditioner */
+  int nullspace;     /* nonzero: pure-Neumann problem (op = SFEM_DIFFUSION, no essential
+                        DoFs): b is made orthogonal to the constants, every preconditioner
+                        application is orthogonalized against them (Section 5.3), and x is
+                        returned with int x = 0 (eq. meanZero); mode 0 and x0_zero only */
 } sfem_pcg_opts;
 
 typedef struct {
@@ -156,8 +177,8 @@ typedef struct {
   int status;          /* per-member sfem_status */
 } sfem_pcg_info;
 
-/* Solve A x = b for nbatch right-hand sides by Jacobi-PCG (preconditioner: the
- * exact operator diagonal).  b: [nbatch][ndof] float64; x: [nbatch][ndof]
+/* Solve A x = b for nbatch right-hand sides by diagonally preconditioned CG
+ * (opts->precond: the exact operator diagonal or the collocated mass).  b: [nbatch][ndof] float64; x: [nbatch][ndof]
  * float64, initial guess on entry (unless opts->x0_zero), solution on exit.
  * info: host array of nbatch entries (may be NULL).  Returns SFEM_OK when every
  * member converged, SFEM_NOCONV if some did not (x = last iterate), or an error. */

@@ -13,7 +13,8 @@ import ctypes as C
 import torch  # loads the HIP runtime the library binds to
 
 from . import _lib
-from ._lib import F32, F64, MASS, DIFFUSION, HELMHOLTZ, SfemError, PcgOpts, PcgInfo, CtxInfo  # noqa: F401
+from ._lib import (F32, F64, MASS, DIFFUSION, HELMHOLTZ, PRECOND_JACOBI, PRECOND_COLLOCATED_MASS,  # noqa: F401
+                   SfemError, PcgOpts, PcgInfo, CtxInfo)
 
 __all__ = ["Operator", "SfemError", "MASS", "DIFFUSION", "HELMHOLTZ", "F64", "F32", "PcgResult"]
 
@@ -179,9 +180,20 @@ class Operator:
         self._check(self._lib.sfem_grad_nu(self._h, nb, _ptr(uu), _ptr(ll), _ptr(g)))
         return g[0] if uu.ndim == 1 else g
 
+    def collocated_mass(self):
+        """Collocated (GLL-integrated) mass diagonal [ndof], essential entries 1 (float64)."""
+        self._sync_stream()
+        d = torch.empty(self.ndof, dtype=torch.float64, device=self.device)
+        self._check(self._lib.sfem_collocated_mass(self._h, _ptr(d)))
+        return d
+
     def pcg(self, b, x=None, op=HELMHOLTZ, rtol=1e-10, maxit=10000, mode=0, inner_rtol=1e-5,
-            max_outer=30, check_every=8):
-        """Jacobi-PCG (mode 0) or FP32-inner PCG inside FP64 refinement (mode 1).
+            max_outer=30, check_every=8, precond=PRECOND_JACOBI, nullspace=False):
+        """Diagonally preconditioned CG (mode 0) or FP32-inner CG inside FP64 refinement
+        (mode 1).  precond: PRECOND_JACOBI (exact operator diagonal) or
+        PRECOND_COLLOCATED_MASS.  nullspace=True: pure-Neumann diffusion solve (no
+        essential DoFs) with the preconditioner orthogonalized against the constants and
+        the mean-zero solution returned.
 
         Returns (x, PcgResult).  Raises SfemError on errors; a non-converged solve
         returns the last iterate with status SFEM_NOCONV.
@@ -192,7 +204,7 @@ class Operator:
         x0_zero = x is None
         xv = torch.empty_like(bv) if x0_zero else self._vec(x, torch.float64, "x").clone()
         opts = PcgOpts(float(rtol), int(maxit), int(mode), float(inner_rtol), int(max_outer),
-                       int(check_every), 1 if x0_zero else 0)
+                       int(check_every), 1 if x0_zero else 0, int(precond), 1 if nullspace else 0)
         infos = (PcgInfo * nb)()
         st = self._check(self._lib.sfem_pcg(self._h, op, nb, _ptr(bv), _ptr(xv), C.byref(opts), infos))
         return xv, PcgResult(list(infos), st)

@@ -15,19 +15,20 @@ STATUS_NAMES = {
     -8: "SFEM_E_STATE",
 }
 F64, F32 = 0, 1
+PRECOND_JACOBI, PRECOND_COLLOCATED_MASS = 0, 1
 MASS, DIFFUSION, HELMHOLTZ = 0, 1, 2
 
 EXPORTED = [
     "sfem_abi_version", "sfem_create", "sfem_destroy", "sfem_set_stream", "sfem_last_error",
     "sfem_setup", "sfem_qpoint_coords", "sfem_set_coeffs", "sfem_apply", "sfem_diagonal",
-    "sfem_load", "sfem_pcg", "sfem_grad_nu", "sfem_get_info",
+    "sfem_load", "sfem_collocated_mass", "sfem_pcg", "sfem_grad_nu", "sfem_get_info",
 ]
 
 
 class PcgOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("maxit", C.c_int), ("mode", C.c_int),
                 ("inner_rtol", C.c_double), ("max_outer", C.c_int), ("check_every", C.c_int),
-                ("x0_zero", C.c_int)]
+                ("x0_zero", C.c_int), ("precond", C.c_int), ("nullspace", C.c_int)]
 
 
 class PcgInfo(C.Structure):
@@ -71,6 +72,7 @@ def load(path: str = LIB_PATH):
         "sfem_apply": (i32, [vp, i32, i32, i32, vp, vp]),
         "sfem_diagonal": (i32, [vp, i32, i32, vp]),
         "sfem_load": (i32, [vp, i32, vp, vp]),
+        "sfem_collocated_mass": (i32, [vp, vp]),
         "sfem_pcg": (i32, [vp, i32, i32, vp, vp, C.POINTER(PcgOpts), C.POINTER(PcgInfo)]),
         "sfem_grad_nu": (i32, [vp, i32, vp, vp, vp]),
         "sfem_get_info": (i32, [vp, C.POINTER(CtxInfo)]),

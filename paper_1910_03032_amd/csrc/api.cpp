@@ -48,6 +48,13 @@ struct sfem_ctx {
   int32_t *d_aoff = nullptr;       // [na + 1] CSR offsets of their E-vector entries
   int32_t *d_pos = nullptr;        // [nelem][epe] E-vector entry of each element node
   int64_t nentries = 0;            // E-vector entries per member
+  int64_t n_ess = 0;               // essential DoFs
+  // geometry-only vectors, computed on first use
+  double *d_cm = nullptr;          // collocated mass diagonal (essential rows 1)
+  double *d_cminv = nullptr;       // its inverse, FP64 and FP32
+  float *d_cminv32 = nullptr;
+  double *d_m1 = nullptr;          // M 1 (the integral of a DoF vector is m1^T x)
+  double m1sum = 0.0;              // 1^T M 1 = |Omega| (no essential DoFs)
   AsmPlan plan{};                  // the three arrays above, for the assembly kernel
 
   // ---- coefficients
@@ -162,6 +169,10 @@ void free_all(sfem_ctx *c) {
   c->d_aoff = nullptr;
   c->d_pos = nullptr;
   c->nentries = 0;
+  c->n_ess = 0;
+  c->d_cm = c->d_cminv = c->d_m1 = nullptr;
+  c->d_cminv32 = nullptr;
+  c->m1sum = 0.0;
   c->plan = AsmPlan{};
   c->na = 0;
   c->d_fold64 = nullptr;
@@ -262,6 +273,50 @@ sfem_status ensure_diag(sfem_ctx *c, int op) {
   HIPCHK(c, VecOps<float>::recip(c->d_diag[op], c->d_dinv32[op], n, c->stream));
   HIPCHK(c, launch_cast_f32(c->d_diag[op], c->d_diag32[op], n, c->stream));
   c->diag_ok[op] = true;
+  return SFEM_OK;
+}
+
+// Collocated mass diagonal and its inverses (geometry only; computed once per setup).
+sfem_status ensure_cmass(sfem_ctx *c) {
+  if (c->d_cm) return SFEM_OK;
+  const int64_t n = c->ndof;
+  sfem_status st;
+  double *cm = nullptr, *cminv = nullptr;
+  float *cminv32 = nullptr;
+  if ((st = dalloc(c, &cm, n)) != SFEM_OK) return st;
+  if ((st = dalloc(c, &cminv, n)) != SFEM_OK) return st;
+  if ((st = dalloc(c, &cminv32, n)) != SFEM_OK) return st;
+  if ((st = ensure_evec(c, (size_t)c->nentries * sizeof(double))) != SFEM_OK) return st;
+  HIPCHK(c, launch_colloc_mass(c->p, c->rules.gll_x.data(), c->rules.gll_w.data(), c->d_xyz, c->d_map,
+                               c->d_pos, c->compact, c->nelem, cm, (double *)c->evec.p, c->stream));
+  HIPCHK(c, launch_assemble<double>(c->plan, (const double *)c->evec.p, 0, nullptr, cm, n, 1, kEssOne,
+                                    nullptr, 0, c->stream));
+  HIPCHK(c, VecOps<double>::recip(cm, cminv, n, c->stream));
+  HIPCHK(c, VecOps<float>::recip(cm, cminv32, n, c->stream));
+  c->d_cm = cm;
+  c->d_cminv = cminv;
+  c->d_cminv32 = cminv32;
+  return SFEM_OK;
+}
+
+sfem_status do_apply(sfem_ctx *c, int op, bool f32, int nbatch, const void *x, void *y,
+                     double *part);
+
+// m1 = M 1 and 1^T M 1 (geometry only), for the mean-zero condition int x = m1^T x.
+sfem_status ensure_m1(sfem_ctx *c, double *tmp_ones, double *tmp_part, double *tmp_out) {
+  if (c->d_m1) return SFEM_OK;
+  const int64_t n = c->ndof;
+  sfem_status st;
+  double *m1 = nullptr;
+  if ((st = dalloc(c, &m1, n)) != SFEM_OK) return st;
+  HIPCHK(c, VecOps<double>::fill(tmp_ones, 1.0, n, c->stream));
+  if ((st = do_apply(c, SFEM_MASS, false, 1, tmp_ones, m1, nullptr)) != SFEM_OK) return st;
+  const int nblk = vec_nblk(n);
+  HIPCHK(c, VecOps<double>::dot(m1, nullptr, 0, tmp_part, nblk, n, 1, c->stream));
+  HIPCHK(c, launch_reduce1(tmp_part, nblk, 1, tmp_out, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&c->m1sum, tmp_out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->d_m1 = m1;
   return SFEM_OK;
 }
 
@@ -382,7 +437,7 @@ struct Carver {
 template <typename T>
 struct PcgWork {
   T *r, *p, *w;
-  double *part;   // vector-kernel partials [nb][3][nblk]
+  double *part;   // vector-kernel partials [nb][5][nblk]
   double *dpart;  // p^T A p partials of the apply [nb][nparts]
   PcgScalars *sc;
   int nblk, nparts;
@@ -391,7 +446,7 @@ struct PcgWork {
 template <typename T>
 size_t pcg_work_bytes(const sfem_ctx *c, int64_t n, int nb) {
   const int nblk = vec_nblk(n);
-  return 3 * align_up((size_t)n * nb * sizeof(T)) + align_up((size_t)nb * 3 * nblk * sizeof(double)) +
+  return 3 * align_up((size_t)n * nb * sizeof(T)) + align_up((size_t)nb * 5 * nblk * sizeof(double)) +
          align_up((size_t)nb * apply_nparts(c) * sizeof(double)) +
          align_up((size_t)nb * sizeof(PcgScalars));
 }
@@ -404,7 +459,7 @@ PcgWork<T> carve_pcg(const sfem_ctx *c, Carver &cv, int64_t n, int nb) {
   w.r = cv.take<T>(n * nb);
   w.p = cv.take<T>(n * nb);
   w.w = cv.take<T>(n * nb);
-  w.part = cv.take<double>((int64_t)nb * 3 * w.nblk);
+  w.part = cv.take<double>((int64_t)nb * 5 * w.nblk);
   w.dpart = cv.take<double>((int64_t)nb * w.nparts);
   w.sc = cv.take<PcgScalars>(nb);
   return w;
@@ -414,7 +469,7 @@ PcgWork<T> carve_pcg(const sfem_ctx *c, Carver &cv, int64_t n, int nb) {
 template <typename T>
 sfem_status run_pcg(sfem_ctx *c, int op, int nb, const T *b, T *x, bool x0_zero, double rtol,
                     int maxit, int check_every, const T *dinv, int64_t dms, PcgWork<T> &w,
-                    PcgScalars *hs) {
+                    PcgScalars *hs, int nullspace = 0) {
   const int64_t n = c->ndof;
   const bool f32 = sizeof(T) == 4;
   hipStream_t s = c->stream;
@@ -425,7 +480,8 @@ sfem_status run_pcg(sfem_ctx *c, int op, int nb, const T *b, T *x, bool x0_zero,
     if ((st = do_apply(c, op, f32, nb, x, w.w)) != SFEM_OK) return st;
     HIPCHK(c, VecOps<T>::start(b, w.w, nullptr, w.r, dinv, dms, w.p, w.part, w.nblk, n, nb, s));
   }
-  HIPCHK(c, launch_pcg_init(w.part, w.nblk, nb, rtol, w.sc, s));
+  HIPCHK(c, launch_pcg_init(w.part, w.nblk, nb, rtol, w.sc, s, nullspace, n));
+  if (nullspace) HIPCHK(c, launch_zshift<T>(w.p, w.sc, n, nb, s));
   auto all_done = [&]() -> sfem_status {
     HIPCHK(c, hipMemcpyAsync(hs, w.sc, sizeof(PcgScalars) * nb, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
@@ -444,7 +500,7 @@ sfem_status run_pcg(sfem_ctx *c, int op, int nb, const T *b, T *x, bool x0_zero,
     if ((st = do_apply(c, op, f32, nb, w.p, w.w, w.dpart)) != SFEM_OK) return st;
     HIPCHK(c, launch_pcg_alpha(w.dpart, w.nparts, nb, w.sc, s));
     HIPCHK(c, VecOps<T>::update(x, w.p, w.r, w.w, dinv, dms, w.sc, w.part, w.nblk, n, nb, s));
-    HIPCHK(c, launch_pcg_beta(w.part, w.nblk, nb, w.sc, s));
+    HIPCHK(c, launch_pcg_beta(w.part, w.nblk, nb, w.sc, s, nullspace, n));
     HIPCHK(c, VecOps<T>::newdir(w.r, dinv, dms, w.p, w.sc, n, nb, s));
     if ((it + 1) % check_every == 0 || it + 1 == maxit) {
       if ((st = all_done()) != SFEM_OK) return st;
@@ -602,6 +658,8 @@ sfem_status sfem_setup(sfem_ctx *c, int p, int q, int64_t nelem, const double *e
   c->plan.alist = c->d_alist;
   c->plan.aoff = c->d_aoff;
   c->nentries = hp.nentries;
+  c->n_ess = 0;
+  for (int64_t gd = 0; gd < ndof; ++gd) c->n_ess += ess[(size_t)gd] ? 1 : 0;
   c->plan.na = na;
   if (nelem > 0) {
     HIPCHK(c, hipMemcpyAsync(c->d_map, imap.data(), imap.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
@@ -704,6 +762,18 @@ sfem_status sfem_load(sfem_ctx *c, int nbatch, const double *f_q, double *b) {
   return SFEM_OK;
 }
 
+sfem_status sfem_collocated_mass(sfem_ctx *c, double *diag) {
+  sfem_status st = require_ready(c);
+  if (st != SFEM_OK) return st;
+  if (c->ndof == 0) return SFEM_OK;
+  if (!diag) return fail(c, SFEM_E_ARG, "diag must not be NULL");
+  DeviceGuard g(c->device);
+  if ((st = ensure_cmass(c)) != SFEM_OK) return st;
+  HIPCHK(c, hipMemcpyAsync(diag, c->d_cm, (size_t)c->ndof * sizeof(double), hipMemcpyDeviceToDevice,
+                           c->stream));
+  return SFEM_OK;
+}
+
 sfem_status sfem_grad_nu(sfem_ctx *c, int nbatch, const double *u, const double *lam, double *gq) {
   sfem_status st = require_ready(c);
   if (st != SFEM_OK) return st;
@@ -737,6 +807,12 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
     return fail(c, SFEM_E_ARG, "invalid options (rtol >= 0, maxit >= 0, check_every >= 1, mode 0/1)");
   if (opts->mode == 1 && (!(opts->inner_rtol > 0.0) || opts->max_outer < 1))
     return fail(c, SFEM_E_ARG, "mode 1 needs inner_rtol > 0 and max_outer >= 1");
+  if (opts->precond != SFEM_PRECOND_JACOBI && opts->precond != SFEM_PRECOND_COLLOCATED_MASS)
+    return fail(c, SFEM_E_ARG, "precond must be SFEM_PRECOND_JACOBI or SFEM_PRECOND_COLLOCATED_MASS");
+  const int ns = opts->nullspace ? 1 : 0;
+  if (ns && (op != SFEM_DIFFUSION || c->n_ess != 0 || opts->mode != 0 || !opts->x0_zero))
+    return fail(c, SFEM_E_ARG,
+                "nullspace solves need op = SFEM_DIFFUSION, no essential DoFs, mode 0 and x0_zero");
   const int nb = nbatch;
   const int64_t n = c->ndof;
   if (nb == 0) return SFEM_OK;
@@ -748,8 +824,11 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
   if (!b || !x) return fail(c, SFEM_E_ARG, "b and x must not be NULL");
   if ((const void *)b == (const void *)x) return fail(c, SFEM_E_ARG, "b and x must not alias");
   DeviceGuard g(c->device);
-  if ((st = ensure_diag(c, op)) != SFEM_OK) return st;
-  const int64_t dms = nfields_of(c, op) > 1 ? n : 0;
+  const bool cmass = opts->precond == SFEM_PRECOND_COLLOCATED_MASS;
+  if ((st = cmass ? ensure_cmass(c) : ensure_diag(c, op)) != SFEM_OK) return st;
+  const int64_t dms = (!cmass && nfields_of(c, op) > 1) ? n : 0;
+  const double *dinv64 = cmass ? c->d_cminv : c->d_dinv[op];
+  const float *dinv32 = cmass ? c->d_cminv32 : c->d_dinv32[op];
   hipStream_t s = c->stream;
   const int nblk = vec_nblk(n);
   std::vector<int> iters(nb, 0), status(nb, 0);
@@ -757,20 +836,38 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
   int outer = 0;
 
   if (opts->mode == 0) {
-    const size_t bytes = pcg_work_bytes<double>(c, n, nb) + align_up((size_t)nb * sizeof(double));
+    const size_t bytes = pcg_work_bytes<double>(c, n, nb) + align_up((size_t)nb * sizeof(double)) +
+                         (ns ? align_up((size_t)n * nb * sizeof(double)) : 0);
     if ((st = ensure_ws(c, bytes)) != SFEM_OK) return st;
     if ((st = ensure_pinned(c, std::max(sizeof(PcgScalars), sizeof(double)) * nb)) != SFEM_OK) return st;
     Carver cv{(char *)c->ws.p};
     PcgWork<double> w = carve_pcg<double>(c, cv, n, nb);
     double *d_out = cv.take<double>(nb);
+    const double *bs = b;  // the right-hand side actually solved for
+    if (ns) {
+      // the pure-Neumann right-hand side is made orthogonal to the constants: b - mean(b) 1
+      double *bc = cv.take<double>(n * nb);
+      if ((st = ensure_m1(c, w.r, w.part, d_out)) != SFEM_OK) return st;
+      HIPCHK(c, VecOps<double>::dot(b, nullptr, 0, w.part, nblk, n, nb, s));
+      HIPCHK(c, launch_reduce1(w.part, nblk, nb, d_out, s));
+      HIPCHK(c, hipMemcpyAsync(bc, b, (size_t)n * nb * sizeof(double), hipMemcpyDeviceToDevice, s));
+      HIPCHK(c, launch_shift(bc, d_out, 1.0 / (double)n, n, nb, s));
+      bs = bc;
+    }
     PcgScalars *hs = (PcgScalars *)c->h_pinned;
-    if ((st = run_pcg<double>(c, op, nb, b, x, opts->x0_zero != 0, opts->rtol, opts->maxit,
-                              opts->check_every, c->d_dinv[op], dms, w, hs)) != SFEM_OK)
+    if ((st = run_pcg<double>(c, op, nb, bs, x, opts->x0_zero != 0, opts->rtol, opts->maxit,
+                              opts->check_every, dinv64, dms, w, hs, ns)) != SFEM_OK)
       return st;
     std::vector<PcgScalars> fin(hs, hs + nb);
+    if (ns) {
+      // mean-zero condition: x <- x - (m1^T x / 1^T m1) 1
+      HIPCHK(c, VecOps<double>::dot(x, c->d_m1, 0, w.part, nblk, n, nb, s));
+      HIPCHK(c, launch_reduce1(w.part, nblk, nb, d_out, s));
+      HIPCHK(c, launch_shift(x, d_out, 1.0 / c->m1sum, n, nb, s));
+    }
     // true residual ||b - A x|| in FP64
     if ((st = do_apply(c, op, false, nb, x, w.w)) != SFEM_OK) return st;
-    HIPCHK(c, launch_sub_norm(b, w.w, nullptr, w.part, nblk, n, nb, s));
+    HIPCHK(c, launch_sub_norm(bs, w.w, nullptr, w.part, nblk, n, nb, s));
     HIPCHK(c, launch_reduce1(w.part, nblk, nb, d_out, s));
     std::vector<double> tr(nb);
     HIPCHK(c, hipMemcpyAsync(tr.data(), d_out, nb * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -841,7 +938,7 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
       if (need >= opts->inner_rtol) itol = 0.5 * need;
       PcgScalars *hs = (PcgScalars *)c->h_pinned;
       if ((st = run_pcg<float>(c, op, nb, r32, d32, true, itol,
-                               opts->maxit - total_inner, opts->check_every, c->d_dinv32[op], dms,
+                               opts->maxit - total_inner, opts->check_every, dinv32, dms,
                                w, hs)) != SFEM_OK)
         return st;
       int mx = 0;

@@ -42,6 +42,7 @@ struct PcgScalars {
   int status;     // 0 ok, SFEM_E_BREAKDOWN, SFEM_E_NAN
   int iters;      // completed iterations
   int pad;
+  double zshift;  // null-space solves: mean of dinv r, removed from the preconditioned residual
 };
 
 // ---------------------------------------------------------------------------
@@ -104,6 +105,11 @@ hipError_t launch_diag(const DiagArgs &a, hipStream_t s);
 
 hipError_t launch_qdata_setup(int q, const double *gx, const double *gw, const double *xyz,
                               int64_t nei, double *qd, int *bad, hipStream_t s);
+// Collocated (GLL-integrated) mass contributions of every element node: sole DoFs into
+// diag, shared nodes into their E-vector entry (then assembled with ess rows = 1).
+hipError_t launch_colloc_mass(int p, const double *gll_x, const double *gll_w, const double *xyz,
+                              const int32_t *map, const int32_t *pos, int compact, int64_t nelem,
+                              double *diag, double *evec, hipStream_t s);
 hipError_t launch_qpoint_coords(int q, const double *gx, const double *gw, const double *xyz,
                                 int64_t nei, double *xq, hipStream_t s);
 hipError_t launch_fold(int q, const double *qd, const double *nu_user, int64_t nei, int nfield,
@@ -145,8 +151,10 @@ template <typename T>
 struct VecOps {
   static hipError_t start(const T *b, const T *w, T *x, T *r, const T *dinv, int64_t dms, T *p,
                           double *part, int nblk, int64_t n, int nb, hipStream_t s);
-  static hipError_t dot(const T *a, const T *c, double *part, int nblk, int64_t n, int nb,
-                        hipStream_t s);
+  // per-member partial sums of a[m] . c[m] (a: [nb][n]; c: member stride c_mstride, 0 for
+  // one vector shared by all members, or null for the all-ones vector)
+  static hipError_t dot(const T *a, const T *c, int64_t c_mstride, double *part, int nblk,
+                        int64_t n, int nb, hipStream_t s);
   static hipError_t update(T *x, const T *p, T *r, const T *w, const T *dinv, int64_t dms,
                            const PcgScalars *sc, double *part, int nblk, int64_t n, int nb,
                            hipStream_t s);
@@ -158,10 +166,19 @@ struct VecOps {
 int vec_nblk(int64_t n);
 hipError_t launch_sub_norm(const double *b, const double *w, double *r, double *part, int nblk,
                            int64_t n, int nb, hipStream_t s);
+// Scalar steps of the CG.  With nullspace != 0 (constants in the operator's null space,
+// n unknowns per member) the preconditioned residual z = dinv r is orthogonalized,
+// z - mean(z) 1, and rho = r^T z of that vector (Section 5.3).
 hipError_t launch_pcg_init(const double *part, int nblk, int nb, double rtol, PcgScalars *sc,
-                           hipStream_t s);
+                           hipStream_t s, int nullspace = 0, int64_t n = 0);
 hipError_t launch_pcg_alpha(const double *part, int nblk, int nb, PcgScalars *sc, hipStream_t s);
-hipError_t launch_pcg_beta(const double *part, int nblk, int nb, PcgScalars *sc, hipStream_t s);
+hipError_t launch_pcg_beta(const double *part, int nblk, int nb, PcgScalars *sc, hipStream_t s,
+                           int nullspace = 0, int64_t n = 0);
+// v[m][i] -= sc[m].zshift (the initial direction of a null-space solve)
+template <typename T>
+hipError_t launch_zshift(T *v, const PcgScalars *sc, int64_t n, int nb, hipStream_t s);
+// v[m][i] -= c[m] * scale (member-wise constant shift)
+hipError_t launch_shift(double *v, const double *c, double scale, int64_t n, int nb, hipStream_t s);
 hipError_t launch_reduce1(const double *part, int nblk, int nb, double *out, hipStream_t s);
 hipError_t launch_ir_norm(const double *part, int nblk, int nb, int set_bb, double rtol, double *ir,
                           hipStream_t s);

@@ -41,6 +41,52 @@ __device__ inline void trilinear(const double *X, const double xi[3], double pos
   }
 }
 
+// Rank of local node l among the surface nodes of an order-p element (same order as the
+// host plan and the element kernels), -1 for an interior node.
+__device__ inline int surface_rank_rt(int p, int l) {
+  const int n = p + 1;
+  const int i = l % n, j = (l / n) % n, k = l / (n * n);
+  if (k == 0) return i + n * j;
+  if (k == p) return n * n + i + n * j;
+  const int base = 2 * n * n + (k - 1) * 4 * p;
+  if (j == 0) return base + i;
+  if (j == p) return base + n + i;
+  if (i == 0 || i == p) return base + 2 * n + 2 * (j - 1) + (i == 0 ? 0 : 1);
+  return -1;
+}
+
+// Collocated mass (Section 5.1): integrating the mass matrix with the GLL rule at the
+// nodes themselves makes it diagonal; element node l contributes w_l |J(xi_l)| (tensor
+// GLL weight times the Jacobian determinant at the node).  Written like an element
+// output: sole DoFs directly into diag, shared nodes into their E-vector entry,
+// essential DoFs not at all (the assembly sets them).
+__global__ void colloc_mass_kernel(GaussArg g, int p, const double *__restrict__ xyz,
+                                   const int32_t *__restrict__ map, const int32_t *__restrict__ pos,
+                                   int compact, int64_t nelem, double *__restrict__ diag,
+                                   double *__restrict__ Y) {
+  const int n = p + 1, n3 = n * n * n;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= nelem * n3) return;
+  const int64_t e = gid / n3;
+  const int l = (int)(gid - e * n3);
+  const int i = l % n, j = (l / n) % n, k = l / (n * n);
+  const int32_t c = map[gid];
+  if (c < 0) return;
+  const double xi[3] = {g.x[i], g.x[j], g.x[k]};
+  double x3[3], J[3][3];
+  trilinear(xyz + e * 24, xi, x3, J);
+  const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                     J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                     J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+  const double v = g.w[i] * g.w[j] * g.w[k] * det;
+  if (c & kSoleBit) {
+    diag[c & kDofMask] = v;
+  } else {
+    const int S = p == 1 ? 8 : 2 * n * n + (n - 2) * 4 * p;
+    Y[pos[compact ? e * S + surface_rank_rt(p, l) : gid]] = v;
+  }
+}
+
 __global__ void qdata_setup_kernel(GaussArg g, int q, const double *__restrict__ xyz, int64_t nei,
                                    double *__restrict__ qd, int *__restrict__ bad) {
   const int64_t q3 = (int64_t)q * q * q;
@@ -170,6 +216,16 @@ hipError_t launch_fold(int q, const double *qd, const double *nu_user, int64_t n
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(fold_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s, q3, qd, nu_user,
                      nei, nfield, alpha, beta, fold64, fold32, nu64, nu32);
+  return hipGetLastError();
+}
+
+hipError_t launch_colloc_mass(int p, const double *gll_x, const double *gll_w, const double *xyz,
+                              const int32_t *map, const int32_t *pos, int compact, int64_t nelem,
+                              double *diag, double *evec, hipStream_t s) {
+  const int64_t n = nelem * (int64_t)(p + 1) * (p + 1) * (p + 1);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(colloc_mass_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s,
+                     gauss_arg(gll_x, gll_w, p + 1), p, xyz, map, pos, compact, nelem, diag, evec);
   return hipGetLastError();
 }
 

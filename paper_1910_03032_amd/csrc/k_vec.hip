@@ -120,14 +120,14 @@ __device__ __forceinline__ void set_beta(PcgScalars &s, double rz, double rr) {
 }
 
 // r = b - w (w may be null: r = b); x = 0 if xzero; p = dinv r;
-// partials: r.p (rho), r.r, b.b
+// partials: r.p (rho), r.r, b.b, sum p, sum r
 template <typename T>
 __global__ void start_kernel(const T *__restrict__ b, const T *__restrict__ w, T *__restrict__ x,
                              T *__restrict__ r, const T *__restrict__ dinv, int64_t dinv_mstride,
                              T *__restrict__ p, double *__restrict__ part, int nblk, int64_t n) {
   const int64_t off = (int64_t)blockIdx.y * n;
   const T *dm = dinv + (int64_t)blockIdx.y * dinv_mstride;
-  double v[3] = {0.0, 0.0, 0.0};
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)nblk * VB) {
     const T bi = b[off + i];
     const T ri = w ? (T)(bi - w[off + i]) : bi;
@@ -138,21 +138,24 @@ __global__ void start_kernel(const T *__restrict__ b, const T *__restrict__ w, T
     v[0] += (double)ri * (double)pi;
     v[1] += (double)ri * (double)ri;
     v[2] += (double)bi * (double)bi;
+    v[3] += (double)pi;
+    v[4] += (double)ri;
   }
-  write_part<3>(v, part, nblk);
+  write_part<5>(v, part, nblk);
 }
 
 template <typename T>
-__global__ void dot_kernel(const T *__restrict__ a, const T *__restrict__ c,
+__global__ void dot_kernel(const T *__restrict__ a, const T *__restrict__ c, int64_t c_mstride,
                            double *__restrict__ part, int nblk, int64_t n) {
   const int64_t off = (int64_t)blockIdx.y * n;
+  const T *cm = c ? c + (int64_t)blockIdx.y * c_mstride : nullptr;
   double v[1] = {0.0};
   for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)nblk * VB)
-    v[0] += (double)a[off + i] * (double)c[off + i];
+    v[0] += (double)a[off + i] * (cm ? (double)cm[i] : 1.0);
   write_part<1>(v, part, nblk);
 }
 
-// x += alpha p; r -= alpha w; partials: r.(dinv r), r.r
+// x += alpha p; r -= alpha w; partials: r.z, r.r, sum z, sum r (z = dinv r)
 template <typename T>
 __global__ void update_kernel(T *__restrict__ x, const T *__restrict__ p, T *__restrict__ r,
                               const T *__restrict__ w, const T *__restrict__ dinv,
@@ -162,18 +165,21 @@ __global__ void update_kernel(T *__restrict__ x, const T *__restrict__ p, T *__r
   const int64_t off = (int64_t)m * n;
   const T *dm = dinv + (int64_t)m * dinv_mstride;
   const T alpha = (T)sc[m].alpha;
-  double v[2] = {0.0, 0.0};
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)nblk * VB) {
     x[off + i] += alpha * p[off + i];
     const T ri = r[off + i] - alpha * w[off + i];
     r[off + i] = ri;
-    v[0] += (double)ri * (double)(dm[i] * ri);
+    const T zi = dm[i] * ri;
+    v[0] += (double)ri * (double)zi;
     v[1] += (double)ri * (double)ri;
+    v[2] += (double)zi;
+    v[3] += (double)ri;
   }
-  write_part<2>(v, part, nblk);
+  write_part<4>(v, part, nblk);
 }
 
-// p = dinv r + beta p
+// p = (dinv r - zshift) + beta p
 template <typename T>
 __global__ void newdir_kernel(const T *__restrict__ r, const T *__restrict__ dinv,
                               int64_t dinv_mstride, T *__restrict__ p,
@@ -182,9 +188,10 @@ __global__ void newdir_kernel(const T *__restrict__ r, const T *__restrict__ din
   const int64_t off = (int64_t)m * n;
   const T *dm = dinv + (int64_t)m * dinv_mstride;
   const T beta = (T)sc[m].beta;
+  const T zs = (T)sc[m].zshift;
   for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * VB)
-    p[off + i] = dm[i] * r[off + i] + beta * p[off + i];
+    p[off + i] = (dm[i] * r[off + i] - zs) + beta * p[off + i];
 }
 
 // r = b - w with partial r.r (w may be null: r = b); r may be null (norm only)
@@ -202,12 +209,13 @@ __global__ void sub_norm_kernel(const double *__restrict__ b, const double *__re
 }
 
 __global__ void __launch_bounds__(RB) init_scalars_kernel(const double *__restrict__ part, int nblk, double rtol,
-                                    PcgScalars *__restrict__ sc) {
-  double v[3];
-  reduce_parts<3>(part, nblk, v);
+                                    PcgScalars *__restrict__ sc, int nullspace, int64_t n) {
+  double v[5];
+  reduce_parts<5>(part, nblk, v);
   if (threadIdx.x == 0) {
     PcgScalars &s = sc[blockIdx.x];
-    s.rho = v[0];
+    s.zshift = nullspace ? v[3] / (double)n : 0.0;
+    s.rho = v[0] - s.zshift * v[4];
     s.rr = v[1];
     s.bb = v[2];
     s.pw = 0.0;
@@ -229,10 +237,33 @@ __global__ void __launch_bounds__(RB) alpha_kernel(const double *__restrict__ pa
 }
 
 __global__ void __launch_bounds__(RB) beta_kernel(const double *__restrict__ part, int nblk,
-                                                  PcgScalars *__restrict__ sc) {
-  double v[2];
-  reduce_parts<2>(part, nblk, v);
-  if (threadIdx.x == 0) set_beta(sc[blockIdx.x], v[0], v[1]);
+                                                  PcgScalars *__restrict__ sc, int nullspace, int64_t n) {
+  double v[4];
+  reduce_parts<4>(part, nblk, v);
+  if (threadIdx.x == 0) {
+    PcgScalars &s = sc[blockIdx.x];
+    const double zs = nullspace ? v[2] / (double)n : 0.0;
+    if (s.active) s.zshift = zs;
+    set_beta(s, v[0] - zs * v[3], v[1]);
+  }
+}
+
+// v[m][i] -= sc[m].zshift
+template <typename T>
+__global__ void zshift_kernel(T *__restrict__ v, const PcgScalars *__restrict__ sc, int64_t n) {
+  const int m = blockIdx.y;
+  const T zs = (T)sc[m].zshift;
+  for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB)
+    v[(int64_t)m * n + i] -= zs;
+}
+
+// v[m][i] -= c[m] * scale
+__global__ void shift_kernel(double *__restrict__ v, const double *__restrict__ c, double scale,
+                             int64_t n) {
+  const int m = blockIdx.y;
+  const double d = c[m] * scale;
+  for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB)
+    v[(int64_t)m * n + i] -= d;
 }
 
 // out[m * nv + k] = sum of partials
@@ -385,9 +416,9 @@ hipError_t VecOps<T>::start(const T *b, const T *w, T *x, T *r, const T *dinv, i
 }
 
 template <typename T>
-hipError_t VecOps<T>::dot(const T *a, const T *c, double *part, int nblk, int64_t n, int nb,
-                          hipStream_t s) {
-  hipLaunchKernelGGL((dot_kernel<T>), dim3(nblk, nb), dim3(VB), 0, s, a, c, part, nblk, n);
+hipError_t VecOps<T>::dot(const T *a, const T *c, int64_t c_mstride, double *part, int nblk,
+                          int64_t n, int nb, hipStream_t s) {
+  hipLaunchKernelGGL((dot_kernel<T>), dim3(nblk, nb), dim3(VB), 0, s, a, c, c_mstride, part, nblk, n);
   return hipGetLastError();
 }
 
@@ -452,8 +483,8 @@ hipError_t launch_sub_norm(const double *b, const double *w, double *r, double *
 }
 
 hipError_t launch_pcg_init(const double *part, int nblk, int nb, double rtol, PcgScalars *sc,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(init_scalars_kernel, dim3(nb), dim3(RB), 0, s, part, nblk, rtol, sc);
+                           hipStream_t s, int nullspace, int64_t n) {
+  hipLaunchKernelGGL(init_scalars_kernel, dim3(nb), dim3(RB), 0, s, part, nblk, rtol, sc, nullspace, n);
   return hipGetLastError();
 }
 
@@ -462,8 +493,24 @@ hipError_t launch_pcg_alpha(const double *part, int nblk, int nb, PcgScalars *sc
   return hipGetLastError();
 }
 
-hipError_t launch_pcg_beta(const double *part, int nblk, int nb, PcgScalars *sc, hipStream_t s) {
-  hipLaunchKernelGGL(beta_kernel, dim3(nb), dim3(RB), 0, s, part, nblk, sc);
+hipError_t launch_pcg_beta(const double *part, int nblk, int nb, PcgScalars *sc, hipStream_t s,
+                           int nullspace, int64_t n) {
+  hipLaunchKernelGGL(beta_kernel, dim3(nb), dim3(RB), 0, s, part, nblk, sc, nullspace, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zshift(T *v, const PcgScalars *sc, int64_t n, int nb, hipStream_t s) {
+  if (n <= 0 || nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL((zshift_kernel<T>), dim3(grid_for(n), nb), dim3(VB), 0, s, v, sc, n);
+  return hipGetLastError();
+}
+template hipError_t launch_zshift<double>(double *, const PcgScalars *, int64_t, int, hipStream_t);
+template hipError_t launch_zshift<float>(float *, const PcgScalars *, int64_t, int, hipStream_t);
+
+hipError_t launch_shift(double *v, const double *c, double scale, int64_t n, int nb, hipStream_t s) {
+  if (n <= 0 || nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(shift_kernel, dim3(grid_for(n), nb), dim3(VB), 0, s, v, c, scale, n);
   return hipGetLastError();
 }
 

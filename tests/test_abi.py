@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_pure_host_calls(lib):
-    assert lib.sfem_abi_version() == 1
+    assert lib.sfem_abi_version() == 2
     assert isinstance(lib.sfem_last_error(None), bytes)
     from paper_1910_03032_amd._lib import CtxInfo
     ci = CtxInfo()
@@ -51,8 +51,8 @@ def test_pure_host_calls(lib):
 
 def test_structs_match_header_layout():
     from paper_1910_03032_amd._lib import PcgOpts, PcgInfo
-    # double, int, int, double, int, int, int -> 40 bytes with natural alignment
-    assert C.sizeof(PcgOpts) == 40
+    # double, int, int, double, int, int, int, int, int -> 44 bytes, padded to 48
+    assert C.sizeof(PcgOpts) == 48
     assert C.sizeof(PcgInfo) == 32
 
 
