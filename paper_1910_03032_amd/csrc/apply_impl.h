@@ -18,10 +18,11 @@
 //
 // Assembly (no atomics, deterministic): one launch of the element kernel covers every
 // element.  A DoF that belongs to this element only (the element-interior nodes of a
-// conforming mesh) is written straight to y.  The values of shared nodes (element
-// surface) go to a compact E-vector, Y[e][rank(l)] over the element's surface nodes;
-// an assembly kernel then gives each shared DoF to one thread, which sums its
-// E-vector entries in a fixed order (owner computes) -- and sets the essential DoFs.
+// conforming mesh) is written straight to y.  The value of a shared node (element
+// surface) goes to its own entry of the E-vector, which is ordered by destination DoF
+// (the entry comes from a position table read with the map); an assembly kernel then
+// gives each shared DoF to one thread, which sums its contiguous E-vector entries in
+// element order (owner computes) -- and sets the essential DoFs.
 // Workgroups are mapped to elements so that each of the 8 XCDs works on one
 // contiguous range of elements, which keeps the x values shared by neighbouring
 // elements in that XCD's L2.

@@ -55,8 +55,8 @@ int build_host_plan(int p, int64_t nelem, const int32_t *dofs_ptr, int64_t ndof,
   }
   // ---- a DoF referenced by one element only is written directly by that element
   // ("sole"); the others, and the essential DoFs, are written by the assembly kernel
-  // from the E-vector.  Compact E-vector: only the element's surface nodes get slots,
-  // valid when every element-interior local node is sole or essential.
+  // from the E-vector.  Compact position table: indexed by the element's surface nodes
+  // only, valid when every element-interior local node is sole or essential.
   const int64_t S = (p == 1) ? 8 : (int64_t)(2 * n * n + (n - 2) * 4 * p);
   bool compact = true;
   for (int64_t e = 0; e < nelem && compact; ++e)
@@ -83,8 +83,8 @@ int build_host_plan(int p, int64_t nelem, const int32_t *dofs_ptr, int64_t ndof,
         v |= kSoleBit;
       imap[(size_t)(e * n3 + l)] = v;
     }
-  // assembled DoFs (shared or essential), ascending, and the E-vector slots of their
-  // contributions in element order
+  // assembled DoFs (shared or essential), ascending; the E-vector entries of their
+  // contributions are contiguous per DoF, in element order
   std::vector<int32_t> apos((size_t)ndof, -1);
   std::vector<int32_t> &alist = out.alist;
   for (int64_t gd = 0; gd < ndof; ++gd)
