@@ -60,16 +60,31 @@ def log(*a):
 KERNEL_SOURCES = ["apply_impl.h", "eo.h", "rules.h", "internal.h", "plan.h", "k_apply_f64.hip", "k_vec.hip"]
 MEASURED_TRAFFIC = {
     # profiles/helmholtz_apply_p4_32e_hbm_bytes.md
-    ("c98161d892cc1272", "helmholtz_p4_32e"): 552864747,
+    ("1ea0c64688de0345", "helmholtz_p4_32e"): 552864747,
 }
 
 
-def kernel_source_hash():
+def code_of(text):
+    """Source text without // comments and blank lines (a comment edit is not a kernel
+    change)."""
+    out = []
+    for line in text.splitlines():
+        code = line.split("//", 1)[0].rstrip()
+        if code.strip():
+            out.append(code)
+    return "\n".join(out)
+
+
+def kernel_source_hash(read=None):
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1910_03032_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        if read is None:
+            with open(os.path.join(ROOT, "paper_1910_03032_amd", "csrc", f)) as fh:
+                text = fh.read()
+        else:
+            text = read(f)
+        h.update(code_of(text).encode())
     return h.hexdigest()[:16]
 
 
