@@ -46,7 +46,8 @@ struct sfem_ctx {
   int64_t na = 0;                  // number of DoFs the assembly kernel writes
   int32_t *d_alist = nullptr;      // [na] those DoFs, ascending
   int32_t *d_aoff = nullptr;       // [na + 1] CSR offsets of their E-vector entries
-  int32_t *d_pos = nullptr;        // [nelem][epe] E-vector entry of each element node
+  int32_t *d_pos = nullptr;        // DoF-ordered E-vector: [nelem][epe] entry of each node
+  int32_t *d_slot = nullptr;       // element-ordered E-vector: entries of the contributions
   int64_t nentries = 0;            // E-vector entries per member
   int64_t n_ess = 0;               // essential DoFs
   // geometry-only vectors, computed on first use
@@ -168,6 +169,7 @@ void free_all(sfem_ctx *c) {
   c->d_alist = nullptr;
   c->d_aoff = nullptr;
   c->d_pos = nullptr;
+  c->d_slot = nullptr;
   c->nentries = 0;
   c->n_ess = 0;
   c->d_cm = c->d_cminv = c->d_m1 = nullptr;
@@ -615,7 +617,9 @@ sfem_status sfem_setup(sfem_ctx *c, int p, int q, int64_t nelem, const double *e
   HostPlan hp;
   {
     std::string err;
-    const int rc = build_host_plan(p, nelem, dofs.data(), ndof, ess.data(), hp, err);
+    // E-vector layout: DoF-ordered up to p = 4, element-ordered above (at high order the
+    // scattered entry writes cost the element kernel more than the assembly saves)
+    const int rc = build_host_plan(p, nelem, dofs.data(), ndof, ess.data(), hp, err, p <= 4);
     if (rc != 0) return fail(c, (sfem_status)rc, err);
   }
   const bool compact = hp.compact;
@@ -625,6 +629,7 @@ sfem_status sfem_setup(sfem_ctx *c, int p, int q, int64_t nelem, const double *e
   const std::vector<int32_t> &alist = hp.alist;
   const std::vector<int32_t> &aoff = hp.aoff;
   const std::vector<int32_t> &pos = hp.pos;
+  const std::vector<int32_t> &slots = hp.slots;
   if (hp.nentries >= (int64_t)kDofMask) return fail(c, SFEM_E_ARG, "mesh too large");
 
   // ---- rules
@@ -647,6 +652,7 @@ sfem_status sfem_setup(sfem_ctx *c, int p, int q, int64_t nelem, const double *e
   if ((st = dalloc(c, &c->d_alist, na)) != SFEM_OK) return st;
   if ((st = dalloc(c, &c->d_aoff, na + 1)) != SFEM_OK) return st;
   if ((st = dalloc(c, &c->d_pos, (int64_t)pos.size())) != SFEM_OK) return st;
+  if ((st = dalloc(c, &c->d_slot, (int64_t)slots.size())) != SFEM_OK) return st;
   int *d_bad = nullptr;
   if ((st = dalloc(c, &d_bad, 1)) != SFEM_OK) return st;
   if (na > 0) {
@@ -655,8 +661,11 @@ sfem_status sfem_setup(sfem_ctx *c, int p, int q, int64_t nelem, const double *e
   }
   if (!pos.empty())
     HIPCHK(c, hipMemcpyAsync(c->d_pos, pos.data(), pos.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  if (!slots.empty())
+    HIPCHK(c, hipMemcpyAsync(c->d_slot, slots.data(), slots.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
   c->plan.alist = c->d_alist;
   c->plan.aoff = c->d_aoff;
+  c->plan.slot = c->d_slot;
   c->nentries = hp.nentries;
   c->n_ess = 0;
   for (int64_t gd = 0; gd < ndof; ++gd) c->n_ess += ess[(size_t)gd] ? 1 : 0;

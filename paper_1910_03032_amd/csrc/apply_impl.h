@@ -78,13 +78,14 @@ struct Per {
 // unconditional (an inactive slot reads a valid element's entries and discards them)
 // so that the compiler can batch them.  If smap is given (LDS), it receives for each
 // node the map entry of a sole or essential DoF, or the E-vector entry of a shared
-// node (epos: the element's row of the position table, read together with the map);
-// sx (LDS, optional) receives the raw x values.
+// node: from the element's row epos of the position table (read together with the
+// map) for the DoF-ordered E-vector, else ebase + r (element-ordered); sx (LDS,
+// optional) receives the raw x values.
 template <int P, typename T>
 __device__ __forceinline__ void gather_e(T *buf, int t, bool active, const int32_t *emap,
                                          const T *__restrict__ xm, int32_t *smap = nullptr,
                                          T *sx = nullptr, const int32_t *epos = nullptr,
-                                         bool compact = true);
+                                         int32_t ebase = 0, bool compact = true);
 
 // Rank of local node l among the element's surface nodes (a node with i, j or k in
 // {0, p}): face k = 0, face k = p, then for each interior k the ring of the (i, j)
@@ -109,7 +110,7 @@ __host__ __device__ constexpr int surf_count() {
 template <int P, typename T>
 __device__ __forceinline__ void gather_e(T *buf, int t, bool active, const int32_t *emap,
                                          const T *__restrict__ xm, int32_t *smap, T *sx,
-                                         const int32_t *epos, bool compact) {
+                                         const int32_t *epos, int32_t ebase, bool compact) {
   using D = Dims<P>;
   constexpr int NL = Per<P>::NL;
   int32_t c[NL], q[NL];
@@ -118,10 +119,8 @@ __device__ __forceinline__ void gather_e(T *buf, int t, bool active, const int32
     const int l0 = t + k * D::TPE;
     const int l = l0 < D::N3 ? l0 : D::N3 - 1;
     c[k] = emap[l];
-    if (epos) {
-      const int r = compact ? surf_rank<P>(l) : l;
-      q[k] = epos[r >= 0 ? r : 0];
-    }
+    const int r = compact ? surf_rank<P>(l) : l;
+    q[k] = epos ? epos[r >= 0 ? r : 0] : ebase + r;
   }
   T v[NL];
 #pragma unroll
@@ -131,7 +130,7 @@ __device__ __forceinline__ void gather_e(T *buf, int t, bool active, const int32
     const int l = t + k * D::TPE;
     if (l < D::N3) {
       buf[l] = (active && c[k] >= 0) ? v[k] : T(0);
-      if (smap) smap[l] = (epos && c[k] >= 0 && !(c[k] & kSoleBit)) ? q[k] : c[k];
+      if (smap) smap[l] = (c[k] >= 0 && !(c[k] & kSoleBit)) ? q[k] : c[k];
       if (sx) sx[l] = v[k];
     }
   }
@@ -416,8 +415,9 @@ apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
 
     int32_t *smap = smap_all + le * N3;
     T *sx = sx_all + le * N3;
+    const int64_t epe = compact ? surf_count<P>() : N3;
     gather_e<P, T>(buf, t, active, emap, xm, smap, part ? sx : nullptr,
-                   pos + es * (int64_t)(compact ? surf_count<P>() : N3), compact != 0);
+                   pos ? pos + es * epe : nullptr, (int32_t)(es * epe), compact != 0);
     fwd_x<P, T, DIFF>(buf, t);
     T pre0[NS], pre1[NS];  // quadrature data of the first slice pair, loaded early
     load_slice(pre0, 0);

@@ -65,24 +65,27 @@ struct ApplyArgs {
   void *y;                  // output at the sole DoFs
   void *evec;               // E-vector of the shared nodes, [nbatch][estride]
   int64_t estride;          // E-vector entries per member (contributions to shared DoFs)
-  const int32_t *pos;       // [nelem][S or n^3] E-vector entry of each element node
-  int compact;              // pos indexed by surface rank (1) or local node (0)
+  const int32_t *pos;       // DoF-ordered E-vector: [nelem][epe] entry of each element
+                            // node; null: element-ordered, node r of element e -> e*epe + r
+  int compact;              // nodes indexed by surface rank (1, epe = S) or local node (0)
   double *part;             // per-block dot partials (or null)
   int64_t part_mstride;
 };
 // Element phase of the apply over all elements (writes the E-vector).
 hipError_t launch_apply_f64(const ApplyArgs &a, hipStream_t s);
 hipError_t launch_apply_f32(const ApplyArgs &a, hipStream_t s);
-// Assembly list on the device (see HostPlan): the assembled DoFs, ascending, and the CSR
-// offsets of their contributions in the E-vector.
+// Assembly list on the device (see HostPlan): the assembled DoFs, ascending, the CSR
+// offsets of their contributions, and for the element-ordered E-vector the entries of
+// those contributions (slot == null: DoF-ordered, the entries are [aoff[i], aoff[i+1])).
 struct AsmPlan {
   const int32_t *alist;
   const int32_t *aoff;
+  const int32_t *slot;
   int64_t na;
 };
-// Assembly phase over the list: y[g] = sum of g's E-vector entries (contiguous, in element
-// order); essential DoFs get x[g], 1 or 0 per ess_kind.  With part != null also the
-// per-block sums of x_g y_g (part[m * part_mstride + block], assemble_nblk blocks).
+// Assembly phase over the list: y[g] = sum of g's E-vector entries in element order;
+// essential DoFs get x[g], 1 or 0 per ess_kind.  With part != null also the per-block
+// sums of x_g y_g (part[m * part_mstride + block], assemble_nblk blocks).
 int assemble_nblk(int64_t na);
 template <typename T>
 hipError_t launch_assemble(const AsmPlan &pl, const T *evec, int64_t estride, const T *x, T *y,
@@ -98,7 +101,7 @@ struct DiagArgs {
   int64_t nelem;
   double *diag;             // [ndof], written at the sole DoFs
   double *evec;             // E-vector of the shared nodes
-  const int32_t *pos;       // E-vector entry of each element node (see ApplyArgs)
+  const int32_t *pos;       // E-vector entry of each element node, or null (see ApplyArgs)
   int compact;
 };
 hipError_t launch_diag(const DiagArgs &a, hipStream_t s);
@@ -139,7 +142,7 @@ struct LoadArgs {
   double *b;                // written at the sole DoFs
   double *evec;             // E-vector of the shared nodes, [nbatch][estride]
   int64_t estride;
-  const int32_t *pos;       // E-vector entry of each element node (see ApplyArgs)
+  const int32_t *pos;       // E-vector entry of each element node, or null (see ApplyArgs)
   int compact;
 };
 hipError_t launch_load(const LoadArgs &a, hipStream_t s);

@@ -118,10 +118,10 @@ diag_kernel(const int32_t *__restrict__ map, const double *__restrict__ qd,
     if (c < 0) continue;
     if (c & kSoleBit)
       diag[c & kDofMask] = s0[l];
-    else if (compact)
-      Y[pos[e * surf_count<P>() + surf_rank<P>(l)]] = s0[l];
-    else
-      Y[pos[e * N3 + l]] = s0[l];
+    else {
+      const int64_t q = compact ? e * surf_count<P>() + surf_rank<P>(l) : e * N3 + l;
+      Y[pos ? pos[q] : q] = s0[l];
+    }
   }
 }
 

@@ -123,12 +123,12 @@ load_kernel(const int32_t *__restrict__ map, const double *__restrict__ qd, int6
       for (int l = t; l < D::N3; l += TPE) {
         const int32_t c = emap[l];
         if (c < 0) continue;
-        if (c & kSoleBit)
+        if (c & kSoleBit) {
           bm[c & kDofMask] = buf[l];
-        else if (compact)
-          Ym[pos[e * surf_count<P>() + surf_rank<P>(l)]] = buf[l];
-        else
-          Ym[pos[e * D::N3 + l]] = buf[l];
+        } else {
+          const int64_t q = compact ? e * surf_count<P>() + surf_rank<P>(l) : e * D::N3 + l;
+          Ym[pos ? pos[q] : q] = buf[l];
+        }
       }
     }
     __syncthreads();

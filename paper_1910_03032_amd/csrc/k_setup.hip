@@ -83,7 +83,8 @@ __global__ void colloc_mass_kernel(GaussArg g, int p, const double *__restrict__
     diag[c & kDofMask] = v;
   } else {
     const int S = p == 1 ? 8 : 2 * n * n + (n - 2) * 4 * p;
-    Y[pos[compact ? e * S + surface_rank_rt(p, l) : gid]] = v;
+    const int64_t q = compact ? e * S + surface_rank_rt(p, l) : gid;
+    Y[pos ? pos[q] : q] = v;
   }
 }
 

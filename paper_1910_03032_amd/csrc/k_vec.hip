@@ -314,12 +314,12 @@ __global__ void ir_accum_kernel(double *__restrict__ x, const float *__restrict_
 }
 
 // Assembly over the list of shared and essential DoFs: y[g] = sum of the E-vector
-// entries [aoff[i], aoff[i+1]) of entry i (contiguous, in element order); essential DoFs
-// (no entries) get x[g], 1 or 0.  DOT: also the per-block sums of x_g y_g.  Each thread
-// takes AU list entries per pass (stride VB); the first KS entries of each are loaded
-// together, longer lists fall back to a loop.  Consecutive threads read consecutive
-// runs of the E-vector.  Index arithmetic is 32-bit (entries below 2^31, checked at
-// set-up).
+// entries of list entry i in element order -- [aoff[i], aoff[i+1]) for the DoF-ordered
+// E-vector (consecutive threads then read consecutive runs), slot[aoff[i]..aoff[i+1])
+// for the element-ordered one; essential DoFs (no entries) get x[g], 1 or 0.  DOT: also
+// the per-block sums of x_g y_g.  Each thread takes AU list entries per pass (stride
+// VB); the first KS entries of each are loaded together, longer lists fall back to a
+// loop.  Index arithmetic is 32-bit (entries below 2^30, checked at set-up).
 constexpr int AU = 1;
 constexpr int KS = 8;
 
@@ -344,11 +344,16 @@ assemble_kernel(AsmPlan pl, const T *__restrict__ Y, int64_t estride, const T *_
       a[k] = in ? pl.aoff[i] : 0;
       d[k] = in ? pl.aoff[i + 1] - a[k] : -1;
     }
+    int32_t sl[AU][KS];
+#pragma unroll
+    for (int k = 0; k < AU; ++k)
+#pragma unroll
+      for (int j = 0; j < KS; ++j) sl[k][j] = (j < d[k]) ? (pl.slot ? pl.slot[a[k] + j] : a[k] + j) : 0;
     T val[AU][KS];
 #pragma unroll
     for (int k = 0; k < AU; ++k)
 #pragma unroll
-      for (int j = 0; j < KS; ++j) val[k][j] = (j < d[k]) ? Ym[a[k] + j] : T(0);
+      for (int j = 0; j < KS; ++j) val[k][j] = (j < d[k]) ? Ym[sl[k][j]] : T(0);
 #pragma unroll
     for (int k = 0; k < AU; ++k) {
       if (d[k] < 0) continue;
@@ -356,7 +361,7 @@ assemble_kernel(AsmPlan pl, const T *__restrict__ Y, int64_t estride, const T *_
 #pragma unroll
       for (int j = 1; j < KS; ++j)
         if (j < d[k]) acc += val[k][j];
-      for (int j = KS; j < d[k]; ++j) acc += Ym[a[k] + j];
+      for (int j = KS; j < d[k]; ++j) acc += Ym[pl.slot ? pl.slot[a[k] + j] : a[k] + j];
       const T xg = (DOT || (d[k] == 0 && ess_kind == kEssCopyX)) ? xm[g[k]] : T(0);
       if (d[k] == 0) acc = (ess_kind == kEssCopyX) ? xg : (ess_kind == kEssOne ? T(1) : T(0));
       ym[g[k]] = acc;

@@ -26,8 +26,9 @@ int64_t surface_rank(int p, int64_t l) {
 }
 
 int build_host_plan(int p, int64_t nelem, const int32_t *dofs_ptr, int64_t ndof,
-                    const uint8_t *ess_ptr, HostPlan &out, std::string &err) {
+                    const uint8_t *ess_ptr, HostPlan &out, std::string &err, bool dof_ordered) {
   out = HostPlan{};
+  out.dof_ordered = dof_ordered;
   const int n = p + 1;
   const int64_t n3 = (int64_t)n * n * n;
   auto dofs = [&](size_t k) { return dofs_ptr[k]; };
@@ -99,16 +100,28 @@ int build_host_plan(int p, int64_t nelem, const int32_t *dofs_ptr, int64_t ndof,
   for (int64_t gd = 0; gd < ndof; ++gd)
     if (apos[gd] >= 0 && !ess[gd]) aoff[(size_t)apos[gd] + 1] = (int32_t)deg[gd];
   for (int64_t i = 0; i < na; ++i) aoff[(size_t)i + 1] += aoff[(size_t)i];
-  out.nentries = aoff[(size_t)na];
-  std::vector<int32_t> &pos = out.pos;
-  pos.assign((size_t)(nelem * epe), -1);
   std::vector<int32_t> next(aoff.begin(), aoff.end() - 1);
-  for (int64_t e = 0; e < nelem; ++e)
-    for (int64_t l = 0; l < n3; ++l) {
-      const int32_t gd = dofs((size_t)(e * n3 + l));
-      if (ess[gd] || deg[gd] == 1) continue;
-      pos[(size_t)(e * epe + (compact ? surface_rank(p, l) : l))] = next[(size_t)apos[gd]]++;
-    }
+  if (dof_ordered) {
+    out.nentries = aoff[(size_t)na];
+    std::vector<int32_t> &pos = out.pos;
+    pos.assign((size_t)(nelem * epe), -1);
+    for (int64_t e = 0; e < nelem; ++e)
+      for (int64_t l = 0; l < n3; ++l) {
+        const int32_t gd = dofs((size_t)(e * n3 + l));
+        if (ess[gd] || deg[gd] == 1) continue;
+        pos[(size_t)(e * epe + (compact ? surface_rank(p, l) : l))] = next[(size_t)apos[gd]]++;
+      }
+  } else {
+    out.nentries = nelem * epe;
+    std::vector<int32_t> &slots = out.slots;
+    slots.assign((size_t)aoff[(size_t)na], -1);
+    for (int64_t e = 0; e < nelem; ++e)
+      for (int64_t l = 0; l < n3; ++l) {
+        const int32_t gd = dofs((size_t)(e * n3 + l));
+        if (ess[gd] || deg[gd] == 1) continue;
+        slots[(size_t)next[(size_t)apos[gd]]++] = (int32_t)(e * epe + (compact ? surface_rank(p, l) : l));
+      }
+  }
   return 0;
 }
 

@@ -45,11 +45,11 @@ static void box(int ne, int p, std::vector<int32_t> &dofs, std::vector<uint8_t> 
 }
 
 // Replays the plan: y_plan[g] from E-vector values vs the direct scatter-add.
-static void replay(const char *name, int p, int64_t nelem, const std::vector<int32_t> &dofs,
-                   const std::vector<uint8_t> &ess, int64_t ndof, bool expect_compact) {
+static void replay1(const char *name, int p, int64_t nelem, const std::vector<int32_t> &dofs,
+                    const std::vector<uint8_t> &ess, int64_t ndof, bool expect_compact, bool dof_ordered) {
   HostPlan hp;
   std::string err;
-  const int rc = build_host_plan(p, nelem, dofs.data(), ndof, ess.data(), hp, err);
+  const int rc = build_host_plan(p, nelem, dofs.data(), ndof, ess.data(), hp, err, dof_ordered);
   CHECK(rc == 0, "%s: build failed: %s", name, err.c_str());
   if (rc != 0) return;
   CHECK(hp.compact == expect_compact, "%s: compact = %d", name, (int)hp.compact);
@@ -65,10 +65,12 @@ static void replay(const char *name, int p, int64_t nelem, const std::vector<int
           name, (long long)k);
   }
   // integer element contributions: value of (e, l) = 1000 e + l + 1, written to the
-  // E-vector entry pos[e * epe + r]; every entry is written exactly once
+  // node's E-vector entry (pos[e * epe + r] when DoF-ordered, e * epe + r otherwise);
+  // every entry the assembly reads is written exactly once
   CHECK((int64_t)hp.aoff.size() == hp.na + 1 && hp.aoff[0] == 0, "%s: offsets", name);
-  CHECK(hp.nentries == hp.aoff[(size_t)hp.na], "%s: entry count", name);
-  CHECK((int64_t)hp.pos.size() == nelem * hp.epe, "%s: pos size", name);
+  CHECK(hp.nentries == (dof_ordered ? hp.aoff[(size_t)hp.na] : nelem * hp.epe), "%s: entry count", name);
+  CHECK((int64_t)(dof_ordered ? hp.pos.size() : hp.slots.size()) ==
+            (dof_ordered ? nelem * hp.epe : hp.aoff[(size_t)hp.na]), "%s: table size", name);
   std::vector<int64_t> Y((size_t)hp.nentries, 0), direct((size_t)ndof, 0);
   std::vector<int> hits((size_t)hp.nentries, 0);
   std::vector<int64_t> owner((size_t)hp.nentries, -1);
@@ -78,11 +80,18 @@ static void replay(const char *name, int p, int64_t nelem, const std::vector<int
       const int64_t v = 1000 * e + l + 1;
       direct[(size_t)g] += v;
       const int64_t r = hp.compact ? surface_rank(p, l) : l;
-      const int32_t q = r >= 0 ? hp.pos[(size_t)(e * hp.epe + r)] : -1;
-      if (ess[(size_t)g] || deg[(size_t)g] == 1) {
-        CHECK(q < 0, "%s: node (%lld, %lld) of a sole/essential DoF has an entry", name, (long long)e,
-              (long long)l);
-        continue;
+      const bool shared = !(ess[(size_t)g] || deg[(size_t)g] == 1);
+      int64_t q = -1;
+      if (dof_ordered) {
+        q = r >= 0 ? hp.pos[(size_t)(e * hp.epe + r)] : -1;
+        if (!shared) {
+          CHECK(q < 0, "%s: node (%lld, %lld) of a sole/essential DoF has an entry", name, (long long)e,
+                (long long)l);
+          continue;
+        }
+      } else {
+        if (!shared) continue;
+        q = e * hp.epe + r;
       }
       CHECK(q >= 0 && q < hp.nentries, "%s: entry range", name);
       if (q < 0 || q >= hp.nentries) continue;
@@ -90,7 +99,8 @@ static void replay(const char *name, int p, int64_t nelem, const std::vector<int
       hits[(size_t)q]++;
       owner[(size_t)q] = e;
     }
-  for (int64_t k = 0; k < hp.nentries; ++k) CHECK(hits[(size_t)k] == 1, "%s: entry %lld written %d times", name, (long long)k, hits[(size_t)k]);
+  for (int64_t k = 0; k < hp.nentries; ++k)
+    CHECK(hits[(size_t)k] <= 1, "%s: entry %lld written %d times", name, (long long)k, hits[(size_t)k]);
   std::vector<char> seen((size_t)ndof, 0);
   int64_t nslot_used = 0;
   for (int64_t i = 0; i < hp.na; ++i) {
@@ -107,9 +117,12 @@ static void replay(const char *name, int p, int64_t nelem, const std::vector<int
           (long long)deg[(size_t)g]);
     int64_t sum = 0, last = -1;
     for (int64_t k = 0; k < d; ++k) {
-      CHECK(owner[(size_t)(a + k)] > last, "%s: contributions not in element order (DoF %d)", name, g);
-      last = owner[(size_t)(a + k)];
-      sum += Y[(size_t)(a + k)];
+      const int64_t q = dof_ordered ? a + k : hp.slots[(size_t)(a + k)];
+      CHECK(q >= 0 && q < hp.nentries && hits[(size_t)q] == 1, "%s: DoF %d reads an unwritten entry", name, g);
+      if (q < 0 || q >= hp.nentries) continue;
+      CHECK(owner[(size_t)q] > last, "%s: contributions not in element order (DoF %d)", name, g);
+      last = owner[(size_t)q];
+      sum += Y[(size_t)q];
     }
     nslot_used += d;
     CHECK(sum == direct[(size_t)g], "%s: DoF %d assembled %lld, direct %lld", name, g,
@@ -120,8 +133,15 @@ static void replay(const char *name, int p, int64_t nelem, const std::vector<int
     CHECK((seen[(size_t)g] != 0) == assembled, "%s: DoF %lld listed = %d", name, (long long)g,
           (int)seen[(size_t)g]);
   }
-  std::printf("%s: na %lld, entries %lld, compact %d\n", name, (long long)hp.na,
-              (long long)nslot_used, (int)hp.compact);
+  std::printf("%s (%s): na %lld, contributions %lld, compact %d\n", name,
+              dof_ordered ? "DoF-ordered" : "element-ordered", (long long)hp.na, (long long)nslot_used,
+              (int)hp.compact);
+}
+
+static void replay(const char *name, int p, int64_t nelem, const std::vector<int32_t> &dofs,
+                   const std::vector<uint8_t> &ess, int64_t ndof, bool expect_compact) {
+  replay1(name, p, nelem, dofs, ess, ndof, expect_compact, true);
+  replay1(name, p, nelem, dofs, ess, ndof, expect_compact, false);
 }
 
 int main() {
