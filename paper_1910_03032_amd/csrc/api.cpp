@@ -619,7 +619,7 @@ sfem_status sfem_setup(sfem_ctx *c, int p, int q, int64_t nelem, const double *e
     std::string err;
     // E-vector layout: DoF-ordered up to p = 4, element-ordered above (at high order the
     // scattered entry writes cost the element kernel more than the assembly saves)
-    const int rc = build_host_plan(p, nelem, dofs.data(), ndof, ess.data(), hp, err, p <= 4);
+    const int rc = build_host_plan(p, nelem, dofs.data(), ndof, ess.data(), hp, err, evec_dof_ordered(p));
     if (rc != 0) return fail(c, (sfem_status)rc, err);
   }
   const bool compact = hp.compact;

@@ -73,44 +73,39 @@ struct Per {
   static constexpr int NL = (Dims<P>::N3 + Dims<P>::TPE - 1) / Dims<P>::TPE;
 };
 
-// Gather the element's nodal values (essential DoFs as 0) into buf[k][j][i].  All map
-// loads of the thread are issued together, then all value loads.  Loads are
-// unconditional (an inactive slot reads a valid element's entries and discards them)
-// so that the compiler can batch them.  If smap is given (LDS), it receives for each
-// node the map entry of a sole or essential DoF, or the E-vector entry of a shared
-// node: from the element's row epos of the position table (read together with the
-// map) for the DoF-ordered E-vector, else ebase + r (element-ordered); sx (LDS,
-// optional) receives the raw x values.
-template <int P, typename T>
-__device__ __forceinline__ void gather_e(T *buf, int t, bool active, const int32_t *emap,
-                                         const T *__restrict__ xm, int32_t *smap = nullptr,
-                                         T *sx = nullptr, const int32_t *epos = nullptr,
-                                         int32_t ebase = 0, bool compact = true);
-
 // Rank of local node l among the element's surface nodes (a node with i, j or k in
 // {0, p}): face k = 0, face k = p, then for each interior k the ring of the (i, j)
-// square; -1 for an interior node.
+// square; -1 for an interior node.  Written with selects only (no branches).
 template <int P>
-__host__ __device__ constexpr int surf_rank(int l) {
-  constexpr int N = P + 1;
-  const int i = l % N, j = (l / N) % N, k = l / (N * N);
-  if (k == 0) return i + N * j;
-  if (k == P) return N * N + i + N * j;
-  const int base = 2 * N * N + (k - 1) * 4 * P;
-  if (j == 0) return base + i;
-  if (j == P) return base + N + i;
-  if (i == 0 || i == P) return base + 2 * N + 2 * (j - 1) + (i == 0 ? 0 : 1);
-  return -1;
+__host__ __device__ __forceinline__ int surf_rank(int l) {
+  constexpr unsigned N = P + 1, N2 = N * N;
+  const unsigned ul = (unsigned)l;
+  const unsigned k = ul / N2, rem = ul - k * N2, j = rem / N, i = rem - j * N;
+  const int base = (int)(2 * N2) + ((int)k - 1) * 4 * P;
+  const int ring = (j == 0) ? base + (int)i
+                   : (j == (unsigned)P) ? base + (int)(N + i)
+                                        : base + (int)(2 * N + 2 * (j - 1)) + (i == (unsigned)P ? 1 : 0);
+  const bool side = (i == 0) | (i == (unsigned)P) | (j == 0) | (j == (unsigned)P);
+  const bool face = (k == 0) | (k == (unsigned)P);
+  const int frank = (k == (unsigned)P ? (int)N2 : 0) + (int)rem;
+  return face ? frank : (side ? ring : -1);
 }
 template <int P>
 __host__ __device__ constexpr int surf_count() {
   return 2 * (P + 1) * (P + 1) + (P - 1) * 4 * P;
 }
 
-template <int P, typename T>
+// Gather the element's nodal values (essential DoFs as 0) into buf[k][j][i].  All map
+// loads of the thread are issued together, then all value loads.  Loads are
+// unconditional (an inactive slot reads a valid element's entries and discards them)
+// so that the compiler can batch them.  If smap is given (LDS), it receives each
+// node's map entry -- except, with POS (DoF-ordered E-vector), that a shared node gets
+// its E-vector entry from the element's row epos of the position table, read together
+// with the map.
+template <int P, typename T, bool POS = false>
 __device__ __forceinline__ void gather_e(T *buf, int t, bool active, const int32_t *emap,
-                                         const T *__restrict__ xm, int32_t *smap, T *sx,
-                                         const int32_t *epos, int32_t ebase, bool compact) {
+                                         const T *__restrict__ xm, int32_t *smap = nullptr,
+                                         const int32_t *epos = nullptr, bool compact = true) {
   using D = Dims<P>;
   constexpr int NL = Per<P>::NL;
   int32_t c[NL], q[NL];
@@ -119,8 +114,10 @@ __device__ __forceinline__ void gather_e(T *buf, int t, bool active, const int32
     const int l0 = t + k * D::TPE;
     const int l = l0 < D::N3 ? l0 : D::N3 - 1;
     c[k] = emap[l];
-    const int r = compact ? surf_rank<P>(l) : l;
-    q[k] = epos ? epos[r >= 0 ? r : 0] : ebase + r;
+    if constexpr (POS) {
+      const int r = compact ? surf_rank<P>(l) : l;
+      q[k] = epos[r >= 0 ? r : 0];
+    }
   }
   T v[NL];
 #pragma unroll
@@ -130,35 +127,49 @@ __device__ __forceinline__ void gather_e(T *buf, int t, bool active, const int32
     const int l = t + k * D::TPE;
     if (l < D::N3) {
       buf[l] = (active && c[k] >= 0) ? v[k] : T(0);
-      if (smap) smap[l] = (c[k] >= 0 && !(c[k] & kSoleBit)) ? q[k] : c[k];
-      if (sx) sx[l] = v[k];
+      if (smap) {
+        if constexpr (POS)
+          smap[l] = (c[k] >= 0 && !(c[k] & kSoleBit)) ? q[k] : c[k];
+        else
+          smap[l] = c[k];
+      }
     }
   }
   __syncthreads();
 }
 
-// Output of the element vector buf[l]: sole DoFs -> y, shared nodes -> their E-vector
-// entry, essential -> nothing.  The map entries / E-vector entries (and, with DOT, the
-// x values) come from LDS, kept by the gather.  With DOT, returns this thread's part of
-// sum x_g y_g over the sole DoFs.
-template <int P, typename T, bool DOT>
+// Output of the element vector buf[l] of element e: sole DoFs -> y, shared nodes ->
+// their E-vector entry (POS: the entry kept in smap by the gather; otherwise e * S + the
+// node's surface rank, or e * n^3 + l for the general layout), essential -> nothing.
+// The map entries come from LDS, kept by the gather.  With DOT, returns this thread's
+// part of sum x_g y_g over the sole DoFs (x read again from xm).
+template <int P, typename T, bool DOT, bool POS>
 __device__ __forceinline__ double emit_e(const T *buf, int t, bool active, const int32_t *smap,
-                                         const T *sx, T *__restrict__ Y, T *__restrict__ y) {
+                                         const T *__restrict__ xm, int64_t e, bool compact,
+                                         T *__restrict__ Y, T *__restrict__ y) {
   using D = Dims<P>;
   constexpr int NL = Per<P>::NL;
   double dot = 0.0;
 #pragma unroll
   for (int k = 0; k < NL; ++k) {
-    const int l = t + k * D::TPE;
-    if (!active || l >= D::N3) continue;
+    const int l0 = t + k * D::TPE;
+    const int l = l0 < D::N3 ? l0 : D::N3 - 1;
     const int32_t c = smap[l];
-    if (c < 0) continue;
     const T v = buf[l];
-    if (c & kSoleBit) {
-      y[c & kDofMask] = v;
-      if constexpr (DOT) dot += (double)sx[l] * (double)v;
-    } else {
-      Y[c] = v;
+    // one predicated store per node: the destination is selected, not branched to
+    const bool ok = active && l0 < D::N3 && c >= 0;
+    const bool sole = (c & kSoleBit) != 0;
+    const int32_t g = c & kDofMask;
+    int64_t ye;
+    if constexpr (POS)
+      ye = c;
+    else
+      ye = compact ? e * surf_count<P>() + surf_rank<P>(l) : e * D::N3 + l;
+    T *dst = sole ? y + g : Y + ye;
+    if (ok) *dst = v;
+    if constexpr (DOT) {
+      const T xv = xm[sole ? g : 0];  // in range for every entry
+      if (ok && sole) dot += (double)xv * (double)v;
     }
   }
   return dot;
@@ -351,20 +362,37 @@ __device__ __forceinline__ void bwd_x(T *buf, int t) {
   __syncthreads();
 }
 
-// Element index of this workgroup's first element such that XCD k (workgroups are
-// dispatched round-robin over the 8 XCDs) gets one contiguous range of blocks.
-__device__ __forceinline__ int64_t xcd_block(int64_t nblk) {
-  const int64_t b = blockIdx.x;
-  const int64_t xcd = b & 7, k = b >> 3;
-  const int64_t q8 = nblk >> 3, r8 = nblk & 7;
-  return xcd * q8 + (xcd < r8 ? xcd : r8) + k;
+// Index of the element batch of this workgroup such that XCD k (workgroups are
+// dispatched round-robin over the 8 XCDs) gets one contiguous range of batches.
+__device__ __forceinline__ int xcd_block() {
+  const unsigned nblk = gridDim.x, b = blockIdx.x;
+  const unsigned xcd = b & 7u, k = b >> 3;
+  const unsigned q8 = nblk >> 3, r8 = nblk & 7u;
+  return (int)(xcd * q8 + (xcd < r8 ? xcd : r8) + k);
 }
+
+// How the element kernel of order P and precision T feeds its xi_3 stage (chosen by
+// measurement on MI355X, see the design notes):
+//   ZLDS   the stage's input lines are read from LDS again for every slice pair instead
+//          of being held in registers for the whole stage (fewer registers);
+//   PRE_X, PRE_Y  slice pairs [0, PRE_X) of quadrature data are requested before the
+//          xi_1 contraction and [PRE_X, PRE_Y) before the xi_2 contraction;
+//   LA     in the xi_3 loop, pair c + LA is requested when pair c starts;
+//   OCC    minimum waves per SIMD the kernel is compiled for (launch bound).
+template <int P, typename T>
+struct ApplyCfg {
+  static constexpr bool F64 = sizeof(T) == 8;
+  static constexpr bool ZLDS = F64 ? (P >= 5) : (P == 6 || P == 8);
+  static constexpr bool AHEAD = F64 ? (P == 8) : (P == 6 || P == 8);
+  static constexpr int PRE_X = AHEAD ? 1 : 0, PRE_Y = 1, LA = AHEAD ? 1 : 0;
+  static constexpr int OCC = Dims<P>::OCC;
+};
 
 // OP: 0 mass, 1 diffusion, 2 helmholtz (matches sfem_op).  Writes y at the sole DoFs
 // and the E-vector Y[m] at the shared nodes; with part != null also the per-block sums
 // of x_g y_g over the sole DoFs (part[m * part_mstride + block]).
 template <int P, typename T, int OP>
-__global__ void __launch_bounds__(Dims<P>::THREADS, Dims<P>::OCC)
+__global__ void __launch_bounds__(Dims<P>::THREADS, (ApplyCfg<P, T>::OCC))
 apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
              int64_t qd_mstride, const T *__restrict__ nu, int64_t nu_mstride, int64_t nelem,
              int nbatch, int64_t ndof, const T *__restrict__ x, T *__restrict__ Y,
@@ -377,23 +405,29 @@ apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
   constexpr bool MASS = (OP == 0) || (OP == 2);
   constexpr bool DIFF = (OP == 1) || (OP == 2);
 
-  __shared__ T smem[E * D::BUF];
+  constexpr bool POS = evec_dof_ordered(P);
+  // element buffers; after the output step also the block sum of the fused dot product
+  // (E * BUF * sizeof(T) >= THREADS * 8 bytes)
+  static_assert(E * D::BUF * sizeof(T) >= D::THREADS * sizeof(double), "block sum space");
+  __shared__ __align__(16) T smem[E * D::BUF];
   __shared__ int32_t smap_all[E * N3];  // the elements' map entries, kept for the output
-  __shared__ T sx_all[E * N3];          // their x values (for the fused dot product)
-  __shared__ double red[Dims<P>::THREADS];  // block sum of the fused dot product
   const int le = threadIdx.x / TPE;
-  const int t = threadIdx.x - le * TPE;
-  const int64_t nblk = (nelem + E - 1) / E;
-  const int64_t e = xcd_block(nblk) * E + le;
+  const int t0 = threadIdx.x - le * TPE;
+  // the grid has one workgroup per batch of E elements (nelem < 2^31)
+  const int e = xcd_block() * E + le;
   const bool active = e < nelem;
-  const int64_t es = active ? e : 0;
+  const int es = active ? e : 0;
   T *buf = smem + le * D::BUF;
-  const int32_t *emap = map + es * (int64_t)N3;
 
   // Quadrature values one thread needs per slice c: w|J| (mass), the 6 entries of
   // w|J| J^-1 J^-T (diffusion), and nu for the diffusion operator.
   constexpr int NS = (OP == 0) ? 1 : (OP == 2 ? 7 : 7);
   for (int m = 0; m < nbatch; ++m) {
+    // Everything derived from the thread's place in the element (node indices, surface
+    // ranks, output addresses) is recomputed for each batch member: kept in registers
+    // across the member loop it would raise the register count of the whole pipeline.
+    int t = t0;
+    asm volatile("" : "+v"(t));
     const T *xm = x + (int64_t)m * ndof;
     const T *qe = qd + (int64_t)m * qd_mstride + es * (int64_t)(kQdSlots * Q3);
     const T *ne = nullptr;
@@ -414,14 +448,30 @@ apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
     };
 
     int32_t *smap = smap_all + le * N3;
-    T *sx = sx_all + le * N3;
+    // The map (and position) rows are read again for every batch member: held in
+    // registers across the member loop they would raise the register count of the
+    // whole element pipeline.
+    int64_t moff = (int64_t)es * N3;
+    asm volatile("" : "+v"(moff));
     const int64_t epe = compact ? surf_count<P>() : N3;
-    gather_e<P, T>(buf, t, active, emap, xm, smap, part ? sx : nullptr,
-                   pos ? pos + es * epe : nullptr, (int32_t)(es * epe), compact != 0);
+    gather_e<P, T, POS>(buf, t, active, map + moff, xm, smap,
+                        POS ? pos + (int64_t)es * epe : nullptr, compact != 0);
+    // quadrature data of slice pair c (slices c and q-1-c; the middle slice of an odd q
+    // alone), requested ahead of use as ApplyCfg sets
+    using C = ApplyCfg<P, T>;
+    constexpr int NPR = (Q + 1) / 2;
+    constexpr int PRE_X = C::PRE_X < NPR ? C::PRE_X : NPR;
+    constexpr int PRE_Y = C::PRE_Y < NPR ? C::PRE_Y : NPR;
+    T qlo[NPR][NS], qhi[NPR][NS];
+    auto load_pair = [&](int c) {
+      load_slice(qlo[c], c);
+      if (c != Q - 1 - c) load_slice(qhi[c], Q - 1 - c);
+    };
+#pragma unroll
+    for (int c = 0; c < PRE_X; ++c) load_pair(c);
     fwd_x<P, T, DIFF>(buf, t);
-    T pre0[NS], pre1[NS];  // quadrature data of the first slice pair, loaded early
-    load_slice(pre0, 0);
-    load_slice(pre1, Q - 1);
+#pragma unroll
+    for (int c = PRE_X; c < PRE_Y; ++c) load_pair(c);
     fwd_y<P, T, DIFF>(buf, t);
 
     // xi_3 contraction, quadrature function, transposed xi_3: thread = line (a, b),
@@ -429,14 +479,29 @@ apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
     {
       using BT = eo::Tab1<P, 0>;
       using GT = eo::Tab1<P, 1>;
-      T zbb[N], zgb[N], zbg[N];
-      load_z<P, T, DIFF>(buf, t, zbb, zgb, zbg);
-      const auto sbb = eo::split(zbb);
-      eo::Split<N, T> sgb{}, sbg{};
-      if constexpr (DIFF) {
-        sgb = eo::split(zgb);
-        sbg = eo::split(zbg);
-      }
+      // the stage's input lines (split into even and odd parts), held in registers or,
+      // with ZLDS, read from LDS again for every slice pair
+      eo::Split<N, T> rbb{}, rgb{}, rbg{};
+      auto read_lines = [&](eo::Split<N, T> &sbb, eo::Split<N, T> &sgb, eo::Split<N, T> &sbg) {
+        T zbb[N], zgb[N], zbg[N];
+        load_z<P, T, DIFF>(buf, t, zbb, zgb, zbg);
+        sbb = eo::split(zbb);
+        if constexpr (DIFF) {
+          sgb = eo::split(zgb);
+          sbg = eo::split(zbg);
+        }
+      };
+      if constexpr (!C::ZLDS) read_lines(rbb, rgb, rbg);
+      auto zlines = [&](eo::Split<N, T> &sbb, eo::Split<N, T> &sgb, eo::Split<N, T> &sbg) {
+        if constexpr (C::ZLDS) {
+          asm volatile("" ::: "memory");  // a fresh LDS read, not a reuse of the last one
+          read_lines(sbb, sgb, sbg);
+        } else {
+          sbb = rbb;
+          sgb = rgb;
+          sbg = rbg;
+        }
+      };
       eo::Acc<N, T> A1, A2, A3;
       A1.zero();
       A2.zero();
@@ -463,14 +528,12 @@ apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
       };
       auto qfun = [&](int c, T u, T dx, T dy, T dz, T &v, T &g1, T &g2, T &g3) {
         T cur[NS];
-        if (c == 0) {
-#pragma unroll
-          for (int z = 0; z < NS; ++z) cur[z] = pre0[z];
-        } else if (c == Q - 1) {
-#pragma unroll
-          for (int z = 0; z < NS; ++z) cur[z] = pre1[z];
+        const int pc = c <= Q - 1 - c ? c : Q - 1 - c;  // the slice's pair
+        if (C::LA == 0 && pc >= PRE_Y) {
+          load_slice(cur, c);  // not requested ahead: load at its use
         } else {
-          load_slice(cur, c);
+#pragma unroll
+          for (int z = 0; z < NS; ++z) cur[z] = (c == pc) ? qlo[pc][z] : qhi[pc][z];
         }
         v = g1 = g2 = g3 = T(0);
         if constexpr (MASS) v = cur[0] * u;
@@ -490,7 +553,10 @@ apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
       };
 #pragma unroll
       for (int c = 0; c < Q / 2; ++c) {
+        if (C::LA > 0 && c + C::LA >= PRE_Y && c + C::LA < NPR) load_pair(c + C::LA);
         T u0 = 0, u1 = 0, dx0 = 0, dx1 = 0, dy0 = 0, dy1 = 0, dz0 = 0, dz1 = 0;
+        eo::Split<N, T> sbb, sgb, sbg;
+        zlines(sbb, sgb, sbg);
         if constexpr (MASS) row_pair(BT{}, sbb, c, u0, u1);
         if constexpr (DIFF) {
           row_pair(GT{}, sbb, c, dz0, dz1);
@@ -509,6 +575,8 @@ apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
       }
       if constexpr (Q % 2 == 1) {
         T u = 0, dx = 0, dy = 0, dz = 0;
+        eo::Split<N, T> sbb, sgb, sbg;
+        zlines(sbb, sgb, sbg);
         if constexpr (MASS) u = row_mid(BT{}, sbb);
         if constexpr (DIFF) {
           dz = row_mid(GT{}, sbb);
@@ -545,13 +613,13 @@ apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
     bwd_y<P, T, DIFF>(buf, t);
     bwd_x<P, T, DIFF>(buf, t);
     if (part) {
-      const double dot = emit_e<P, T, true>(buf, t, active, smap, sx,
-                                            Y + (int64_t)m * estride, y + (int64_t)m * ndof);
-      const double sum = block_sum_d(dot, red);
+      const double dot = emit_e<P, T, true, POS>(buf, t, active, smap, xm, es, compact != 0,
+                                                 Y + (int64_t)m * estride, y + (int64_t)m * ndof);
+      const double sum = block_sum_d(dot, reinterpret_cast<double *>(smem));
       if (threadIdx.x == 0) part[(int64_t)m * part_mstride + blockIdx.x] = sum;
     } else {
-      emit_e<P, T, false>(buf, t, active, smap, sx, Y + (int64_t)m * estride,
-                          y + (int64_t)m * ndof);
+      emit_e<P, T, false, POS>(buf, t, active, smap, xm, es, compact != 0,
+                               Y + (int64_t)m * estride, y + (int64_t)m * ndof);
     }
     __syncthreads();
   }
@@ -561,6 +629,7 @@ template <int P, typename T>
 hipError_t launch_apply_pt(const ApplyArgs &a, hipStream_t s) {
   using D = Dims<P>;
   if (a.nelem <= 0 || a.nbatch <= 0) return hipSuccess;
+  if ((a.pos != nullptr) != evec_dof_ordered(P)) return hipErrorInvalidValue;
   dim3 grid((unsigned)((a.nelem + D::E - 1) / D::E));
   dim3 block(D::THREADS);
   const T *qd = (const T *)a.qd;

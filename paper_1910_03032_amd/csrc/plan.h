@@ -17,6 +17,12 @@ namespace sfem {
 constexpr int32_t kDofMask = 0x3fffffff;
 constexpr int32_t kSoleBit = 0x40000000;
 
+// E-vector layout used for order p (see HostPlan): DoF-ordered up to p = 4, where the
+// assembly kernel's share of the apply is largest; element-ordered above, where the
+// element kernel's scattered entry writes and the position table cost more than the
+// assembly saves.
+constexpr bool evec_dof_ordered(int p) { return p <= 4; }
+
 struct HostPlan {
   bool compact = true;         // E-vector holds the surface nodes only (S per element)
   int64_t epe = 0;             // E-vector entries per element (S or n^3)
