@@ -331,14 +331,20 @@ sfem_status check_op_batch(sfem_ctx *c, int op, int nbatch) {
   return SFEM_OK;
 }
 
-// Number of per-block dot partials one apply leaves per member (element kernel blocks
-// followed by assembly blocks).
-int apply_nparts(const sfem_ctx *c) {
-  const int n = c->p + 1, q = c->p + 2;
-  int e = 256 / (q * q);
-  if (e < 1) e = 1;
-  (void)n;
-  return (int)((c->nelem + e - 1) / e) + (c->na > 0 ? assemble_nblk(c->na) : 0);
+// Per-block dot partials of one apply, per member: the element kernel's blocks, then
+// the assembly's (which fold the element partials in, so that the apply's sum is the
+// sum of the assembly partials alone when there is an assembly phase).
+int apply_nparts_elem(const sfem_ctx *c, bool f32) {
+  const int e = f32 ? apply_group_elems_f32(c->p) : apply_group_elems_f64(c->p);
+  return (int)((c->nelem + e - 1) / e);
+}
+int apply_nparts(const sfem_ctx *c, bool f32) {
+  return apply_nparts_elem(c, f32) + (c->na > 0 ? assemble_nblk_dot(c->na) : 0);
+}
+// Offset and count of the partials that sum to the apply's x . y.
+int apply_final_off(const sfem_ctx *c, bool f32) { return c->na > 0 ? apply_nparts_elem(c, f32) : 0; }
+int apply_final_count(const sfem_ctx *c, bool f32) {
+  return c->na > 0 ? assemble_nblk_dot(c->na) : apply_nparts_elem(c, f32);
 }
 
 // Enqueue y = A x on the context stream (no argument checks).  With part != null the
@@ -350,8 +356,8 @@ sfem_status do_apply(sfem_ctx *c, int op, bool f32, int nbatch, const void *x, v
   const size_t esz = f32 ? sizeof(float) : sizeof(double);
   sfem_status st;
   if ((st = ensure_evec(c, (size_t)estride * nbatch * esz)) != SFEM_OK) return st;
-  const int nparts = apply_nparts(c);
-  const int nblk_a = c->na > 0 ? assemble_nblk(c->na) : 0;
+  const int nparts = apply_nparts(c, f32);
+  const int nblk_e = apply_nparts_elem(c, f32);
   ApplyArgs a;
   a.p = c->p;
   a.op = op;
@@ -384,13 +390,14 @@ sfem_status do_apply(sfem_ctx *c, int op, bool f32, int nbatch, const void *x, v
   }
   hipError_t e = f32 ? launch_apply_f32(a, c->stream) : launch_apply_f64(a, c->stream);
   if (e != hipSuccess) return fail(c, SFEM_E_HIP, std::string("apply launch: ") + hipGetErrorString(e));
-  double *pa = part ? part + (nparts - nblk_a) : nullptr;
+  double *pa = part ? part + nblk_e : nullptr;
   if (f32)
     e = launch_assemble<float>(c->plan, (const float *)c->evec.p, estride, (const float *)x, (float *)y,
-                               c->ndof, nbatch, kEssCopyX, pa, nparts, c->stream);
+                               c->ndof, nbatch, kEssCopyX, pa, nparts, c->stream, part, nblk_e);
   else
     e = launch_assemble<double>(c->plan, (const double *)c->evec.p, estride, (const double *)x,
-                                (double *)y, c->ndof, nbatch, kEssCopyX, pa, nparts, c->stream);
+                                (double *)y, c->ndof, nbatch, kEssCopyX, pa, nparts, c->stream, part,
+                                nblk_e);
   if (e != hipSuccess) return fail(c, SFEM_E_HIP, std::string("assembly launch: ") + hipGetErrorString(e));
   return SFEM_OK;
 }
@@ -441,7 +448,7 @@ struct PcgWork {
   T *r, *p, *w;
   double *part;   // vector-kernel partials [nb][5][nblk]
   double *dpart;  // p^T A p partials of the apply [nb][nparts]
-  PcgScalars *sc;
+  PcgScalars *sc;  // [2][nb]: the current and the next iteration's scalars
   int nblk, nparts;
 };
 
@@ -449,21 +456,21 @@ template <typename T>
 size_t pcg_work_bytes(const sfem_ctx *c, int64_t n, int nb) {
   const int nblk = vec_nblk(n);
   return 3 * align_up((size_t)n * nb * sizeof(T)) + align_up((size_t)nb * 5 * nblk * sizeof(double)) +
-         align_up((size_t)nb * apply_nparts(c) * sizeof(double)) +
-         align_up((size_t)nb * sizeof(PcgScalars));
+         align_up((size_t)nb * apply_nparts(c, sizeof(T) == 4) * sizeof(double)) +
+         align_up((size_t)2 * nb * sizeof(PcgScalars));
 }
 
 template <typename T>
 PcgWork<T> carve_pcg(const sfem_ctx *c, Carver &cv, int64_t n, int nb) {
   PcgWork<T> w;
   w.nblk = vec_nblk(n);
-  w.nparts = apply_nparts(c);
+  w.nparts = apply_nparts(c, sizeof(T) == 4);
   w.r = cv.take<T>(n * nb);
   w.p = cv.take<T>(n * nb);
   w.w = cv.take<T>(n * nb);
   w.part = cv.take<double>((int64_t)nb * 5 * w.nblk);
   w.dpart = cv.take<double>((int64_t)nb * w.nparts);
-  w.sc = cv.take<PcgScalars>(nb);
+  w.sc = cv.take<PcgScalars>(2 * (int64_t)nb);
   return w;
 }
 
@@ -484,8 +491,10 @@ sfem_status run_pcg(sfem_ctx *c, int op, int nb, const T *b, T *x, bool x0_zero,
   }
   HIPCHK(c, launch_pcg_init(w.part, w.nblk, nb, rtol, w.sc, s, nullspace, n));
   if (nullspace) HIPCHK(c, launch_zshift<T>(w.p, w.sc, n, nb, s));
+  int cur = 0;  // slot of the current scalars in w.sc
   auto all_done = [&]() -> sfem_status {
-    HIPCHK(c, hipMemcpyAsync(hs, w.sc, sizeof(PcgScalars) * nb, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(hs, w.sc + (int64_t)cur * nb, sizeof(PcgScalars) * nb,
+                             hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     return SFEM_OK;
   };
@@ -500,10 +509,14 @@ sfem_status run_pcg(sfem_ctx *c, int op, int nb, const T *b, T *x, bool x0_zero,
   if (!any_active()) return SFEM_OK;
   for (int it = 0; it < maxit; ++it) {
     if ((st = do_apply(c, op, f32, nb, w.p, w.w, w.dpart)) != SFEM_OK) return st;
-    HIPCHK(c, launch_pcg_alpha(w.dpart, w.nparts, nb, w.sc, s));
-    HIPCHK(c, VecOps<T>::update(x, w.p, w.r, w.w, dinv, dms, w.sc, w.part, w.nblk, n, nb, s));
-    HIPCHK(c, launch_pcg_beta(w.part, w.nblk, nb, w.sc, s, nullspace, n));
-    HIPCHK(c, VecOps<T>::newdir(w.r, dinv, dms, w.p, w.sc, n, nb, s));
+    const double *dp = w.dpart + apply_final_off(c, f32);
+    const int dcount = apply_final_count(c, f32);
+    PcgScalars *sc = w.sc + (int64_t)cur * nb, *sc_next = w.sc + (int64_t)(1 - cur) * nb;
+    HIPCHK(c, VecOps<T>::update(x, w.p, w.r, w.w, dinv, dms, sc, dp, w.nparts, dcount, w.part,
+                                w.nblk, n, nb, s));
+    HIPCHK(c, VecOps<T>::newdir(w.r, dinv, dms, w.p, sc, sc_next, dp, w.nparts, dcount, w.part,
+                                w.nblk, nullspace, n, nb, s));
+    cur = 1 - cur;
     if ((it + 1) % check_every == 0 || it + 1 == maxit) {
       if ((st = all_done()) != SFEM_OK) return st;
       if (!any_active()) break;

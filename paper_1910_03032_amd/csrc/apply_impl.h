@@ -75,20 +75,41 @@ struct Per {
 
 // Rank of local node l among the element's surface nodes (a node with i, j or k in
 // {0, p}): face k = 0, face k = p, then for each interior k the ring of the (i, j)
-// square; -1 for an interior node.  Written with selects only (no branches).
+// square; -1 for an interior node.  The ranks of all local nodes of order P form a
+// table in constant memory: one 2-byte load per node instead of index arithmetic.
 template <int P>
-__host__ __device__ __forceinline__ int surf_rank(int l) {
-  constexpr unsigned N = P + 1, N2 = N * N;
-  const unsigned ul = (unsigned)l;
-  const unsigned k = ul / N2, rem = ul - k * N2, j = rem / N, i = rem - j * N;
-  const int base = (int)(2 * N2) + ((int)k - 1) * 4 * P;
-  const int ring = (j == 0) ? base + (int)i
-                   : (j == (unsigned)P) ? base + (int)(N + i)
-                                        : base + (int)(2 * N + 2 * (j - 1)) + (i == (unsigned)P ? 1 : 0);
-  const bool side = (i == 0) | (i == (unsigned)P) | (j == 0) | (j == (unsigned)P);
-  const bool face = (k == 0) | (k == (unsigned)P);
-  const int frank = (k == (unsigned)P ? (int)N2 : 0) + (int)rem;
-  return face ? frank : (side ? ring : -1);
+struct RankTable {
+  int16_t r[(P + 1) * (P + 1) * (P + 1)];
+};
+template <int P>
+constexpr RankTable<P> make_rank_table() {
+  RankTable<P> t{};
+  constexpr int N = P + 1;
+  for (int l = 0; l < N * N * N; ++l) {
+    const int i = l % N, j = (l / N) % N, k = l / (N * N);
+    int r = -1;
+    if (k == 0) {
+      r = i + N * j;
+    } else if (k == P) {
+      r = N * N + i + N * j;
+    } else {
+      const int base = 2 * N * N + (k - 1) * 4 * P;
+      if (j == 0)
+        r = base + i;
+      else if (j == P)
+        r = base + N + i;
+      else if (i == 0 || i == P)
+        r = base + 2 * N + 2 * (j - 1) + (i == 0 ? 0 : 1);
+    }
+    t.r[l] = (int16_t)r;
+  }
+  return t;
+}
+template <int P>
+__constant__ RankTable<P> kRankTable = make_rank_table<P>();
+template <int P>
+__device__ __forceinline__ int surf_rank(int l) {
+  return kRankTable<P>.r[l];
 }
 template <int P>
 __host__ __device__ constexpr int surf_count() {
@@ -378,10 +399,15 @@ __device__ __forceinline__ int xcd_block() {
 //   PRE_X, PRE_Y  slice pairs [0, PRE_X) of quadrature data are requested before the
 //          xi_1 contraction and [PRE_X, PRE_Y) before the xi_2 contraction;
 //   LA     in the xi_3 loop, pair c + LA is requested when pair c starts;
-//   OCC    minimum waves per SIMD the kernel is compiled for (launch bound).
+//   OCC    minimum waves per SIMD the kernel is compiled for (launch bound);
+//   E      elements per workgroup (q^2 threads each).
 template <int P, typename T>
 struct ApplyCfg {
   static constexpr bool F64 = sizeof(T) == 8;
+  // (p = 8 with 5 elements per workgroup, 500 of 512 lanes busy instead of 200 of 256,
+  // measured 4 % slower in FP64: one workgroup per CU at its register count)
+  static constexpr int E = Dims<P>::E;
+  static constexpr int THREADS = E * Dims<P>::TPE;
   static constexpr bool ZLDS = F64 ? (P >= 5) : (P == 6 || P == 8);
   static constexpr bool AHEAD = F64 ? (P == 8) : (P == 6 || P == 8);
   static constexpr int PRE_X = AHEAD ? 1 : 0, PRE_Y = 1, LA = AHEAD ? 1 : 0;
@@ -392,7 +418,7 @@ struct ApplyCfg {
 // and the E-vector Y[m] at the shared nodes; with part != null also the per-block sums
 // of x_g y_g over the sole DoFs (part[m * part_mstride + block]).
 template <int P, typename T, int OP>
-__global__ void __launch_bounds__(Dims<P>::THREADS, (ApplyCfg<P, T>::OCC))
+__global__ void __launch_bounds__((ApplyCfg<P, T>::THREADS), (ApplyCfg<P, T>::OCC))
 apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
              int64_t qd_mstride, const T *__restrict__ nu, int64_t nu_mstride, int64_t nelem,
              int nbatch, int64_t ndof, const T *__restrict__ x, T *__restrict__ Y,
@@ -401,14 +427,14 @@ apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
              int64_t part_mstride) {
   using D = Dims<P>;
   constexpr int N = D::N, Q = D::Q, Q2 = D::Q2, Q3 = D::Q3, N3 = D::N3;
-  constexpr int TPE = D::TPE, E = D::E;
+  constexpr int TPE = D::TPE, E = ApplyCfg<P, T>::E, THREADS = ApplyCfg<P, T>::THREADS;
   constexpr bool MASS = (OP == 0) || (OP == 2);
   constexpr bool DIFF = (OP == 1) || (OP == 2);
 
   constexpr bool POS = evec_dof_ordered(P);
   // element buffers; after the output step also the block sum of the fused dot product
   // (E * BUF * sizeof(T) >= THREADS * 8 bytes)
-  static_assert(E * D::BUF * sizeof(T) >= D::THREADS * sizeof(double), "block sum space");
+  static_assert(E * D::BUF * sizeof(T) >= THREADS * sizeof(double), "block sum space");
   __shared__ __align__(16) T smem[E * D::BUF];
   __shared__ int32_t smap_all[E * N3];  // the elements' map entries, kept for the output
   const int le = threadIdx.x / TPE;
@@ -630,8 +656,9 @@ hipError_t launch_apply_pt(const ApplyArgs &a, hipStream_t s) {
   using D = Dims<P>;
   if (a.nelem <= 0 || a.nbatch <= 0) return hipSuccess;
   if ((a.pos != nullptr) != evec_dof_ordered(P)) return hipErrorInvalidValue;
-  dim3 grid((unsigned)((a.nelem + D::E - 1) / D::E));
-  dim3 block(D::THREADS);
+  using C = ApplyCfg<P, T>;
+  dim3 grid((unsigned)((a.nelem + C::E - 1) / C::E));
+  dim3 block(C::THREADS);
   const T *qd = (const T *)a.qd;
   const T *nu = (const T *)a.nu;
   const T *x = (const T *)a.x;
@@ -653,6 +680,12 @@ hipError_t launch_apply_pt(const ApplyArgs &a, hipStream_t s) {
   }
 #undef SFEM_APPLY_ARGS
   return hipGetLastError();
+}
+
+// Elements per workgroup of the apply kernel for order P and precision T.
+template <int P, typename T>
+int apply_group_elems_pt() {
+  return ApplyCfg<P, T>::E;
 }
 
 #define SFEM_DISPATCH_P(p, CALL) \

@@ -74,6 +74,9 @@ struct ApplyArgs {
 // Element phase of the apply over all elements (writes the E-vector).
 hipError_t launch_apply_f64(const ApplyArgs &a, hipStream_t s);
 hipError_t launch_apply_f32(const ApplyArgs &a, hipStream_t s);
+// elements per workgroup of the apply kernel (one dot partial per workgroup)
+int apply_group_elems_f64(int p);
+int apply_group_elems_f32(int p);
 // Assembly list on the device (see HostPlan): the assembled DoFs, ascending, the CSR
 // offsets of their contributions, and for the element-ordered E-vector the entries of
 // those contributions (slot == null: DoF-ordered, the entries are [aoff[i], aoff[i+1])).
@@ -85,12 +88,16 @@ struct AsmPlan {
 };
 // Assembly phase over the list: y[g] = sum of g's E-vector entries in element order;
 // essential DoFs get x[g], 1 or 0 per ess_kind.  With part != null also the per-block
-// sums of x_g y_g (part[m * part_mstride + block], assemble_nblk blocks).
+// sums of x_g y_g (part[m * part_mstride + block], assemble_nblk_dot blocks), each
+// including a fixed range of the ne element-kernel partials epart[m * part_mstride + i]:
+// the partials the assembly leaves are then the whole apply's.
+constexpr int kMaxParts = 1024;  // cap of the partial-sum count of a reduction
 int assemble_nblk(int64_t na);
+int assemble_nblk_dot(int64_t na);
 template <typename T>
 hipError_t launch_assemble(const AsmPlan &pl, const T *evec, int64_t estride, const T *x, T *y,
                            int64_t n, int nb, int ess_kind, double *part, int64_t part_mstride,
-                           hipStream_t s);
+                           hipStream_t s, const double *epart = nullptr, int ne = 0);
 
 struct DiagArgs {
   int p;
@@ -158,11 +165,17 @@ struct VecOps {
   // one vector shared by all members, or null for the all-ones vector)
   static hipError_t dot(const T *a, const T *c, int64_t c_mstride, double *part, int nblk,
                         int64_t n, int nb, hipStream_t s);
+  // One CG step after the apply w = A p, whose partial sums of p.Ap are dpart[m * dmstride
+  // + i], i < dcount: update forms alpha and updates x and r, leaving the partials of
+  // r.z, r.r, sum z, sum r in part ([nb][4][nblk]); newdir forms beta from them, updates
+  // p and writes the next scalars to sc_next (the scalars are double-buffered).
   static hipError_t update(T *x, const T *p, T *r, const T *w, const T *dinv, int64_t dms,
-                           const PcgScalars *sc, double *part, int nblk, int64_t n, int nb,
-                           hipStream_t s);
+                           const PcgScalars *sc, const double *dpart, int64_t dmstride,
+                           int dcount, double *part, int nblk, int64_t n, int nb, hipStream_t s);
   static hipError_t newdir(const T *r, const T *dinv, int64_t dms, T *p, const PcgScalars *sc,
-                           int64_t n, int nb, hipStream_t s);
+                           PcgScalars *sc_next, const double *dpart, int64_t dmstride, int dcount,
+                           const double *upart, int unblk, int nullspace, int64_t n, int nb,
+                           hipStream_t s);
   static hipError_t fill(T *p, T v, int64_t n, hipStream_t s);
   static hipError_t recip(const double *d, T *out, int64_t n, hipStream_t s);
 };
@@ -174,9 +187,6 @@ hipError_t launch_sub_norm(const double *b, const double *w, double *r, double *
 // z - mean(z) 1, and rho = r^T z of that vector (Section 5.3).
 hipError_t launch_pcg_init(const double *part, int nblk, int nb, double rtol, PcgScalars *sc,
                            hipStream_t s, int nullspace = 0, int64_t n = 0);
-hipError_t launch_pcg_alpha(const double *part, int nblk, int nb, PcgScalars *sc, hipStream_t s);
-hipError_t launch_pcg_beta(const double *part, int nblk, int nb, PcgScalars *sc, hipStream_t s,
-                           int nullspace = 0, int64_t n = 0);
 // v[m][i] -= sc[m].zshift (the initial direction of a null-space solve)
 template <typename T>
 hipError_t launch_zshift(T *v, const PcgScalars *sc, int64_t n, int nb, hipStream_t s);

@@ -9,4 +9,10 @@ hipError_t launch_apply_f64(const ApplyArgs &a, hipStream_t s) {
 #undef SFEM_CALL
 }
 
+int apply_group_elems_f64(int p) {
+#define SFEM_CALL(P) apply_group_elems_pt<P, double>()
+  SFEM_DISPATCH_P(p, SFEM_CALL)
+#undef SFEM_CALL
+}
+
 }  // namespace sfem

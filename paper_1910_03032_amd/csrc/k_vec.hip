@@ -155,43 +155,82 @@ __global__ void dot_kernel(const T *__restrict__ a, const T *__restrict__ c, int
   write_part<1>(v, part, nblk);
 }
 
-// x += alpha p; r -= alpha w; partials: r.z, r.r, sum z, sum r (z = dinv r)
+// The step length of the current iteration from the scalars sc (rho, active) and the
+// apply's partial sums of p.Ap (member m: dpart[m * dmstride + i], i < dcount), summed
+// in a fixed order by every block that needs it -- the same value in each.
+__device__ __forceinline__ double step_alpha(const PcgScalars &s, double pw) {
+  return (s.active && isfinite(pw) && pw > 0.0) ? s.rho / pw : 0.0;
+}
+
+// x += alpha p; r -= alpha w; partials: r.z, r.r, sum z, sum r (z = dinv r).  alpha is
+// formed by every block from the apply's partials.
 template <typename T>
 __global__ void update_kernel(T *__restrict__ x, const T *__restrict__ p, T *__restrict__ r,
                               const T *__restrict__ w, const T *__restrict__ dinv,
                               int64_t dinv_mstride, const PcgScalars *__restrict__ sc,
+                              const double *__restrict__ dpart, int64_t dmstride, int dcount,
                               double *__restrict__ part, int nblk, int64_t n) {
   const int m = blockIdx.y;
   const int64_t off = (int64_t)m * n;
   const T *dm = dinv + (int64_t)m * dinv_mstride;
-  const T alpha = (T)sc[m].alpha;
+  // the operands of the first entry are requested before the partial sums are read
+  const int64_t i0 = (int64_t)blockIdx.x * VB + threadIdx.x, stride = (int64_t)nblk * VB;
+  const bool has0 = i0 < n;
+  const int64_t j0 = has0 ? i0 : 0;
+  const T x0 = x[off + j0], p0 = p[off + j0], r0 = r[off + j0], w0 = w[off + j0], d0 = dm[j0];
+  double pw[1];
+  reduce_parts_m<1, VB>(dpart + (int64_t)m * dmstride, dcount, 0, pw);
+  const T alpha = (T)step_alpha(sc[m], pw[0]);
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)nblk * VB) {
-    x[off + i] += alpha * p[off + i];
-    const T ri = r[off + i] - alpha * w[off + i];
+  auto step = [&](int64_t i, T xi, T pi, T ri, T wi, T di) {
+    x[off + i] = xi + alpha * pi;
+    ri = ri - alpha * wi;
     r[off + i] = ri;
-    const T zi = dm[i] * ri;
+    const T zi = di * ri;
     v[0] += (double)ri * (double)zi;
     v[1] += (double)ri * (double)ri;
     v[2] += (double)zi;
     v[3] += (double)ri;
-  }
+  };
+  if (has0) step(i0, x0, p0, r0, w0, d0);
+  for (int64_t i = i0 + stride; i < n; i += stride)
+    step(i, x[off + i], p[off + i], r[off + i], w[off + i], dm[i]);
   write_part<4>(v, part, nblk);
 }
 
-// p = (dinv r - zshift) + beta p
+// New direction p = (dinv r - zshift) + beta p, with beta (and the null-space shift)
+// formed by every block from the update's partials.  Block 0 of each member also
+// writes the next iteration's scalars to sc_next (the scalars are double-buffered, so
+// no block reads a value another block of the same launch writes).
 template <typename T>
 __global__ void newdir_kernel(const T *__restrict__ r, const T *__restrict__ dinv,
                               int64_t dinv_mstride, T *__restrict__ p,
-                              const PcgScalars *__restrict__ sc, int64_t n) {
+                              const PcgScalars *__restrict__ sc, PcgScalars *__restrict__ sc_next,
+                              const double *__restrict__ dpart, int64_t dmstride, int dcount,
+                              const double *__restrict__ upart, int unblk, int nullspace,
+                              int64_t n) {
   const int m = blockIdx.y;
   const int64_t off = (int64_t)m * n;
   const T *dm = dinv + (int64_t)m * dinv_mstride;
-  const T beta = (T)sc[m].beta;
-  const T zs = (T)sc[m].zshift;
-  for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * VB)
-    p[off + i] = (dm[i] * r[off + i] - zs) + beta * p[off + i];
+  // the operands of the first entry are requested before the partial sums are read
+  const int64_t i0 = (int64_t)blockIdx.x * VB + threadIdx.x, stride = (int64_t)gridDim.x * VB;
+  const bool has0 = i0 < n;
+  const int64_t j0 = has0 ? i0 : 0;
+  const T r0 = r[off + j0], d0 = dm[j0], p0 = p[off + j0];
+  double pw[1], u[4];
+  reduce_parts_m<1, VB>(dpart + (int64_t)m * dmstride, dcount, 0, pw);
+  reduce_parts_m<4, VB>(upart, unblk, m, u);
+  PcgScalars s = sc[m];
+  set_alpha(s, pw[0]);
+  const double zs = nullspace ? u[2] / (double)n : 0.0;
+  if (s.active) s.zshift = zs;
+  set_beta(s, u[0] - zs * u[3], u[1]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc_next[m] = s;
+  const T beta = (T)s.beta;
+  const T zst = (T)s.zshift;
+  if (has0) p[off + i0] = (d0 * r0 - zst) + beta * p0;
+  for (int64_t i = i0 + stride; i < n; i += stride)
+    p[off + i] = (dm[i] * r[off + i] - zst) + beta * p[off + i];
 }
 
 // r = b - w with partial r.r (w may be null: r = b); r may be null (norm only)
@@ -226,25 +265,6 @@ __global__ void __launch_bounds__(RB) init_scalars_kernel(const double *__restri
     const bool finite = isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]);
     s.status = finite ? 0 : SFEM_E_NAN;
     s.active = (finite && v[2] > 0.0 && v[1] > s.tol2) ? 1 : 0;
-  }
-}
-
-__global__ void __launch_bounds__(RB) alpha_kernel(const double *__restrict__ part, int nblk,
-                                                   PcgScalars *__restrict__ sc) {
-  double v[1];
-  reduce_parts<1>(part, nblk, v);
-  if (threadIdx.x == 0) set_alpha(sc[blockIdx.x], v[0]);
-}
-
-__global__ void __launch_bounds__(RB) beta_kernel(const double *__restrict__ part, int nblk,
-                                                  PcgScalars *__restrict__ sc, int nullspace, int64_t n) {
-  double v[4];
-  reduce_parts<4>(part, nblk, v);
-  if (threadIdx.x == 0) {
-    PcgScalars &s = sc[blockIdx.x];
-    const double zs = nullspace ? v[2] / (double)n : 0.0;
-    if (s.active) s.zshift = zs;
-    set_beta(s, v[0] - zs * v[3], v[1]);
   }
 }
 
@@ -327,7 +347,7 @@ template <typename T, bool DOT>
 __global__ void __launch_bounds__(VB)
 assemble_kernel(AsmPlan pl, const T *__restrict__ Y, int64_t estride, const T *__restrict__ x,
                 T *__restrict__ y, int64_t n, int ess_kind, double *__restrict__ part,
-                int64_t part_mstride, int nblk) {
+                int64_t part_mstride, int nblk, const double *__restrict__ epart, int ne) {
   const int mb = blockIdx.y;
   const T *Ym = Y + (int64_t)mb * estride;
   const T *xm = x ? x + (int64_t)mb * n : nullptr;
@@ -369,6 +389,12 @@ assemble_kernel(AsmPlan pl, const T *__restrict__ Y, int64_t estride, const T *_
     }
   }
   if constexpr (DOT) {
+    // this block's share of the element kernel's partial sums (a fixed range), so that
+    // the apply leaves one partial per assembly block
+    const double *ep = epart + (int64_t)mb * part_mstride;
+    const int lo = (int)((int64_t)ne * blockIdx.x / nblk);
+    const int hi = (int)((int64_t)ne * (blockIdx.x + 1) / nblk);
+    for (int i = lo + (int)threadIdx.x; i < hi; i += VB) v[0] += ep[i];
     block_sum<1>(v);
     if (threadIdx.x == 0) part[(int64_t)mb * part_mstride + blockIdx.x] = v[0];
   }
@@ -405,10 +431,15 @@ int assemble_nblk(int64_t na) {
 }
 
 
+int assemble_nblk_dot(int64_t na) {
+  const int b = assemble_nblk(na);
+  return b < kMaxParts ? b : kMaxParts;
+}
+
 int vec_nblk(int64_t n) {
   int64_t b = (n + VB * 2 - 1) / (VB * 2);
   if (b < 1) b = 1;
-  if (b > 8192) b = 8192;
+  if (b > kMaxParts) b = kMaxParts;
   return (int)b;
 }
 
@@ -429,18 +460,21 @@ hipError_t VecOps<T>::dot(const T *a, const T *c, int64_t c_mstride, double *par
 
 template <typename T>
 hipError_t VecOps<T>::update(T *x, const T *p, T *r, const T *w, const T *dinv, int64_t dms,
-                             const PcgScalars *sc, double *part, int nblk, int64_t n, int nb,
+                             const PcgScalars *sc, const double *dpart, int64_t dmstride,
+                             int dcount, double *part, int nblk, int64_t n, int nb,
                              hipStream_t s) {
   hipLaunchKernelGGL((update_kernel<T>), dim3(nblk, nb), dim3(VB), 0, s, x, p, r, w, dinv, dms, sc,
-                     part, nblk, n);
+                     dpart, dmstride, dcount, part, nblk, n);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t VecOps<T>::newdir(const T *r, const T *dinv, int64_t dms, T *p, const PcgScalars *sc,
-                             int64_t n, int nb, hipStream_t s) {
-  hipLaunchKernelGGL((newdir_kernel<T>), dim3(grid_for(n), nb), dim3(VB), 0, s, r, dinv, dms, p, sc,
-                     n);
+                             PcgScalars *sc_next, const double *dpart, int64_t dmstride,
+                             int dcount, const double *upart, int unblk, int nullspace, int64_t n,
+                             int nb, hipStream_t s) {
+  hipLaunchKernelGGL((newdir_kernel<T>), dim3(vec_nblk(n), nb), dim3(VB), 0, s, r, dinv, dms, p, sc,
+                     sc_next, dpart, dmstride, dcount, upart, unblk, nullspace, n);
   return hipGetLastError();
 }
 
@@ -461,22 +495,23 @@ hipError_t VecOps<T>::recip(const double *d, T *out, int64_t n, hipStream_t s) {
 template <typename T>
 hipError_t launch_assemble(const AsmPlan &pl, const T *evec, int64_t estride, const T *x, T *y,
                            int64_t n, int nb, int ess_kind, double *part, int64_t part_mstride,
-                           hipStream_t s) {
+                           hipStream_t s, const double *epart, int ne) {
   if (pl.na <= 0 || nb <= 0) return hipSuccess;
-  const int nblk = assemble_nblk(pl.na);
+  const int nblk = part ? assemble_nblk_dot(pl.na) : assemble_nblk(pl.na);
   if (part)
     hipLaunchKernelGGL((assemble_kernel<T, true>), dim3(nblk, nb), dim3(VB), 0, s, pl, evec, estride,
-                       x, y, n, ess_kind, part, part_mstride, nblk);
+                       x, y, n, ess_kind, part, part_mstride, nblk, epart, ne);
   else
     hipLaunchKernelGGL((assemble_kernel<T, false>), dim3(nblk, nb), dim3(VB), 0, s, pl, evec, estride,
-                       x, y, n, ess_kind, part, part_mstride, nblk);
+                       x, y, n, ess_kind, part, part_mstride, nblk, epart, ne);
   return hipGetLastError();
 }
 template hipError_t launch_assemble<double>(const AsmPlan &, const double *, int64_t, const double *,
                                             double *, int64_t, int, int, double *, int64_t,
-                                            hipStream_t);
+                                            hipStream_t, const double *, int);
 template hipError_t launch_assemble<float>(const AsmPlan &, const float *, int64_t, const float *,
-                                           float *, int64_t, int, int, double *, int64_t, hipStream_t);
+                                           float *, int64_t, int, int, double *, int64_t, hipStream_t,
+                                           const double *, int);
 
 template struct VecOps<double>;
 template struct VecOps<float>;
@@ -490,17 +525,6 @@ hipError_t launch_sub_norm(const double *b, const double *w, double *r, double *
 hipError_t launch_pcg_init(const double *part, int nblk, int nb, double rtol, PcgScalars *sc,
                            hipStream_t s, int nullspace, int64_t n) {
   hipLaunchKernelGGL(init_scalars_kernel, dim3(nb), dim3(RB), 0, s, part, nblk, rtol, sc, nullspace, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_pcg_alpha(const double *part, int nblk, int nb, PcgScalars *sc, hipStream_t s) {
-  hipLaunchKernelGGL(alpha_kernel, dim3(nb), dim3(RB), 0, s, part, nblk, sc);
-  return hipGetLastError();
-}
-
-hipError_t launch_pcg_beta(const double *part, int nblk, int nb, PcgScalars *sc, hipStream_t s,
-                           int nullspace, int64_t n) {
-  hipLaunchKernelGGL(beta_kernel, dim3(nb), dim3(RB), 0, s, part, nblk, sc, nullspace, n);
   return hipGetLastError();
 }
 

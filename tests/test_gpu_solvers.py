@@ -7,7 +7,7 @@ import scipy.sparse.linalg as spla
 import torch
 
 from gpu_common import case, gpu, host, rel, say, nu_c2_gpu
-from oracle import pcg as oracle_pcg, adjoint_gradient
+from oracle import Discretization, pcg as oracle_pcg, adjoint_gradient
 from workloads import rhs_uniform, nu_uniform, f_manufactured, u_manufactured, uniform
 
 pytestmark = pytest.mark.gpu
@@ -252,3 +252,31 @@ def test_empty_inputs():
     m, d, op = case(2, 1)
     e = torch.empty(0, m.ndof, dtype=torch.float64, device="cuda")
     assert op.apply(e, op=2).shape == (0, m.ndof)
+
+
+@pytest.mark.parametrize("p", [2, 8])
+def test_pcg_disjoint_elements_without_assembly_phase(p):
+    """Elements that share no DoF and no essential DoFs: the apply has no assembly phase,
+    so the CG step length is summed from the element kernel's partials directly.
+    Helmholtz solves (FP64 and FP32+IR) against a sparse direct solve of the oracle's
+    matrix."""
+    from paper_1910_03032_amd import Operator
+    from workloads import BoxMesh
+    m = BoxMesh(2, p, seed=4)
+    n3 = (p + 1) ** 3
+    dofs = np.arange(m.nelem * n3, dtype=np.int32).reshape(m.nelem, n3)
+    ndof = int(dofs.size)
+    ess = np.zeros(ndof, dtype=np.uint8)
+    d = Discretization(m.elem_xyz, dofs, ess, ndof, p, p + 2)
+    op = Operator(m.elem_xyz, dofs, ndof, p, ess=ess)
+    assert op.info()["nassembled"] == 0
+    nu = nu_uniform(m.nelem, d.q, seed=2)
+    op.set_coeffs(1e2, 1.0, gpu(nu))
+    b = uniform(ndof, seed=1)
+    xd = spla.spsolve(d.assemble(1e2, 1.0, nu).tocsc(), b)
+    for mode in (0, 1):
+        x, res = op.pcg(gpu(b), rtol=1e-11, mode=mode, check_every=1)
+        say(f"  p={p} mode={mode}: {res}")
+        assert res.converged and res.true_rel_res[0] <= 1e-10
+        assert rel(host(x), xd) <= 1e-8
+    op.close()
