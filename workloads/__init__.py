@@ -100,6 +100,26 @@ class BoxMesh:
         return g % self.n1, (g // self.n1) % self.n1, g // (self.n1 * self.n1)
 
 
+class TaylorHoodMesh:
+    """Velocity (order p) and pressure (order p - 1) DoF maps on one ``ne^3`` box mesh.
+
+    vel: the order-p BoxMesh (with its boundary mask, the velocity Dirichlet DoFs);
+    pres_dofs [NE, p^3] int32 and npres: the order-(p-1) map of the same elements,
+    numbered like BoxMesh (no essential pressure DoFs).
+    """
+
+    def __init__(self, ne: int, p: int, amp: float = 0.1, seed: int = SEED_MESH):
+        if p < 2:
+            raise ValueError("the Taylor-Hood pair needs p >= 2")
+        self.vel = BoxMesh(ne, p, amp=amp, seed=seed)
+        pm = BoxMesh(ne, p - 1, amp=amp, seed=seed)
+        if not np.array_equal(pm.elem_xyz, self.vel.elem_xyz):
+            raise AssertionError("velocity and pressure meshes differ")
+        self.pres_dofs = pm.elem_dofs
+        self.npres = pm.ndof
+        self.ne, self.p, self.nelem = ne, p, self.vel.nelem
+
+
 class FanMesh:
     """An unstructured hex mesh: ``nsect`` kite-shaped columns around the z axis, each
     split into ``nlayer`` layers on z in [0, 1], so that the nodes on the axis are
