@@ -13,6 +13,7 @@ Jacobi-PCG solve and the FP32-inner iterative-refinement solve to relative resid
 the same workload.  Prints one JSON line.
 
 Other workloads (`--workload`): vector_helmholtz_p7_24e, adjoint_p5_20e, large_p8_40e,
+stokes_32e (Taylor-Hood block operator apply, 32^3 hexes, p = 2..6),
 poisson_p2_4e, `sweep` (FP64/FP32 apply for p = 4..8 on meshes of 15-33M DoFs) and
 `mass_neumann` (collocated-mass-preconditioned mass solve and pure-Neumann Poisson solve).
 """
@@ -436,6 +437,58 @@ def run_sweep(a):
     return {"workload": "sweep", "rows": rows}
 
 
+def stokes_bytes(nelem, p, nv, npres):
+    """Bytes a Stokes block apply must move: the folded Helmholtz factors (7 per point) and
+    the coupling factors (9 per point) once, u and p read and y_u, y_p written once, both
+    element->DoF maps once."""
+    q = p + 2
+    return nelem * q ** 3 * (7 + 9) * 8 + 2 * (3 * nv + npres) * 8 + nelem * ((p + 1) ** 3 + p ** 3) * 4
+
+
+def run_stokes(a):
+    """Taylor-Hood Stokes block operator apply (velocity Q_p, pressure Q_{p-1}) on 32^3
+    hexes for p = 2..6: y_u = H u + G p, y_p = -D u with H = 1e3 M + K(nu)."""
+    import torch
+    from paper_1910_03032_amd import Operator
+    from workloads import TaylorHoodMesh, normal, nu_c2
+    rows = []
+    for p in (2, 3, 4, 5, 6):
+        m = TaylorHoodMesh(32, p)
+        v = m.vel
+        op = Operator(v.elem_xyz, v.elem_dofs, v.ndof, p, ess=v.ess)
+        xq = op.qpoint_coords()
+        op.set_coeffs(1e3, 1.0, nu_c2(xq[0], xq[1], xq[2]))
+        op.setup_pressure(m.pres_dofs, m.npres)
+        dev = torch.device("cuda", 0)
+        u = torch.as_tensor(normal(3 * v.ndof, seed=1), device=dev).reshape(3, -1)
+        pres = torch.as_tensor(normal(m.npres, seed=2), device=dev)
+        for _ in range(a.warmup):
+            op.stokes_apply(u, pres)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        stream = torch.cuda.current_stream()
+        e0.record(stream)
+        for _ in range(a.steps):
+            op.stokes_apply(u, pres)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / a.steps
+        ndof = 3 * v.ndof + m.npres
+        nbytes = stokes_bytes(v.nelem, p, v.ndof, m.npres)
+        row = {"p": p, "elements": "32^3", "velocity_dofs": 3 * v.ndof, "pressure_dofs": m.npres,
+               "us": round(ms * 1e3, 2), "GDoF/s": round(ndof / (ms * 1e-3) / 1e9, 3),
+               "algorithmic_bytes": nbytes,
+               "algorithmic_GBps": round(nbytes / (ms * 1e-3) / 1e9, 1),
+               "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        rows.append(row)
+        log(f"[bench] stokes p={p}: {row['us']} us, {row['GDoF/s']} GDoF/s, {row['hbm_frac']:.3f} of HBM")
+        op.close()
+        del op
+        torch.cuda.empty_cache()
+    return {"workload": "stokes_32e", "rows": rows}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -452,6 +505,8 @@ def main():
         out = run_sweep(a)
     elif a.workload == "mass_neumann":
         out = run_mass_neumann(a)
+    elif a.workload == "stokes_32e":
+        out = run_stokes(a)
     else:
         wl = WORKLOADS[a.workload]
         if a.workload == "vector_helmholtz_p7_24e":

@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define SFEM_ABI_VERSION 2
+#define SFEM_ABI_VERSION 3
 #define SFEM_MAX_P 8
 
 typedef struct sfem_ctx sfem_ctx;
@@ -190,6 +190,27 @@ sfem_status sfem_pcg(sfem_ctx *ctx, int op, int nbatch, const double *b, double 
  * so that dJ/dnu_q = g_q when A(nu) u = b and A lam = dJ/du.
  * u, lam: [nbatch][ndof] float64; g: [nbatch][nelem * q^3] float64 (device). */
 sfem_status sfem_grad_nu(sfem_ctx *ctx, int nbatch, const double *u, const double *lam, double *g);
+
+/* Taylor-Hood pressure space for the Stokes blocks (Section 3: velocity (Q_p)^3, pressure
+ * Q_{p-1}, nodal GLL bases; p >= 2): the order-(p-1) element->DoF map of the same elements
+ * as sfem_setup, pres_dofs [nelem][p^3] int32 (device, local l = i + p (j + p k)), with
+ * npres pressure DoFs; the pressure space has no essential DoFs.  Also stores the
+ * coupling factors w |J| J^{-T} at the quadrature points.  Once per sfem_setup.
+ * Errors: SFEM_E_UNSUPPORTED for p < 2, SFEM_E_MESH for an invalid map, SFEM_E_STATE
+ * before sfem_setup or when called twice. */
+sfem_status sfem_setup_pressure(sfem_ctx *ctx, const int32_t *pres_dofs, int64_t npres);
+
+/* Constrained Stokes block operator of one implicit stage (eq. unsteadyStokesDiscrete,
+ * with the coefficients of sfem_set_coeffs, one nu field: H = alpha M + beta K(nu) on each
+ * velocity component):
+ *   y_u = P H P u + (I - P) u + P G p,    y_p = -D P u,
+ * G and D the gradient and divergence blocks (eq. gradient, eq. divergence), P zeroing
+ * the essential velocity DoFs.  u, y_u: [3][ndof] float64 (component-major); p, y_p:
+ * [npres] float64 (device).  Asynchronous on the context stream.  Errors: SFEM_E_STATE
+ * before sfem_setup_pressure, SFEM_E_ARG for NULL or aliased arrays or several nu
+ * fields. */
+sfem_status sfem_stokes_apply(sfem_ctx *ctx, const double *u, const double *p, double *yu,
+                              double *yp);
 
 typedef struct {
   int p, q;

@@ -180,6 +180,31 @@ class Operator:
         self._check(self._lib.sfem_grad_nu(self._h, nb, _ptr(uu), _ptr(ll), _ptr(g)))
         return g[0] if uu.ndim == 1 else g
 
+    def setup_pressure(self, pres_dofs, npres):
+        """Taylor-Hood pressure space (order p - 1) on the same elements: pres_dofs
+        [nelem, p^3] int32 (local l = i + p (j + p k)), npres DoFs (no essential DoFs)."""
+        self._sync_stream()
+        d = torch.as_tensor(pres_dofs).to(device=self.device, dtype=torch.int32).contiguous()
+        if d.numel() != self.nelem * self.p ** 3:
+            raise ValueError("pres_dofs must hold nelem * p^3 entries")
+        self._check(self._lib.sfem_setup_pressure(self._h, _ptr(d), int(npres)))
+        self.npres = int(npres)
+
+    def stokes_apply(self, u, pres):
+        """Constrained Stokes block operator: (y_u [3, ndof], y_p [npres]) for u [3, ndof],
+        pres [npres] (float64), with the Helmholtz coefficients of set_coeffs."""
+        self._sync_stream()
+        uu = self._vec(u, torch.float64, "u")
+        if uu.ndim != 2 or uu.shape[0] != 3:
+            raise ValueError("u must have shape [3, ndof]")
+        pp = torch.as_tensor(pres).to(device=self.device, dtype=torch.float64).contiguous()
+        if pp.numel() != getattr(self, "npres", -1):
+            raise ValueError("pres must hold npres values (call setup_pressure first)")
+        yu = torch.empty_like(uu)
+        yp = torch.empty_like(pp)
+        self._check(self._lib.sfem_stokes_apply(self._h, _ptr(uu), _ptr(pp), _ptr(yu), _ptr(yp)))
+        return yu, yp
+
     def collocated_mass(self):
         """Collocated (GLL-integrated) mass diagonal [ndof], essential entries 1 (float64)."""
         self._sync_stream()

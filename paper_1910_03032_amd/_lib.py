@@ -22,6 +22,7 @@ EXPORTED = [
     "sfem_abi_version", "sfem_create", "sfem_destroy", "sfem_set_stream", "sfem_last_error",
     "sfem_setup", "sfem_qpoint_coords", "sfem_set_coeffs", "sfem_apply", "sfem_diagonal",
     "sfem_load", "sfem_collocated_mass", "sfem_pcg", "sfem_grad_nu", "sfem_get_info",
+    "sfem_setup_pressure", "sfem_stokes_apply",
 ]
 
 
@@ -76,6 +77,8 @@ def load(path: str = LIB_PATH):
         "sfem_pcg": (i32, [vp, i32, i32, vp, vp, C.POINTER(PcgOpts), C.POINTER(PcgInfo)]),
         "sfem_grad_nu": (i32, [vp, i32, vp, vp, vp]),
         "sfem_get_info": (i32, [vp, C.POINTER(CtxInfo)]),
+        "sfem_setup_pressure": (i32, [vp, vp, i64]),
+        "sfem_stokes_apply": (i32, [vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -28,6 +28,7 @@ SOURCES = [
     "k_grad_load.hip",
     "k_setup.hip",
     "k_vec.hip",
+    "k_stokes.hip",
     "rules.cpp",
     "plan.cpp",
     "api.cpp",

@@ -57,6 +57,14 @@ struct sfem_ctx {
   double *d_m1 = nullptr;          // M 1 (the integral of a DoF vector is m1^T x)
   double m1sum = 0.0;              // 1^T M 1 = |Omega| (no essential DoFs)
   AsmPlan plan{};                  // the three arrays above, for the assembly kernel
+  // Taylor-Hood pressure space (order p - 1) and the Stokes coupling factors
+  bool pres_ready = false;
+  int64_t npres = 0;
+  int32_t *d_pmap = nullptr;       // [nelem][p^3] flagged pressure map
+  int pcompact = 0;
+  int64_t pnentries = 0;           // pressure E-vector entries (element-ordered)
+  AsmPlan pplan{};
+  double *d_cq = nullptr;          // [nelem][9][q^3] coupling factors w |J| J^{-T}
 
   // ---- coefficients
   double alpha = 1.0, beta = 1.0;
@@ -177,6 +185,13 @@ void free_all(sfem_ctx *c) {
   c->m1sum = 0.0;
   c->plan = AsmPlan{};
   c->na = 0;
+  c->pres_ready = false;
+  c->npres = 0;
+  c->d_pmap = nullptr;
+  c->pcompact = 0;
+  c->pnentries = 0;
+  c->pplan = AsmPlan{};
+  c->d_cq = nullptr;
   c->d_fold64 = nullptr;
   c->d_fold32 = nullptr;
   c->d_nu64 = nullptr;
@@ -984,6 +999,119 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
   }
   if (ret < 0) fail(c, ret, ret == SFEM_E_BREAKDOWN ? "CG breakdown: p^T A p <= 0" : "non-finite value in the solve");
   return ret;
+}
+
+sfem_status sfem_setup_pressure(sfem_ctx *c, const int32_t *pres_dofs, int64_t npres) {
+  sfem_status st;
+  if ((st = require_ready(c)) != SFEM_OK) return st;
+  DeviceGuard g(c->device);
+  if (c->p < 2) return fail(c, SFEM_E_UNSUPPORTED, "the Taylor-Hood pressure space needs p >= 2");
+  if (npres < 0 || npres > kDofMask) return fail(c, SFEM_E_ARG, "0 <= npres < 2^30 is required");
+  if (c->nelem > 0 && !pres_dofs) return fail(c, SFEM_E_ARG, "pres_dofs must not be NULL");
+  if (c->nelem == 0 && npres > 0)
+    return fail(c, SFEM_E_MESH, "pressure DoFs without elements");
+  const int pp = c->p - 1;
+  const int64_t n3p = (int64_t)(pp + 1) * (pp + 1) * (pp + 1);
+  std::vector<int32_t> dofs((size_t)(c->nelem * n3p));
+  if (c->nelem > 0) {
+    HIPCHK(c, hipMemcpyAsync(dofs.data(), pres_dofs, dofs.size() * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  HostPlan hp;
+  {
+    std::string err;
+    std::vector<uint8_t> none((size_t)npres, 0);
+    // the pressure space has no essential DoFs; its E-vector is element-ordered
+    const int rc = build_host_plan(pp, c->nelem, dofs.data(), npres, none.data(), hp, err, false);
+    if (rc != 0) return fail(c, (sfem_status)rc, "pressure map: " + err);
+  }
+  if (hp.nentries >= (int64_t)kDofMask) return fail(c, SFEM_E_ARG, "mesh too large");
+  if (c->pres_ready) return fail(c, SFEM_E_STATE, "the pressure space is already set up");
+  const int64_t q3 = (int64_t)c->q * c->q * c->q;
+  if ((st = dalloc(c, &c->d_pmap, c->nelem * n3p)) != SFEM_OK) return st;
+  int32_t *d_alist = nullptr, *d_aoff = nullptr, *d_slot = nullptr;
+  if ((st = dalloc(c, &d_alist, hp.na)) != SFEM_OK) return st;
+  if ((st = dalloc(c, &d_aoff, hp.na + 1)) != SFEM_OK) return st;
+  if ((st = dalloc(c, &d_slot, (int64_t)hp.slots.size())) != SFEM_OK) return st;
+  if ((st = dalloc(c, &c->d_cq, c->nelem * 9 * q3)) != SFEM_OK) return st;
+  if (c->nelem > 0)
+    HIPCHK(c, hipMemcpyAsync(c->d_pmap, hp.imap.data(), hp.imap.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, c->stream));
+  if (hp.na > 0) {
+    HIPCHK(c, hipMemcpyAsync(d_alist, hp.alist.data(), hp.alist.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d_aoff, hp.aoff.data(), hp.aoff.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, c->stream));
+  }
+  if (!hp.slots.empty())
+    HIPCHK(c, hipMemcpyAsync(d_slot, hp.slots.data(), hp.slots.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, launch_coupling_setup(c->q, c->rules.gauss_x.data(), c->rules.gauss_w.data(), c->d_xyz,
+                                  c->nelem, c->d_cq, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->pplan.alist = d_alist;
+  c->pplan.aoff = d_aoff;
+  c->pplan.slot = d_slot;
+  c->pplan.na = hp.na;
+  c->pcompact = hp.compact ? 1 : 0;
+  c->pnentries = hp.nentries;
+  c->npres = npres;
+  c->pres_ready = true;
+  return SFEM_OK;
+}
+
+sfem_status sfem_stokes_apply(sfem_ctx *c, const double *u, const double *pres, double *yu,
+                              double *yp) {
+  sfem_status st;
+  if ((st = require_ready(c)) != SFEM_OK) return st;
+  if (!c->pres_ready) return fail(c, SFEM_E_STATE, "sfem_setup_pressure has not succeeded");
+  if (c->nfield != 1)
+    return fail(c, SFEM_E_ARG, "the Stokes operator takes one nu field (sfem_set_coeffs with nbatch_nu = 1)");
+  const int64_t nv = c->ndof, np = c->npres;
+  if (nv == 0 && np == 0) return SFEM_OK;
+  if (!u || !pres || !yu || !yp) return fail(c, SFEM_E_ARG, "u, pres, yu and yp must not be NULL");
+  if ((const void *)u == (const void *)yu || (const void *)pres == (const void *)yp)
+    return fail(c, SFEM_E_ARG, "outputs must not alias inputs");
+  DeviceGuard g(c->device);
+  // workspace: G p on the velocity space [3][nv], then the pressure E-vector
+  const size_t tbytes = align_up((size_t)3 * nv * sizeof(double));
+  if ((st = ensure_ws(c, tbytes + align_up((size_t)c->pnentries * sizeof(double)) + 256)) != SFEM_OK)
+    return st;
+  double *tu = (double *)c->ws.p;
+  double *Yp = (double *)((char *)c->ws.p + tbytes);
+  // y_u = H u (constrained: essential rows copy u)
+  if ((st = do_apply(c, SFEM_HELMHOLTZ, false, 3, u, yu)) != SFEM_OK) return st;
+  // t = P G p, y_u += t
+  if ((st = ensure_evec(c, (size_t)c->nentries * 3 * sizeof(double))) != SFEM_OK) return st;
+  StokesArgs a{};
+  a.p = c->p;
+  a.nelem = c->nelem;
+  a.vmap = c->d_map;
+  a.vpos = c->d_pos;
+  a.vcompact = c->compact;
+  a.pmap = c->d_pmap;
+  a.pcompact = c->pcompact;
+  a.cq = c->d_cq;
+  a.pres = pres;
+  a.Yv = (double *)c->evec.p;
+  a.vestride = c->nentries;
+  a.yv = tu;
+  a.nv = nv;
+  a.u = u;
+  a.Yp = Yp;
+  a.yp = yp;
+  a.which = 0;
+  HIPCHK(c, launch_stokes(a, c->stream));
+  HIPCHK(c, launch_assemble<double>(c->plan, (const double *)c->evec.p, c->nentries, nullptr, tu, nv, 3,
+                                    kEssZero, nullptr, 0, c->stream));
+  HIPCHK(c, launch_add(yu, tu, 3 * nv, c->stream));
+  // y_p = -D P u
+  a.which = 1;
+  HIPCHK(c, launch_stokes(a, c->stream));
+  HIPCHK(c, launch_assemble<double>(c->pplan, Yp, 0, nullptr, yp, np, 1, kEssZero, nullptr, 0,
+                                    c->stream));
+  return SFEM_OK;
 }
 
 sfem_status sfem_get_info(const sfem_ctx *c, sfem_ctx_info *out) {

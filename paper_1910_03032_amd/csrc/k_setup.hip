@@ -129,6 +129,35 @@ __global__ void qdata_setup_kernel(GaussArg g, int q, const double *__restrict__
   o[6 * q3] = Gm[1][2];
 }
 
+// Coupling factors of the Stokes blocks: C = w |J| J^{-T} = w adj(J)^T, slot 3c + d
+// holds C_cd = w adj(J)_dc.
+__global__ void coupling_setup_kernel(GaussArg g, int q, const double *__restrict__ xyz,
+                                      int64_t nei, double *__restrict__ cq) {
+  const int64_t q3 = (int64_t)q * q * q;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= nei * q3) return;
+  const int64_t e = gid / q3;
+  const int qi = (int)(gid - e * q3);
+  const int a = qi % q, b = (qi / q) % q, c = qi / (q * q);
+  const double xi[3] = {g.x[a], g.x[b], g.x[c]};
+  const double w = g.w[a] * g.w[b] * g.w[c];
+  double pos[3], J[3][3];
+  trilinear(xyz + e * 24, xi, pos, J);
+  double A[3][3];  // adj(J) = det(J) J^{-1}
+  A[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  A[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+  A[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+  A[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  A[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+  A[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+  A[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  A[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+  A[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  double *o = cq + e * (int64_t)(9 * q3) + qi;
+  for (int r = 0; r < 3; ++r)
+    for (int d = 0; d < 3; ++d) o[(3 * r + d) * q3] = w * A[d][r];
+}
+
 __global__ void qpoint_coords_kernel(GaussArg g, int q, const double *__restrict__ xyz,
                                      int64_t nei, double *__restrict__ xq) {
   const int64_t q3 = (int64_t)q * q * q;
@@ -197,6 +226,15 @@ hipError_t launch_qdata_setup(int q, const double *gx, const double *gw, const d
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(qdata_setup_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s,
                      gauss_arg(gx, gw, q), q, xyz, nei, qd, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_coupling_setup(int q, const double *gx, const double *gw, const double *xyz,
+                                 int64_t nei, double *cq, hipStream_t s) {
+  const int64_t n = nei * (int64_t)q * q * q;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(coupling_setup_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s,
+                     gauss_arg(gx, gw, q), q, xyz, nei, cq);
   return hipGetLastError();
 }
 
