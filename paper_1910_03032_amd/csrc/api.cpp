@@ -1074,15 +1074,12 @@ sfem_status sfem_stokes_apply(sfem_ctx *c, const double *u, const double *pres, 
   if ((const void *)u == (const void *)yu || (const void *)pres == (const void *)yp)
     return fail(c, SFEM_E_ARG, "outputs must not alias inputs");
   DeviceGuard g(c->device);
-  // workspace: G p on the velocity space [3][nv], then the pressure E-vector
-  const size_t tbytes = align_up((size_t)3 * nv * sizeof(double));
-  if ((st = ensure_ws(c, tbytes + align_up((size_t)c->pnentries * sizeof(double)) + 256)) != SFEM_OK)
-    return st;
-  double *tu = (double *)c->ws.p;
-  double *Yp = (double *)((char *)c->ws.p + tbytes);
+  // workspace: the pressure E-vector
+  if ((st = ensure_ws(c, align_up((size_t)c->pnentries * sizeof(double)) + 256)) != SFEM_OK) return st;
+  double *Yp = (double *)c->ws.p;
   // y_u = H u (constrained: essential rows copy u)
   if ((st = do_apply(c, SFEM_HELMHOLTZ, false, 3, u, yu)) != SFEM_OK) return st;
-  // t = P G p, y_u += t
+  // y_u += P G p (essential rows untouched), y_p = -D P u
   if ((st = ensure_evec(c, (size_t)c->nentries * 3 * sizeof(double))) != SFEM_OK) return st;
   StokesArgs a{};
   a.p = c->p;
@@ -1093,22 +1090,17 @@ sfem_status sfem_stokes_apply(sfem_ctx *c, const double *u, const double *pres, 
   a.pmap = c->d_pmap;
   a.pcompact = c->pcompact;
   a.cq = c->d_cq;
+  a.u = u;
   a.pres = pres;
+  a.nv = nv;
   a.Yv = (double *)c->evec.p;
   a.vestride = c->nentries;
-  a.yv = tu;
-  a.nv = nv;
-  a.u = u;
+  a.yv = yu;
   a.Yp = Yp;
   a.yp = yp;
-  a.which = 0;
   HIPCHK(c, launch_stokes(a, c->stream));
-  HIPCHK(c, launch_assemble<double>(c->plan, (const double *)c->evec.p, c->nentries, nullptr, tu, nv, 3,
-                                    kEssZero, nullptr, 0, c->stream));
-  HIPCHK(c, launch_add(yu, tu, 3 * nv, c->stream));
-  // y_p = -D P u
-  a.which = 1;
-  HIPCHK(c, launch_stokes(a, c->stream));
+  HIPCHK(c, launch_assemble<double>(c->plan, (const double *)c->evec.p, c->nentries, nullptr, yu, nv, 3,
+                                    kEssAdd, nullptr, 0, c->stream));
   HIPCHK(c, launch_assemble<double>(c->pplan, Yp, 0, nullptr, yp, np, 1, kEssZero, nullptr, 0,
                                     c->stream));
   return SFEM_OK;

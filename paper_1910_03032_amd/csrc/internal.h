@@ -13,7 +13,9 @@
 namespace sfem {
 
 // How the assembly sets essential DoFs: copy x (operator apply), 1 (diagonal), 0 (load)
-enum EssKind { kEssCopyX = 0, kEssOne = 1, kEssZero = 2 };
+// What the assembly kernel writes at the essential DoFs (kEssAdd: it adds the assembled
+// sums to y at the other listed DoFs and leaves the essential entries as they are).
+enum EssKind { kEssCopyX = 0, kEssOne = 1, kEssZero = 2, kEssAdd = 3 };
 
 // Quadrature-data slots per point, layout [elem][kQdSlots][q^3]:
 //   0: w|J|      1..6: w|J| (J^-1 J^-T) as (11, 22, 33, 12, 13, 23)
@@ -77,13 +79,13 @@ hipError_t launch_apply_f32(const ApplyArgs &a, hipStream_t s);
 // elements per workgroup of the apply kernel (one dot partial per workgroup)
 int apply_group_elems_f64(int p);
 int apply_group_elems_f32(int p);
-// Coupling blocks of the Taylor-Hood Stokes operator (velocity order p, pressure p - 1).
-// which = 0: G, pressure -> velocity (3 members of the velocity E-vector and of yv,
-// member stride vestride / nv); which = 1: -D on the free velocity DoFs, u -> pressure
-// (element-ordered pressure E-vector Yp, sole DoFs into yp).
+// Coupling blocks of the Taylor-Hood Stokes operator (velocity order p, pressure p - 1),
+// one pass over the elements: G p added into the velocity vector yv ([3][nv]; sole DoFs
+// directly, shared nodes into the velocity E-vector Yv, members at stride vestride, to be
+// assembled with kEssAdd) and -D P u into the pressure space (sole DoFs of yp, shared
+// nodes into the element-ordered pressure E-vector Yp).
 struct StokesArgs {
   int p;
-  int which;
   int64_t nelem;
   const int32_t *vmap;      // velocity flagged map [nelem][(p+1)^3]
   const int32_t *vpos;      // velocity position table (DoF-ordered E-vector) or null
@@ -91,18 +93,16 @@ struct StokesArgs {
   const int32_t *pmap;      // pressure flagged map [nelem][p^3]
   int pcompact;
   const double *cq;         // coupling factors [nelem][9][q^3]
-  const double *pres;       // G input [np]
-  double *Yv;               // G output: velocity E-vector [3][vestride]
-  int64_t vestride;
-  double *yv;               // G output at the sole velocity DoFs [3][nv]
+  const double *u;          // [3][nv]
+  const double *pres;       // [np]
   int64_t nv;
-  const double *u;          // D input [3][nv]
-  double *Yp;               // D output: pressure E-vector [nelem * epe_p]
-  double *yp;               // D output at the sole pressure DoFs [np]
+  double *Yv;               // [3][vestride]
+  int64_t vestride;
+  double *yv;               // [3][nv], added into
+  double *Yp;               // [nelem * epe_p]
+  double *yp;               // [np]
 };
 hipError_t launch_stokes(const StokesArgs &a, hipStream_t s);
-// y += t (n entries)
-hipError_t launch_add(double *y, const double *t, int64_t n, hipStream_t s);
 // coupling factors C = w |J| J^{-T} at the q^3 Gauss points, [nelem][9][q^3], slot 3c + d
 hipError_t launch_coupling_setup(int q, const double *gx, const double *gw, const double *xyz,
                                  int64_t nei, double *cq, hipStream_t s);

@@ -265,94 +265,86 @@ struct SDims {
                 "element buffer");
 };
 
-// G: pressure -> the three velocity components (member c of the velocity E-vector and
-// of y).  cq: [nelem][9][q^3], slot 3c + d holds C_cd.
+// Output of a velocity element vector that adds into y: sole DoFs y[g] += v (each has
+// exactly one writer), shared nodes -> their E-vector entry (as the apply), essential ->
+// nothing.
 template <int P, bool POS>
-__global__ void __launch_bounds__(Dims<P>::THREADS)
-gradient_kernel(const int32_t *__restrict__ pmap, const int32_t *__restrict__ vmap,
-                const int32_t *__restrict__ vpos, int vcompact, const double *__restrict__ cq,
-                int64_t nelem, const double *__restrict__ pres, double *__restrict__ Yv,
-                int64_t vestride, double *__restrict__ yv, int64_t nv) {
-  using S = SDims<P>;
+__device__ __forceinline__ void emit_add_vel(const double *buf, int t, bool active,
+                                             const int32_t *smap, int64_t e, bool compact,
+                                             double *__restrict__ Y, double *__restrict__ y) {
   using D = Dims<P>;
-  constexpr int N = S::N, NP = S::NP, Q = S::Q, Q2 = S::Q2, Q3 = S::Q3, TPE = S::TPE, E = S::E;
-  using TP = Tab2<P - 1, Q>;
-  using TV = Tab2<P, Q>;
-  __shared__ __align__(16) double smem[E * D::BUF];
-  __shared__ int32_t smap_all[E * (N * N * N)];
-  const int le = threadIdx.x / TPE;
-  const int t = threadIdx.x - le * TPE;
-  const int e = xcd_block() * E + le;
-  const bool active = e < nelem;
-  const int es = active ? e : 0;
-  double *buf = smem + le * D::BUF;
-  int32_t *smap = smap_all + le * (N * N * N);
-  // pressure element -> reference gradient lines
-  gather_pres<P>(buf, t, active, pmap + (int64_t)es * (NP * NP * NP), pres, smap);
-  fwd_grad_xy<NP, Q, TP>(buf, t);
-  double zbb[NP], zgb[NP], zbg[NP];
+  constexpr int NL = Per<P>::NL;
 #pragma unroll
-  for (int k = 0; k < NP; ++k) {
-    zbb[k] = buf[k * Q2 + t];
-    zgb[k] = buf[NP * Q2 + k * Q2 + t];
-    zbg[k] = buf[2 * NP * Q2 + k * Q2 + t];
-  }
-  const double *ce = cq + (int64_t)es * (9 * Q3) + t;
-  double v[3][Q];
-#pragma unroll
-  for (int c = 0; c < Q; ++c) {
-    double gx = 0.0, gy = 0.0, gz = 0.0;
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-      gz += TP::G(c, k) * zbb[k];
-      gy += TP::B(c, k) * zgb[k];
-      gx += TP::B(c, k) * zbg[k];
-    }
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      const double *cr = ce + (int64_t)(3 * r) * Q3 + c * Q2;
-      v[r][c] = cr[0] * gx + cr[Q3] * gy + cr[2 * Q3] * gz;
+  for (int k = 0; k < NL; ++k) {
+    const int l0 = t + k * D::TPE;
+    const int l = l0 < D::N3 ? l0 : D::N3 - 1;
+    const int32_t c = smap[l];
+    const double v = buf[l];
+    if (!(active && l0 < D::N3 && c >= 0)) continue;
+    if (c & kSoleBit) {
+      y[c & kDofMask] += v;
+    } else if constexpr (POS) {
+      Y[c] = v;
+    } else {
+      Y[compact ? e * surf_count<P>() + surf_rank<P>(l) : e * D::N3 + l] = v;
     }
   }
-  bwd_mass<N, Q, 3, TV>(buf, t, v);
-  // the velocity map entries (essential DoFs get nothing: their rows are constrained)
-  const int64_t vepe = vcompact ? surf_count<P>() : N * N * N;
-  vel_entries<P, POS>(t, vmap + (int64_t)es * (N * N * N), smap,
-                      POS ? vpos + (int64_t)es * vepe : nullptr, vcompact != 0);
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-    emit_e<P, double, false, POS>(buf + r * (N * N * N), t, active, smap, yv, es, vcompact != 0,
-                                  Yv + r * vestride, yv + r * nv);
 }
 
-// -D (restricted to the free velocity DoFs): the three velocity components -> pressure.
+// Both coupling blocks in one pass over the elements, so that the coupling factors are
+// read once: G p added into the three velocity components (their E-vector for the shared
+// nodes, members at stride vestride; the sole DoFs of yv directly) and -D P u into the
+// pressure space (element-ordered E-vector Yp, sole DoFs of yp).  cq: [nelem][9][q^3],
+// slot 3c + d holds C_cd.
 template <int P, bool POS>
 __global__ void __launch_bounds__(Dims<P>::THREADS)
-divergence_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ pmap,
-                  int pcompact, const double *__restrict__ cq, int64_t nelem,
-                  const double *__restrict__ u, int64_t nv, double *__restrict__ Yp,
-                  double *__restrict__ yp) {
+coupling_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ vpos, int vcompact,
+                const int32_t *__restrict__ pmap, int pcompact, const double *__restrict__ cq,
+                int64_t nelem, const double *__restrict__ u, const double *__restrict__ pres,
+                int64_t nv, double *__restrict__ Yv, int64_t vestride, double *__restrict__ yv,
+                double *__restrict__ Yp, double *__restrict__ yp) {
   using S = SDims<P>;
   using D = Dims<P>;
   constexpr int N = S::N, NP = S::NP, Q = S::Q, Q2 = S::Q2, Q3 = S::Q3, TPE = S::TPE, E = S::E;
-  using TV = Tab2<P, Q>;
+  constexpr int N3 = N * N * N, NP3 = NP * NP * NP;
   using TP = Tab2<P - 1, Q>;
+  using TV = Tab2<P, Q>;
   __shared__ __align__(16) double smem[E * D::BUF];
-  __shared__ int32_t smap_all[E * (N * N * N)];
+  __shared__ int32_t smap_all[E * N3];
   const int le = threadIdx.x / TPE;
-  const int t = threadIdx.x - le * TPE;
+  const int t0 = threadIdx.x - le * TPE;
+  const int t = t0;
   const int e = xcd_block() * E + le;
   const bool active = e < nelem;
   const int es = active ? e : 0;
   double *buf = smem + le * D::BUF;
-  int32_t *smap = smap_all + le * (N * N * N);
-  const double *ce = cq + (int64_t)es * (9 * Q3) + t;
-  double s[Q];
+  int32_t *smap = smap_all + le * N3;
+  // pressure element: the xi_3 lines of its reference gradient
+  gather_pres<P>(buf, t, active, pmap + (int64_t)es * NP3, pres, smap);
+  fwd_grad_xy<NP, Q, TP>(buf, t);
+  double pbb[NP], pgb[NP], pbg[NP];
 #pragma unroll
-  for (int c = 0; c < Q; ++c) s[c] = 0.0;
+  for (int k = 0; k < NP; ++k) {
+    pbb[k] = buf[k * Q2 + t];
+    pgb[k] = buf[NP * Q2 + k * Q2 + t];
+    pbg[k] = buf[2 * NP * Q2 + k * Q2 + t];
+  }
+  // the velocity element's map entries for the output
+  const int64_t vepe = vcompact ? surf_count<P>() : N3;
+  vel_entries<P, POS>(t, vmap + (int64_t)es * N3, smap, POS ? vpos + (int64_t)es * vepe : nullptr,
+                      vcompact != 0);
+  const double *ce = cq + (int64_t)es * (9 * Q3) + t;
+  double s[1][Q];
+#pragma unroll
+  for (int c = 0; c < Q; ++c) s[0][c] = 0.0;
+  // (one component at a time, not unrolled: fewer live registers)
+#pragma unroll 1
   for (int r = 0; r < 3; ++r) {
-    // component r (essential DoFs read as 0)
-    gather_e<P, double, false>(buf, t, active, vmap + (int64_t)es * (N * N * N), u + r * nv);
+    // indices derived from the thread are recomputed per component rather than kept live
+    int t = t0;
+    asm volatile("" : "+v"(t));
+    // velocity component r (essential DoFs read as 0)
+    gather_e<P, double, false>(buf, t, active, vmap + (int64_t)es * N3, u + r * nv);
     fwd_grad_xy<N, Q, TV>(buf, t);
     double zbb[N], zgb[N], zbg[N];
 #pragma unroll
@@ -362,26 +354,36 @@ divergence_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ 
       zbg[k] = buf[2 * N * Q2 + k * Q2 + t];
     }
     const double *cr = ce + (int64_t)(3 * r) * Q3;
+    double v[1][Q];
 #pragma unroll
     for (int c = 0; c < Q; ++c) {
-      double gx = 0.0, gy = 0.0, gz = 0.0;
+      double ux = 0.0, uy = 0.0, uz = 0.0, px = 0.0, py = 0.0, pz = 0.0;
 #pragma unroll
       for (int k = 0; k < N; ++k) {
-        gz += TV::G(c, k) * zbb[k];
-        gy += TV::B(c, k) * zgb[k];
-        gx += TV::B(c, k) * zbg[k];
+        uz += TV::G(c, k) * zbb[k];
+        uy += TV::B(c, k) * zgb[k];
+        ux += TV::B(c, k) * zbg[k];
       }
-      s[c] -= cr[c * Q2] * gx + cr[Q3 + c * Q2] * gy + cr[2 * Q3 + c * Q2] * gz;
-    }
-    __syncthreads();  // buf is reused by the next component's gather
-  }
-  double v[1][Q];
 #pragma unroll
-  for (int c = 0; c < Q; ++c) v[0][c] = s[c];
-  bwd_mass<NP, Q, 1, TP>(buf, t, v);
-  // map entries of the pressure element for the output
+      for (int k = 0; k < NP; ++k) {
+        pz += TP::G(c, k) * pbb[k];
+        py += TP::B(c, k) * pgb[k];
+        px += TP::B(c, k) * pbg[k];
+      }
+      // row r of C times grad_ref p (G) and times grad_ref u_r (D)
+      const double c0 = cr[c * Q2], c1 = cr[Q3 + c * Q2], c2 = cr[2 * Q3 + c * Q2];
+      v[0][c] = c0 * px + c1 * py + c2 * pz;
+      s[0][c] -= c0 * ux + c1 * uy + c2 * uz;
+    }
+    // G p, component r: added into yv / the velocity E-vector
+    bwd_mass<N, Q, 1, TV>(buf, t, v);
+    emit_add_vel<P, POS>(buf, t, active, smap, es, vcompact != 0, Yv + r * vestride, yv + r * nv);
+    __syncthreads();  // buf is reused by the next gather
+  }
+  // -D P u: one pressure field
+  bwd_mass<NP, Q, 1, TP>(buf, t, s);
   {
-    constexpr int NP3 = NP * NP * NP, NL = (NP3 + TPE - 1) / TPE;
+    constexpr int NL = (NP3 + TPE - 1) / TPE;
     const int32_t *em = pmap + (int64_t)es * NP3;
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
@@ -404,20 +406,11 @@ hipError_t launch_stokes_pt(const StokesArgs &a, hipStream_t s) {
     if ((a.vpos != nullptr) != POS) return hipErrorInvalidValue;
     dim3 grid((unsigned)((a.nelem + D::E - 1) / D::E));
     dim3 block(D::THREADS);
-    if (a.which == 0)
-      hipLaunchKernelGGL((gradient_kernel<P, POS>), grid, block, 0, s, a.pmap, a.vmap, a.vpos,
-                         a.vcompact, a.cq, a.nelem, a.pres, a.Yv, a.vestride, a.yv, a.nv);
-    else
-      hipLaunchKernelGGL((divergence_kernel<P, POS>), grid, block, 0, s, a.vmap, a.pmap,
-                         a.pcompact, a.cq, a.nelem, a.u, a.nv, a.Yp, a.yp);
+    hipLaunchKernelGGL((coupling_kernel<P, POS>), grid, block, 0, s, a.vmap, a.vpos, a.vcompact,
+                       a.pmap, a.pcompact, a.cq, a.nelem, a.u, a.pres, a.nv, a.Yv, a.vestride,
+                       a.yv, a.Yp, a.yp);
     return hipGetLastError();
   }
-}
-
-__global__ void add_kernel(double *__restrict__ y, const double *__restrict__ t, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    y[i] += t[i];
 }
 
 }  // namespace
@@ -426,14 +419,6 @@ hipError_t launch_stokes(const StokesArgs &a, hipStream_t s) {
 #define SFEM_CALL(P) launch_stokes_pt<P>(a, s)
   SFEM_DISPATCH_P(a.p, SFEM_CALL)
 #undef SFEM_CALL
-}
-
-hipError_t launch_add(double *y, const double *t, int64_t n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  int64_t b = (n + 1023) / 1024;
-  if (b > 4096) b = 4096;
-  hipLaunchKernelGGL(add_kernel, dim3((unsigned)b), dim3(256), 0, s, y, t, n);
-  return hipGetLastError();
 }
 
 }  // namespace sfem

@@ -336,7 +336,8 @@ __global__ void ir_accum_kernel(double *__restrict__ x, const float *__restrict_
 // Assembly over the list of shared and essential DoFs: y[g] = sum of the E-vector
 // entries of list entry i in element order -- [aoff[i], aoff[i+1]) for the DoF-ordered
 // E-vector (consecutive threads then read consecutive runs), slot[aoff[i]..aoff[i+1])
-// for the element-ordered one; essential DoFs (no entries) get x[g], 1 or 0.  DOT: also
+// for the element-ordered one; essential DoFs (no entries) get x[g], 1 or 0 (kEssAdd:
+// y[g] += the sum at the other DoFs, essential entries untouched).  DOT: also
 // the per-block sums of x_g y_g.  Each thread takes AU list entries per pass (stride
 // VB); the first KS entries of each are loaded together, longer lists fall back to a
 // loop.  Index arithmetic is 32-bit (entries below 2^30, checked at set-up).
@@ -383,6 +384,10 @@ assemble_kernel(AsmPlan pl, const T *__restrict__ Y, int64_t estride, const T *_
         if (j < d[k]) acc += val[k][j];
       for (int j = KS; j < d[k]; ++j) acc += Ym[pl.slot ? pl.slot[a[k] + j] : a[k] + j];
       const T xg = (DOT || (d[k] == 0 && ess_kind == kEssCopyX)) ? xm[g[k]] : T(0);
+      if (ess_kind == kEssAdd) {
+        if (d[k] > 0) ym[g[k]] += acc;
+        continue;
+      }
       if (d[k] == 0) acc = (ess_kind == kEssCopyX) ? xg : (ess_kind == kEssOne ? T(1) : T(0));
       ym[g[k]] = acc;
       if constexpr (DOT) v[0] += (double)xg * (double)acc;
