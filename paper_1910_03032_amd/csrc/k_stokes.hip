@@ -27,13 +27,52 @@ struct Tab2 {
   static constexpr double B(int a, int i) { return c.B[a][i]; }
   static constexpr double G(int a, int i) { return c.G[a][i]; }
 };
+// The same tables in the accessor form of the even-odd helpers (WHICH 0 = B, 1 = G): the
+// GLL nodes of any order and the Gauss points are symmetric about 0, so B is
+// centro-symmetric and G centro-antisymmetric for every (order, q) pair.
+template <int PO, int Q, int WHICH>
+struct TabEO {
+  static constexpr int NO = Q, NI = PO + 1;
+  static constexpr int S = WHICH == 0 ? 1 : -1;
+  static constexpr double t(int a, int i) { return WHICH == 0 ? Tab2<PO, Q>::B(a, i) : Tab2<PO, Q>::G(a, i); }
+  static constexpr double e(int a, int i) { return 0.5 * (t(a, i) + t(a, NI - 1 - i)); }
+  static constexpr double o(int a, int i) { return 0.5 * (t(a, i) - t(a, NI - 1 - i)); }
+};
 
-// Forward reference gradient of a nodal field with NI nodes per direction (in buf,
-// [k][j][i]) for the q x q threads of an element: stage xi_1 and xi_2 through LDS, the
-// xi_3 contraction is done by the caller from the three lines this returns.
-template <int NI, int Q, typename TB>
+// Outputs (a, q-1-a) of a 1D contraction from the even-odd split x of its input line.
+template <typename TB>
+__device__ __forceinline__ void row_pair(const eo::Split<TB::NI, double> &x, int a, double &lo,
+                                         double &hi) {
+  double Ev = 0.0, Od = 0.0;
+#pragma unroll
+  for (int i = 0; i < TB::NI / 2; ++i) {
+    Ev += TB::e(a, i) * x.e[i];
+    Od += TB::o(a, i) * x.o[i];
+  }
+  if constexpr (TB::NI % 2 == 1) Ev += TB::t(a, TB::NI / 2) * x.e[TB::NI / 2];
+  lo = Ev + Od;
+  hi = (TB::S > 0) ? (Ev - Od) : (Od - Ev);
+}
+// The middle output (a = q/2) of an odd q.
+template <typename TB>
+__device__ __forceinline__ double row_mid(const eo::Split<TB::NI, double> &x) {
+  constexpr int M = TB::NO / 2;
+  double v = 0.0;
+#pragma unroll
+  for (int i = 0; i < TB::NI / 2; ++i) v += TB::t(M, i) * (TB::S > 0 ? x.e[i] : x.o[i]);
+  if constexpr (TB::NI % 2 == 1 && TB::S > 0) v += TB::t(M, TB::NI / 2) * x.e[TB::NI / 2];
+  return v;
+}
+
+// Forward reference gradient of a nodal field of order PO (NI = PO + 1 nodes per
+// direction, in buf as [k][j][i]) for the q x q threads of an element: stages xi_1 and
+// xi_2 through LDS (even-odd contractions); the xi_3 contraction is the caller's.
+template <int PO, int Q>
 __device__ __forceinline__ void fwd_grad_xy(double *buf, int t) {
+  constexpr int NI = PO + 1;
   constexpr int N2 = NI * NI, QN2 = Q * N2, NQ2 = NI * Q * Q;
+  using BT = TabEO<PO, Q, 0>;
+  using GT = TabEO<PO, Q, 1>;
   {  // xi_1: [k][j][i] -> [k][j][a] (B and G)
     const bool w = t < N2;
     const int j = t % NI, k = t / NI;
@@ -42,17 +81,9 @@ __device__ __forceinline__ void fwd_grad_xy(double *buf, int t) {
       double in[NI];
 #pragma unroll
       for (int i = 0; i < NI; ++i) in[i] = buf[(k * NI + j) * NI + i];
-#pragma unroll
-      for (int a = 0; a < Q; ++a) {
-        double sb = 0.0, sg = 0.0;
-#pragma unroll
-        for (int i = 0; i < NI; ++i) {
-          sb += TB::B(a, i) * in[i];
-          sg += TB::G(a, i) * in[i];
-        }
-        ob[a] = sb;
-        og[a] = sg;
-      }
+      const auto sp = eo::split(in);
+      eo::apply<BT>(sp, ob);
+      eo::apply<GT>(sp, og);
     }
     __syncthreads();
     if (w) {
@@ -75,19 +106,10 @@ __device__ __forceinline__ void fwd_grad_xy(double *buf, int t) {
         ib[j] = buf[(k * NI + j) * Q + a];
         ig[j] = buf[QN2 + (k * NI + j) * Q + a];
       }
-#pragma unroll
-      for (int b = 0; b < Q; ++b) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll
-        for (int j = 0; j < NI; ++j) {
-          s0 += TB::B(b, j) * ib[j];
-          s1 += TB::G(b, j) * ib[j];
-          s2 += TB::B(b, j) * ig[j];
-        }
-        obb[b] = s0;
-        ogb[b] = s1;
-        obg[b] = s2;
-      }
+      const auto sb = eo::split(ib);
+      eo::apply<BT>(sb, obb);
+      eo::apply<GT>(sb, ogb);
+      eo::apply<BT>(eo::split(ig), obg);
     }
     __syncthreads();
     if (w) {
@@ -103,22 +125,25 @@ __device__ __forceinline__ void fwd_grad_xy(double *buf, int t) {
 }
 
 // Transposed mass-type contractions of NF fields given at the q^3 points (each thread
-// holds its xi_3 line v[f][c]) down to nodal fields with NO nodes per direction, field f
-// at buf + f * NO^3 ([k][j][i]).  Ends with a barrier.
-template <int NO, int Q, int NF, typename TB>
+// holds its xi_3 line v[f][c]) down to nodal fields of order PO (NO = PO + 1 nodes per
+// direction), field f at buf + f * NO^3 ([k][j][i]); even-odd form.  Ends with a barrier.
+template <int PO, int Q, int NF>
 __device__ __forceinline__ void bwd_mass(double *buf, int t, const double (&v)[NF][Q]) {
+  constexpr int NO = PO + 1;
   constexpr int NQ2 = NO * Q * Q, N2Q = NO * NO * Q, N3 = NO * NO * NO;
+  using BT = TabEO<PO, Q, 0>;
+  auto line = [](const double (&in)[Q], double (&out)[NO]) {
+    eo::Acc<NO, double> A;
+    A.zero();
+#pragma unroll
+    for (int c = 0; c < Q / 2; ++c) A.template add_pair<BT>(c, in[c], in[Q - 1 - c]);
+    if constexpr (Q % 2 == 1) A.template add_mid<BT>(in[Q / 2]);
+    A.finish(out);
+  };
   {  // xi_3: [c] -> [k][b][a]
     double r[NF][NO];
 #pragma unroll
-    for (int f = 0; f < NF; ++f)
-#pragma unroll
-      for (int k = 0; k < NO; ++k) {
-        double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < Q; ++c) s += TB::B(c, k) * v[f][c];
-        r[f][k] = s;
-      }
+    for (int f = 0; f < NF; ++f) line(v[f], r[f]);
     __syncthreads();
 #pragma unroll
     for (int f = 0; f < NF; ++f)
@@ -136,13 +161,7 @@ __device__ __forceinline__ void bwd_mass(double *buf, int t, const double (&v)[N
         double in[Q];
 #pragma unroll
         for (int b = 0; b < Q; ++b) in[b] = buf[f * NQ2 + (k * Q + b) * Q + a];
-#pragma unroll
-        for (int j = 0; j < NO; ++j) {
-          double s = 0.0;
-#pragma unroll
-          for (int b = 0; b < Q; ++b) s += TB::B(b, j) * in[b];
-          r[f][j] = s;
-        }
+        line(in, r[f]);
       }
     }
     __syncthreads();
@@ -164,13 +183,7 @@ __device__ __forceinline__ void bwd_mass(double *buf, int t, const double (&v)[N
         double in[Q];
 #pragma unroll
         for (int a = 0; a < Q; ++a) in[a] = buf[f * N2Q + (k * NO + j) * Q + a];
-#pragma unroll
-        for (int i = 0; i < NO; ++i) {
-          double s = 0.0;
-#pragma unroll
-          for (int a = 0; a < Q; ++a) s += TB::B(a, i) * in[a];
-          r[f][i] = s;
-        }
+        line(in, r[f]);
       }
     }
     __syncthreads();
@@ -307,8 +320,6 @@ coupling_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ vp
   using D = Dims<P>;
   constexpr int N = S::N, NP = S::NP, Q = S::Q, Q2 = S::Q2, Q3 = S::Q3, TPE = S::TPE, E = S::E;
   constexpr int N3 = N * N * N, NP3 = NP * NP * NP;
-  using TP = Tab2<P - 1, Q>;
-  using TV = Tab2<P, Q>;
   __shared__ __align__(16) double smem[E * D::BUF];
   __shared__ int32_t smap_all[E * N3];
   const int le = threadIdx.x / TPE;
@@ -321,13 +332,19 @@ coupling_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ vp
   int32_t *smap = smap_all + le * N3;
   // pressure element: the xi_3 lines of its reference gradient
   gather_pres<P>(buf, t, active, pmap + (int64_t)es * NP3, pres, smap);
-  fwd_grad_xy<NP, Q, TP>(buf, t);
-  double pbb[NP], pgb[NP], pbg[NP];
+  fwd_grad_xy<P - 1, Q>(buf, t);
+  eo::Split<NP, double> pbb, pgb, pbg;  // xi_3 lines of the pressure, even-odd split
+  {
+    double zb[NP], zg[NP], zx[NP];
 #pragma unroll
-  for (int k = 0; k < NP; ++k) {
-    pbb[k] = buf[k * Q2 + t];
-    pgb[k] = buf[NP * Q2 + k * Q2 + t];
-    pbg[k] = buf[2 * NP * Q2 + k * Q2 + t];
+    for (int k = 0; k < NP; ++k) {
+      zb[k] = buf[k * Q2 + t];
+      zg[k] = buf[NP * Q2 + k * Q2 + t];
+      zx[k] = buf[2 * NP * Q2 + k * Q2 + t];
+    }
+    pbb = eo::split(zb);
+    pgb = eo::split(zg);
+    pbg = eo::split(zx);
   }
   // the velocity element's map entries for the output
   const int64_t vepe = vcompact ? surf_count<P>() : N3;
@@ -345,43 +362,54 @@ coupling_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ vp
     asm volatile("" : "+v"(t));
     // velocity component r (essential DoFs read as 0)
     gather_e<P, double, false>(buf, t, active, vmap + (int64_t)es * N3, u + r * nv);
-    fwd_grad_xy<N, Q, TV>(buf, t);
-    double zbb[N], zgb[N], zbg[N];
+    fwd_grad_xy<P, Q>(buf, t);
+    eo::Split<N, double> ubb, ugb, ubg;
+    {
+      double zb[N], zg[N], zx[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) {
-      zbb[k] = buf[k * Q2 + t];
-      zgb[k] = buf[N * Q2 + k * Q2 + t];
-      zbg[k] = buf[2 * N * Q2 + k * Q2 + t];
+      for (int k = 0; k < N; ++k) {
+        zb[k] = buf[k * Q2 + t];
+        zg[k] = buf[N * Q2 + k * Q2 + t];
+        zx[k] = buf[2 * N * Q2 + k * Q2 + t];
+      }
+      ubb = eo::split(zb);
+      ugb = eo::split(zg);
+      ubg = eo::split(zx);
     }
     const double *cr = ce + (int64_t)(3 * r) * Q3;
     double v[1][Q];
-#pragma unroll
-    for (int c = 0; c < Q; ++c) {
-      double ux = 0.0, uy = 0.0, uz = 0.0, px = 0.0, py = 0.0, pz = 0.0;
-#pragma unroll
-      for (int k = 0; k < N; ++k) {
-        uz += TV::G(c, k) * zbb[k];
-        uy += TV::B(c, k) * zgb[k];
-        ux += TV::B(c, k) * zbg[k];
-      }
-#pragma unroll
-      for (int k = 0; k < NP; ++k) {
-        pz += TP::G(c, k) * pbb[k];
-        py += TP::B(c, k) * pgb[k];
-        px += TP::B(c, k) * pbg[k];
-      }
-      // row r of C times grad_ref p (G) and times grad_ref u_r (D)
+    // row r of C times grad_ref p (G) and times grad_ref u_r (D) at slice c
+    auto point = [&](int c, double ux, double uy, double uz, double px, double py, double pz) {
       const double c0 = cr[c * Q2], c1 = cr[Q3 + c * Q2], c2 = cr[2 * Q3 + c * Q2];
       v[0][c] = c0 * px + c1 * py + c2 * pz;
       s[0][c] -= c0 * ux + c1 * uy + c2 * uz;
+    };
+    using VB = TabEO<P, Q, 0>;
+    using VG = TabEO<P, Q, 1>;
+    using PB = TabEO<P - 1, Q, 0>;
+    using PG = TabEO<P - 1, Q, 1>;
+#pragma unroll
+    for (int c = 0; c < Q / 2; ++c) {
+      double uz0, uz1, uy0, uy1, ux0, ux1, pz0, pz1, py0, py1, px0, px1;
+      row_pair<VG>(ubb, c, uz0, uz1);
+      row_pair<VB>(ugb, c, uy0, uy1);
+      row_pair<VB>(ubg, c, ux0, ux1);
+      row_pair<PG>(pbb, c, pz0, pz1);
+      row_pair<PB>(pgb, c, py0, py1);
+      row_pair<PB>(pbg, c, px0, px1);
+      point(c, ux0, uy0, uz0, px0, py0, pz0);
+      point(Q - 1 - c, ux1, uy1, uz1, px1, py1, pz1);
     }
+    if constexpr (Q % 2 == 1)
+      point(Q / 2, row_mid<VB>(ubg), row_mid<VB>(ugb), row_mid<VG>(ubb), row_mid<PB>(pbg),
+            row_mid<PB>(pgb), row_mid<PG>(pbb));
     // G p, component r: added into yv / the velocity E-vector
-    bwd_mass<N, Q, 1, TV>(buf, t, v);
+    bwd_mass<P, Q, 1>(buf, t, v);
     emit_add_vel<P, POS>(buf, t, active, smap, es, vcompact != 0, Yv + r * vestride, yv + r * nv);
     __syncthreads();  // buf is reused by the next gather
   }
   // -D P u: one pressure field
-  bwd_mass<NP, Q, 1, TP>(buf, t, s);
+  bwd_mass<P - 1, Q, 1>(buf, t, s);
   {
     constexpr int NL = (NP3 + TPE - 1) / TPE;
     const int32_t *em = pmap + (int64_t)es * NP3;
