@@ -1006,6 +1006,7 @@ sfem_status sfem_setup_pressure(sfem_ctx *c, const int32_t *pres_dofs, int64_t n
   if ((st = require_ready(c)) != SFEM_OK) return st;
   DeviceGuard g(c->device);
   if (c->p < 2) return fail(c, SFEM_E_UNSUPPORTED, "the Taylor-Hood pressure space needs p >= 2");
+  if (c->pres_ready) return fail(c, SFEM_E_STATE, "the pressure space is already set up");
   if (npres < 0 || npres > kDofMask) return fail(c, SFEM_E_ARG, "0 <= npres < 2^30 is required");
   if (c->nelem > 0 && !pres_dofs) return fail(c, SFEM_E_ARG, "pres_dofs must not be NULL");
   if (c->nelem == 0 && npres > 0)
@@ -1027,7 +1028,6 @@ sfem_status sfem_setup_pressure(sfem_ctx *c, const int32_t *pres_dofs, int64_t n
     if (rc != 0) return fail(c, (sfem_status)rc, "pressure map: " + err);
   }
   if (hp.nentries >= (int64_t)kDofMask) return fail(c, SFEM_E_ARG, "mesh too large");
-  if (c->pres_ready) return fail(c, SFEM_E_STATE, "the pressure space is already set up");
   const int64_t q3 = (int64_t)c->q * c->q * c->q;
   if ((st = dalloc(c, &c->d_pmap, c->nelem * n3p)) != SFEM_OK) return st;
   int32_t *d_alist = nullptr, *d_aoff = nullptr, *d_slot = nullptr;
