@@ -11,7 +11,8 @@ Contents:
               load vector, adjoint-gradient integrand (Section 3, Section 3.1), the
               collocated (GLL-integrated) mass diagonal (Section 5.1)
   stokes      the Taylor-Hood gradient and divergence blocks and the constrained Stokes
-              block operator (Section 3, eq. gradient, eq. divergence)
+              block operator (Section 3, eq. gradient, eq. divergence); the convection
+              term N(u) (eq. nonlinear)
   solvers     diagonally preconditioned CG (optionally orthogonalized against the
               constants), FP32-inner iterative refinement, adjoint gradient, pure-Neumann
               Poisson with the mean-zero condition (Section 5, Section 5.3)
@@ -22,4 +23,4 @@ nothing here is "parity unpinned".
 from .quadrature import gauss_legendre, gll, lagrange_values, lagrange_derivs, legendre_p  # noqa: F401
 from .fem import Discretization, OP_MASS, OP_DIFFUSION, OP_HELMHOLTZ, op_coeffs  # noqa: F401
 from .solvers import pcg, ir_pcg, adjoint_gradient, objective, neumann_poisson  # noqa: F401
-from .stokes import StokesDiscretization  # noqa: F401
+from .stokes import StokesDiscretization, convection  # noqa: F401

@@ -17,6 +17,15 @@ velocity Dirichlet DoFs constrained as for the scalar operators (P zeroes them):
     y_u = P H P u + (I - P) u + P G p,     y_p = -D P u.
 
 Velocity vectors are component-major, [3][nv], every component on the scalar map.
+
+The explicit convection term of the Navier-Stokes problem (eq. nonlinear) on the
+velocity space, component c:
+
+    N(u)_{c, i} = sum_e sum_Q w_Q |J_Q| phi_i(Q) sum_d u_d(Q) (J_Q^{-T} grad_ref u_c(Q))_d
+
+i.e. the integral of phi_i ((u . grad) u)_c, evaluated with the same dense tensors and
+Gauss points (convection()).  The boundary values of u enter as they are; rows of
+essential DoFs are set to 0 (the term is a right-hand side of the constrained solves).
 """
 from __future__ import annotations
 
@@ -134,3 +143,24 @@ class StokesDiscretization:
     def velocity_node_coords(self):
         """Physical coordinates of the velocity nodes [nv, 3] (trilinear map)."""
         return self._node_coords(self.p, self.vel.elem_dofs, self.nv)
+
+
+def convection(d: Discretization, u):
+    """N(u) [3, N] on the scalar discretization d (see the module docstring)."""
+    u = np.asarray(u, dtype=np.float64).reshape(3, d.ndof)
+    y = np.zeros((3, d.ndof))
+    for e0 in range(0, d.nelem, d.chunk):
+        e1 = min(d.nelem, e0 + d.chunk)
+        det, inv, _ = d.geometry(e0, e1)
+        wd = d.Wq[None, :] * det  # [C, Q]
+        dofs = d.elem_dofs[e0:e1]
+        ue = np.stack([u[c][dofs] for c in range(3)], axis=1)  # [C, 3, l]
+        uq = np.einsum("Ql,ecl->eQc", d.Phi, ue)  # u at the points [C, Q, 3]
+        gref = np.einsum("Qld,ecl->eQcd", d.dPhi, ue)  # grad_ref u_c [C, Q, c, d]
+        gphys = np.einsum("eQkr,eQck->eQcr", inv, gref)  # (J^{-T} grad_ref u_c)_r
+        adv = np.einsum("eQr,eQcr->eQc", uq, gphys)  # ((u . grad) u)_c
+        ye = np.einsum("eQ,Ql,eQc->ecl", wd, d.Phi, adv)
+        for c in range(3):
+            np.add.at(y[c], dofs.reshape(-1), ye[:, c].reshape(-1))
+    y[:, d.ess] = 0.0
+    return y

@@ -124,3 +124,68 @@ def test_planted_mistakes_fail_the_pins():
     A = np.array([[0.3, -0.2, 0.5], [1.1, -0.4, 0.25], [-0.6, 0.8, 0.9]])
     u = (S.velocity_node_coords() @ A.T).T
     assert rel(S.divergence(u), np.trace(A) * S.pressure_mass_rowsums()) > 1e-3
+
+
+# ---------------------------------------------------------------- convection N(u)
+def _vel_nodes(ne, p, seed=0):
+    from oracle import Discretization
+    from workloads import BoxMesh
+    m = BoxMesh(ne, p, seed=seed)
+    d = Discretization(m.elem_xyz, m.elem_dofs, m.ess, m.ndof, p, p + 2)
+    # velocity node coordinates through the Stokes helper (any pressure map will do)
+    pm = BoxMesh(ne, max(p - 1, 1), seed=seed)
+    S = StokesDiscretization(m.elem_xyz, m.elem_dofs, m.ess, m.ndof, pm.elem_dofs, pm.ndof,
+                             max(p, 2), p + 2) if p >= 2 else None
+    return m, d, S
+
+
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_convection_of_linear_velocity(p):
+    """u = A x + b is linear, so (u . grad) u = A (A x + b) is linear too and lies in the
+    velocity space: N(u)_c = M (A (A x + b))_c on the free rows, with the unconstrained
+    mass matrix of the scalar oracle (no gradients involved)."""
+    from oracle import convection
+    m, d, S = _vel_nodes(3, p)
+    A = np.array([[0.3, -0.2, 0.5], [1.1, -0.4, 0.25], [-0.6, 0.8, 0.9]])
+    b = np.array([0.1, -0.2, 0.3])
+    x = S.velocity_node_coords()
+    u = (x @ A.T + b).T
+    adv = ((x @ A.T + b) @ A.T).T  # A (A x + b), [3, N]
+    y = convection(d, u)
+    free = ~m.ess.astype(bool)
+    for c in range(3):
+        ref = d.apply_unconstrained(adv[c], 1.0, 0.0)
+        assert rel(y[c, free], ref[free]) <= 1e-13
+    assert np.all(y[:, ~free] == 0.0)
+
+
+def test_convection_is_quadratic_and_vanishes_for_constants():
+    from oracle import convection
+    m, d, S = _vel_nodes(2, 3)
+    u = uniform(3 * m.ndof, seed=13).reshape(3, -1)
+    assert rel(convection(d, 2.0 * u), 4.0 * convection(d, u)) <= 1e-14
+    c0 = np.stack([np.full(m.ndof, v) for v in (0.3, -1.0, 2.0)])
+    assert np.abs(convection(d, c0)).max() <= 1e-13
+
+
+def test_convection_planted_transpose_fails():
+    """J^{-1} in place of J^{-T} in the physical gradient breaks the linear-field pin."""
+    import oracle.stokes as st
+    m, d, S = _vel_nodes(3, 2)
+    A = np.array([[0.3, -0.2, 0.5], [1.1, -0.4, 0.25], [-0.6, 0.8, 0.9]])
+    x = S.velocity_node_coords()
+    u = (x @ A.T).T
+    adv = ((x @ A.T) @ A.T).T
+    orig = np.einsum
+    def wrong(spec, *ops, **kw):
+        if spec == "eQkr,eQck->eQcr":
+            spec = "eQrk,eQck->eQcr"
+        return orig(spec, *ops, **kw)
+    st.np.einsum = wrong
+    try:
+        y = st.convection(d, u)
+    finally:
+        st.np.einsum = orig
+    free = ~m.ess.astype(bool)
+    ref = d.apply_unconstrained(adv[0], 1.0, 0.0)
+    assert rel(y[0, free], ref[free]) > 1e-6
