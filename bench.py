@@ -13,7 +13,8 @@ Jacobi-PCG solve and the FP32-inner iterative-refinement solve to relative resid
 the same workload.  Prints one JSON line.
 
 Other workloads (`--workload`): vector_helmholtz_p7_24e, adjoint_p5_20e, large_p8_40e,
-stokes_32e (Taylor-Hood block operator apply, 32^3 hexes, p = 2..6),
+stokes_32e (Taylor-Hood block operator apply, 32^3 hexes, p = 2..6), convection (the
+N(u) term, 32^3 p = 4 and 24^3 p = 7),
 poisson_p2_4e, `sweep` (FP64/FP32 apply for p = 4..8 on meshes of 15-33M DoFs) and
 `mass_neumann` (collocated-mass-preconditioned mass solve and pure-Neumann Poisson solve).
 """
@@ -489,6 +490,44 @@ def run_stokes(a):
     return {"workload": "stokes_32e", "rows": rows}
 
 
+def run_convection(a):
+    """Convection term N(u) (three velocity components) on 32^3 hexes at p = 4 and 24^3 at
+    p = 7: GDoF/s over the 3 N velocity DoFs; bytes = coupling factors (9 per point) once,
+    u read and N(u) written once, the map once."""
+    import torch
+    from paper_1910_03032_amd import Operator
+    from workloads import BoxMesh, normal
+    rows = []
+    for ne, p in ((32, 4), (24, 7)):
+        m = BoxMesh(ne, p)
+        op = Operator(m.elem_xyz, m.elem_dofs, m.ndof, p, ess=m.ess)
+        dev = torch.device("cuda", 0)
+        u = torch.as_tensor(normal(3 * m.ndof, seed=1), device=dev).reshape(3, -1)
+        for _ in range(a.warmup):
+            op.convection(u)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        stream = torch.cuda.current_stream()
+        e0.record(stream)
+        for _ in range(a.steps):
+            op.convection(u)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / a.steps
+        q = p + 2
+        nbytes = m.nelem * q ** 3 * 9 * 8 + 2 * 3 * m.ndof * 8 + m.nelem * (p + 1) ** 3 * 4
+        row = {"p": p, "elements": f"{ne}^3", "velocity_dofs": 3 * m.ndof, "us": round(ms * 1e3, 2),
+               "GDoF/s": round(3 * m.ndof / (ms * 1e-3) / 1e9, 3), "algorithmic_bytes": nbytes,
+               "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        rows.append(row)
+        log(f"[bench] convection p={p}: {row['us']} us, {row['GDoF/s']} GDoF/s, {row['hbm_frac']:.3f} of HBM")
+        op.close()
+        del op
+        torch.cuda.empty_cache()
+    return {"workload": "convection", "rows": rows}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -507,6 +546,8 @@ def main():
         out = run_mass_neumann(a)
     elif a.workload == "stokes_32e":
         out = run_stokes(a)
+    elif a.workload == "convection":
+        out = run_convection(a)
     else:
         wl = WORKLOADS[a.workload]
         if a.workload == "vector_helmholtz_p7_24e":

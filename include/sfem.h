@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define SFEM_ABI_VERSION 3
+#define SFEM_ABI_VERSION 4
 #define SFEM_MAX_P 8
 
 typedef struct sfem_ctx sfem_ctx;
@@ -211,6 +211,14 @@ sfem_status sfem_setup_pressure(sfem_ctx *ctx, const int32_t *pres_dofs, int64_t
  * fields. */
 sfem_status sfem_stokes_apply(sfem_ctx *ctx, const double *u, const double *p, double *yu,
                               double *yp);
+
+/* Convection term of the Navier-Stokes problem (eq. nonlinear) on the velocity space:
+ *   y_{c,i} = sum_e sum_q w|J| phi_i ((u . grad) u)_c,
+ * u, y: [3][ndof] float64 (device, component-major).  u is taken with its boundary values;
+ * rows of essential DoFs are set to 0 (the term is a right-hand side of the constrained
+ * solves).  Uses the coupling factors w |J| J^{-T} (computed on first use).
+ * Asynchronous on the context stream.  Errors: SFEM_E_ARG for NULL or aliased arrays. */
+sfem_status sfem_convection(sfem_ctx *ctx, const double *u, double *y);
 
 typedef struct {
   int p, q;

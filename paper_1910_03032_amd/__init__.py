@@ -205,6 +205,17 @@ class Operator:
         self._check(self._lib.sfem_stokes_apply(self._h, _ptr(uu), _ptr(pp), _ptr(yu), _ptr(yp)))
         return yu, yp
 
+    def convection(self, u):
+        """Convection term N(u) [3, ndof] (float64) for the velocity u [3, ndof]; rows of
+        essential DoFs are 0."""
+        self._sync_stream()
+        uu = self._vec(u, torch.float64, "u")
+        if uu.ndim != 2 or uu.shape[0] != 3:
+            raise ValueError("u must have shape [3, ndof]")
+        y = torch.empty_like(uu)
+        self._check(self._lib.sfem_convection(self._h, _ptr(uu), _ptr(y)))
+        return y
+
     def collocated_mass(self):
         """Collocated (GLL-integrated) mass diagonal [ndof], essential entries 1 (float64)."""
         self._sync_stream()

@@ -22,7 +22,7 @@ EXPORTED = [
     "sfem_abi_version", "sfem_create", "sfem_destroy", "sfem_set_stream", "sfem_last_error",
     "sfem_setup", "sfem_qpoint_coords", "sfem_set_coeffs", "sfem_apply", "sfem_diagonal",
     "sfem_load", "sfem_collocated_mass", "sfem_pcg", "sfem_grad_nu", "sfem_get_info",
-    "sfem_setup_pressure", "sfem_stokes_apply",
+    "sfem_setup_pressure", "sfem_stokes_apply", "sfem_convection",
 ]
 
 
@@ -79,6 +79,7 @@ def load(path: str = LIB_PATH):
         "sfem_get_info": (i32, [vp, C.POINTER(CtxInfo)]),
         "sfem_setup_pressure": (i32, [vp, vp, i64]),
         "sfem_stokes_apply": (i32, [vp, vp, vp, vp, vp]),
+        "sfem_convection": (i32, [vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -1001,6 +1001,18 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
   return ret;
 }
 
+// Coupling factors w |J| J^{-T} at the quadrature points (Stokes blocks, convection),
+// computed on first use.
+sfem_status ensure_cq(sfem_ctx *c) {
+  if (c->d_cq || c->nelem == 0) return SFEM_OK;
+  sfem_status st;
+  const int64_t q3 = (int64_t)c->q * c->q * c->q;
+  if ((st = dalloc(c, &c->d_cq, c->nelem * 9 * q3)) != SFEM_OK) return st;
+  HIPCHK(c, launch_coupling_setup(c->q, c->rules.gauss_x.data(), c->rules.gauss_w.data(), c->d_xyz,
+                                  c->nelem, c->d_cq, c->stream));
+  return SFEM_OK;
+}
+
 sfem_status sfem_setup_pressure(sfem_ctx *c, const int32_t *pres_dofs, int64_t npres) {
   sfem_status st;
   if ((st = require_ready(c)) != SFEM_OK) return st;
@@ -1034,7 +1046,6 @@ sfem_status sfem_setup_pressure(sfem_ctx *c, const int32_t *pres_dofs, int64_t n
   if ((st = dalloc(c, &d_alist, hp.na)) != SFEM_OK) return st;
   if ((st = dalloc(c, &d_aoff, hp.na + 1)) != SFEM_OK) return st;
   if ((st = dalloc(c, &d_slot, (int64_t)hp.slots.size())) != SFEM_OK) return st;
-  if ((st = dalloc(c, &c->d_cq, c->nelem * 9 * q3)) != SFEM_OK) return st;
   if (c->nelem > 0)
     HIPCHK(c, hipMemcpyAsync(c->d_pmap, hp.imap.data(), hp.imap.size() * sizeof(int32_t),
                              hipMemcpyHostToDevice, c->stream));
@@ -1047,8 +1058,7 @@ sfem_status sfem_setup_pressure(sfem_ctx *c, const int32_t *pres_dofs, int64_t n
   if (!hp.slots.empty())
     HIPCHK(c, hipMemcpyAsync(d_slot, hp.slots.data(), hp.slots.size() * sizeof(int32_t),
                              hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, launch_coupling_setup(c->q, c->rules.gauss_x.data(), c->rules.gauss_w.data(), c->d_xyz,
-                                  c->nelem, c->d_cq, c->stream));
+  if ((st = ensure_cq(c)) != SFEM_OK) return st;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->pplan.alist = d_alist;
   c->pplan.aoff = d_aoff;
@@ -1103,6 +1113,34 @@ sfem_status sfem_stokes_apply(sfem_ctx *c, const double *u, const double *pres, 
                                     kEssAdd, nullptr, 0, c->stream));
   HIPCHK(c, launch_assemble<double>(c->pplan, Yp, 0, nullptr, yp, np, 1, kEssZero, nullptr, 0,
                                     c->stream));
+  return SFEM_OK;
+}
+
+sfem_status sfem_convection(sfem_ctx *c, const double *u, double *y) {
+  sfem_status st;
+  if ((st = require_ready(c)) != SFEM_OK) return st;
+  const int64_t nv = c->ndof;
+  if (nv == 0) return SFEM_OK;
+  if (!u || !y) return fail(c, SFEM_E_ARG, "u and y must not be NULL");
+  if ((const void *)u == (const void *)y) return fail(c, SFEM_E_ARG, "y must not alias u");
+  DeviceGuard g(c->device);
+  if ((st = ensure_cq(c)) != SFEM_OK) return st;
+  if ((st = ensure_evec(c, (size_t)c->nentries * 3 * sizeof(double))) != SFEM_OK) return st;
+  ConvArgs a{};
+  a.p = c->p;
+  a.nelem = c->nelem;
+  a.vmap = c->d_map;
+  a.vpos = c->d_pos;
+  a.vcompact = c->compact;
+  a.cq = c->d_cq;
+  a.u = u;
+  a.nv = nv;
+  a.Yv = (double *)c->evec.p;
+  a.vestride = c->nentries;
+  a.yv = y;
+  HIPCHK(c, launch_convection(a, c->stream));
+  HIPCHK(c, launch_assemble<double>(c->plan, (const double *)c->evec.p, c->nentries, nullptr, y, nv, 3,
+                                    kEssZero, nullptr, 0, c->stream));
   return SFEM_OK;
 }
 

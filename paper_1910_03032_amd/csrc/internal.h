@@ -103,6 +103,22 @@ struct StokesArgs {
   double *yp;               // [np]
 };
 hipError_t launch_stokes(const StokesArgs &a, hipStream_t s);
+// Convection term N(u) on the velocity space (three members): sole DoFs of y directly,
+// shared nodes into the velocity E-vector (assembled with kEssZero).
+struct ConvArgs {
+  int p;
+  int64_t nelem;
+  const int32_t *vmap;
+  const int32_t *vpos;
+  int vcompact;
+  const double *cq;         // coupling factors [nelem][9][q^3]
+  const double *u;          // [3][nv]
+  int64_t nv;
+  double *Yv;               // [3][vestride]
+  int64_t vestride;
+  double *yv;               // [3][nv]
+};
+hipError_t launch_convection(const ConvArgs &a, hipStream_t s);
 // coupling factors C = w |J| J^{-T} at the q^3 Gauss points, [nelem][9][q^3], slot 3c + d
 hipError_t launch_coupling_setup(int q, const double *gx, const double *gw, const double *xyz,
                                  int64_t nei, double *cq, hipStream_t s);

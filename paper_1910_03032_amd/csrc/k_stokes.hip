@@ -423,6 +423,169 @@ coupling_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ vp
   emit_pres<P>(buf, t, active, smap, es, pcompact != 0, Yp, yp);
 }
 
+// Gather of a velocity component with the values of every DoF, essential ones included
+// (the convection term takes u as it is).
+template <int P>
+__device__ __forceinline__ void gather_all(double *buf, int t, bool active, const int32_t *emap,
+                                           const double *__restrict__ x) {
+  using D = Dims<P>;
+  constexpr int NL = Per<P>::NL;
+  int32_t c[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int l0 = t + k * D::TPE;
+    c[k] = emap[l0 < D::N3 ? l0 : D::N3 - 1];
+  }
+  double v[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) v[k] = x[c[k] & kDofMask];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int l = t + k * D::TPE;
+    if (l < D::N3) buf[l] = active ? v[k] : 0.0;
+  }
+  __syncthreads();
+}
+
+// Interpolation of a nodal field of order P to the points, stages xi_1 and xi_2 (B only):
+// afterwards buf holds [k][b][a] and each thread reads its xi_3 line.
+template <int P, int Q>
+__device__ __forceinline__ void fwd_val_xy(double *buf, int t) {
+  constexpr int NI = P + 1, N2 = NI * NI;
+  using BT = TabEO<P, Q, 0>;
+  {
+    const bool w = t < N2;
+    const int j = t % NI, k = t / NI;
+    double ob[Q];
+    if (w) {
+      double in[NI];
+#pragma unroll
+      for (int i = 0; i < NI; ++i) in[i] = buf[(k * NI + j) * NI + i];
+      eo::apply<BT>(eo::split(in), ob);
+    }
+    __syncthreads();
+    if (w) {
+#pragma unroll
+      for (int a = 0; a < Q; ++a) buf[(k * NI + j) * Q + a] = ob[a];
+    }
+    __syncthreads();
+  }
+  {
+    const bool w = t < Q * NI;
+    const int a = t % Q, k = t / Q;
+    double ob[Q];
+    if (w) {
+      double in[NI];
+#pragma unroll
+      for (int j = 0; j < NI; ++j) in[j] = buf[(k * NI + j) * Q + a];
+      eo::apply<BT>(eo::split(in), ob);
+    }
+    __syncthreads();
+    if (w) {
+#pragma unroll
+      for (int b = 0; b < Q; ++b) buf[(k * Q + b) * Q + a] = ob[b];
+    }
+    __syncthreads();
+  }
+}
+
+// Convection term N(u) (eq. nonlinear) on the velocity space: per point, with the
+// coupling factor C = w |J| J^{-T}, n_c = sum_d u_d (C grad_ref u_c)_d, tested against
+// the velocity basis.  First the three components' values at the points (held per
+// thread), then per component its reference gradient, n_c, and the output (member c of
+// the velocity E-vector and of y; essential rows get nothing).
+template <int P, bool POS>
+__global__ void __launch_bounds__(Dims<P>::THREADS)
+convection_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ vpos,
+                  int vcompact, const double *__restrict__ cq, int64_t nelem,
+                  const double *__restrict__ u, int64_t nv, double *__restrict__ Yv,
+                  int64_t vestride, double *__restrict__ yv) {
+  using S = SDims<P>;
+  using D = Dims<P>;
+  constexpr int N = S::N, Q = S::Q, Q2 = S::Q2, Q3 = S::Q3, TPE = S::TPE, E = S::E;
+  constexpr int N3 = N * N * N;
+  using VB = TabEO<P, Q, 0>;
+  using VG = TabEO<P, Q, 1>;
+  __shared__ __align__(16) double smem[E * D::BUF];
+  __shared__ int32_t smap_all[E * N3];
+  const int le = threadIdx.x / TPE;
+  const int t0 = threadIdx.x - le * TPE;
+  const int e = xcd_block() * E + le;
+  const bool active = e < nelem;
+  const int es = active ? e : 0;
+  double *buf = smem + le * D::BUF;
+  int32_t *smap = smap_all + le * N3;
+  const int32_t *emap = vmap + (int64_t)es * N3;
+  // values of the three components at the points of this thread's xi_3 line
+  double uq[3][Q];
+  auto values = [&](int r, double (&out)[Q]) {
+    gather_all<P>(buf, t0, active, emap, u + r * nv);
+    fwd_val_xy<P, Q>(buf, t0);
+    double zb[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) zb[k] = buf[k * Q2 + t0];
+    const auto sb = eo::split(zb);
+#pragma unroll
+    for (int c = 0; c < Q / 2; ++c) row_pair<VB>(sb, c, out[c], out[Q - 1 - c]);
+    if constexpr (Q % 2 == 1) out[Q / 2] = row_mid<VB>(sb);
+    __syncthreads();  // buf is reused by the next gather
+  };
+  values(0, uq[0]);
+  values(1, uq[1]);
+  values(2, uq[2]);
+  const int64_t vepe = vcompact ? surf_count<P>() : N3;
+  vel_entries<P, POS>(t0, emap, smap, POS ? vpos + (int64_t)es * vepe : nullptr, vcompact != 0);
+  const double *ce = cq + (int64_t)es * (9 * Q3) + t0;
+#pragma unroll 1
+  for (int r = 0; r < 3; ++r) {
+    // indices derived from the thread are recomputed per component rather than kept live
+    int t = t0;
+    asm volatile("" : "+v"(t));
+    gather_all<P>(buf, t, active, emap, u + r * nv);
+    fwd_grad_xy<P, Q>(buf, t);
+    eo::Split<N, double> sbb, sgb, sbg;
+    {
+      double zb[N], zg[N], zx[N];
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        zb[k] = buf[k * Q2 + t];
+        zg[k] = buf[N * Q2 + k * Q2 + t];
+        zx[k] = buf[2 * N * Q2 + k * Q2 + t];
+      }
+      sbb = eo::split(zb);
+      sgb = eo::split(zg);
+      sbg = eo::split(zx);
+    }
+    // the coupling factors are read again for each component (L2 hits) rather than held
+    // in registers across the component loop
+    const double *cl = ce;
+    asm volatile("" : "+v"(cl));
+    double n[1][Q];
+    auto point = [&](int c, double gx, double gy, double gz) {
+      const double *cp = cl + c * Q2;
+      double acc = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        acc += uq[d][c] * (cp[(3 * d) * Q3] * gx + cp[(3 * d + 1) * Q3] * gy + cp[(3 * d + 2) * Q3] * gz);
+      n[0][c] = acc;
+    };
+#pragma unroll
+    for (int c = 0; c < Q / 2; ++c) {
+      double gz0, gz1, gy0, gy1, gx0, gx1;
+      row_pair<VG>(sbb, c, gz0, gz1);
+      row_pair<VB>(sgb, c, gy0, gy1);
+      row_pair<VB>(sbg, c, gx0, gx1);
+      point(c, gx0, gy0, gz0);
+      point(Q - 1 - c, gx1, gy1, gz1);
+    }
+    if constexpr (Q % 2 == 1) point(Q / 2, row_mid<VB>(sbg), row_mid<VB>(sgb), row_mid<VG>(sbb));
+    bwd_mass<P, Q, 1>(buf, t, n);
+    emit_e<P, double, false, POS>(buf, t, active, smap, u, es, vcompact != 0, Yv + r * vestride,
+                                  yv + r * nv);
+    __syncthreads();  // buf is reused by the next gather
+  }
+}
+
 template <int P>
 hipError_t launch_stokes_pt(const StokesArgs &a, hipStream_t s) {
   if constexpr (P < 2) {
@@ -441,10 +604,29 @@ hipError_t launch_stokes_pt(const StokesArgs &a, hipStream_t s) {
   }
 }
 
+template <int P>
+hipError_t launch_convection_pt(const ConvArgs &a, hipStream_t s) {
+  using D = Dims<P>;
+  if (a.nelem <= 0) return hipSuccess;
+  constexpr bool POS = evec_dof_ordered(P);
+  if ((a.vpos != nullptr) != POS) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((a.nelem + D::E - 1) / D::E));
+  dim3 block(D::THREADS);
+  hipLaunchKernelGGL((convection_kernel<P, POS>), grid, block, 0, s, a.vmap, a.vpos, a.vcompact,
+                     a.cq, a.nelem, a.u, a.nv, a.Yv, a.vestride, a.yv);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_stokes(const StokesArgs &a, hipStream_t s) {
 #define SFEM_CALL(P) launch_stokes_pt<P>(a, s)
+  SFEM_DISPATCH_P(a.p, SFEM_CALL)
+#undef SFEM_CALL
+}
+
+hipError_t launch_convection(const ConvArgs &a, hipStream_t s) {
+#define SFEM_CALL(P) launch_convection_pt<P>(a, s)
   SFEM_DISPATCH_P(a.p, SFEM_CALL)
 #undef SFEM_CALL
 }
