@@ -62,7 +62,7 @@ def log(*a):
 KERNEL_SOURCES = ["apply_impl.h", "eo.h", "rules.h", "internal.h", "plan.h", "k_apply_f64.hip", "k_vec.hip"]
 MEASURED_TRAFFIC = {
     # profiles/helmholtz_apply_p4_32e_hbm_bytes.md
-    ("410540c333c684a2", "helmholtz_p4_32e"): 558513072,
+    ("2edf44f0d6ea3141", "helmholtz_p4_32e"): 558234274,
 }
 
 
@@ -438,6 +438,37 @@ def run_sweep(a):
     return {"workload": "sweep", "rows": rows}
 
 
+def run_size_sweep(a):
+    """Throughput of the FP64 mass (M) and diffusion (L = K(nu)) applies against problem size
+    for p = 2..6, the view of the paper's operator-throughput figure (Section 6): from a
+    few thousand DoFs (launch-bound, working set inside the 256 MB last-level cache) to
+    1e7+ DoFs.  One operator copy, so small sizes run from that cache, as in the paper."""
+    torch = __import__("torch")
+    from paper_1910_03032_amd import DIFFUSION, MASS
+    from workloads import normal
+    rows = []
+    for p in (2, 3, 4, 5, 6):
+        sizes = (2, 4, 8, 16, 32, 64, 128) if p == 2 else (2, 4, 8, 16, 32, 64) if p == 3 else \
+            (2, 4, 8, 16, 32, 48)
+        for ne in sizes:
+            B = Bench(ne, p, 1.0, 1.0)
+            N = B.m.ndof
+            x = torch.as_tensor(normal(N, seed=1), device=B.dev)
+            y = torch.empty_like(x)
+            row = {"p": p, "elements": f"{ne}^3", "ndof": N}
+            for name, opk in (("M", MASS), ("L", DIFFUSION)):
+                ms = B.timed(lambda: B.op.apply(x, op=opk, out=y), steps=max(a.steps, 20),
+                             warmup=max(a.warmup, 3))
+                row[name] = {"us": round(ms * 1e3, 2), "GDoF/s": round(N / (ms * 1e-3) / 1e9, 3)}
+            rows.append(row)
+            log(f"[bench] size sweep p={p} {ne}^3 ({N} DoFs): M {row['M']['GDoF/s']} GDoF/s, "
+                f"L {row['L']['GDoF/s']} GDoF/s")
+            B.close()
+            del B, x, y
+            torch.cuda.empty_cache()
+    return {"workload": "size_sweep", "rows": rows}
+
+
 def stokes_bytes(nelem, p, nv, npres):
     """Bytes a Stokes block apply must move: the folded Helmholtz factors (7 per point) and
     the coupling factors (9 per point) once, u and p read and y_u, y_p written once, both
@@ -491,14 +522,16 @@ def run_stokes(a):
 
 
 def run_convection(a):
-    """Convection term N(u) (three velocity components) on 32^3 hexes at p = 4 and 24^3 at
-    p = 7: GDoF/s over the 3 N velocity DoFs; bytes = coupling factors (9 per point) once,
-    u read and N(u) written once, the map once."""
+    """Convection term N(u) (three velocity components) over p = 1..8, the throughput-vs-order
+    view of the nonlinear term (Section 6, figure on the shared-memory convection
+    evaluation), 1.8-4.8 M DoFs per component (32^3 hexes at p = 4, 24^3 at p = 7): GDoF/s
+    over the 3 N velocity DoFs; bytes = coupling factors (9 per point) once, u read and N(u)
+    written once, the map once."""
     import torch
     from paper_1910_03032_amd import Operator
     from workloads import BoxMesh, normal
     rows = []
-    for ne, p in ((32, 4), (24, 7)):
+    for p, ne in ((1, 128), (2, 64), (3, 40), (4, 32), (5, 28), (6, 24), (7, 24), (8, 20)):
         m = BoxMesh(ne, p)
         op = Operator(m.elem_xyz, m.elem_dofs, m.ndof, p, ess=m.ess)
         dev = torch.device("cuda", 0)
@@ -531,8 +564,9 @@ def run_convection(a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of "
-                                   "this build (the sharding design is described in DESIGN.md)",
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the library has no "
+                                   "multi-GPU path (the apply would shard by element slabs with "
+                                   "an interface-plane exchange, which is not built)",
                           "n_gpus": a.gpus}))
         return 2
     if a.copy_mb > 0:
@@ -548,6 +582,8 @@ def main():
         out = run_stokes(a)
     elif a.workload == "convection":
         out = run_convection(a)
+    elif a.workload == "size_sweep":
+        out = run_size_sweep(a)
     else:
         wl = WORKLOADS[a.workload]
         if a.workload == "vector_helmholtz_p7_24e":

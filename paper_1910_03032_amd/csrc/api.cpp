@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "flow.h"
 
 using namespace sfem;
 

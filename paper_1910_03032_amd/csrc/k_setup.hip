@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "flow.h"
 
 namespace sfem {
 namespace {

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include "apply_impl.h"
+#include "flow.h"
 
 namespace sfem {
 namespace {

@@ -129,3 +129,27 @@ def test_stokes_errors():
     with pytest.raises(SfemError, match="SFEM_E_ARG"):
         op.stokes_apply(gpu(np.zeros((3, v.ndof))), gpu(np.zeros(m.npres)))
     op.close()
+
+
+@pytest.mark.parametrize("p", [2, 5])
+def test_stokes_and_convection_on_fan_mesh(p):
+    """Unstructured fan mesh (axis DoFs shared by 3 or 6 elements in both the velocity and
+    the pressure maps): the block apply and the convection term match the oracle."""
+    from oracle import convection
+    from paper_1910_03032_amd import Operator
+    from workloads import FanMesh
+    m, pm = FanMesh(p), FanMesh(p - 1)
+    say(f"[stokes] fan mesh p={p} nv={m.ndof} np={pm.ndof}")
+    q = p + 2
+    nu = nu_uniform(m.nelem, q, seed=4)
+    op = Operator(m.elem_xyz, m.elem_dofs, m.ndof, p, ess=m.ess)
+    op.set_coeffs(2.0, 0.7, gpu(nu))
+    op.setup_pressure(pm.elem_dofs, pm.ndof)
+    S = StokesDiscretization(m.elem_xyz, m.elem_dofs, m.ess, m.ndof, pm.elem_dofs, pm.ndof, p, q)
+    u = uniform(3 * m.ndof, seed=14).reshape(3, -1)
+    pres = uniform(pm.ndof, seed=15)
+    yu, yp = op.stokes_apply(gpu(u), gpu(pres))
+    ou, opp = S.apply(u, pres, 2.0, 0.7, nu)
+    assert rel(host(yu), ou) <= 1e-12 and rel(host(yp), opp) <= 1e-12
+    assert rel(host(op.convection(gpu(u))), convection(S.vel, u)) <= 1e-12
+    op.close()

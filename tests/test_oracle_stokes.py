@@ -189,3 +189,33 @@ def test_convection_planted_transpose_fails():
     free = ~m.ess.astype(bool)
     ref = d.apply_unconstrained(adv[0], 1.0, 0.0)
     assert rel(y[0, free], ref[free]) > 1e-6
+
+
+def test_fan_mesh_blocks_pins():
+    """On the unstructured fan mesh (axis nodes shared by 3 or 6 elements, pressure map
+    from the same mesh at order p - 1) the linear-field pins of the gradient, the
+    divergence and the convection term hold as on the box."""
+    from oracle import Discretization, convection
+    from workloads import FanMesh
+    p = 3
+    m, pm = FanMesh(p), FanMesh(p - 1)
+    S = StokesDiscretization(m.elem_xyz, m.elem_dofs, m.ess, m.ndof, pm.elem_dofs, pm.ndof, p,
+                             p + 2)
+    a = np.array([0.7, -1.3, 2.1])
+    mass1 = S.vel.apply_unconstrained(np.ones(m.ndof), 1.0, 0.0)
+    g = S.gradient(S.pressure_node_coords() @ a + 0.4)
+    for c in range(3):
+        assert rel(g[c], a[c] * mass1) <= 1e-13
+    A = np.array([[0.3, -0.2, 0.5], [1.1, -0.4, 0.25], [-0.6, 0.8, 0.9]])
+    b = np.array([0.1, -0.2, 0.3])
+    x = S.velocity_node_coords()
+    u = (x @ A.T + b).T
+    assert rel(S.divergence(u), np.trace(A) * S.pressure_mass_rowsums()) <= 1e-13
+    assert abs(S.pressure_mass_rowsums().sum() - 3 * np.sin(np.pi / 3)) <= 1e-13
+    d = Discretization(m.elem_xyz, m.elem_dofs, m.ess, m.ndof, p, p + 2)
+    y = convection(d, u)
+    adv = ((x @ A.T + b) @ A.T).T
+    free = ~m.ess.astype(bool)
+    for c in range(3):
+        ref = d.apply_unconstrained(adv[c], 1.0, 0.0)
+        assert rel(y[c, free], ref[free]) <= 1e-13
