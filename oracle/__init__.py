@@ -13,6 +13,8 @@ Contents:
   stokes      the Taylor-Hood gradient and divergence blocks and the constrained Stokes
               block operator (Section 3, eq. gradient, eq. divergence); the convection
               term N(u) (eq. nonlinear)
+  flow        equal-order weak gradient, curl and divergence, BDF-k/EXT-k coefficients
+              and the velocity-correction projection step (Section 4.2)
   solvers     diagonally preconditioned CG (optionally orthogonalized against the
               constants), FP32-inner iterative refinement, adjoint gradient, pure-Neumann
               Poisson with the mean-zero condition (Section 5, Section 5.3)
@@ -24,3 +26,5 @@ from .quadrature import gauss_legendre, gll, lagrange_values, lagrange_derivs, l
 from .fem import Discretization, OP_MASS, OP_DIFFUSION, OP_HELMHOLTZ, op_coeffs  # noqa: F401
 from .solvers import pcg, ir_pcg, adjoint_gradient, objective, neumann_poisson  # noqa: F401
 from .stokes import StokesDiscretization, convection  # noqa: F401
+from .flow import (weak_gradient, weak_curl, weak_divergence, bdf_ext,  # noqa: F401
+                   ProjectionStepper)
