@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define SFEM_ABI_VERSION 4
+#define SFEM_ABI_VERSION 5
 #define SFEM_MAX_P 8
 
 typedef struct sfem_ctx sfem_ctx;
@@ -219,6 +219,36 @@ sfem_status sfem_stokes_apply(sfem_ctx *ctx, const double *u, const double *p, d
  * solves).  Uses the coupling factors w |J| J^{-T} (computed on first use).
  * Asynchronous on the context stream.  Errors: SFEM_E_ARG for NULL or aliased arrays. */
 sfem_status sfem_convection(sfem_ctx *ctx, const double *u, double *y);
+
+/* Equal-order weak vector operators of the projection step (Section 4.2, the pressure
+ * Poisson right-hand side of eq. pres-poisson and the pressure gradient of
+ * eq. proj-helmholtz), every field in the scalar space of the context:
+ *   SFEM_WEAK_GRADIENT    y_{c,i} = sum_e sum_q w|J| phi_i (grad x)_c
+ *                         x: [ndof], y: [3][ndof]
+ *   SFEM_WEAK_CURL        y_{c,i} = sum_e sum_q w|J| phi_i (curl x)_c
+ *                         x, y: [3][ndof]
+ *   SFEM_WEAK_DIVERGENCE  y_i = sum_e sum_q w|J| grad phi_i . x
+ *                         x: [3][ndof], y: [ndof]
+ * (float64, device, component-major; grad = J^{-T} grad_ref at the Gauss points.)  x is
+ * taken with all its values; rows of essential DoFs are set to 0 (a context without
+ * essential DoFs gives every row).  Uses the coupling factors w |J| J^{-T} (computed on
+ * first use).  Asynchronous on the context stream.  Errors: SFEM_E_ARG for a bad kind or
+ * NULL or aliased arrays. */
+#define SFEM_WEAK_GRADIENT 1
+#define SFEM_WEAK_CURL 2
+#define SFEM_WEAK_DIVERGENCE 3
+sfem_status sfem_weak_op(sfem_ctx *ctx, int kind, const double *x, double *y);
+
+/* Nodal combination of the projection step (eq. projKnown, the extrapolations of
+ * Section 4.2 and the nodal fields B^{-1} y of the collocated mass B, Section 5.1):
+ *   y[m][i] = (sum_{j < nterm} coef[j] xs[j][m][i]) / scale[i],   0 where mask[i] != 0,
+ * for nb members of length n.  coef: host array [nterm] (1 <= nterm <= 8); xs: host array
+ * of nterm device pointers to [nb][n] float64; scale: device [n] float64 or NULL (no
+ * division); mask: device [n] uint8 or NULL; y: device [nb][n] float64, which may be one
+ * of the xs[j].  Asynchronous on the context stream.  Errors: SFEM_E_ARG for a bad nterm,
+ * sizes or NULL arrays. */
+sfem_status sfem_lincomb(sfem_ctx *ctx, int nterm, const double *coef, const double *const *xs,
+                         const double *scale, const uint8_t *mask, int64_t n, int nb, double *y);
 
 typedef struct {
   int p, q;

@@ -14,9 +14,10 @@ import torch  # loads the HIP runtime the library binds to
 
 from . import _lib
 from ._lib import (F32, F64, MASS, DIFFUSION, HELMHOLTZ, PRECOND_JACOBI, PRECOND_COLLOCATED_MASS,  # noqa: F401
-                   SfemError, PcgOpts, PcgInfo, CtxInfo)
+                   WEAK_GRADIENT, WEAK_CURL, WEAK_DIVERGENCE, SfemError, PcgOpts, PcgInfo, CtxInfo)
 
-__all__ = ["Operator", "SfemError", "MASS", "DIFFUSION", "HELMHOLTZ", "F64", "F32", "PcgResult"]
+__all__ = ["Operator", "SfemError", "MASS", "DIFFUSION", "HELMHOLTZ", "F64", "F32", "PcgResult",
+           "WEAK_GRADIENT", "WEAK_CURL", "WEAK_DIVERGENCE", "ProjectionStepper"]
 
 
 def _ptr(t):
@@ -216,6 +217,39 @@ class Operator:
         self._check(self._lib.sfem_convection(self._h, _ptr(uu), _ptr(y)))
         return y
 
+    def weak_op(self, kind, x):
+        """Equal-order weak gradient ([ndof] -> [3, ndof]), curl ([3, ndof] -> [3, ndof]) or
+        divergence ([3, ndof] -> [ndof]) of the projection step (float64); rows of
+        essential DoFs are 0."""
+        self._sync_stream()
+        xx = self._vec(x, torch.float64, "x")
+        nin = 1 if kind == WEAK_GRADIENT else 3
+        if (nin == 1 and xx.ndim != 1) or (nin == 3 and (xx.ndim != 2 or xx.shape[0] != 3)):
+            raise ValueError("x must have shape [ndof] (gradient) or [3, ndof] (curl, divergence)")
+        shape = (self.ndof,) if kind == WEAK_DIVERGENCE else (3, self.ndof)
+        y = torch.empty(shape, dtype=torch.float64, device=self.device)
+        self._check(self._lib.sfem_weak_op(self._h, int(kind), _ptr(xx), _ptr(y)))
+        return y
+
+    def lincomb(self, coefs, xs, scale=None, mask=None, out=None):
+        """sum_j coefs[j] xs[j], divided by scale [ndof] and zeroed where mask [ndof] != 0
+        (both optional); every xs[j] of the same shape [..., ndof] (float64)."""
+        self._sync_stream()
+        xs = [self._vec(x, torch.float64, "x") for x in xs]
+        if len(xs) != len(coefs) or not xs or any(x.shape != xs[0].shape for x in xs):
+            raise ValueError("one coefficient per input, all inputs of one shape")
+        nb = xs[0].numel() // self.ndof
+        sc = None if scale is None else self._vec(scale, torch.float64, "scale")
+        mk = None if mask is None else self._vec(mask, torch.uint8, "mask")
+        y = torch.empty_like(xs[0]) if out is None else out
+        if y.shape != xs[0].shape or y.dtype != torch.float64 or not y.is_contiguous():
+            raise ValueError("out must be a contiguous float64 tensor of the inputs' shape")
+        cf = (C.c_double * len(xs))(*[float(c) for c in coefs])
+        pv = (C.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
+        self._check(self._lib.sfem_lincomb(self._h, len(xs), cf, pv, _ptr(sc), _ptr(mk), self.ndof,
+                                           nb, _ptr(y)))
+        return y
+
     def collocated_mass(self):
         """Collocated (GLL-integrated) mass diagonal [ndof], essential entries 1 (float64)."""
         self._sync_stream()
@@ -244,3 +278,6 @@ class Operator:
         infos = (PcgInfo * nb)()
         st = self._check(self._lib.sfem_pcg(self._h, op, nb, _ptr(bv), _ptr(xv), C.byref(opts), infos))
         return xv, PcgResult(list(infos), st)
+
+
+from .flow import ProjectionStepper  # noqa: E402,F401

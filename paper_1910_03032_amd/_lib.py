@@ -17,12 +17,13 @@ STATUS_NAMES = {
 F64, F32 = 0, 1
 PRECOND_JACOBI, PRECOND_COLLOCATED_MASS = 0, 1
 MASS, DIFFUSION, HELMHOLTZ = 0, 1, 2
+WEAK_GRADIENT, WEAK_CURL, WEAK_DIVERGENCE = 1, 2, 3
 
 EXPORTED = [
     "sfem_abi_version", "sfem_create", "sfem_destroy", "sfem_set_stream", "sfem_last_error",
     "sfem_setup", "sfem_qpoint_coords", "sfem_set_coeffs", "sfem_apply", "sfem_diagonal",
     "sfem_load", "sfem_collocated_mass", "sfem_pcg", "sfem_grad_nu", "sfem_get_info",
-    "sfem_setup_pressure", "sfem_stokes_apply", "sfem_convection",
+    "sfem_setup_pressure", "sfem_stokes_apply", "sfem_convection", "sfem_weak_op", "sfem_lincomb",
 ]
 
 
@@ -80,6 +81,8 @@ def load(path: str = LIB_PATH):
         "sfem_setup_pressure": (i32, [vp, vp, i64]),
         "sfem_stokes_apply": (i32, [vp, vp, vp, vp, vp]),
         "sfem_convection": (i32, [vp, vp, vp]),
+        "sfem_weak_op": (i32, [vp, i32, vp, vp]),
+        "sfem_lincomb": (i32, [vp, i32, C.POINTER(dbl), C.POINTER(vp), vp, vp, i64, i32, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -1145,6 +1145,59 @@ sfem_status sfem_convection(sfem_ctx *c, const double *u, double *y) {
   return SFEM_OK;
 }
 
+sfem_status sfem_weak_op(sfem_ctx *c, int kind, const double *x, double *y) {
+  sfem_status st;
+  if ((st = require_ready(c)) != SFEM_OK) return st;
+  if (kind != SFEM_WEAK_GRADIENT && kind != SFEM_WEAK_CURL && kind != SFEM_WEAK_DIVERGENCE)
+    return fail(c, SFEM_E_ARG, "kind must be SFEM_WEAK_GRADIENT, SFEM_WEAK_CURL or SFEM_WEAK_DIVERGENCE");
+  const int64_t nv = c->ndof;
+  if (nv == 0) return SFEM_OK;
+  if (!x || !y) return fail(c, SFEM_E_ARG, "x and y must not be NULL");
+  if ((const void *)x == (const void *)y) return fail(c, SFEM_E_ARG, "y must not alias x");
+  DeviceGuard g(c->device);
+  if ((st = ensure_cq(c)) != SFEM_OK) return st;
+  if ((st = ensure_evec(c, (size_t)c->nentries * 3 * sizeof(double))) != SFEM_OK) return st;
+  ConvArgs a{};
+  a.kind = kind == SFEM_WEAK_GRADIENT ? kWeakGradient
+                                      : (kind == SFEM_WEAK_CURL ? kWeakCurl : kWeakDivergence);
+  a.p = c->p;
+  a.nelem = c->nelem;
+  a.vmap = c->d_map;
+  a.vpos = c->d_pos;
+  a.vcompact = c->compact;
+  a.cq = c->d_cq;
+  a.u = x;
+  a.nv = nv;
+  a.Yv = (double *)c->evec.p;
+  a.vestride = c->nentries;
+  a.yv = y;
+  HIPCHK(c, launch_convection(a, c->stream));
+  const int nout = kind == SFEM_WEAK_DIVERGENCE ? 1 : 3;
+  HIPCHK(c, launch_assemble<double>(c->plan, (const double *)c->evec.p, c->nentries, nullptr, y, nv,
+                                    nout, kEssZero, nullptr, 0, c->stream));
+  return SFEM_OK;
+}
+
+sfem_status sfem_lincomb(sfem_ctx *c, int nterm, const double *coef, const double *const *xs,
+                         const double *scale, const uint8_t *mask, int64_t n, int nb, double *y) {
+  sfem_status st;
+  if ((st = require_ready(c)) != SFEM_OK) return st;
+  if (nterm < 1 || nterm > kMaxLinTerms) return fail(c, SFEM_E_ARG, "1 <= nterm <= 8 is required");
+  if (n < 0 || nb < 0) return fail(c, SFEM_E_ARG, "n and nb must be >= 0");
+  if (n == 0 || nb == 0) return SFEM_OK;
+  if (!coef || !xs || !y) return fail(c, SFEM_E_ARG, "coef, xs and y must not be NULL");
+  LinComb lc{};
+  lc.nterm = nterm;
+  for (int j = 0; j < nterm; ++j) {
+    if (!xs[j]) return fail(c, SFEM_E_ARG, "xs[j] must not be NULL");
+    lc.c[j] = coef[j];
+    lc.x[j] = xs[j];
+  }
+  DeviceGuard g(c->device);
+  HIPCHK(c, launch_lincomb(lc, scale, mask, y, n, nb, c->stream));
+  return SFEM_OK;
+}
+
 sfem_status sfem_get_info(const sfem_ctx *c, sfem_ctx_info *out) {
   if (!c || !out) return SFEM_E_ARG;
   out->p = c->p;

@@ -32,9 +32,13 @@ struct StokesArgs {
   double *yp;               // [np]
 };
 hipError_t launch_stokes(const StokesArgs &a, hipStream_t s);
-// Convection term N(u) on the velocity space (three members): sole DoFs of y directly,
-// shared nodes into the velocity E-vector (assembled with kEssZero).
+// Convection term N(u) on the velocity space (three members), or one of the equal-order
+// weak vector operators of the projection step (gradient: one input member, three
+// outputs; curl: three and three; divergence: three inputs, one output): sole DoFs of y
+// directly, shared nodes into the E-vector (assembled with kEssZero).
+enum WeakKind { kWeakConvection = 0, kWeakGradient = 1, kWeakCurl = 2, kWeakDivergence = 3 };
 struct ConvArgs {
+  int kind;                 // WeakKind (the convection term or a weak vector operator)
   int p;
   int64_t nelem;
   const int32_t *vmap;
@@ -48,6 +52,16 @@ struct ConvArgs {
   double *yv;               // [3][nv]
 };
 hipError_t launch_convection(const ConvArgs &a, hipStream_t s);
+// y[m][i] = (sum_j c_j x_j[m][i]) / scale[i] (scale optional), 0 where mask[i] != 0
+// (mask optional), for nb members of length n; y may be one of the x_j.
+constexpr int kMaxLinTerms = 8;
+struct LinComb {
+  int nterm;
+  double c[kMaxLinTerms];
+  const double *x[kMaxLinTerms];
+};
+hipError_t launch_lincomb(const LinComb &lc, const double *scale, const uint8_t *mask, double *y,
+                          int64_t n, int nb, hipStream_t s);
 // coupling factors C = w |J| J^{-T} at the q^3 Gauss points, [nelem][9][q^3], slot 3c + d
 hipError_t launch_coupling_setup(int q, const double *gx, const double *gw, const double *xyz,
                                  int64_t nei, double *cq, hipStream_t s);

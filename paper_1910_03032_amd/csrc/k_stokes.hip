@@ -490,24 +490,34 @@ __device__ __forceinline__ void fwd_val_xy(double *buf, int t) {
   }
 }
 
-// Convection term N(u) (eq. nonlinear) on the velocity space: per point, with the
-// coupling factor C = w |J| J^{-T}, n_c = sum_d u_d (C grad_ref u_c)_d, tested against
-// the velocity basis.  One gather and forward pass per component (value and reference
-// gradient from the same xi_1/xi_2 stages), the three components' xi_3 lines held per
-// thread, C read once per point, then the three outputs (member c of the velocity
-// E-vector and of y; essential rows get nothing).  (Two passes, values first and then
-// per component its gradient, hold fewer registers but measured 441 vs 264 us at 32^3
-// p = 4 and 620 vs 576 us at 24^3 p = 7.)
-template <int P, bool POS>
-__global__ void __launch_bounds__(Dims<P>::THREADS)
-convection_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ vpos,
-                  int vcompact, const double *__restrict__ cq, int64_t nelem,
-                  const double *__restrict__ u, int64_t nv, double *__restrict__ Yv,
-                  int64_t vestride, double *__restrict__ yv) {
+// Pointwise products of the element kernels below that test against the basis values
+// (the three outputs are tested against phi): with the coupling factor C = w |J| J^{-T}
+// and Gamma_dr = sum_k C_dk d_ref_k u_r = w |J| d u_r / d x_d,
+//   kConvection:   n_c = sum_d u_d Gamma_dc               (eq. nonlinear)
+//   kCurl:         n_c = eps_cde Gamma_de                  (w |J| (curl u)_c)
+//   kGradient:     n_c = Gamma_c0 (one input field s)      (w |J| (grad s)_c)
+enum PointMode { kConvection = 0, kCurl = 1, kGradient = 2 };
+
+// Convection term N(u) (eq. nonlinear) on the velocity space, and the equal-order weak
+// curl and gradient of the projection step (Section 4.2), which share its stages: one
+// gather and forward pass per input component (value and reference gradient from the
+// same xi_1/xi_2 stages), the components' xi_3 lines held per thread, C read once per
+// point, then the three outputs (member c of the velocity E-vector and of y; essential
+// rows get nothing).  (For the convection term, two passes, values first and then per
+// component its gradient, hold fewer registers but measured 441 vs 264 us at 32^3 p = 4
+// and 620 vs 576 us at 24^3 p = 7.)
+template <int P, bool POS, int MODE>
+__device__ __forceinline__ void phi_test_body(const int32_t *__restrict__ vmap,
+                                              const int32_t *__restrict__ vpos, int vcompact,
+                                              const double *__restrict__ cq, int64_t nelem,
+                                              const double *__restrict__ u, int64_t nv,
+                                              double *__restrict__ Yv, int64_t vestride,
+                                              double *__restrict__ yv) {
   using S = SDims<P>;
   using D = Dims<P>;
   constexpr int N = S::N, Q = S::Q, Q2 = S::Q2, Q3 = S::Q3, TPE = S::TPE, E = S::E;
   constexpr int N3 = N * N * N;
+  constexpr int NIN = MODE == kGradient ? 1 : 3;
   using VB = TabEO<P, Q, 0>;
   using VG = TabEO<P, Q, 1>;
   __shared__ __align__(16) double smem[E * D::BUF];
@@ -520,11 +530,11 @@ convection_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ 
   double *buf = smem + le * D::BUF;
   int32_t *smap = smap_all + le * N3;
   const int32_t *emap = vmap + (int64_t)es * N3;
-  // the three components' xi_3 lines (value and reference-gradient fields, even-odd
+  // the input components' xi_3 lines (value and reference-gradient fields, even-odd
   // split), one gather and one forward pass each
-  eo::Split<N, double> sbb[3], sgb[3], sbg[3];
+  eo::Split<N, double> sbb[NIN], sgb[NIN], sbg[NIN];
 #pragma unroll
-  for (int r = 0; r < 3; ++r) {
+  for (int r = 0; r < NIN; ++r) {
     gather_all<P>(buf, t0, active, emap, u + r * nv);
     fwd_grad_xy<P, Q>(buf, t0);
     double zb[N], zg[N], zx[N];
@@ -542,27 +552,39 @@ convection_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ 
   const int64_t vepe = vcompact ? surf_count<P>() : N3;
   vel_entries<P, POS>(t0, emap, smap, POS ? vpos + (int64_t)es * vepe : nullptr, vcompact != 0);
   const double *ce = cq + (int64_t)es * (9 * Q3) + t0;
-  // n_c at the points of the line: sum_d u_d (C grad_ref u_c)_d
+  // the three outputs at the points of the line
   double n[3][Q];
-  auto point = [&](int c, const double (&uv)[3], const double (&g)[3][3]) {
+  auto point = [&](int c, const double (&uv)[NIN], const double (&g)[NIN][3]) {
     const double *cp = ce + c * Q2;
     double cm[9];
 #pragma unroll
     for (int z = 0; z < 9; ++z) cm[z] = cp[z * Q3];
+    // Gamma_dr = (C grad_ref u_r)_d
+    auto gam = [&](int d, int r) {
+      return cm[3 * d] * g[r][0] + cm[3 * d + 1] * g[r][1] + cm[3 * d + 2] * g[r][2];
+    };
+    if constexpr (MODE == kConvection) {
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      double acc = 0.0;
+      for (int r = 0; r < 3; ++r) {
+        double acc = 0.0;
 #pragma unroll
-      for (int d = 0; d < 3; ++d)
-        acc += uv[d] * (cm[3 * d] * g[r][0] + cm[3 * d + 1] * g[r][1] + cm[3 * d + 2] * g[r][2]);
-      n[r][c] = acc;
+        for (int d = 0; d < 3; ++d) acc += uv[d] * gam(d, r);
+        n[r][c] = acc;
+      }
+    } else if constexpr (MODE == kCurl) {
+      n[0][c] = gam(1, 2) - gam(2, 1);
+      n[1][c] = gam(2, 0) - gam(0, 2);
+      n[2][c] = gam(0, 1) - gam(1, 0);
+    } else {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) n[d][c] = gam(d, 0);
     }
   };
 #pragma unroll
   for (int c = 0; c < Q / 2; ++c) {
-    double u0[3], u1[3], g0[3][3], g1[3][3];
+    double u0[NIN], u1[NIN], g0[NIN][3], g1[NIN][3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
+    for (int r = 0; r < NIN; ++r) {
       row_pair<VB>(sbb[r], c, u0[r], u1[r]);
       row_pair<VB>(sbg[r], c, g0[r][0], g1[r][0]);
       row_pair<VB>(sgb[r], c, g0[r][1], g1[r][1]);
@@ -572,9 +594,9 @@ convection_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ 
     point(Q - 1 - c, u1, g1);
   }
   if constexpr (Q % 2 == 1) {
-    double um[3], gm[3][3];
+    double um[NIN], gm[NIN][3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
+    for (int r = 0; r < NIN; ++r) {
       um[r] = row_mid<VB>(sbb[r]);
       gm[r][0] = row_mid<VB>(sbg[r]);
       gm[r][1] = row_mid<VB>(sgb[r]);
@@ -588,6 +610,182 @@ convection_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ 
   for (int r = 0; r < 3; ++r)
     emit_e<P, double, false, POS>(buf + r * N3, t0, active, smap, u, es, vcompact != 0,
                                   Yv + r * vestride, yv + r * nv);
+}
+
+template <int P, bool POS>
+__global__ void __launch_bounds__(Dims<P>::THREADS)
+convection_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ vpos,
+                  int vcompact, const double *__restrict__ cq, int64_t nelem,
+                  const double *__restrict__ u, int64_t nv, double *__restrict__ Yv,
+                  int64_t vestride, double *__restrict__ yv) {
+  phi_test_body<P, POS, kConvection>(vmap, vpos, vcompact, cq, nelem, u, nv, Yv, vestride, yv);
+}
+
+// Weak curl (MODE = kCurl) or weak gradient (MODE = kGradient) of the projection step.
+template <int P, bool POS, int MODE>
+__global__ void __launch_bounds__(Dims<P>::THREADS)
+weak_phi_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ vpos,
+                int vcompact, const double *__restrict__ cq, int64_t nelem,
+                const double *__restrict__ u, int64_t nv, double *__restrict__ Yv,
+                int64_t vestride, double *__restrict__ yv) {
+  phi_test_body<P, POS, MODE>(vmap, vpos, vcompact, cq, nelem, u, nv, Yv, vestride, yv);
+}
+
+// Transposed reference-gradient contraction: from the three channels v_k at the points
+// of the thread's xi_3 line (the components of the field to be tested against the
+// reference gradient d_ref_k phi), the element vector sum_Q sum_k d_ref_k phi_l(Q) v_k(Q)
+// in buf[0 .. n^3).  Channel k carries G along xi_k and B along the other two directions.
+template <int PO, int Q>
+__device__ __forceinline__ void bwd_grad(double *buf, int t, const double (&v)[3][Q]) {
+  constexpr int NO = PO + 1;
+  constexpr int NQ2 = NO * Q * Q, N2Q = NO * NO * Q;
+  using BT = TabEO<PO, Q, 0>;
+  using GT = TabEO<PO, Q, 1>;
+  // out[i] += sum_c T(c, i) in[c] for c over the q points (T = B or G)
+  auto line = [](auto tag, const double (&in)[Q], eo::Acc<NO, double> &A) {
+    using TB = decltype(tag);
+#pragma unroll
+    for (int c = 0; c < Q / 2; ++c) A.template add_pair<TB>(c, in[c], in[Q - 1 - c]);
+    if constexpr (Q % 2 == 1) A.template add_mid<TB>(in[Q / 2]);
+  };
+  {  // xi_3: channels 0, 1 with B, channel 2 with G: [c] -> [k][b][a]
+    double r[3][NO];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      eo::Acc<NO, double> A;
+      A.zero();
+      if (f == 2) line(GT{}, v[f], A);
+      else line(BT{}, v[f], A);
+      A.finish(r[f]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+      for (int k = 0; k < NO; ++k) buf[f * NQ2 + k * Q * Q + t] = r[f][k];
+    __syncthreads();
+  }
+  {  // xi_2: [k][b][a] -> [k][j][a]; s0 = B^T ch0 (G along xi_1 pending), s1 = G^T ch1 + B^T ch2
+    const bool w = t < Q * NO;
+    const int a = t % Q, k = t / Q;
+    double r[2][NO];
+    if (w) {
+      double in0[Q], in1[Q], in2[Q];
+#pragma unroll
+      for (int b = 0; b < Q; ++b) {
+        in0[b] = buf[(k * Q + b) * Q + a];
+        in1[b] = buf[NQ2 + (k * Q + b) * Q + a];
+        in2[b] = buf[2 * NQ2 + (k * Q + b) * Q + a];
+      }
+      eo::Acc<NO, double> A0, A1;
+      A0.zero();
+      A1.zero();
+      line(BT{}, in0, A0);
+      line(GT{}, in1, A1);
+      line(BT{}, in2, A1);
+      A0.finish(r[0]);
+      A1.finish(r[1]);
+    }
+    __syncthreads();
+    if (w) {
+#pragma unroll
+      for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int j = 0; j < NO; ++j) buf[f * N2Q + (k * NO + j) * Q + a] = r[f][j];
+    }
+    __syncthreads();
+  }
+  {  // xi_1: [k][j][a] -> [k][j][i]; out = G^T s0 + B^T s1
+    const bool w = t < NO * NO;
+    const int j = t % NO, k = t / NO;
+    double r[NO];
+    if (w) {
+      double in0[Q], in1[Q];
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        in0[a] = buf[(k * NO + j) * Q + a];
+        in1[a] = buf[N2Q + (k * NO + j) * Q + a];
+      }
+      eo::Acc<NO, double> A;
+      A.zero();
+      line(GT{}, in0, A);
+      line(BT{}, in1, A);
+      A.finish(r);
+    }
+    __syncthreads();
+    if (w) {
+#pragma unroll
+      for (int i = 0; i < NO; ++i) buf[(k * NO + j) * NO + i] = r[i];
+    }
+    __syncthreads();
+  }
+}
+
+// Weak divergence of a nodal vector field V (the pressure right-hand side of the
+// projection step, Section 4.2): r_l = sum_Q w |J| grad phi_l . V = sum_Q
+// grad_ref phi_l . (C^T V) with C = w |J| J^{-T}.  The three components are gathered
+// and interpolated (values only), C^T V is formed per point, and one backward
+// reference-gradient pass gives the single output (member 0 of the E-vector and of y).
+template <int P, bool POS>
+__global__ void __launch_bounds__(Dims<P>::THREADS)
+weak_div_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ vpos,
+                int vcompact, const double *__restrict__ cq, int64_t nelem,
+                const double *__restrict__ u, int64_t nv, double *__restrict__ Yv,
+                double *__restrict__ yv) {
+  using S = SDims<P>;
+  using D = Dims<P>;
+  constexpr int N = S::N, Q = S::Q, Q2 = S::Q2, Q3 = S::Q3, TPE = S::TPE, E = S::E;
+  constexpr int N3 = N * N * N;
+  using VB = TabEO<P, Q, 0>;
+  __shared__ __align__(16) double smem[E * D::BUF];
+  __shared__ int32_t smap_all[E * N3];
+  const int le = threadIdx.x / TPE;
+  const int t0 = threadIdx.x - le * TPE;
+  const int e = xcd_block() * E + le;
+  const bool active = e < nelem;
+  const int es = active ? e : 0;
+  double *buf = smem + le * D::BUF;
+  int32_t *smap = smap_all + le * N3;
+  const int32_t *emap = vmap + (int64_t)es * N3;
+  eo::Split<N, double> sv[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    gather_all<P>(buf, t0, active, emap, u + r * nv);
+    fwd_val_xy<P, Q>(buf, t0);
+    double z[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) z[k] = buf[k * Q2 + t0];
+    sv[r] = eo::split(z);
+    __syncthreads();
+  }
+  const int64_t vepe = vcompact ? surf_count<P>() : N3;
+  vel_entries<P, POS>(t0, emap, smap, POS ? vpos + (int64_t)es * vepe : nullptr, vcompact != 0);
+  const double *ce = cq + (int64_t)es * (9 * Q3) + t0;
+  double h[3][Q];  // (C^T V)_k at the points of the line
+  auto point = [&](int c, const double (&vv)[3]) {
+    const double *cp = ce + c * Q2;
+    double cm[9];
+#pragma unroll
+    for (int z = 0; z < 9; ++z) cm[z] = cp[z * Q3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) h[k][c] = cm[k] * vv[0] + cm[3 + k] * vv[1] + cm[6 + k] * vv[2];
+  };
+#pragma unroll
+  for (int c = 0; c < Q / 2; ++c) {
+    double v0[3], v1[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) row_pair<VB>(sv[r], c, v0[r], v1[r]);
+    point(c, v0);
+    point(Q - 1 - c, v1);
+  }
+  if constexpr (Q % 2 == 1) {
+    double vm[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) vm[r] = row_mid<VB>(sv[r]);
+    point(Q / 2, vm);
+  }
+  bwd_grad<P, Q>(buf, t0, h);
+  emit_e<P, double, false, POS>(buf, t0, active, smap, u, es, vcompact != 0, Yv, yv);
 }
 
 template <int P>
@@ -616,9 +814,41 @@ hipError_t launch_convection_pt(const ConvArgs &a, hipStream_t s) {
   if ((a.vpos != nullptr) != POS) return hipErrorInvalidValue;
   dim3 grid((unsigned)((a.nelem + D::E - 1) / D::E));
   dim3 block(D::THREADS);
-  hipLaunchKernelGGL((convection_kernel<P, POS>), grid, block, 0, s, a.vmap, a.vpos, a.vcompact,
-                     a.cq, a.nelem, a.u, a.nv, a.Yv, a.vestride, a.yv);
+  switch (a.kind) {
+    case kWeakConvection:
+      hipLaunchKernelGGL((convection_kernel<P, POS>), grid, block, 0, s, a.vmap, a.vpos,
+                         a.vcompact, a.cq, a.nelem, a.u, a.nv, a.Yv, a.vestride, a.yv);
+      break;
+    case kWeakCurl:
+      hipLaunchKernelGGL((weak_phi_kernel<P, POS, kCurl>), grid, block, 0, s, a.vmap, a.vpos,
+                         a.vcompact, a.cq, a.nelem, a.u, a.nv, a.Yv, a.vestride, a.yv);
+      break;
+    case kWeakGradient:
+      hipLaunchKernelGGL((weak_phi_kernel<P, POS, kGradient>), grid, block, 0, s, a.vmap, a.vpos,
+                         a.vcompact, a.cq, a.nelem, a.u, a.nv, a.Yv, a.vestride, a.yv);
+      break;
+    case kWeakDivergence:
+      hipLaunchKernelGGL((weak_div_kernel<P, POS>), grid, block, 0, s, a.vmap, a.vpos, a.vcompact,
+                         a.cq, a.nelem, a.u, a.nv, a.Yv, a.yv);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256)
+lincomb_kernel(LinComb lc, const double *__restrict__ scale, const uint8_t *__restrict__ mask,
+               double *y, int64_t n, int64_t total) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * 256) {
+    double v = 0.0;
+    for (int j = 0; j < lc.nterm; ++j) v += lc.c[j] * lc.x[j][i];
+    const int64_t g = i % n;
+    if (scale) v /= scale[g];
+    if (mask && mask[g]) v = 0.0;
+    y[i] = v;
+  }
 }
 
 }  // namespace
@@ -633,6 +863,18 @@ hipError_t launch_convection(const ConvArgs &a, hipStream_t s) {
 #define SFEM_CALL(P) launch_convection_pt<P>(a, s)
   SFEM_DISPATCH_P(a.p, SFEM_CALL)
 #undef SFEM_CALL
+}
+
+hipError_t launch_lincomb(const LinComb &lc, const double *scale, const uint8_t *mask, double *y,
+                          int64_t n, int nb, hipStream_t s) {
+  const int64_t total = n * nb;
+  if (total <= 0) return hipSuccess;
+  if (lc.nterm < 1 || lc.nterm > kMaxLinTerms) return hipErrorInvalidValue;
+  int64_t blocks = (total + 1023) / 1024;
+  if (blocks > 65535) blocks = 65535;
+  hipLaunchKernelGGL(lincomb_kernel, dim3((unsigned)blocks), dim3(256), 0, s, lc, scale, mask, y, n,
+                     total);
+  return hipGetLastError();
 }
 
 }  // namespace sfem

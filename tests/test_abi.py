@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_pure_host_calls(lib):
-    assert lib.sfem_abi_version() == 4
+    assert lib.sfem_abi_version() == 5
     assert isinstance(lib.sfem_last_error(None), bytes)
     from paper_1910_03032_amd._lib import CtxInfo
     ci = CtxInfo()

@@ -1,0 +1,19 @@
+"""Host logic of the projection stepper (no GPU): the BDF/EXT weights the product derives
+from their exactness conditions equal the oracle's table."""
+import numpy as np
+import pytest
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_bdf_ext_weights_match_the_oracle(k):
+    from oracle import bdf_ext
+    from paper_1910_03032_amd.flow import bdf_ext_weights
+    b, a = bdf_ext_weights(k)
+    bo, ao = bdf_ext(k)
+    assert np.allclose(b, bo, rtol=0, atol=1e-14) and np.allclose(a, ao, rtol=0, atol=1e-14)
+
+
+def test_bad_order():
+    from paper_1910_03032_amd.flow import bdf_ext_weights
+    with pytest.raises(ValueError):
+        bdf_ext_weights(4)

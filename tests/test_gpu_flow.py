@@ -1,0 +1,138 @@
+"""The projection step of Section 4.2 on the GPU (through the C ABI) against the oracle:
+the equal-order weak gradient, curl and divergence at p = 1..8, the nodal combination,
+a hydrostatic step (the pressure takes a gradient forcing, the velocity stays 0), and
+three BDF/EXT steps (orders 1, 2, 3) from a smooth velocity with forcing."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import gpu, host, rel, say
+from oracle import Discretization, ProjectionStepper as OracleStepper
+from oracle import weak_curl, weak_divergence, weak_gradient
+from workloads import BoxMesh, uniform
+
+pytestmark = pytest.mark.gpu
+
+
+def node_coords(m, p):
+    from oracle.fem import trilinear_shape
+    from oracle.quadrature import gll
+    pn, _ = gll(p)
+    n = p + 1
+    l = np.arange(n ** 3)
+    XI = np.stack([pn[l % n], pn[(l // n) % n], pn[l // (n * n)]], axis=-1)
+    N, _ = trilinear_shape(XI)
+    x = np.zeros((m.ndof, 3))
+    x[m.elem_dofs.reshape(-1)] = np.einsum("evr,mv->emr", m.elem_xyz, N).reshape(-1, 3)
+    return x
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_weak_operators_vs_oracle(p):
+    from paper_1910_03032_amd import WEAK_CURL, WEAK_DIVERGENCE, WEAK_GRADIENT, Operator
+    ne = 3 if p <= 4 else 2
+    m = BoxMesh(ne, p)
+    say(f"[flow] weak operators ne={ne} p={p} ndof={m.ndof}")
+    free = np.zeros(m.ndof, dtype=np.uint8)
+    d = Discretization(m.elem_xyz, m.elem_dofs, free, m.ndof, p, p + 2)
+    op = Operator(m.elem_xyz, m.elem_dofs, m.ndof, p)
+    s = uniform(m.ndof, seed=31)
+    v = uniform(3 * m.ndof, seed=32).reshape(3, -1)
+    eg = rel(host(op.weak_op(WEAK_GRADIENT, gpu(s))), weak_gradient(d, s))
+    ec = rel(host(op.weak_op(WEAK_CURL, gpu(v))), weak_curl(d, v))
+    ed = rel(host(op.weak_op(WEAK_DIVERGENCE, gpu(v))), weak_divergence(d, v))
+    say(f"  gradient {eg:.2e}, curl {ec:.2e}, divergence {ed:.2e}")
+    assert eg <= 1e-12 and ec <= 1e-12 and ed <= 1e-12
+    op.close()
+
+
+def test_weak_operators_zero_essential_rows():
+    from paper_1910_03032_amd import WEAK_CURL, WEAK_DIVERGENCE, Operator
+    m = BoxMesh(3, 3)
+    d = Discretization(m.elem_xyz, m.elem_dofs, np.zeros(m.ndof, dtype=np.uint8), m.ndof, 3, 5)
+    op = Operator(m.elem_xyz, m.elem_dofs, m.ndof, 3, ess=m.ess)
+    v = uniform(3 * m.ndof, seed=33).reshape(3, -1)
+    ess = m.ess.astype(bool)
+    wc, wd = weak_curl(d, v), weak_divergence(d, v)
+    wc[:, ess] = 0.0
+    wd[ess] = 0.0
+    assert rel(host(op.weak_op(WEAK_CURL, gpu(v))), wc) <= 1e-12
+    assert rel(host(op.weak_op(WEAK_DIVERGENCE, gpu(v))), wd) <= 1e-12
+    op.close()
+
+
+def test_lincomb():
+    from paper_1910_03032_amd import Operator, SfemError
+    m = BoxMesh(2, 2)
+    op = Operator(m.elem_xyz, m.elem_dofs, m.ndof, 2)
+    xs = [uniform(3 * m.ndof, seed=40 + j).reshape(3, -1) for j in range(8)]
+    c = [0.5, -1.25, 2.0, 3.0, -0.75, 1.0, 0.125, -2.5]
+    sc = uniform(m.ndof, seed=50, lo=1.0, hi=2.0)
+    mk = (np.arange(m.ndof) % 3 == 0).astype(np.uint8)
+    y = host(op.lincomb(c, [gpu(x) for x in xs], scale=gpu(sc), mask=torch.as_tensor(mk)))
+    ref = sum(cj * x for cj, x in zip(c, xs)) / sc
+    ref[:, mk.astype(bool)] = 0.0
+    assert rel(y, ref) <= 1e-14
+    # in place: y may be one of the inputs
+    a = gpu(xs[0])
+    op.lincomb([2.0, 1.0], [a, gpu(xs[1])], out=a)
+    assert rel(host(a), 2.0 * xs[0] + xs[1]) <= 1e-14
+    with pytest.raises(SfemError, match="SFEM_E_ARG"):
+        op._check(op._lib.sfem_lincomb(op._h, 9, None, None, None, None, m.ndof, 1, None))
+    with pytest.raises(SfemError, match="SFEM_E_ARG"):
+        op._check(op._lib.sfem_weak_op(op._h, 0, None, None))
+    op.close()
+
+
+@pytest.mark.parametrize("ne,p", [(2, 2), (16, 4)])
+def test_hydrostatic_step(ne, p):
+    """u = 0 and f = grad phi (phi quadratic) on an affine mesh: p^{n+1} = phi - mean,
+    u^{n+1} = 0, to the solve tolerance (relative residuals 1e-12, Jacobi-PCG on the
+    pure-Neumann Poisson problem: errors up to its conditioning times that, < 1e-8).
+    16^3 p = 4 is a 275k-DoF case."""
+    from paper_1910_03032_amd import ProjectionStepper
+    m = BoxMesh(ne, p, amp=0.0)
+    say(f"[flow] hydrostatic ne={ne} p={p} ndof={m.ndof}")
+    x = node_coords(m, p)
+    phi = x[:, 0] ** 2 - x[:, 1] * x[:, 2] + 0.5 * x[:, 2]
+    f = np.stack([2 * x[:, 0], -x[:, 2], -x[:, 1] + 0.5])
+    st = ProjectionStepper(m.elem_xyz, m.elem_dofs, m.ndof, p, m.ess, dt=0.01, nu=0.1, order=2,
+                           rtol=1e-12)
+    un, pn = st.step(gpu(np.zeros((3, m.ndof))), gpu(f))
+    m1 = host(st.free.apply(gpu(np.ones(m.ndof)), op=0))
+    ref = phi - (m1 @ phi) / m1.sum()
+    e = rel(host(pn), ref)
+    say(f"  pressure {e:.2e}, max |u| {np.abs(host(un)).max():.2e}, "
+        f"iterations {st.last['pressure'].iters} / {st.last['velocity'].iters}")
+    assert e <= 1e-8
+    assert np.abs(host(un)).max() <= 1e-8 * np.abs(f).max()
+    st.close()
+
+
+@pytest.mark.parametrize("p", [2, 4])
+def test_three_steps_vs_oracle(p):
+    """Orders 1, 2, 3 on a perturbed 3^3 mesh from a smooth velocity vanishing on the walls,
+    with a forcing; both sides solve to 1e-12 (the oracle directly), so the difference is
+    bounded by the solve tolerance times the conditioning (< 1e-8)."""
+    from paper_1910_03032_amd import ProjectionStepper
+    m = BoxMesh(3, p)
+    say(f"[flow] three steps p={p} ndof={m.ndof}")
+    d = Discretization(m.elem_xyz, m.elem_dofs, m.ess, m.ndof, p, p + 2)
+    x = node_coords(m, p)
+    bump = (x * (1 - x)).prod(axis=1)  # 0 on the walls
+    u = np.stack([bump * np.sin(np.pi * x[:, 1]), bump * np.cos(np.pi * x[:, 2]), bump * x[:, 0]])
+    u[:, m.ess.astype(bool)] = 0.0
+    f = np.stack([np.sin(np.pi * x[:, 2]), x[:, 0] * x[:, 1], np.cos(np.pi * x[:, 0])])
+    dt, nu = 0.02, 0.05
+    so = OracleStepper(d, dt=dt, nu=nu, order=3)
+    sg = ProjectionStepper(m.elem_xyz, m.elem_dofs, m.ndof, p, m.ess, dt=dt, nu=nu, order=3,
+                           rtol=1e-12)
+    uo, ug = u.copy(), gpu(u)
+    for n in range(3):
+        uo, po = so.step(uo, f)
+        ug, pg = sg.step(ug, gpu(f))
+        eu, ep = rel(host(ug), uo), rel(host(pg), po)
+        say(f"  step {n} (order {sg.last['order']}): velocity {eu:.2e}, pressure {ep:.2e}")
+        assert eu <= 1e-8 and ep <= 1e-8
+        assert np.all(host(ug)[:, m.ess.astype(bool)] == 0.0)
+    sg.close()
