@@ -166,7 +166,8 @@ typedef struct {
   int nullspace;     /* nonzero: pure-Neumann problem (op = SFEM_DIFFUSION, no essential
                         DoFs): b is made orthogonal to the constants, every preconditioner
                         application is orthogonalized against them (Section 5.3), and x is
-                        returned with int x = 0 (eq. meanZero); mode 0 and x0_zero only */
+                        returned with int x = 0 (eq. meanZero); mode 0 only (an initial
+                        guess is allowed: its constant part does not matter) */
 } sfem_pcg_opts;
 
 typedef struct {

@@ -848,9 +848,8 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
   if (opts->precond != SFEM_PRECOND_JACOBI && opts->precond != SFEM_PRECOND_COLLOCATED_MASS)
     return fail(c, SFEM_E_ARG, "precond must be SFEM_PRECOND_JACOBI or SFEM_PRECOND_COLLOCATED_MASS");
   const int ns = opts->nullspace ? 1 : 0;
-  if (ns && (op != SFEM_DIFFUSION || c->n_ess != 0 || opts->mode != 0 || !opts->x0_zero))
-    return fail(c, SFEM_E_ARG,
-                "nullspace solves need op = SFEM_DIFFUSION, no essential DoFs, mode 0 and x0_zero");
+  if (ns && (op != SFEM_DIFFUSION || c->n_ess != 0 || opts->mode != 0))
+    return fail(c, SFEM_E_ARG, "nullspace solves need op = SFEM_DIFFUSION, no essential DoFs and mode 0");
   const int nb = nbatch;
   const int64_t n = c->ndof;
   if (nb == 0) return SFEM_OK;

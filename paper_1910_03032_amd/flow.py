@@ -17,6 +17,8 @@ first steps):
   5. Helmholtz (eq. proj-helmholtz): (b_0 / dt) M u + nu K u = M F* - grad_w(p) on the
      free rows, u = 0 on the walls, solved by Jacobi-PCG for the three components at once.
 
+The solves start from the previous step's pressure and from the extrapolated velocity u*.
+
 Every arithmetic step runs in the library's kernels (convection, weak operators, nodal
 combinations, applies, solves); this class only orders the calls and keeps the history.
 The BDF and EXT weights are computed on the host from their exactness conditions.
@@ -68,6 +70,7 @@ class ProjectionStepper:
         self.us, self.ns = [], []  # newest first
         self.nstep = 0
         self._alpha = None
+        self.p_prev = None
         self.last = {}
 
     def close(self):
@@ -97,14 +100,16 @@ class ProjectionStepper:
         w = fr.lincomb([1.0], [fr.weak_op(WEAK_CURL, ustar)], scale=self.B)
         L = fr.lincomb([-nu], [fr.weak_op(WEAK_CURL, w)], scale=self.B)
         r = fr.weak_op(WEAK_DIVERGENCE, fr.lincomb([1.0, 1.0], [F, L]))
-        p, res_p = fr.pcg(r, op=DIFFUSION, rtol=self.rtol, nullspace=True)
+        # initial guesses: the previous pressure, the extrapolated velocity (0 on the walls)
+        p, res_p = fr.pcg(r, x=self.p_prev, op=DIFFUSION, rtol=self.rtol, nullspace=True)
+        self.p_prev = p
         R = fr.lincomb([1.0, -1.0], [fr.apply(F, op=MASS), fr.weak_op(WEAK_GRADIENT, p)],
                        mask=self.mask)
         alpha = b[0] / dt
         if self._alpha != alpha:
             self.vel.set_coeffs(alpha, nu, None)
             self._alpha = alpha
-        un, res_u = self.vel.pcg(R, op=HELMHOLTZ, rtol=self.rtol)
+        un, res_u = self.vel.pcg(R, x=ustar, op=HELMHOLTZ, rtol=self.rtol)
         if not (res_p.converged and res_u.converged):
             raise SfemError(1, f"projection step {self.nstep}: a solve did not converge")
         self.nstep += 1

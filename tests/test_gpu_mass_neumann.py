@@ -72,6 +72,13 @@ def test_neumann_poisson_vs_oracle_and_bordered_solve(p):
     xd = spla.spsolve(A, np.concatenate([b - b.mean(), [0.0]]))[:-1]
     assert rel(host(x), xd) <= 1e-9
     assert abs(np.dot(m1, host(x))) <= 1e-12 * np.linalg.norm(host(x))
+    # from an initial guess (with a constant part, which the null space ignores): the same
+    # solution in fewer iterations
+    x0 = xd + 1e-6 * uniform(m.ndof, seed=9) + 3.0
+    x2, res2 = op.pcg(gpu(b), x=gpu(x0), op=DIFFUSION, rtol=1e-12, check_every=1, nullspace=True)
+    say(f"  p={p}: from a close initial guess {res2.iters[0]} iterations")
+    assert res2.converged and res2.iters[0] < res.iters[0]
+    assert rel(host(x2), xd) <= 1e-9
 
 
 def test_neumann_poisson_manufactured_rate_gpu():
