@@ -166,8 +166,9 @@ typedef struct {
   int nullspace;     /* nonzero: pure-Neumann problem (op = SFEM_DIFFUSION, no essential
                         DoFs): b is made orthogonal to the constants, every preconditioner
                         application is orthogonalized against them (Section 5.3), and x is
-                        returned with int x = 0 (eq. meanZero); mode 0 only (an initial
-                        guess is allowed: its constant part does not matter) */
+                        returned with int x = 0 (eq. meanZero); modes 0 and 1 (in mode 1
+                        the inner FP32 solves are orthogonalized the same way), with or
+                        without an initial guess (its constant part does not matter) */
 } sfem_pcg_opts;
 
 typedef struct {

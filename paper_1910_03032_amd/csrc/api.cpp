@@ -848,8 +848,8 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
   if (opts->precond != SFEM_PRECOND_JACOBI && opts->precond != SFEM_PRECOND_COLLOCATED_MASS)
     return fail(c, SFEM_E_ARG, "precond must be SFEM_PRECOND_JACOBI or SFEM_PRECOND_COLLOCATED_MASS");
   const int ns = opts->nullspace ? 1 : 0;
-  if (ns && (op != SFEM_DIFFUSION || c->n_ess != 0 || opts->mode != 0))
-    return fail(c, SFEM_E_ARG, "nullspace solves need op = SFEM_DIFFUSION, no essential DoFs and mode 0");
+  if (ns && (op != SFEM_DIFFUSION || c->n_ess != 0))
+    return fail(c, SFEM_E_ARG, "nullspace solves need op = SFEM_DIFFUSION and no essential DoFs");
   const int nb = nbatch;
   const int64_t n = c->ndof;
   if (nb == 0) return SFEM_OK;
@@ -922,7 +922,8 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
     const size_t bytes = pcg_work_bytes<float>(c, n, nb) + 2 * align_up((size_t)n * nb * sizeof(double)) +
                          2 * align_up((size_t)n * nb * sizeof(float)) +
                          align_up((size_t)nb * 3 * sizeof(double)) +
-                         align_up((size_t)nb * nblk * sizeof(double));
+                         align_up((size_t)nb * nblk * sizeof(double)) +
+                         (ns ? align_up((size_t)n * nb * sizeof(double)) : 0);
     if ((st = ensure_ws(c, bytes)) != SFEM_OK) return st;
     if ((st = ensure_pinned(c, std::max(sizeof(PcgScalars), 3 * sizeof(double)) * nb)) != SFEM_OK) return st;
     Carver cv{(char *)c->ws.p};
@@ -936,14 +937,26 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
     std::vector<double> hir(3 * nb);
     std::vector<int> conv(nb, 0);
     int total_inner = 0;
+    const double *bs = b;  // the right-hand side actually solved for
+    if (ns) {
+      // pure Neumann: b - mean(b) 1 as in mode 0; the inner solves orthogonalize their
+      // preconditioner against the constants, the mean-zero shift comes at the end
+      double *bc = cv.take<double>(n * nb);
+      if ((st = ensure_m1(c, r64, part, ir)) != SFEM_OK) return st;
+      HIPCHK(c, VecOps<double>::dot(b, nullptr, 0, part, nblk, n, nb, s));
+      HIPCHK(c, launch_reduce1(part, nblk, nb, ir, s));
+      HIPCHK(c, hipMemcpyAsync(bc, b, (size_t)n * nb * sizeof(double), hipMemcpyDeviceToDevice, s));
+      HIPCHK(c, launch_shift(bc, ir, 1.0 / (double)n, n, nb, s));
+      bs = bc;
+    }
     // ||b||^2
-    HIPCHK(c, launch_sub_norm(b, nullptr, nullptr, part, nblk, n, nb, s));
+    HIPCHK(c, launch_sub_norm(bs, nullptr, nullptr, part, nblk, n, nb, s));
     HIPCHK(c, launch_ir_norm(part, nblk, nb, 1, opts->rtol, ir, s));
     if (opts->x0_zero) HIPCHK(c, VecOps<double>::fill(x, 0.0, n * nb, s));
     for (;;) {
       // outer residual in FP64 with the FP64 operator
       if ((st = do_apply(c, op, false, nb, x, w64)) != SFEM_OK) return st;
-      HIPCHK(c, launch_sub_norm(b, w64, r64, part, nblk, n, nb, s));
+      HIPCHK(c, launch_sub_norm(bs, w64, r64, part, nblk, n, nb, s));
       HIPCHK(c, launch_ir_norm(part, nblk, nb, 0, opts->rtol, ir, s));
       HIPCHK(c, hipMemcpyAsync(hir.data(), ir, 3 * nb * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(c, hipStreamSynchronize(s));
@@ -959,6 +972,12 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
         all = all && conv[m];
       }
       if (all || outer >= opts->max_outer || total_inner >= opts->maxit) break;
+      if (ns) {
+        // keep the inner right-hand side orthogonal to the constants (w64 is free here)
+        HIPCHK(c, VecOps<double>::dot(r64, nullptr, 0, part, nblk, n, nb, s));
+        HIPCHK(c, launch_reduce1(part, nblk, nb, w64, s));
+        HIPCHK(c, launch_shift(r64, w64, 1.0 / (double)n, n, nb, s));
+      }
       HIPCHK(c, launch_ir_cast(r64, ir, r32, n, nb, s));
       // Inner tolerance: a standard refinement step reduces the residual by inner_rtol;
       // when the reduction still needed to reach rtol is within reach of one FP32
@@ -976,7 +995,7 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
       PcgScalars *hs = (PcgScalars *)c->h_pinned;
       if ((st = run_pcg<float>(c, op, nb, r32, d32, true, itol,
                                opts->maxit - total_inner, opts->check_every, dinv32, dms,
-                               w, hs)) != SFEM_OK)
+                               w, hs, ns)) != SFEM_OK)
         return st;
       int mx = 0;
       for (int m = 0; m < nb; ++m) {
@@ -990,6 +1009,12 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
     }
     for (int m = 0; m < nb; ++m)
       if (status[m] == 0 && !conv[m]) status[m] = SFEM_NOCONV;
+    if (ns) {
+      // mean-zero condition: x <- x - (m1^T x / 1^T m1) 1 (the residual does not change)
+      HIPCHK(c, VecOps<double>::dot(x, c->d_m1, 0, part, nblk, n, nb, s));
+      HIPCHK(c, launch_reduce1(part, nblk, nb, ir, s));
+      HIPCHK(c, launch_shift(x, ir, 1.0 / c->m1sum, n, nb, s));
+    }
   }
   sfem_status ret = SFEM_OK;
   for (int m = 0; m < nb; ++m) {

@@ -13,7 +13,8 @@ first steps):
      w = B^{-1} curl_w(u*), L* = -nu B^{-1} curl_w(w);
   4. pressure Poisson (eq. pres-poisson with the Neumann condition eq. presPoissonBC,
      natural in the weak form since u . n = 0 on the walls, and eq. meanZero):
-     K p = div_w(F* + L*), solved by the orthogonalized Jacobi-PCG, int p = 0;
+     K p = div_w(F* + L*), solved by the orthogonalized Jacobi-PCG (by default with FP32
+     inner solves inside FP64 refinement), int p = 0;
   5. Helmholtz (eq. proj-helmholtz): (b_0 / dt) M u + nu K u = M F* - grad_w(p) on the
      free rows, u = 0 on the walls, solved by Jacobi-PCG for the three components at once.
 
@@ -56,13 +57,14 @@ class ProjectionStepper:
     operators, the mass and the pure-Neumann pressure solve."""
 
     def __init__(self, elem_xyz, elem_dofs, ndof, p, ess, dt, nu, order=3, rtol=1e-10,
-                 device=None):
+                 pressure_mode=1, device=None):
         self.vel = Operator(elem_xyz, elem_dofs, ndof, p, ess=ess, device=device)
         self.free = Operator(elem_xyz, elem_dofs, ndof, p, device=device)
         self.free.set_coeffs(1.0, 1.0, None)
         self.device = self.free.device
         self.ndof = int(ndof)
         self.dt, self.nu, self.order, self.rtol = float(dt), float(nu), int(order), float(rtol)
+        self.pressure_mode = int(pressure_mode)  # 0: FP64 PCG, 1: FP32 inner PCG + FP64 refinement
         if not 1 <= self.order <= 3:
             raise ValueError("order 1, 2 or 3")
         self.B = self.free.collocated_mass()
@@ -101,7 +103,8 @@ class ProjectionStepper:
         L = fr.lincomb([-nu], [fr.weak_op(WEAK_CURL, w)], scale=self.B)
         r = fr.weak_op(WEAK_DIVERGENCE, fr.lincomb([1.0, 1.0], [F, L]))
         # initial guesses: the previous pressure, the extrapolated velocity (0 on the walls)
-        p, res_p = fr.pcg(r, x=self.p_prev, op=DIFFUSION, rtol=self.rtol, nullspace=True)
+        p, res_p = fr.pcg(r, x=self.p_prev, op=DIFFUSION, rtol=self.rtol, nullspace=True,
+                          mode=self.pressure_mode)
         self.p_prev = p
         R = fr.lincomb([1.0, -1.0], [fr.apply(F, op=MASS), fr.weak_op(WEAK_GRADIENT, p)],
                        mask=self.mask)

@@ -79,6 +79,12 @@ def test_neumann_poisson_vs_oracle_and_bordered_solve(p):
     say(f"  p={p}: from a close initial guess {res2.iters[0]} iterations")
     assert res2.converged and res2.iters[0] < res.iters[0]
     assert rel(host(x2), xd) <= 1e-9
+    # FP32 inner solves inside FP64 refinement, orthogonalized the same way
+    x3, res3 = op.pcg(gpu(b), op=DIFFUSION, rtol=1e-12, mode=1, nullspace=True)
+    say(f"  p={p}: FP32+IR {res3.iters[0]} inner iterations in {res3.outer[0]} refinement steps")
+    assert res3.converged and res3.true_rel_res[0] <= 1e-11
+    assert rel(host(x3), xd) <= 1e-9
+    assert abs(np.dot(m1, host(x3))) <= 1e-12 * np.linalg.norm(host(x3))
 
 
 def test_neumann_poisson_manufactured_rate_gpu():
@@ -112,7 +118,5 @@ def test_nullspace_option_errors():
     b = gpu(uniform(m.ndof, seed=1))
     with pytest.raises(SfemError):
         op.pcg(b, op=HELMHOLTZ, nullspace=True)  # not the diffusion operator
-    with pytest.raises(SfemError):
-        op.pcg(b, op=DIFFUSION, nullspace=True, mode=1)
     with pytest.raises(SfemError):
         op.pcg(b, op=DIFFUSION, precond=7)
