@@ -30,6 +30,13 @@ DoFs of d) and a constant viscosity nu:
      u = 0 on the walls.
 
 Returns u^{n+1} and p^{n+1}; the history shifts.  The solves are sparse direct.
+
+Pins: the weak operators and the BDF/EXT weights are pinned (tests/test_oracle_flow.py),
+and so is one step in hydrostatic balance.  The step's time integration (the history
+terms, the rotational term, the convection history) is parity unpinned: no closed-form
+discrete solution exercises it, and a self-convergence study in the step size on small
+meshes does not isolate it (run-to-run differences at dt, dt/2, dt/4 stay at the level
+of the mesh's equal-order consistency error).
 """
 from __future__ import annotations
 
