@@ -31,12 +31,10 @@ DoFs of d) and a constant viscosity nu:
 
 Returns u^{n+1} and p^{n+1}; the history shifts.  The solves are sparse direct.
 
-Pins: the weak operators and the BDF/EXT weights are pinned (tests/test_oracle_flow.py),
-and so is one step in hydrostatic balance.  The step's time integration (the history
-terms, the rotational term, the convection history) is parity unpinned: no closed-form
-discrete solution exercises it, and a self-convergence study in the step size on small
-meshes does not isolate it (run-to-run differences at dt, dt/2, dt/4 stay at the level
-of the mesh's equal-order consistency error).
+Pins (tests/test_oracle_flow.py): the weak operators, the BDF/EXT weights, one step in
+hydrostatic balance, and the time integration through self-convergence in the step
+size on a 4^3, p = 4 mesh (order 1 and order 2 rates; on coarser meshes the run-to-run
+differences stall at the mesh's equal-order consistency error).
 """
 from __future__ import annotations
 
@@ -137,8 +135,9 @@ class ProjectionStepper:
         K = self.free.assemble(0.0, 1.0, constrained=False)
         m1 = np.asarray(self.M @ np.ones(d.ndof)).reshape(-1, 1)
         # [K m1; m1^T 0]: K p = r with int p = m1^T p = 0 (r is orthogonal to 1)
-        self.Kb = sp.bmat([[K, sp.csr_matrix(m1)], [sp.csr_matrix(m1.T), None]]).tocsc()
+        self.Kb = spla.splu(sp.bmat([[K, sp.csr_matrix(m1)], [sp.csr_matrix(m1.T), None]]).tocsc())
         self.m1 = m1.reshape(-1)
+        self.hlu = {}  # factorized Helmholtz matrix per b_0 / dt
         self.us, self.ns = [], []  # newest first
         self.nstep = 0
 
@@ -159,11 +158,13 @@ class ProjectionStepper:
         w = self.binv * weak_curl(self.free, ustar)
         L = -nu * self.binv * weak_curl(self.free, w)
         r = weak_divergence(self.free, F + L)
-        p = spla.spsolve(self.Kb, np.concatenate([r - r.mean(), [0.0]]))[:-1]
+        p = self.Kb.solve(np.concatenate([r - r.mean(), [0.0]]))[:-1]
         R = np.stack([self.M @ F[c] for c in range(3)]) - weak_gradient(self.free, p)
         R[:, d.ess] = 0.0
-        H = d.assemble(b[0] / dt, nu, constrained=True).tocsc()
-        lu = spla.splu(H)
+        alpha = b[0] / dt
+        if alpha not in self.hlu:
+            self.hlu[alpha] = spla.splu(d.assemble(alpha, nu, constrained=True).tocsc())
+        lu = self.hlu[alpha]
         un = np.stack([lu.solve(R[c]) for c in range(3)])
         self.nstep += 1
         return un, p

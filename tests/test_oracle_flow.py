@@ -8,7 +8,12 @@ mathematics fixes:
 * the weak gradient and the weak divergence are transposes: s . div_w(V) = V . grad_w(s);
 * a hydrostatic step: u = 0 and a gradient forcing f = grad phi (phi quadratic, affine
   mesh) is balanced by the pressure alone: p = phi - mean, u^{n+1} = 0;
-* planted mistakes (a sign in the curl, a dropped EXT term) fail the pins.
+* the time integration converges at its order: self-convergence in the step size
+  (differences between runs at dt, dt/2, dt/4 to the same time) at rate ~1 for BDF1/EXT1
+  and ~2 for BDF2/EXT2 on a 4^3, p = 4 mesh (on coarser meshes the differences stall at
+  the mesh's equal-order consistency error);
+* planted mistakes (a sign in the curl, a dropped pressure gradient, a wrong BDF
+  weight) fail the pins.
 """
 import numpy as np
 import pytest
@@ -129,3 +134,43 @@ def test_planted_mistakes_fail():
     finally:
         fl.weak_gradient = og
     assert np.abs(un).max() > 1e-4
+
+
+def _self_convergence(order, bdf=None):
+    m, d = disc(4, 4, amp=0.0)
+    x = nodes(m, 4)
+    f = np.stack([10 * np.sin(np.pi * x[:, 2]), 10 * x[:, 0] * x[:, 1], 10 * np.cos(np.pi * x[:, 0])])
+    T, res = 0.05, []
+    orig = fl.bdf_ext
+    if bdf is not None:
+        fl.bdf_ext = bdf
+    try:
+        for nsteps in (5, 10, 20):
+            st = fl.ProjectionStepper(d, dt=T / nsteps, nu=0.1, order=order)
+            u = np.zeros((3, m.ndof))
+            for _ in range(nsteps):
+                u, _p = st.step(u, f)
+            res.append(u)
+    finally:
+        fl.bdf_ext = orig
+    e = [np.linalg.norm(res[i] - res[i + 1]) for i in range(2)]
+    return np.log2(e[0] / e[1])
+
+
+@pytest.mark.parametrize("order,lo,hi", [(1, 0.8, 1.2), (2, 1.7, 2.3)])
+def test_time_integration_order(order, lo, hi):
+    rate = _self_convergence(order)
+    assert lo <= rate <= hi, rate
+
+
+def test_wrong_bdf_weight_loses_the_order():
+    good = fl.bdf_ext
+
+    def bad(k):
+        b, a = good(k)
+        b = b.copy()
+        if k == 2:
+            b[2] = 0.45  # instead of 1/2
+        return b, a
+    rate = _self_convergence(2, bad)
+    assert not (1.7 <= rate <= 2.3), rate
