@@ -136,3 +136,28 @@ def test_three_steps_vs_oracle(p, mode):
         assert eu <= 1e-8 and ep <= 1e-8
         assert np.all(host(ug)[:, m.ess.astype(bool)] == 0.0)
     sg.close()
+
+
+@pytest.mark.parametrize("ne,order,lo,hi", [(4, 2, 1.7, 2.3), (8, 2, 1.7, 2.3), (8, 3, 1.7, 3.3)])
+def test_time_order_self_convergence(ne, order, lo, hi):
+    """The GPU steps converge in the step size at the scheme's order: runs to T = 0.05 with
+    dt = T/5, T/10, T/20 from rest under a steady forcing (affine ne^3 mesh, p = 4,
+    nu = 0.1); the rate of the run-to-run differences is ~2 (order 3 starts with a BDF1
+    and a BDF2 step, which limits its global order to 2 at these step counts)."""
+    from paper_1910_03032_amd import ProjectionStepper
+    m = BoxMesh(ne, 4, amp=0.0)
+    x = node_coords(m, 4)
+    f = gpu(np.stack([10 * np.sin(np.pi * x[:, 2]), 10 * x[:, 0] * x[:, 1], 10 * np.cos(np.pi * x[:, 0])]))
+    T, res = 0.05, []
+    for nsteps in (5, 10, 20):
+        st = ProjectionStepper(m.elem_xyz, m.elem_dofs, m.ndof, 4, m.ess, dt=T / nsteps, nu=0.1,
+                               order=order, rtol=1e-12)
+        u = gpu(np.zeros((3, m.ndof)))
+        for _ in range(nsteps):
+            u, _p = st.step(u, f)
+        res.append(host(u))
+        st.close()
+    e = [np.linalg.norm(res[i] - res[i + 1]) for i in range(2)]
+    rate = np.log2(e[0] / e[1])
+    say(f"[flow] {ne}^3 order {order}: differences {e[0]:.3e} {e[1]:.3e}, rate {rate:.2f}")
+    assert lo <= rate <= hi
