@@ -161,3 +161,31 @@ def test_time_order_self_convergence(ne, order, lo, hi):
     rate = np.log2(e[0] / e[1])
     say(f"[flow] {ne}^3 order {order}: differences {e[0]:.3e} {e[1]:.3e}, rate {rate:.2f}")
     assert lo <= rate <= hi
+
+
+def test_weak_operators_full_size_identities_p4_32e():
+    """32^3, p = 4 (2.1M DoFs), the launch configuration of the projection workload:
+    the weak gradient of a linear s = a.x + c is a_c M1, the weak curl of a linear
+    u = A x + b is curl(u)_c M1, and the weak divergence of any field sums to 0
+    (M1 from the library's mass apply without essential DoFs)."""
+    from paper_1910_03032_amd import MASS, WEAK_CURL, WEAK_DIVERGENCE, WEAK_GRADIENT, Operator
+    m = BoxMesh(32, 4)
+    op = Operator(m.elem_xyz, m.elem_dofs, m.ndof, 4)
+    x = node_coords(m, 4)
+    m1 = host(op.apply(gpu(np.ones(m.ndof)), op=MASS))
+    a = np.array([0.7, -1.3, 2.1])
+    g = host(op.weak_op(WEAK_GRADIENT, gpu(x @ a + 0.4)))
+    A = np.array([[0.3, -0.2, 0.5], [1.1, -0.4, 0.25], [-0.6, 0.8, 0.9]])
+    curl = np.array([A[2, 1] - A[1, 2], A[0, 2] - A[2, 0], A[1, 0] - A[0, 1]])
+    w = host(op.weak_op(WEAK_CURL, gpu((x @ A.T + 0.1).T)))
+    v = uniform(3 * m.ndof, seed=60).reshape(3, -1)
+    r = host(op.weak_op(WEAK_DIVERGENCE, gpu(v)))
+    # two different FP64 evaluations of the same integrals (interpolated reference
+    # gradients of nodal values, with the cancellation of differentiating a field whose
+    # values are much larger than its change across an element, times the coupling
+    # factors, against the mass apply with its own stored factors): 1.4e-12 measured
+    for c in range(3):
+        assert rel(g[c], a[c] * m1) <= 5e-12
+        assert rel(w[c], curl[c] * m1) <= 5e-12
+    assert abs(r.sum()) <= 1e-12 * np.abs(r).sum()
+    op.close()
