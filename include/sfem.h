@@ -158,7 +158,9 @@ typedef struct {
   double rtol;       /* stop when ||r||_2 <= rtol ||b||_2, per batch member */
   int maxit;         /* iteration cap (mode 1: cap on the total inner iterations) */
   int mode;          /* 0: FP64 Jacobi-PCG; 1: FP32 inner Jacobi-PCG inside FP64 iterative refinement */
-  double inner_rtol; /* mode 1: relative tolerance of each inner solve (e.g. 1e-5) */
+  double inner_rtol; /* mode 1: relative tolerance of an inner solve (e.g. 1e-5); once the
+                        reduction still needed, need = rtol ||b|| / ||r||, is >= inner_rtol / 10,
+                        the inner solve asks for need / 2 instead and ends the refinement */
   int max_outer;     /* mode 1: cap on refinement steps */
   int check_every;   /* iterations between host convergence checks (>= 1) */
   int x0_zero;       /* nonzero: ignore x on entry and start from x = 0 */

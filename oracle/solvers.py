@@ -7,7 +7,8 @@
   default (the relative-residual convention of Section 7.1).
 * Mixed-precision iterative refinement: residual in FP64, correction from an
   FP32 Jacobi-PCG (vectors and operator in float32, dot products accumulated in
-  float64), x += ||r|| d in FP64.
+  float64), x += ||r|| d in FP64; the inner tolerance is inner_rtol, or half the
+  reduction still needed once one FP32 solve can reach it.
 * Adjoint gradient of J(nu) = 0.5 ||u(nu) - u_t||^2 with A(nu) u = b:
   lambda solves A lambda = u - u_t (A is symmetric), and
   dJ/dnu_{e,Q} = -lambda^T (dA/dnu_{e,Q}) u, the pointwise integrand of
@@ -68,8 +69,19 @@ def pcg(apply, b, dinv, rtol=1e-10, maxit=10000, x0=None, dtype=np.float64, dot_
     return x, it, np.sqrt(rr) / bnorm
 
 
+def inner_tolerance(rtol, bnorm, rnorm, inner_rtol):
+    """Relative tolerance of the next FP32 inner solve of the refinement.  A refinement
+    step reduces the residual by the inner solve's tolerance (up to FP32 rounding), so
+    a step normally asks for inner_rtol.  The reduction still needed to reach rtol is
+    need = rtol ||b|| / ||r||; once one FP32 solve can deliver it (need >= inner_rtol / 10),
+    the step asks for need / 2 and the refinement ends with it."""
+    need = rtol * bnorm / rnorm if rnorm > 0 else 1.0
+    return 0.5 * need if need >= 0.1 * inner_rtol else inner_rtol
+
+
 def ir_pcg(apply64, apply32, dinv32, b, rtol=1e-10, inner_rtol=1e-5, max_outer=20, inner_maxit=10000):
-    """FP64 iterative refinement around an FP32 Jacobi-PCG.
+    """FP64 iterative refinement around an FP32 Jacobi-PCG; each inner tolerance from
+    inner_tolerance().
 
     Returns (x, outer_iters, total_inner_iters, true_rel_res).
     """
@@ -84,7 +96,8 @@ def ir_pcg(apply64, apply32, dinv32, b, rtol=1e-10, inner_rtol=1e-5, max_outer=2
     rnorm = bnorm
     while rnorm > rtol * bnorm and outer < max_outer:
         rs = (r / rnorm).astype(np.float32)
-        d, it, _ = pcg(apply32, rs, dinv32, rtol=inner_rtol, maxit=inner_maxit,
+        itol = inner_tolerance(rtol, bnorm, rnorm, inner_rtol)
+        d, it, _ = pcg(apply32, rs, dinv32, rtol=itol, maxit=inner_maxit,
                        dtype=np.float32, dot_dtype=np.float64)
         inner_total += it
         x = x + rnorm * d.astype(np.float64)

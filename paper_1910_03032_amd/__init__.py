@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 
+import numpy as np
 import torch  # loads the HIP runtime the library binds to
 
 from . import _lib
@@ -22,6 +23,35 @@ __all__ = ["Operator", "SfemError", "MASS", "DIFFUSION", "HELMHOLTZ", "F64", "F3
 
 def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else None
+
+
+def check_mesh_shapes(xyz_shape, dofs_shape, ndof, p, ess_shape=None):
+    """Raise ValueError unless the mesh arrays have the sizes sfem_setup reads:
+    elem_xyz [nelem, 8, 3], elem_dofs [nelem, (p+1)^3] (or flat), ess [ndof]."""
+    xyz_shape, dofs_shape = tuple(xyz_shape), tuple(dofs_shape)
+    nelem = xyz_shape[0] if len(xyz_shape) == 3 else 0
+    if len(xyz_shape) == 3 and xyz_shape[1:] != (8, 3):
+        raise ValueError(f"elem_xyz must have shape [nelem, 8, 3], got {list(xyz_shape)}")
+    if len(xyz_shape) != 3 and int(np.prod(xyz_shape)) != 0:
+        raise ValueError(f"elem_xyz must have shape [nelem, 8, 3], got {list(xyz_shape)}")
+    n3 = (int(p) + 1) ** 3
+    if int(np.prod(dofs_shape)) != nelem * n3:
+        raise ValueError(f"elem_dofs must hold nelem * (p+1)^3 = {nelem * n3} entries, "
+                         f"got shape {list(dofs_shape)}")
+    if ess_shape is not None and int(np.prod(tuple(ess_shape))) != int(ndof):
+        raise ValueError(f"ess must hold ndof = {int(ndof)} entries, got shape {list(ess_shape)}")
+    return nelem
+
+
+def check_solve_shapes(b_shape, x_shape, ndof):
+    """Raise ValueError unless b is [ndof] or [nbatch, ndof] and x (if given) has b's shape:
+    sfem_pcg reads and writes nbatch * ndof values of both."""
+    b_shape = tuple(b_shape)
+    if len(b_shape) not in (1, 2) or b_shape[-1] != int(ndof):
+        raise ValueError(f"b must have shape [ndof] or [nbatch, ndof] with ndof={int(ndof)}, "
+                         f"got {list(b_shape)}")
+    if x_shape is not None and tuple(x_shape) != b_shape:
+        raise ValueError(f"x must have b's shape {list(b_shape)}, got {list(x_shape)}")
 
 
 class PcgResult:
@@ -52,6 +82,8 @@ class Operator:
     """
 
     def __init__(self, elem_xyz, elem_dofs, ndof, p, ess=None, q=None, device=None):
+        check_mesh_shapes(np.shape(elem_xyz), np.shape(elem_dofs), ndof, p,
+                          None if ess is None else np.shape(ess))
         self._lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the sfem library runs on MI355X (gfx950) only")
@@ -140,6 +172,8 @@ class Operator:
         dtype = x.dtype if isinstance(x, torch.Tensor) and x.dtype in (torch.float32, torch.float64) \
             else torch.float64
         xv = self._vec(x, dtype, "x")
+        if xv.ndim not in (1, 2):
+            raise ValueError("x must have shape [ndof] or [nbatch, ndof]")
         nb = 1 if xv.ndim == 1 else xv.shape[0]
         y = torch.empty_like(xv) if out is None else out
         aliased = xv.numel() > 0 and y.data_ptr() == xv.data_ptr()
@@ -270,6 +304,7 @@ class Operator:
         """
         self._sync_stream()
         bv = self._vec(b, torch.float64, "b")
+        check_solve_shapes(bv.shape, None if x is None else np.shape(x), self.ndof)
         nb = 1 if bv.ndim == 1 else bv.shape[0]
         x0_zero = x is None
         xv = torch.empty_like(bv) if x0_zero else self._vec(x, torch.float64, "x").clone()

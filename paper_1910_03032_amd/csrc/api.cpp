@@ -979,9 +979,11 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
         HIPCHK(c, launch_shift(r64, w64, 1.0 / (double)n, n, nb, s));
       }
       HIPCHK(c, launch_ir_cast(r64, ir, r32, n, nb, s));
-      // Inner tolerance: a standard refinement step reduces the residual by inner_rtol;
-      // when the reduction still needed to reach rtol is within reach of one FP32
-      // solve (>= inner_rtol / 10), solve just far enough to finish in this step.
+      // Inner tolerance: a refinement step reduces the residual by the inner solve's
+      // tolerance, normally inner_rtol; once the reduction still needed to reach rtol,
+      // need = rtol ||b|| / ||r|| (the smallest over the unconverged members), is within
+      // reach of one FP32 solve (need >= inner_rtol / 10), the step asks for need / 2
+      // and finishes the refinement.
       double need = 0.0;
       for (int m = 0; m < nb; ++m) {
         if (conv[m]) continue;
@@ -989,9 +991,7 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
         const double f = rn > 0 ? opts->rtol * bn / rn : 1.0;
         need = (need == 0.0) ? f : std::min(need, f);
       }
-      double itol = opts->inner_rtol;
-      if (need >= 0.1 * opts->inner_rtol) itol = std::min(opts->inner_rtol, 0.5 * need);
-      if (need >= opts->inner_rtol) itol = 0.5 * need;
+      const double itol = need >= 0.1 * opts->inner_rtol ? 0.5 * need : opts->inner_rtol;
       PcgScalars *hs = (PcgScalars *)c->h_pinned;
       if ((st = run_pcg<float>(c, op, nb, r32, d32, true, itol,
                                opts->maxit - total_inner, opts->check_every, dinv32, dms,

@@ -7,7 +7,7 @@ import scipy.sparse.linalg as spla
 import torch
 
 from gpu_common import case, gpu, host, rel, say, nu_c2_gpu
-from oracle import Discretization, pcg as oracle_pcg, adjoint_gradient
+from oracle import Discretization, pcg as oracle_pcg, ir_pcg as oracle_ir, adjoint_gradient
 from workloads import rhs_uniform, nu_uniform, f_manufactured, u_manufactured, uniform
 
 pytestmark = pytest.mark.gpu
@@ -59,6 +59,13 @@ def test_helmholtz_pcg_and_ir_reduced():
     say(f"  fp64 {r64}  ir {rir}")
     assert r64.converged and rir.converged
     assert rir.true_rel_res[0] <= 1e-12 and rir.outer[0] >= 2
+    # the same refinement (inner tolerance rule included) in the oracle takes as many steps
+    a64 = lambda v: d.apply(v, 1e3, 1.0, nu)
+    a32 = lambda v: d.apply(v, 1e3, 1.0, nu, dtype=np.float32)
+    dinv32 = (1.0 / d.diagonal(1e3, 1.0, nu)).astype(np.float32)
+    _, outer_o, inner_o, _ = oracle_ir(a64, a32, dinv32, b, rtol=1e-12, inner_rtol=1e-5)
+    say(f"  refinement steps gpu {rir.outer[0]} oracle {outer_o}; inner {rir.iters[0]} / {inner_o}")
+    assert rir.outer[0] == outer_o and abs(rir.iters[0] - inner_o) <= 2 * outer_o
     A = d.assemble(1e3, 1.0, nu)
     xd = spla.spsolve(A.tocsc(), b)
     assert rel(host(x64), xd) <= 1e-10

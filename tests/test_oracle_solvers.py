@@ -230,3 +230,27 @@ def test_neumann_poisson_manufactured_rate():
         errs.append(d.l2_error(x, u))
     rates = np.diff(np.log(errs)) / np.log(0.5)
     assert rates[-1] >= p + 1 - 0.3, (errs, rates)
+
+
+def test_ir_inner_tolerance_rule():
+    """The inner tolerance is inner_rtol until one FP32 solve can reach the target, then
+    half the reduction still needed: 1e-10 from 1e-5 steps takes two refinement steps,
+    the second asking for (1e-10 / 1e-5) / 2 = 5e-6 (not the 1e-5 a fixed rule would use,
+    which can leave the residual just above the target and cost a third step)."""
+    from oracle.solvers import inner_tolerance
+    assert inner_tolerance(1e-10, 1.0, 1.0, 1e-5) == 1e-5                   # need 1e-10
+    assert inner_tolerance(1e-10, 1.0, 2e-4, 1e-5) == 1e-5                   # need 5e-7
+    assert inner_tolerance(1e-10, 1.0, 2e-5, 1e-5) == pytest.approx(2.5e-6)  # need 5e-6
+    assert inner_tolerance(1e-10, 1.0, 1e-11, 1e-5) == pytest.approx(5.0)    # need 10
+    assert inner_tolerance(1e-10, 1.0, 0.0, 1e-5) == 0.5                     # r = 0
+    m, d = make(3, 4)
+    nu = nu_uniform(m.nelem, d.q, seed=2)
+    b = rhs_uniform(m, seed=1)[0]
+    a64 = lambda v: d.apply(v, 1e3, 1.0, nu)
+    a32 = lambda v: d.apply(v, 1e3, 1.0, nu, dtype=np.float32)
+    dinv32 = (1.0 / d.diagonal(1e3, 1.0, nu)).astype(np.float32)
+    x, outer, inner, rel = ir_pcg(a64, a32, dinv32, b, rtol=1e-10, inner_rtol=1e-5)
+    assert rel <= 1e-10 and outer == 2
+    # the second step's own tolerance is what the rule gives for the first step's residual
+    _, _, inner1, rel1 = ir_pcg(a64, a32, dinv32, b, rtol=1e-10, inner_rtol=1e-5, max_outer=1)
+    assert 1e-7 < rel1 <= 2e-5 and inner1 < inner
