@@ -32,9 +32,13 @@ DoFs of d) and a constant viscosity nu:
 Returns u^{n+1} and p^{n+1}; the history shifts.  The solves are sparse direct.
 
 Pins (tests/test_oracle_flow.py): the weak operators, the BDF/EXT weights, one step in
-hydrostatic balance, and the time integration through self-convergence in the step
-size on a 4^3, p = 4 mesh (order 1 and order 2 rates; on coarser meshes the run-to-run
-differences stall at the mesh's equal-order consistency error).
+hydrostatic balance, the time integration through self-convergence in the step size on
+a 4^3, p = 4 mesh (order 1 and order 2 rates; on coarser meshes the run-to-run
+differences stall at the mesh's equal-order consistency error), and a manufactured
+Navier-Stokes solution with no-slip walls whose velocity and pressure errors fall at
+the scheme's order in the step size, while a flipped or unscaled rotational term L*
+or a flipped convection term N* leaves the errors large (each term is its own method,
+convection_term and rotational_term, so that a test can replace it).
 """
 from __future__ import annotations
 
@@ -141,6 +145,15 @@ class ProjectionStepper:
         self.us, self.ns = [], []  # newest first
         self.nstep = 0
 
+    def convection_term(self, u):
+        """N = -B^{-1} C(u) (nodal): the explicit convection term of the step."""
+        return -self.binv * convection(self.d, u)
+
+    def rotational_term(self, ustar):
+        """L* = -nu B^{-1} curl_w(B^{-1} curl_w u*) (nodal -nu curl curl u*, eq. projLinear)."""
+        w = self.binv * weak_curl(self.free, ustar)
+        return -self.nu * self.binv * weak_curl(self.free, w)
+
     def step(self, u, f=None):
         """Advance from u = u^n [3][N] (walls 0); f = f^{n+1} [3][N] nodal or None.
         Returns (u^{n+1}, p^{n+1})."""
@@ -149,14 +162,13 @@ class ProjectionStepper:
         k = min(self.nstep + 1, self.order)
         b, a = bdf_ext(k)
         self.us.insert(0, u)
-        self.ns.insert(0, -self.binv * convection(d, u))
+        self.ns.insert(0, self.convection_term(u))
         del self.us[k:], self.ns[k:]
         F = sum(a[j] * self.ns[j] - (b[j + 1] / dt) * self.us[j] for j in range(k))
         if f is not None:
             F = F + np.asarray(f, dtype=np.float64).reshape(3, d.ndof)
         ustar = sum(a[j] * self.us[j] for j in range(k))
-        w = self.binv * weak_curl(self.free, ustar)
-        L = -nu * self.binv * weak_curl(self.free, w)
+        L = self.rotational_term(ustar)
         r = weak_divergence(self.free, F + L)
         p = self.Kb.solve(np.concatenate([r - r.mean(), [0.0]]))[:-1]
         R = np.stack([self.M @ F[c] for c in range(3)]) - weak_gradient(self.free, p)

@@ -1,7 +1,8 @@
 """The projection step of Section 4.2 on the GPU (through the C ABI) against the oracle:
 the equal-order weak gradient, curl and divergence at p = 1..8, the nodal combination,
 a hydrostatic step (the pressure takes a gradient forcing, the velocity stays 0), and
-three BDF/EXT steps (orders 1, 2, 3) from a smooth velocity with forcing."""
+three BDF/EXT steps (orders 1, 2, 3) from a smooth velocity with forcing, and a manufactured
+Navier-Stokes solution against the oracle and the exact fields."""
 import numpy as np
 import pytest
 import torch
@@ -189,3 +190,33 @@ def test_weak_operators_full_size_identities_p4_32e():
         assert rel(w[c], curl[c] * m1) <= 5e-12
     assert abs(r.sum()) <= 1e-12 * np.abs(r).sum()
     op.close()
+
+
+def test_manufactured_navier_stokes_vs_oracle():
+    """The manufactured Navier-Stokes case that pins the oracle's step (tests/ns_manufactured.py:
+    3^3 affine mesh, p = 4, nu = 0.1, T = 0.3, BDF2/EXT2) run through the library: after 8
+    and 16 steps the GPU fields equal the oracle's (both solve to 1e-12) and their errors
+    against the exact velocity and pressure fall at rate ~2 in the step size."""
+    from ns_manufactured import run as ns_run
+    from paper_1910_03032_amd import ProjectionStepper
+    nu, T = 0.1, 0.3
+    m = BoxMesh(3, 4, amp=0.0)
+    say(f"[flow] manufactured Navier-Stokes ndof={m.ndof}")
+    d = Discretization(m.elem_xyz, m.elem_dofs, m.ess, m.ndof, 4, 6)
+    x = node_coords(m, 4)
+    m1 = d.apply_unconstrained(np.ones(m.ndof), 1.0, 0.0)
+    gstep = lambda st, u, f: tuple(host(v) for v in st.step(gpu(u), gpu(f)))
+    errs = []
+    for ns in (8, 16):
+        sg = ProjectionStepper(m.elem_xyz, m.elem_dofs, m.ndof, 4, m.ess, dt=T / ns, nu=nu, order=2,
+                               rtol=1e-12)
+        eu, ep, ug, pg = ns_run(lambda dt: sg, x, m1, nu, T, ns, step=gstep)
+        sg.close()
+        euo, epo, uo, po = ns_run(lambda dt: OracleStepper(d, dt=dt, nu=nu, order=2), x, m1, nu, T, ns)
+        du, dp = rel(ug, uo), rel(pg, po)
+        say(f"  {ns} steps: gpu errors u {eu:.3e} p {ep:.3e}, oracle {euo:.3e} {epo:.3e}, "
+            f"gpu - oracle {du:.1e} {dp:.1e}")
+        assert du <= 1e-8 and dp <= 1e-8
+        errs.append((eu, ep))
+    ru, rp = np.log2(errs[0][0] / errs[1][0]), np.log2(errs[0][1] / errs[1][1])
+    assert 1.6 <= ru <= 2.4 and rp >= 1.6, (ru, rp)

@@ -12,8 +12,12 @@ mathematics fixes:
   (differences between runs at dt, dt/2, dt/4 to the same time) at rate ~1 for BDF1/EXT1
   and ~2 for BDF2/EXT2 on a 4^3, p = 4 mesh (on coarser meshes the differences stall at
   the mesh's equal-order consistency error);
+* a manufactured Navier-Stokes solution (no-slip walls, nonzero convection and
+  nonzero normal curl curl u on the walls): the errors of the steps against the exact
+  velocity and pressure fall at rate ~1 (BDF1/EXT1) and ~2 (BDF2/EXT2) in the step size;
 * planted mistakes (a sign in the curl, a dropped pressure gradient, a wrong BDF
-  weight) fail the pins.
+  weight, a flipped or unscaled rotational term, a flipped convection term) fail the
+  pins.
 """
 import numpy as np
 import pytest
@@ -174,3 +178,58 @@ def test_wrong_bdf_weight_loses_the_order():
         return b, a
     rate = _self_convergence(2, bad)
     assert not (1.7 <= rate <= 2.3), rate
+
+
+# ---------------------------------------------------------------------------------
+# Manufactured Navier-Stokes solution (tests/ns_manufactured.py): the errors of the
+# oracle's steps against the exact velocity and pressure fall at the scheme's order in
+# the step size, and each term of the step is pinned by a planted mistake that breaks
+# the convergence: the sign of the rotational term L* (eq. projLinear), its factor nu,
+# and the sign of the extrapolated convection term N* (eq. projKnown).  3^3 affine
+# mesh, p = 4, nu = 0.1, T = 0.3; the time errors stay above the spatial floor for
+# 8 and 16 steps.
+from ns_manufactured import run as ns_run  # noqa: E402  (tests/ is on the path)
+
+NS_NU, NS_T = 0.1, 0.3
+
+
+def _ns(order, nsteps, cls=fl.ProjectionStepper):
+    m, d = disc(3, 4, amp=0.0)
+    x = nodes(m, 4)
+    m1 = d.apply_unconstrained(np.ones(m.ndof), 1.0, 0.0)
+    eu, ep, _, _ = ns_run(lambda dt: cls(d, dt=dt, nu=NS_NU, order=order), x, m1, NS_NU, NS_T, nsteps)
+    return eu, ep
+
+
+@pytest.mark.parametrize("order,lo,hi,plo", [(1, 0.8, 1.2, 0.8), (2, 1.6, 2.4, 1.6)])
+def test_manufactured_navier_stokes_converges_in_time(order, lo, hi, plo):
+    eu8, ep8 = _ns(order, 8)
+    eu16, ep16 = _ns(order, 16)
+    ru, rp = np.log2(eu8 / eu16), np.log2(ep8 / ep16)
+    assert lo <= ru <= hi, (eu8, eu16, ru)
+    assert rp >= plo, (ep8, ep16, rp)
+    if order == 2:
+        assert eu16 < 5e-3 and ep16 < 0.3, (eu16, ep16)
+
+
+class _FlippedRotational(fl.ProjectionStepper):
+    def rotational_term(self, ustar):
+        return -super().rotational_term(ustar)
+
+
+class _RotationalWithoutNu(fl.ProjectionStepper):
+    def rotational_term(self, ustar):
+        return super().rotational_term(ustar) / self.nu
+
+
+class _FlippedConvection(fl.ProjectionStepper):
+    def convection_term(self, u):
+        return -super().convection_term(u)
+
+
+@pytest.mark.parametrize("cls", [_FlippedRotational, _RotationalWithoutNu, _FlippedConvection])
+def test_manufactured_navier_stokes_rejects_planted_terms(cls):
+    good, _ = _ns(2, 16)
+    with np.errstate(all="ignore"):
+        bad, _ = _ns(2, 16, cls)
+    assert not np.isfinite(bad) or bad > 5 * good, (good, bad)
