@@ -385,7 +385,13 @@ def run_large(a, wl):
     torch.cuda.synchronize()
     out["batched_gradient_4_fields"] = {"ms": round((time.perf_counter() - t) * 1e3, 1),
                                         "forward_inner_iters": r1.iters, "adjoint_inner_iters": r2.iters,
+                                        "forward_outer": r1.outer, "adjoint_outer": r2.outer,
+                                        "forward_true_rel_res": r1.true_rel_res,
+                                        "adjoint_true_rel_res": r2.true_rel_res,
+                                        "converged": bool(r1.converged and r2.converged),
                                         "grad_norms": [float(G[k].norm()) for k in range(4)]}
+    if not (r1.converged and r2.converged):
+        raise RuntimeError(f"4-field batched solves did not converge: {r1} {r2}")
     return out
 
 
