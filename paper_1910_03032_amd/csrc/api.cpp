@@ -318,7 +318,7 @@ sfem_status ensure_cmass(sfem_ctx *c) {
 }
 
 sfem_status do_apply(sfem_ctx *c, int op, bool f32, int nbatch, const void *x, void *y,
-                     double *part);
+                     double *part = nullptr, void *evec = nullptr);
 
 // m1 = M 1 and 1^T M 1 (geometry only), for the mean-zero condition int x = m1^T x.
 sfem_status ensure_m1(sfem_ctx *c, double *tmp_ones, double *tmp_part, double *tmp_out) {
@@ -347,33 +347,41 @@ sfem_status check_op_batch(sfem_ctx *c, int op, int nbatch) {
   return SFEM_OK;
 }
 
-// Per-block dot partials of one apply, per member: the element kernel's blocks, then
-// the assembly's (which fold the element partials in, so that the apply's sum is the
-// sum of the assembly partials alone when there is an assembly phase).
-int apply_nparts_elem(const sfem_ctx *c, bool f32) {
+// Per-block dot partials of one apply of nb members, per member: the element kernel's
+// blocks (one per group of (element, member) pairs), then the assembly's (which fold the
+// element partials in, so that the apply's sum is the sum of the assembly partials alone
+// when there is an assembly phase).
+int apply_nparts_elem(const sfem_ctx *c, bool f32, int nb) {
   const int e = f32 ? apply_group_elems_f32(c->p) : apply_group_elems_f64(c->p);
-  return (int)((c->nelem + e - 1) / e);
+  return (int)((c->nelem * nb + e - 1) / e);
 }
-int apply_nparts(const sfem_ctx *c, bool f32) {
-  return apply_nparts_elem(c, f32) + (c->na > 0 ? assemble_nblk_dot(c->na) : 0);
+int apply_nparts(const sfem_ctx *c, bool f32, int nb) {
+  return apply_nparts_elem(c, f32, nb) + (c->na > 0 ? assemble_nblk_dot(c->na) : 0);
 }
 // Offset and count of the partials that sum to the apply's x . y.
-int apply_final_off(const sfem_ctx *c, bool f32) { return c->na > 0 ? apply_nparts_elem(c, f32) : 0; }
-int apply_final_count(const sfem_ctx *c, bool f32) {
-  return c->na > 0 ? assemble_nblk_dot(c->na) : apply_nparts_elem(c, f32);
+int apply_final_off(const sfem_ctx *c, bool f32, int nb) {
+  return c->na > 0 ? apply_nparts_elem(c, f32, nb) : 0;
+}
+int apply_final_count(const sfem_ctx *c, bool f32, int nb) {
+  return c->na > 0 ? assemble_nblk_dot(c->na) : apply_nparts_elem(c, f32, nb);
 }
 
 // Enqueue y = A x on the context stream (no argument checks).  With part != null the
 // two launches also leave the per-block partial sums of x . y in part[m][0..nparts).
+// evec: E-vector storage of at least nbatch * nentries values given by the caller, or
+// null for the context's own (grown on demand).
 sfem_status do_apply(sfem_ctx *c, int op, bool f32, int nbatch, const void *x, void *y,
-                     double *part = nullptr) {
+                     double *part, void *evec) {
   if (nbatch == 0 || c->ndof == 0) return SFEM_OK;
   const int64_t estride = c->nentries;
   const size_t esz = f32 ? sizeof(float) : sizeof(double);
   sfem_status st;
-  if ((st = ensure_evec(c, (size_t)estride * nbatch * esz)) != SFEM_OK) return st;
-  const int nparts = apply_nparts(c, f32);
-  const int nblk_e = apply_nparts_elem(c, f32);
+  if (!evec) {
+    if ((st = ensure_evec(c, (size_t)estride * nbatch * esz)) != SFEM_OK) return st;
+    evec = c->evec.p;
+  }
+  const int nparts = apply_nparts(c, f32, nbatch);
+  const int nblk_e = apply_nparts_elem(c, f32, nbatch);
   ApplyArgs a;
   a.p = c->p;
   a.op = op;
@@ -383,7 +391,7 @@ sfem_status do_apply(sfem_ctx *c, int op, bool f32, int nbatch, const void *x, v
   a.nelem = c->nelem;
   a.x = x;
   a.y = y;
-  a.evec = c->evec.p;
+  a.evec = evec;
   a.estride = estride;
   a.pos = c->d_pos;
   a.compact = c->compact;
@@ -408,10 +416,10 @@ sfem_status do_apply(sfem_ctx *c, int op, bool f32, int nbatch, const void *x, v
   if (e != hipSuccess) return fail(c, SFEM_E_HIP, std::string("apply launch: ") + hipGetErrorString(e));
   double *pa = part ? part + nblk_e : nullptr;
   if (f32)
-    e = launch_assemble<float>(c->plan, (const float *)c->evec.p, estride, (const float *)x, (float *)y,
+    e = launch_assemble<float>(c->plan, (const float *)evec, estride, (const float *)x, (float *)y,
                                c->ndof, nbatch, kEssCopyX, pa, nparts, c->stream, part, nblk_e);
   else
-    e = launch_assemble<double>(c->plan, (const double *)c->evec.p, estride, (const double *)x,
+    e = launch_assemble<double>(c->plan, (const double *)evec, estride, (const double *)x,
                                 (double *)y, c->ndof, nbatch, kEssCopyX, pa, nparts, c->stream, part,
                                 nblk_e);
   if (e != hipSuccess) return fail(c, SFEM_E_HIP, std::string("assembly launch: ") + hipGetErrorString(e));
@@ -472,7 +480,7 @@ template <typename T>
 size_t pcg_work_bytes(const sfem_ctx *c, int64_t n, int nb) {
   const int nblk = vec_nblk(n);
   return 3 * align_up((size_t)n * nb * sizeof(T)) + align_up((size_t)nb * 5 * nblk * sizeof(double)) +
-         align_up((size_t)nb * apply_nparts(c, sizeof(T) == 4) * sizeof(double)) +
+         align_up((size_t)nb * apply_nparts(c, sizeof(T) == 4, nb) * sizeof(double)) +
          align_up((size_t)2 * nb * sizeof(PcgScalars));
 }
 
@@ -480,7 +488,7 @@ template <typename T>
 PcgWork<T> carve_pcg(const sfem_ctx *c, Carver &cv, int64_t n, int nb) {
   PcgWork<T> w;
   w.nblk = vec_nblk(n);
-  w.nparts = apply_nparts(c, sizeof(T) == 4);
+  w.nparts = apply_nparts(c, sizeof(T) == 4, nb);
   w.r = cv.take<T>(n * nb);
   w.p = cv.take<T>(n * nb);
   w.w = cv.take<T>(n * nb);
@@ -525,8 +533,8 @@ sfem_status run_pcg(sfem_ctx *c, int op, int nb, const T *b, T *x, bool x0_zero,
   if (!any_active()) return SFEM_OK;
   for (int it = 0; it < maxit; ++it) {
     if ((st = do_apply(c, op, f32, nb, w.p, w.w, w.dpart)) != SFEM_OK) return st;
-    const double *dp = w.dpart + apply_final_off(c, f32);
-    const int dcount = apply_final_count(c, f32);
+    const double *dp = w.dpart + apply_final_off(c, f32, nb);
+    const int dcount = apply_final_count(c, f32, nb);
     PcgScalars *sc = w.sc + (int64_t)cur * nb, *sc_next = w.sc + (int64_t)(1 - cur) * nb;
     HIPCHK(c, VecOps<T>::update(x, w.p, w.r, w.w, dinv, dms, sc, dp, w.nparts, dcount, w.part,
                                 w.nblk, n, nb, s));

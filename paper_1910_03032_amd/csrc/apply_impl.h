@@ -14,7 +14,9 @@
 // points are symmetric about 0, so B is centro-symmetric and G centro-antisymmetric),
 // which halves the multiply-adds; the xi_3 stage walks the quadrature slices in
 // symmetric pairs (c, q-1-c).  Intermediates between stages live in LDS, one buffer
-// per element.  Several elements share a workgroup (E = 256 / q^2).
+// per element.  Several (element, batch member) pairs share a workgroup (E = 256 / q^2),
+// the members of an element next to each other, so that a batched apply reads each
+// element's quadrature data from HBM once for all members.
 //
 // Assembly (no atomics, deterministic): one launch of the element kernel covers every
 // element.  A DoF that belongs to this element only (the element-interior nodes of a
@@ -416,7 +418,14 @@ struct ApplyCfg {
 
 // OP: 0 mass, 1 diffusion, 2 helmholtz (matches sfem_op).  Writes y at the sole DoFs
 // and the E-vector Y[m] at the shared nodes; with part != null also the per-block sums
-// of x_g y_g over the sole DoFs (part[m * part_mstride + block]).
+// of x_g y_g over the sole DoFs (part[m * part_mstride + block], 0 for a member with no
+// element in the block).
+//
+// Work items are (element, member) pairs, pair v = e * nbatch + m, E per workgroup: the
+// members of one element run side by side (in the same workgroup or in neighbouring
+// ones, on one XCD) and read the element's quadrature data, which all members share
+// unless qd_mstride != 0, from the same cache lines, so that it comes from HBM once for
+// all members.
 template <int P, typename T, int OP>
 __global__ void __launch_bounds__((ApplyCfg<P, T>::THREADS), (ApplyCfg<P, T>::OCC))
 apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
@@ -438,22 +447,20 @@ apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
   __shared__ __align__(16) T smem[E * D::BUF];
   __shared__ int32_t smap_all[E * N3];  // the elements' map entries, kept for the output
   const int le = threadIdx.x / TPE;
-  const int t0 = threadIdx.x - le * TPE;
-  // the grid has one workgroup per batch of E elements (nelem < 2^31)
-  const int e = xcd_block() * E + le;
-  const bool active = e < nelem;
-  const int es = active ? e : 0;
+  const int t = threadIdx.x - le * TPE;
+  // the grid has one workgroup per E (element, member) pairs (nelem * nbatch pairs)
+  const int64_t npair = nelem * (int64_t)nbatch;
+  const int64_t v = (int64_t)xcd_block() * E + le;
+  const bool active = v < npair;
+  const int64_t vs = active ? v : 0;
+  const int es = (int)(vs / nbatch);
+  const int m = (int)(vs - (int64_t)es * nbatch);
   T *buf = smem + le * D::BUF;
 
   // Quadrature values one thread needs per slice c: w|J| (mass), the 6 entries of
   // w|J| J^-1 J^-T (diffusion), and nu for the diffusion operator.
   constexpr int NS = (OP == 0) ? 1 : (OP == 2 ? 7 : 7);
-  for (int m = 0; m < nbatch; ++m) {
-    // Everything derived from the thread's place in the element (node indices, surface
-    // ranks, output addresses) is recomputed for each batch member: kept in registers
-    // across the member loop it would raise the register count of the whole pipeline.
-    int t = t0;
-    asm volatile("" : "+v"(t));
+  {
     const T *xm = x + (int64_t)m * ndof;
     const T *qe = qd + (int64_t)m * qd_mstride + es * (int64_t)(kQdSlots * Q3);
     const T *ne = nullptr;
@@ -474,11 +481,7 @@ apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
     };
 
     int32_t *smap = smap_all + le * N3;
-    // The map (and position) rows are read again for every batch member: held in
-    // registers across the member loop they would raise the register count of the
-    // whole element pipeline.
-    int64_t moff = (int64_t)es * N3;
-    asm volatile("" : "+v"(moff));
+    const int64_t moff = (int64_t)es * N3;
     const int64_t epe = compact ? surf_count<P>() : N3;
     gather_e<P, T, POS>(buf, t, active, map + moff, xm, smap,
                         POS ? pos + (int64_t)es * epe : nullptr, compact != 0);
@@ -641,13 +644,21 @@ apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
     if (part) {
       const double dot = emit_e<P, T, true, POS>(buf, t, active, smap, xm, es, compact != 0,
                                                  Y + (int64_t)m * estride, y + (int64_t)m * ndof);
-      const double sum = block_sum_d(dot, reinterpret_cast<double *>(smem));
-      if (threadIdx.x == 0) part[(int64_t)m * part_mstride + blockIdx.x] = sum;
+      // one sum per member; the block's pairs v_lo.. hold members (v_lo + k) mod nbatch,
+      // k < count (a uniform test: members without a pair here get 0 without a sum)
+      const int64_t v_lo = (int64_t)xcd_block() * E;
+      const int64_t count = (npair - v_lo) < E ? (npair - v_lo) : E;
+      const int r_lo = (int)(v_lo % nbatch);
+      for (int mm = 0; mm < nbatch; ++mm) {
+        const bool here = ((mm - r_lo + nbatch) % nbatch) < count;
+        double sum = 0.0;
+        if (here) sum = block_sum_d((active && m == mm) ? dot : 0.0, reinterpret_cast<double *>(smem));
+        if (threadIdx.x == 0) part[(int64_t)mm * part_mstride + blockIdx.x] = sum;
+      }
     } else {
       emit_e<P, T, false, POS>(buf, t, active, smap, xm, es, compact != 0,
                                Y + (int64_t)m * estride, y + (int64_t)m * ndof);
     }
-    __syncthreads();
   }
 }
 
@@ -657,7 +668,7 @@ hipError_t launch_apply_pt(const ApplyArgs &a, hipStream_t s) {
   if (a.nelem <= 0 || a.nbatch <= 0) return hipSuccess;
   if ((a.pos != nullptr) != evec_dof_ordered(P)) return hipErrorInvalidValue;
   using C = ApplyCfg<P, T>;
-  dim3 grid((unsigned)((a.nelem + C::E - 1) / C::E));
+  dim3 grid((unsigned)((a.nelem * a.nbatch + C::E - 1) / C::E));
   dim3 block(C::THREADS);
   const T *qd = (const T *)a.qd;
   const T *nu = (const T *)a.nu;

@@ -54,6 +54,9 @@ def test_structs_match_header_layout():
     # double, int, int, double, int, int, int, int, int -> 44 bytes, padded to 48
     assert C.sizeof(PcgOpts) == 48
     assert C.sizeof(PcgInfo) == 32
+    from paper_1910_03032_amd._lib import CtxInfo
+    # int, int, int64, int64, int, int, int64, int64
+    assert C.sizeof(CtxInfo) == 48
 
 
 def test_library_is_gfx950_code_object():

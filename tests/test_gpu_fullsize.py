@@ -101,8 +101,10 @@ def test_adjoint_p5_20e_central_differences_16_directions():
 def test_helmholtz_p4_32e_solves_checked_by_oracle_rows():
     """32^3, p = 4 (2.1M DoFs), b ~ U(-1, 1): the FP64 PCG and the FP32+IR solutions to a
     relative residual of 1e-10 (the benchmark's solves); the residual b - A x on sampled
-    rows, with A evaluated by the oracle, is below 1e-10 max|b|, and the two solutions
-    agree to the solve tolerance times the conditioning."""
+    rows, with A evaluated by the oracle, is within what the solve tolerance allows for
+    one entry (|r_i| <= ||r||_2 <= 1e-10 ||b||_2) plus the rounding of two FP64
+    evaluations of A x (1e-12 of the largest |A x| entry), and the two solutions agree to
+    the solve tolerance times the conditioning."""
     m, d, op = case(32, 4)
     op.set_coeffs(1e3, 1.0, nu_c2_gpu(op))
     nu_o = nu_c2_oracle(d)
@@ -116,7 +118,9 @@ def test_helmholtz_p4_32e_solves_checked_by_oracle_rows():
     rows = np.concatenate([rng.integers(0, m.ndof, 24), [0, m.ndof // 2, m.ndof - 1]])
     bh = host(b)
     for name, x in (("fp64", x64), ("ir", xir)):
-        r = bh[rows] - d.apply_rows(rows, host(x), 1e3, 1.0, nu_o)
-        say(f"  {name}: max sampled-row residual {np.abs(r).max():.2e}")
-        assert np.abs(r).max() <= 1e-10 * np.abs(bh).max()
+        ax = d.apply_rows(rows, host(x), 1e3, 1.0, nu_o)
+        r = bh[rows] - ax
+        bound = 1e-10 * np.linalg.norm(bh) + 1e-12 * np.abs(ax).max()
+        say(f"  {name}: max sampled-row residual {np.abs(r).max():.2e} (bound {bound:.2e})")
+        assert np.abs(r).max() <= bound
     assert float((xir - x64).norm() / x64.norm()) <= 1e-8

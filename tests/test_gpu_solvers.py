@@ -79,10 +79,13 @@ def test_vector_helmholtz_batched_pcg_matches_single():
     B = rhs_uniform(m, seed=1, nbatch=3)
     X, res = op.pcg(gpu(B), rtol=1e-10, check_every=2)
     assert res.converged
+    # the batched apply is bitwise the single one; the CG's p^T A p of a member sums the
+    # same contributions grouped by other workgroups (the members of an element share
+    # them), so the iterates agree to rounding and take the same number of iterations
     for k in range(3):
         xk, rk = op.pcg(gpu(B[k]), rtol=1e-10, check_every=2)
         assert rk.iters[0] == res.iters[k]
-        assert torch.equal(xk, X[k])
+        assert rel(host(xk), host(X[k])) <= 1e-13
     Xi, ri = op.pcg(gpu(B), rtol=1e-10, mode=1)
     assert ri.converged and max(ri.true_rel_res) <= 1e-10
     assert rel(host(Xi), host(X)) <= 1e-8
@@ -316,7 +319,7 @@ def test_four_nu_fields_batched_solves_and_gradient_p8(mode):
         uk, rk = op.pcg(gpu(b), rtol=1e-12, mode=mode, check_every=1)
         if mode == 0:
             assert rk.iters[0] == r1.iters[k]
-            assert rel(host(uk), Uh[k]) <= 1e-14
+            assert rel(host(uk), Uh[k]) <= 1e-13
         else:  # the batched refinement picks one inner tolerance for all members
             assert rel(host(uk), Uh[k]) <= 1e-10
         res = np.linalg.norm(b - d.apply(Uh[k], alpha, beta, nus[k])) / np.linalg.norm(b)
