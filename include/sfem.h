@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define SFEM_ABI_VERSION 5
+#define SFEM_ABI_VERSION 6
 #define SFEM_MAX_P 8
 
 typedef struct sfem_ctx sfem_ctx;
@@ -131,6 +131,21 @@ sfem_status sfem_set_coeffs(sfem_ctx *ctx, double alpha, double beta, const doub
  * float32 (SFEM_F32), device, not aliased.  FP32 uses float32 copies of the 1D
  * tables and the quadrature data rounded from FP64. */
 sfem_status sfem_apply(sfem_ctx *ctx, int op, int prec, int nbatch, const void *x, void *y);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): y = A x exactly as sfem_apply (same
+ * kernels, same results), except that the E-vector of the shared-node contributions lives
+ * in a fixed library scratch array of SFEM_APPLY_NOALLOC_MAX_BYTES on each GPU instead of
+ * context memory.  The call allocates and frees nothing (no hipMalloc, hipFree or
+ * allocating library routine); the context must be set up (sfem_setup, sfem_set_coeffs)
+ * beforehand.  Needs nbatch * nentries * (8 for SFEM_F64, 4 for SFEM_F32) bytes of scratch
+ * (nentries from sfem_get_info); larger calls return SFEM_E_ARG without launching.  Every
+ * context on one GPU shares that GPU's scratch, which keeps the last call's contents: each
+ * call writes every scratch entry it reads before reading it, so nothing needs clearing,
+ * but calls that overlap in time on one GPU (other streams, other host threads) race and
+ * must be ordered by the caller.  The scratch is held until the process ends. */
+#define SFEM_APPLY_NOALLOC_MAX_BYTES (64ull << 20)
+sfem_status sfem_apply_noalloc(sfem_ctx *ctx, int op, int prec, int nbatch, const void *x, void *y);
 
 /* Exact diagonal of the constrained assembled operator (1 on essential DoFs).
  * diag: [nfield][ndof] with nfield = 1 for MASS (and when nu is NULL), otherwise
@@ -261,6 +276,7 @@ typedef struct {
   int nfields;            /* nu fields set by sfem_set_coeffs (1 when nu is NULL) */
   int64_t device_bytes;   /* device memory held by the context */
   int64_t nassembled;     /* DoFs shared by several elements, plus essential DoFs */
+  int64_t nentries;       /* E-vector entries per batch member (shared-node contributions) */
 } sfem_ctx_info;
 
 /* Sizes and counters of a set-up context (host struct). */

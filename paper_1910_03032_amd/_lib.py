@@ -9,6 +9,7 @@ LIB_PATH = os.path.join(_HERE, "libsfem.so")
 
 SFEM_OK = 0
 SFEM_NOCONV = 1
+APPLY_NOALLOC_MAX_BYTES = 64 << 20  # SFEM_APPLY_NOALLOC_MAX_BYTES
 STATUS_NAMES = {
     0: "SFEM_OK", 1: "SFEM_NOCONV", -1: "SFEM_E_ARG", -2: "SFEM_E_MESH", -3: "SFEM_E_HIP",
     -4: "SFEM_E_NOMEM", -5: "SFEM_E_UNSUPPORTED", -6: "SFEM_E_NAN", -7: "SFEM_E_BREAKDOWN",
@@ -24,6 +25,7 @@ EXPORTED = [
     "sfem_setup", "sfem_qpoint_coords", "sfem_set_coeffs", "sfem_apply", "sfem_diagonal",
     "sfem_load", "sfem_collocated_mass", "sfem_pcg", "sfem_grad_nu", "sfem_get_info",
     "sfem_setup_pressure", "sfem_stokes_apply", "sfem_convection", "sfem_weak_op", "sfem_lincomb",
+    "sfem_apply_noalloc",
 ]
 
 
@@ -41,7 +43,7 @@ class PcgInfo(C.Structure):
 class CtxInfo(C.Structure):
     _fields_ = [("p", C.c_int), ("q", C.c_int), ("nelem", C.c_int64), ("ndof", C.c_int64),
                 ("compact", C.c_int), ("nfields", C.c_int), ("device_bytes", C.c_int64),
-                ("nassembled", C.c_int64)]
+                ("nassembled", C.c_int64), ("nentries", C.c_int64)]
 
 
 class SfemError(RuntimeError):
@@ -72,6 +74,7 @@ def load(path: str = LIB_PATH):
         "sfem_qpoint_coords": (i32, [vp, vp]),
         "sfem_set_coeffs": (i32, [vp, dbl, dbl, vp, i32]),
         "sfem_apply": (i32, [vp, i32, i32, i32, vp, vp]),
+        "sfem_apply_noalloc": (i32, [vp, i32, i32, i32, vp, vp]),
         "sfem_diagonal": (i32, [vp, i32, i32, vp]),
         "sfem_load": (i32, [vp, i32, vp, vp]),
         "sfem_collocated_mass": (i32, [vp, vp]),

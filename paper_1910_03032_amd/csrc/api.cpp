@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -16,9 +17,39 @@
 
 using namespace sfem;
 
+// Scratch of the allocation-free apply (sfem_apply_noalloc): the E-vector of the
+// shared-node contributions.  Each GPU the library runs on holds its own copy of this
+// array until the process ends.  In host code its name is only a stand-in: the device
+// address comes from hipGetSymbolAddress, resolved once per device (resolve_scratch).
+static __device__ __align__(256) char scratch[SFEM_APPLY_NOALLOC_MAX_BYTES];
+
 namespace {
 
 std::string g_create_error;  // message of the last failed sfem_create
+
+// Device address of `scratch` per device, resolved at the first sfem_create on that
+// device (with the device current).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+bool g_scratch_done[kMaxDevices] = {};
+void *g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+hipError_t resolve_scratch(int device, void **out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_done[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) (void)hipGetLastError();
+    g_scratch_ptr[device] = e == hipSuccess ? p : nullptr;
+    g_scratch_err[device] = e;
+    g_scratch_done[device] = true;
+  }
+  *out = g_scratch_ptr[device];
+  return g_scratch_err[device];
+}
 
 struct DevBuf {
   void *p = nullptr;
@@ -31,6 +62,8 @@ struct sfem_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
+  void *scratch = nullptr;             // this device's `scratch` array (device address)
+  hipError_t scratch_err = hipSuccess;  // outcome of resolving it
 
   // ---- mesh
   bool ready = false;
@@ -594,6 +627,10 @@ sfem_status sfem_create(int device, void *stream, sfem_ctx **out) {
   }
   c->device = device;
   c->stream = (hipStream_t)stream;
+  {
+    DeviceGuard g(device);
+    c->scratch_err = resolve_scratch(device, &c->scratch);
+  }
   *out = c;
   return SFEM_OK;
 }
@@ -761,6 +798,28 @@ sfem_status sfem_apply(sfem_ctx *c, int op, int prec, int nbatch, const void *x,
   }
   DeviceGuard g(c->device);
   return do_apply(c, op, prec == SFEM_F32, nbatch, x, y);
+}
+
+sfem_status sfem_apply_noalloc(sfem_ctx *c, int op, int prec, int nbatch, const void *x, void *y) {
+  sfem_status st = require_ready(c);
+  if (st != SFEM_OK) return st;
+  if ((st = check_op_batch(c, op, nbatch)) != SFEM_OK) return st;
+  if (prec != SFEM_F64 && prec != SFEM_F32) return fail(c, SFEM_E_ARG, "prec must be SFEM_F64 or SFEM_F32");
+  if (nbatch == 0 || c->ndof == 0) return SFEM_OK;
+  if (!x || !y) return fail(c, SFEM_E_ARG, "x and y must not be NULL");
+  if (x == y) return fail(c, SFEM_E_ARG, "x and y must not alias");
+  const size_t esz = prec == SFEM_F32 ? sizeof(float) : sizeof(double);
+  const double need = (double)c->nentries * (double)nbatch * (double)esz;
+  if (need > (double)SFEM_APPLY_NOALLOC_MAX_BYTES)
+    return fail(c, SFEM_E_ARG,
+                "sfem_apply_noalloc: the E-vector of this apply needs " + std::to_string((int64_t)need) +
+                    " bytes, more than the " + std::to_string((int64_t)SFEM_APPLY_NOALLOC_MAX_BYTES) +
+                    "-byte scratch (use sfem_apply or fewer members)");
+  if (c->scratch_err != hipSuccess || !c->scratch)
+    return fail(c, SFEM_E_HIP, std::string("scratch address of this device: ") +
+                                   hipGetErrorString(c->scratch_err));
+  DeviceGuard g(c->device);
+  return do_apply(c, op, prec == SFEM_F32, nbatch, x, y, nullptr, c->scratch);
 }
 
 sfem_status sfem_diagonal(sfem_ctx *c, int op, int prec, void *diag) {
@@ -1240,6 +1299,7 @@ sfem_status sfem_get_info(const sfem_ctx *c, sfem_ctx_info *out) {
   out->nassembled = c->na;
   out->nfields = c->nfield;
   out->device_bytes = c->bytes + (int64_t)c->ws.bytes + (int64_t)c->evec.bytes;
+  out->nentries = c->nentries;
   return SFEM_OK;
 }
 

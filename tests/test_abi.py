@@ -40,13 +40,14 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_pure_host_calls(lib):
-    assert lib.sfem_abi_version() == 5
+    assert lib.sfem_abi_version() == 6
     assert isinstance(lib.sfem_last_error(None), bytes)
     from paper_1910_03032_amd._lib import CtxInfo
     ci = CtxInfo()
     assert lib.sfem_get_info(None, C.byref(ci)) == -1  # SFEM_E_ARG on a NULL context
     assert lib.sfem_set_stream(None, None) == -1
     lib.sfem_destroy(None)  # no-op
+    assert lib.sfem_apply_noalloc(None, 2, 0, 1, None, None) == -1
 
 
 def test_structs_match_header_layout():
@@ -55,8 +56,8 @@ def test_structs_match_header_layout():
     assert C.sizeof(PcgOpts) == 48
     assert C.sizeof(PcgInfo) == 32
     from paper_1910_03032_amd._lib import CtxInfo
-    # int, int, int64, int64, int, int, int64, int64
-    assert C.sizeof(CtxInfo) == 48
+    # int, int, int64, int64, int, int, int64, int64, int64
+    assert C.sizeof(CtxInfo) == 56
 
 
 def test_library_is_gfx950_code_object():
