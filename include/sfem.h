@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define SFEM_ABI_VERSION 6
+#define SFEM_ABI_VERSION 7
 #define SFEM_MAX_P 8
 
 typedef struct sfem_ctx sfem_ctx;
@@ -268,6 +268,67 @@ sfem_status sfem_weak_op(sfem_ctx *ctx, int kind, const double *x, double *y);
  * sizes or NULL arrays. */
 sfem_status sfem_lincomb(sfem_ctx *ctx, int nterm, const double *coef, const double *const *xs,
                          const double *scale, const uint8_t *mask, int64_t n, int nb, double *y);
+
+/* ---- Projection time stepping (Section 4.2) ------------------------------------------
+ *
+ * BDF-k / EXT-k weights for a constant step (k = 1, 2, 3): b[0..k] with
+ * sum_j b_j g(t_{n+1-j}) = dt g'(t_{n+1}) for every polynomial g of degree <= k, and
+ * a[0..k-1] (a_j of u^{n+1-j}, j = 1..k) with sum_j a_j g(t_{n+1-j}) = g(t_{n+1}) for
+ * degree <= k - 1; solved from these exactness conditions.  b, a: host arrays of k + 1 and
+ * k doubles.  A host computation (no device call).  Errors: SFEM_E_ARG for k outside 1..3
+ * or NULL arrays. */
+sfem_status sfem_bdf_ext_weights(int k, double *b, double *a);
+
+typedef struct sfem_flow sfem_flow; /* opaque, library-owned */
+
+typedef struct {
+  double dt;          /* time step (> 0), constant */
+  double nu;          /* kinematic viscosity (>= 0), constant */
+  double rtol;        /* relative residual tolerance of the pressure and velocity solves */
+  int order;          /* BDF/EXT order 1..3; the first steps ramp up 1, 2, .. to it */
+  int pressure_mode;  /* pressure Poisson: 0 FP64 Jacobi-PCG, 1 FP32 inner solves in FP64 refinement */
+  int check_every;    /* iterations between host convergence checks of the solves (>= 1) */
+  int maxit;          /* iteration cap of each solve (>= 1) */
+} sfem_flow_opts;
+
+typedef struct {
+  int order;                  /* BDF/EXT order of the step just taken */
+  sfem_pcg_info pressure;     /* the pressure Poisson solve */
+  sfem_pcg_info velocity[3];  /* the Helmholtz solve of each velocity component */
+} sfem_flow_info;
+
+/* Velocity-correction projection stepper (Section 4.2: eq. projKnown, eq. projLinear,
+ * eq. pres-poisson with eq. presPoissonBC and eq. meanZero, eq. proj-helmholtz) for
+ * equal-order velocity and pressure (each velocity component and the pressure in the
+ * continuous Q_p space of the mesh), no-slip walls on the essential DoFs given by ess_mask,
+ * constant nu and dt.  Mesh arguments as for sfem_setup (device arrays, copied; ess_mask
+ * must not be NULL).  The stepper holds two set-up contexts on the mesh (with and without
+ * the walls), the collocated GLL mass B (Section 5.1), the step history and its work
+ * vectors (about 25 ndof doubles).  *out receives the handle; on failure it is NULL and
+ * sfem_flow_last_error(NULL) holds the message. */
+sfem_status sfem_flow_create(int device, void *stream, int p, int64_t nelem, const double *elem_xyz,
+                             const int32_t *elem_dofs, int64_t ndof, const uint8_t *ess_mask,
+                             const sfem_flow_opts *opts, sfem_flow **out);
+void sfem_flow_destroy(sfem_flow *flow);
+const char *sfem_flow_last_error(const sfem_flow *flow);
+sfem_status sfem_flow_set_stream(sfem_flow *flow, void *stream);
+
+/* One step of order k = min(steps taken + 1, order) from u = u^n [3][ndof] (device, float64,
+ * component-major, 0 on the walls) with the nodal forcing f = f^{n+1} [3][ndof] (device) or
+ * NULL:
+ *   N^n = -B^{-1} C(u^n) (the convection term, rows of wall DoFs 0);
+ *   F* = sum_j a_j N^{n+1-j} - sum_j (b_j / dt) u^{n+1-j} + f^{n+1};
+ *   u* = sum_j a_j u^{n+1-j};  L* = -nu B^{-1} curl_w(B^{-1} curl_w u*);
+ *   K p = div_w(F* + L*) with int p = 0, by the orthogonalized pure-Neumann Jacobi-PCG
+ *   (pressure_mode), from the previous step's pressure;
+ *   (b_0/dt) M u + nu K u = M F* - grad_w p on the free rows, u = 0 on the walls, by
+ *   three-member Jacobi-PCG from u*.
+ * Writes u_out = u^{n+1} [3][ndof] and p_out = p^{n+1} [ndof] (device, not aliasing u) and
+ * shifts the history; info (host, may be NULL) gets the order and the solves' outcomes.
+ * Returns SFEM_NOCONV (the step is taken) if a solve reached maxit, negative on error.
+ * Synchronizes with the host at the solves' convergence checks. */
+sfem_status sfem_flow_step(sfem_flow *flow, const double *u, const double *f, double *u_out,
+                           double *p_out, sfem_flow_info *info);
 
 typedef struct {
   int p, q;

@@ -25,7 +25,8 @@ EXPORTED = [
     "sfem_setup", "sfem_qpoint_coords", "sfem_set_coeffs", "sfem_apply", "sfem_diagonal",
     "sfem_load", "sfem_collocated_mass", "sfem_pcg", "sfem_grad_nu", "sfem_get_info",
     "sfem_setup_pressure", "sfem_stokes_apply", "sfem_convection", "sfem_weak_op", "sfem_lincomb",
-    "sfem_apply_noalloc",
+    "sfem_apply_noalloc", "sfem_bdf_ext_weights", "sfem_flow_create", "sfem_flow_destroy",
+    "sfem_flow_last_error", "sfem_flow_set_stream", "sfem_flow_step",
 ]
 
 
@@ -44,6 +45,15 @@ class CtxInfo(C.Structure):
     _fields_ = [("p", C.c_int), ("q", C.c_int), ("nelem", C.c_int64), ("ndof", C.c_int64),
                 ("compact", C.c_int), ("nfields", C.c_int), ("device_bytes", C.c_int64),
                 ("nassembled", C.c_int64), ("nentries", C.c_int64)]
+
+
+class FlowOpts(C.Structure):
+    _fields_ = [("dt", C.c_double), ("nu", C.c_double), ("rtol", C.c_double), ("order", C.c_int),
+                ("pressure_mode", C.c_int), ("check_every", C.c_int), ("maxit", C.c_int)]
+
+
+class FlowInfo(C.Structure):
+    _fields_ = [("order", C.c_int), ("pressure", PcgInfo), ("velocity", PcgInfo * 3)]
 
 
 class SfemError(RuntimeError):
@@ -86,6 +96,12 @@ def load(path: str = LIB_PATH):
         "sfem_convection": (i32, [vp, vp, vp]),
         "sfem_weak_op": (i32, [vp, i32, vp, vp]),
         "sfem_lincomb": (i32, [vp, i32, C.POINTER(dbl), C.POINTER(vp), vp, vp, i64, i32, vp]),
+        "sfem_bdf_ext_weights": (i32, [i32, C.POINTER(dbl), C.POINTER(dbl)]),
+        "sfem_flow_create": (i32, [i32, vp, i32, i64, vp, vp, i64, vp, C.POINTER(FlowOpts), C.POINTER(vp)]),
+        "sfem_flow_destroy": (None, [vp]),
+        "sfem_flow_last_error": (C.c_char_p, [vp]),
+        "sfem_flow_set_stream": (i32, [vp, vp]),
+        "sfem_flow_step": (i32, [vp, vp, vp, vp, vp, C.POINTER(FlowInfo)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -32,6 +32,7 @@ SOURCES = [
     "rules.cpp",
     "plan.cpp",
     "api.cpp",
+    "flow_step.cpp",
 ]
 
 ARCH = "gfx950"

@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_pure_host_calls(lib):
-    assert lib.sfem_abi_version() == 6
+    assert lib.sfem_abi_version() == 7
     assert isinstance(lib.sfem_last_error(None), bytes)
     from paper_1910_03032_amd._lib import CtxInfo
     ci = CtxInfo()
@@ -48,6 +48,10 @@ def test_pure_host_calls(lib):
     assert lib.sfem_set_stream(None, None) == -1
     lib.sfem_destroy(None)  # no-op
     assert lib.sfem_apply_noalloc(None, 2, 0, 1, None, None) == -1
+    assert lib.sfem_flow_step(None, None, None, None, None, None) == -1
+    assert lib.sfem_flow_create(0, None, 2, 0, None, None, 0, None, None, None) == -1
+    assert isinstance(lib.sfem_flow_last_error(None), bytes)
+    lib.sfem_flow_destroy(None)  # no-op
 
 
 def test_structs_match_header_layout():
@@ -58,6 +62,9 @@ def test_structs_match_header_layout():
     from paper_1910_03032_amd._lib import CtxInfo
     # int, int, int64, int64, int, int, int64, int64, int64
     assert C.sizeof(CtxInfo) == 56
+    from paper_1910_03032_amd._lib import FlowOpts, FlowInfo
+    assert C.sizeof(FlowOpts) == 40  # 3 doubles, 4 ints
+    assert C.sizeof(FlowInfo) == 136  # int (padded to 8), 4 sfem_pcg_info
 
 
 def test_library_is_gfx950_code_object():

@@ -1,5 +1,6 @@
-"""Host logic of the projection stepper (no GPU): the BDF/EXT weights the product derives
-from their exactness conditions equal the oracle's table."""
+"""Host logic of the projection stepper (no GPU): the BDF/EXT weights the library derives
+from their exactness conditions (sfem_bdf_ext_weights, a host computation behind the C
+ABI) equal the oracle's table."""
 import numpy as np
 import pytest
 
@@ -17,3 +18,13 @@ def test_bad_order():
     from paper_1910_03032_amd.flow import bdf_ext_weights
     with pytest.raises(ValueError):
         bdf_ext_weights(4)
+
+
+def test_bdf_ext_weights_c_abi_rejects_bad_arguments():
+    import ctypes as C
+    from paper_1910_03032_amd import _lib
+    lib = _lib.load()
+    b, a = (C.c_double * 5)(), (C.c_double * 4)()
+    assert lib.sfem_bdf_ext_weights(0, b, a) == -1
+    assert lib.sfem_bdf_ext_weights(4, b, a) == -1
+    assert lib.sfem_bdf_ext_weights(2, None, a) == -1
