@@ -16,8 +16,11 @@ Contents:
   flow        equal-order weak gradient, curl and divergence, BDF-k/EXT-k coefficients
               and the velocity-correction projection step (Section 4.2)
   solvers     diagonally preconditioned CG (optionally orthogonalized against the
-              constants), FP32-inner iterative refinement, adjoint gradient, pure-Neumann
-              Poisson with the mean-zero condition (Section 5, Section 5.3)
+              constants, or with a general preconditioner), FP32-inner iterative
+              refinement, adjoint gradient, pure-Neumann Poisson with the mean-zero
+              condition (Section 5, Section 5.3)
+  lor         the low-order-refined operator A_LOR = alpha M_LOR + beta K_LOR on the
+              GLL-refined mesh (Section 5.2)
 
 Pins (tests/test_oracle_*.py) tie each part to closed forms and invariants;
 nothing here is "parity unpinned".

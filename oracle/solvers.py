@@ -21,9 +21,11 @@ import numpy as np
 
 
 def pcg(apply, b, dinv, rtol=1e-10, maxit=10000, x0=None, dtype=np.float64, dot_dtype=np.float64,
-        nullspace=False):
+        nullspace=False, precond=None):
     """Diagonally preconditioned CG.  Returns (x, iters, rel_res_recursive).  ``apply`` maps
-    a vector to A v, ``dinv`` is the inverse of the diagonal preconditioner.
+    a vector to A v, ``dinv`` is the inverse of the diagonal preconditioner; ``precond``
+    (a callable r -> z), if given, replaces the diagonal (e.g. a solve with the LOR
+    operator of Section 5.2).
 
     nullspace=True: the operator has the constant vectors as null space (pure Neumann
     Poisson, Section 5.3); every application of the preconditioner is followed by the
@@ -40,8 +42,10 @@ def pcg(apply, b, dinv, rtol=1e-10, maxit=10000, x0=None, dtype=np.float64, dot_
         return np.zeros_like(b), 0, 0.0
     r = b - apply(x) if x0 is not None else b.copy()
 
+    user = precond
+
     def precond(v):
-        z = (dinv * v).astype(dtype)
+        z = (dinv * v).astype(dtype) if user is None else np.asarray(user(v), dtype=dtype)
         if nullspace:
             z = (z - dtype(np.mean(z.astype(dot_dtype)))).astype(dtype)
         return z
