@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define SFEM_ABI_VERSION 7
+#define SFEM_ABI_VERSION 9
 #define SFEM_MAX_P 8
 
 typedef struct sfem_ctx sfem_ctx;
@@ -147,6 +147,35 @@ sfem_status sfem_apply(sfem_ctx *ctx, int op, int prec, int nbatch, const void *
 #define SFEM_APPLY_NOALLOC_MAX_BYTES (64ull << 20)
 sfem_status sfem_apply_noalloc(sfem_ctx *ctx, int op, int prec, int nbatch, const void *x, void *y);
 
+/* Low-order-refined preconditioner (Section 5.2).  A_LOR = a M_LOR + b K_LOR is the
+ * trilinear (Q1) discretization of the operator kind op (MASS: a = 1, b = 0; DIFFUSION:
+ * 0, 1; HELMHOLTZ: alpha, beta of sfem_set_coeffs) on the refined mesh that splits every
+ * element into the p^3 sub-hexahedra between its GLL points (each the trilinear element
+ * through its 8 corner nodes, 2 x 2 x 2 Gauss points); nu enters as its mean over each
+ * element's quadrature points; essential DoFs are constrained as in the operator.  A_LOR
+ * has the operator's unknowns, is spectrally equivalent to it with h- and p-independent
+ * constants, and has at most 27 nonzeros per row on a structured mesh.  Its solver is a
+ * smoothed-aggregation algebraic multigrid V-cycle (strength threshold 0.02, three-pass
+ * aggregation, Jacobi-smoothed prolongator, Galerkin coarse operators down to <= 200 rows,
+ * dense pseudo-inverse there, two damped-Jacobi sweeps before and after each coarse
+ * correction): the setup runs on the host (the mesh copy kept by sfem_setup), every step
+ * of the V-cycle on the GPU.  sfem_pcg with precond = SFEM_PRECOND_LOR builds it on first
+ * use; sfem_set_coeffs discards it.  One nu field only (SFEM_E_ARG otherwise).
+ *   sfem_lor_setup   build it now; info (host, may be NULL) gets the level sizes
+ *   sfem_lor_apply   y = A_LOR x  (device [ndof] float64)
+ *   sfem_lor_vcycle  x = one V-cycle for A_LOR x = b from x = 0 (device [ndof] float64)
+ * Synchronous (setup); apply and vcycle are asynchronous on the context stream. */
+#define SFEM_LOR_MAX_LEVELS 12
+typedef struct {
+  int levels;                          /* multigrid levels (the finest is A_LOR) */
+  int64_t rows[SFEM_LOR_MAX_LEVELS];   /* rows per level */
+  int64_t nnz[SFEM_LOR_MAX_LEVELS];    /* nonzeros per level */
+  double setup_ms;                     /* host setup time of the hierarchy */
+} sfem_lor_info;
+sfem_status sfem_lor_setup(sfem_ctx *ctx, int op, sfem_lor_info *info);
+sfem_status sfem_lor_apply(sfem_ctx *ctx, int op, const double *x, double *y);
+sfem_status sfem_lor_vcycle(sfem_ctx *ctx, int op, const double *b, double *x);
+
 /* Exact diagonal of the constrained assembled operator (1 on essential DoFs).
  * diag: [nfield][ndof] with nfield = 1 for MASS (and when nu is NULL), otherwise
  * the number of nu fields; float64 or float32 per prec (device). */
@@ -165,8 +194,10 @@ sfem_status sfem_load(sfem_ctx *ctx, int nbatch, const double *f_q, double *b);
 sfem_status sfem_collocated_mass(sfem_ctx *ctx, double *diag);
 
 typedef enum {
-  SFEM_PRECOND_JACOBI = 0,         /* exact diagonal of the (constrained) operator */
-  SFEM_PRECOND_COLLOCATED_MASS = 1 /* collocated mass diagonal (for mass solves, Section 5.1) */
+  SFEM_PRECOND_JACOBI = 0,          /* exact diagonal of the (constrained) operator */
+  SFEM_PRECOND_COLLOCATED_MASS = 1, /* collocated mass diagonal (for mass solves, Section 5.1) */
+  SFEM_PRECOND_LOR = 2              /* one multigrid V-cycle on the low-order-refined operator
+                                       (Section 5.2, see sfem_lor_setup); FP64 CG (mode 0) */
 } sfem_precond;
 
 typedef struct {
@@ -289,6 +320,8 @@ typedef struct {
   int pressure_mode;  /* pressure Poisson: 0 FP64 Jacobi-PCG, 1 FP32 inner solves in FP64 refinement */
   int check_every;    /* iterations between host convergence checks of the solves (>= 1) */
   int maxit;          /* iteration cap of each solve (>= 1) */
+  int pressure_precond; /* pressure Poisson preconditioner: SFEM_PRECOND_JACOBI or
+                           SFEM_PRECOND_LOR (Section 5.2; FP64 CG, pressure_mode ignored) */
 } sfem_flow_opts;
 
 typedef struct {

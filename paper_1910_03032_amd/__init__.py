@@ -15,7 +15,8 @@ import torch  # loads the HIP runtime the library binds to
 
 from . import _lib
 from ._lib import (F32, F64, MASS, DIFFUSION, HELMHOLTZ, PRECOND_JACOBI, PRECOND_COLLOCATED_MASS,  # noqa: F401
-                   WEAK_GRADIENT, WEAK_CURL, WEAK_DIVERGENCE, SfemError, PcgOpts, PcgInfo, CtxInfo)
+                   PRECOND_LOR, WEAK_GRADIENT, WEAK_CURL, WEAK_DIVERGENCE, SfemError, PcgOpts, PcgInfo,
+                   CtxInfo, LorInfo)
 
 __all__ = ["Operator", "SfemError", "MASS", "DIFFUSION", "HELMHOLTZ", "F64", "F32", "PcgResult",
            "WEAK_GRADIENT", "WEAK_CURL", "WEAK_DIVERGENCE", "ProjectionStepper"]
@@ -291,11 +292,41 @@ class Operator:
         self._check(self._lib.sfem_collocated_mass(self._h, _ptr(d)))
         return d
 
+    def lor_setup(self, op=HELMHOLTZ):
+        """Build the LOR multigrid of operator kind op (Section 5.2); returns its level sizes
+        and the host setup time."""
+        self._sync_stream()
+        info = LorInfo()
+        self._check(self._lib.sfem_lor_setup(self._h, op, C.byref(info)))
+        L = info.levels
+        return {"levels": L, "rows": list(info.rows[:L]), "nnz": list(info.nnz[:L]),
+                "setup_ms": info.setup_ms}
+
+    def lor_apply(self, x, op=HELMHOLTZ):
+        """y = A_LOR x (float64 [ndof])."""
+        self._sync_stream()
+        xv = self._vec(x, torch.float64, "x")
+        if xv.ndim != 1:
+            raise ValueError("x must have shape [ndof]")
+        y = torch.empty_like(xv)
+        self._check(self._lib.sfem_lor_apply(self._h, op, _ptr(xv), _ptr(y)))
+        return y
+
+    def lor_vcycle(self, b, op=HELMHOLTZ):
+        """One multigrid V-cycle for A_LOR x = b from x = 0 (float64 [ndof])."""
+        self._sync_stream()
+        bv = self._vec(b, torch.float64, "b")
+        if bv.ndim != 1:
+            raise ValueError("b must have shape [ndof]")
+        x = torch.empty_like(bv)
+        self._check(self._lib.sfem_lor_vcycle(self._h, op, _ptr(bv), _ptr(x)))
+        return x
+
     def pcg(self, b, x=None, op=HELMHOLTZ, rtol=1e-10, maxit=10000, mode=0, inner_rtol=1e-5,
             max_outer=30, check_every=8, precond=PRECOND_JACOBI, nullspace=False):
-        """Diagonally preconditioned CG (mode 0) or FP32-inner CG inside FP64 refinement
-        (mode 1).  precond: PRECOND_JACOBI (exact operator diagonal) or
-        PRECOND_COLLOCATED_MASS.  nullspace=True: pure-Neumann diffusion solve (no
+        """Preconditioned CG (mode 0) or FP32-inner CG inside FP64 refinement (mode 1).
+        precond: PRECOND_JACOBI (exact operator diagonal), PRECOND_COLLOCATED_MASS, or
+        PRECOND_LOR (a multigrid V-cycle on the low-order-refined operator; mode 0).  nullspace=True: pure-Neumann diffusion solve (no
         essential DoFs) with the preconditioner orthogonalized against the constants and
         the mean-zero solution returned.
 

@@ -16,7 +16,8 @@ STATUS_NAMES = {
     -8: "SFEM_E_STATE",
 }
 F64, F32 = 0, 1
-PRECOND_JACOBI, PRECOND_COLLOCATED_MASS = 0, 1
+PRECOND_JACOBI, PRECOND_COLLOCATED_MASS, PRECOND_LOR = 0, 1, 2
+LOR_MAX_LEVELS = 12
 MASS, DIFFUSION, HELMHOLTZ = 0, 1, 2
 WEAK_GRADIENT, WEAK_CURL, WEAK_DIVERGENCE = 1, 2, 3
 
@@ -26,7 +27,8 @@ EXPORTED = [
     "sfem_load", "sfem_collocated_mass", "sfem_pcg", "sfem_grad_nu", "sfem_get_info",
     "sfem_setup_pressure", "sfem_stokes_apply", "sfem_convection", "sfem_weak_op", "sfem_lincomb",
     "sfem_apply_noalloc", "sfem_bdf_ext_weights", "sfem_flow_create", "sfem_flow_destroy",
-    "sfem_flow_last_error", "sfem_flow_set_stream", "sfem_flow_step",
+    "sfem_flow_last_error", "sfem_flow_set_stream", "sfem_flow_step", "sfem_lor_setup",
+    "sfem_lor_apply", "sfem_lor_vcycle",
 ]
 
 
@@ -49,11 +51,17 @@ class CtxInfo(C.Structure):
 
 class FlowOpts(C.Structure):
     _fields_ = [("dt", C.c_double), ("nu", C.c_double), ("rtol", C.c_double), ("order", C.c_int),
-                ("pressure_mode", C.c_int), ("check_every", C.c_int), ("maxit", C.c_int)]
+                ("pressure_mode", C.c_int), ("check_every", C.c_int), ("maxit", C.c_int),
+                ("pressure_precond", C.c_int)]
 
 
 class FlowInfo(C.Structure):
     _fields_ = [("order", C.c_int), ("pressure", PcgInfo), ("velocity", PcgInfo * 3)]
+
+
+class LorInfo(C.Structure):
+    _fields_ = [("levels", C.c_int), ("rows", C.c_int64 * LOR_MAX_LEVELS),
+                ("nnz", C.c_int64 * LOR_MAX_LEVELS), ("setup_ms", C.c_double)]
 
 
 class SfemError(RuntimeError):
@@ -102,6 +110,9 @@ def load(path: str = LIB_PATH):
         "sfem_flow_last_error": (C.c_char_p, [vp]),
         "sfem_flow_set_stream": (i32, [vp, vp]),
         "sfem_flow_step": (i32, [vp, vp, vp, vp, vp, C.POINTER(FlowInfo)]),
+        "sfem_lor_setup": (i32, [vp, i32, C.POINTER(LorInfo)]),
+        "sfem_lor_apply": (i32, [vp, i32, vp, vp]),
+        "sfem_lor_vcycle": (i32, [vp, i32, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -33,6 +33,9 @@ SOURCES = [
     "plan.cpp",
     "api.cpp",
     "flow_step.cpp",
+    "lor_host.cpp",
+    "lor.cpp",
+    "k_lor.hip",
 ]
 
 ARCH = "gfx950"

@@ -14,6 +14,7 @@
 
 #include "internal.h"
 #include "flow.h"
+#include "lor.h"
 
 using namespace sfem;
 
@@ -116,6 +117,15 @@ struct sfem_ctx {
   float *d_diag32[3] = {nullptr, nullptr, nullptr};
   float *d_dinv32[3] = {nullptr, nullptr, nullptr};
 
+  // ---- host copies of the mesh (the LOR assembly) and the LOR multigrid per operator kind
+  std::vector<double> h_xyz;
+  std::vector<int32_t> h_dofs;     // unflagged element->DoF map
+  std::vector<uint8_t> h_ess;
+  bool lor_ok[3] = {false, false, false};
+  Amg lor[3];
+  double *lor_work = nullptr;      // [5][ndof] vectors of the LOR-preconditioned CG
+  double *lor_scal = nullptr;      // [8] device scalars
+
   // ---- E-vector of the apply and solver workspace (grown on demand)
   DevBuf evec;
   DevBuf ws;
@@ -180,7 +190,15 @@ void dfree(sfem_ctx *c, void *p) {
   }
 }
 
+void free_lor(sfem_ctx *c) {
+  for (int o = 0; o < 3; ++o) {
+    amg_free(c->lor[o]);
+    c->lor_ok[o] = false;
+  }
+}
+
 void free_coeffs(sfem_ctx *c) {
+  free_lor(c);
   dfree(c, c->d_fold64);
   dfree(c, c->d_fold32);
   dfree(c, c->d_nu64);
@@ -201,6 +219,9 @@ void free_coeffs(sfem_ctx *c) {
 }
 
 void free_all(sfem_ctx *c) {
+  free_lor(c);
+  c->lor_work = nullptr;
+  c->lor_scal = nullptr;
   for (auto &b : c->owned) (void)hipFree(b.p);
   c->owned.clear();
   c->bytes = 0;
@@ -582,6 +603,171 @@ sfem_status run_pcg(sfem_ctx *c, int op, int nb, const T *b, T *x, bool x0_zero,
   return SFEM_OK;
 }
 
+// ---- LOR preconditioner (Section 5.2) --------------------------------------------------
+
+// Multigrid parameters: strength threshold, coarsest size, level cap, Jacobi sweeps.
+constexpr double kLorTheta = 0.02;
+constexpr int64_t kLorCoarse = 200;
+constexpr int kLorMaxLevels = 12;
+constexpr int kLorSweeps = 2;
+
+// Build (once per operator kind and coefficients) A_LOR of op and its multigrid hierarchy.
+sfem_status ensure_lor(sfem_ctx *c, int op) {
+  if (c->lor_ok[op]) return SFEM_OK;
+  if (op != SFEM_MASS && c->nfield > 1)
+    return fail(c, SFEM_E_ARG, "the LOR preconditioner takes one nu field");
+  double a = 1.0, b = 0.0;
+  if (op == SFEM_DIFFUSION) {
+    a = 0.0;
+    b = 1.0;
+  } else if (op == SFEM_HELMHOLTZ) {
+    a = c->alpha;
+    b = c->beta;
+  }
+  // nu enters as its mean over each element's quadrature points
+  std::vector<double> nu_e;
+  if (op != SFEM_MASS && c->has_nu && c->nelem > 0) {
+    const int64_t q3 = q3_of(c);
+    std::vector<double> nu((size_t)(c->nelem * q3));
+    HIPCHK(c, hipMemcpyAsync(nu.data(), c->d_nu64, nu.size() * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    nu_e.assign((size_t)c->nelem, 0.0);
+    for (int64_t e = 0; e < c->nelem; ++e) {
+      double sum = 0.0;
+      for (int64_t k = 0; k < q3; ++k) sum += nu[(size_t)(e * q3 + k)];
+      nu_e[(size_t)e] = sum / (double)q3;
+    }
+  }
+  HostCsr A;
+  lor_assemble(c->p, c->rules.gll_x.data(), c->nelem, c->h_xyz.data(), c->h_dofs.data(), c->ndof,
+               c->h_ess.data(), a, b, nu_e.empty() ? nullptr : nu_e.data(), A);
+  const std::string e = amg_setup(A, kLorTheta, kLorCoarse, kLorMaxLevels, kLorSweeps, c->lor[op]);
+  if (!e.empty()) {
+    amg_free(c->lor[op]);
+    return fail(c, SFEM_E_NOMEM, e);
+  }
+  if (!c->lor_work) {
+    sfem_status st;
+    if ((st = dalloc(c, &c->lor_work, 5 * c->ndof)) != SFEM_OK) return st;
+    if ((st = dalloc(c, &c->lor_scal, 8)) != SFEM_OK) return st;
+  }
+  c->lor_ok[op] = true;
+  return SFEM_OK;
+}
+
+// Host-side scalar of a device dot product a . b (b == null: sum of a).
+sfem_status dev_dot(sfem_ctx *c, const double *a, const double *b, double *part, double *out_dev,
+                    double *out) {
+  const int64_t n = c->ndof;
+  const int nblk = vec_nblk(n);
+  HIPCHK(c, VecOps<double>::dot(a, b, 0, part, nblk, n, 1, c->stream));
+  HIPCHK(c, launch_reduce1(part, nblk, 1, out_dev, c->stream));
+  HIPCHK(c, hipMemcpyAsync(out, out_dev, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SFEM_OK;
+}
+
+// Host-side scalars r . r and r . z (one pass over both vectors, one synchronization).
+sfem_status dev_dot_rr_rz(sfem_ctx *c, const double *r, const double *z, double *part, double *out_dev,
+                          double *out) {
+  const int64_t n = c->ndof;
+  const int nblk = vec_nblk(n);
+  HIPCHK(c, launch_dot2(n, r, z, part, nblk, c->stream));
+  HIPCHK(c, launch_reduce1(part, nblk, 2, out_dev, c->stream));
+  HIPCHK(c, hipMemcpyAsync(out, out_dev, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SFEM_OK;
+}
+
+// z = M_LOR^-1 r by one V-cycle; orthogonalized against the constants for a null-space
+// solve (Section 5.3).
+sfem_status lor_precond(sfem_ctx *c, int op, const double *r, double *z, int nullspace, double *part) {
+  HIPCHK(c, amg_vcycle(c->lor[op], r, z, c->stream));
+  if (nullspace) {
+    const int64_t n = c->ndof;
+    const int nblk = vec_nblk(n);
+    HIPCHK(c, VecOps<double>::dot(z, nullptr, 0, part, nblk, n, 1, c->stream));
+    HIPCHK(c, launch_reduce1(part, nblk, 1, c->lor_scal, c->stream));
+    HIPCHK(c, launch_shift(z, c->lor_scal, 1.0 / (double)n, n, 1, c->stream));
+  }
+  return SFEM_OK;
+}
+
+// CG for one member preconditioned by the LOR multigrid V-cycle, scalars on the host
+// (two synchronizations per iteration: p.Ap, then r.r with r.z).  On return hs holds
+// iters, rr, bb, status, active.
+sfem_status run_pcg_lor(sfem_ctx *c, int op, const double *b, double *x, bool x0_zero, double rtol,
+                        int maxit, int nullspace, double *part, PcgScalars &hs) {
+  const int64_t n = c->ndof;
+  hipStream_t s = c->stream;
+  double *r = c->lor_work, *z = r + n, *pv = z + n, *w = pv + n;
+  double *sc = c->lor_scal + 1;
+  sfem_status st;
+  hs = PcgScalars{};
+  double bb = 0.0;
+  if ((st = dev_dot(c, b, b, part, sc, &bb)) != SFEM_OK) return st;
+  hs.bb = bb;
+  if (!std::isfinite(bb)) {
+    hs.status = SFEM_E_NAN;
+    return SFEM_OK;
+  }
+  if (bb == 0.0) {
+    HIPCHK(c, VecOps<double>::fill(x, 0.0, n, s));
+    return SFEM_OK;
+  }
+  if (x0_zero) {
+    HIPCHK(c, VecOps<double>::fill(x, 0.0, n, s));
+    HIPCHK(c, hipMemcpyAsync(r, b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    if ((st = do_apply(c, op, false, 1, x, w)) != SFEM_OK) return st;
+    HIPCHK(c, launch_axpby(n, 1.0, b, -1.0, w, r, s));  // r = b - A x
+  }
+  double rr = 0.0;
+  if ((st = dev_dot(c, r, r, part, sc, &rr)) != SFEM_OK) return st;
+  const double tol2 = rtol * rtol * bb;
+  hs.rr = rr;
+  if (rr <= tol2) return SFEM_OK;
+  if ((st = lor_precond(c, op, r, z, nullspace, part)) != SFEM_OK) return st;
+  HIPCHK(c, hipMemcpyAsync(pv, z, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  double rho = 0.0;
+  if ((st = dev_dot(c, r, z, part, sc, &rho)) != SFEM_OK) return st;
+  hs.active = 1;
+  for (int it = 0; it < maxit; ++it) {
+    if ((st = do_apply(c, op, false, 1, pv, w)) != SFEM_OK) return st;
+    double pw = 0.0;
+    if ((st = dev_dot(c, pv, w, part, sc, &pw)) != SFEM_OK) return st;
+    if (!std::isfinite(pw) || !std::isfinite(rho)) {
+      hs.status = SFEM_E_NAN;
+      hs.active = 0;
+      return SFEM_OK;
+    }
+    if (!(pw > 0.0)) {
+      hs.status = SFEM_E_BREAKDOWN;
+      hs.active = 0;
+      return SFEM_OK;
+    }
+    const double alpha = rho / pw;
+    HIPCHK(c, launch_cg_update(n, alpha, pv, w, x, r, s));  // x += alpha p, r -= alpha w
+    hs.iters = it + 1;
+    // the next preconditioned residual is computed with the convergence test (one sync)
+    if ((st = lor_precond(c, op, r, z, nullspace, part)) != SFEM_OK) return st;
+    double two[2];
+    if ((st = dev_dot_rr_rz(c, r, z, part, sc, two)) != SFEM_OK) return st;
+    rr = two[0];
+    hs.rr = rr;
+    if (rr <= tol2) {
+      hs.active = 0;
+      return SFEM_OK;
+    }
+    const double rho_new = two[1];
+    const double beta = rho_new / rho;
+    rho = rho_new;
+    HIPCHK(c, launch_axpby(n, 1.0, z, beta, pv, pv, s));   // p = z + beta p
+  }
+  return SFEM_OK;  // active stays 1: not converged within maxit
+}
+
 sfem_status require_ready(sfem_ctx *c) {
   if (!c) return SFEM_E_ARG;
   if (!c->ready) return fail(c, SFEM_E_STATE, "sfem_setup has not succeeded on this context");
@@ -708,6 +894,9 @@ sfem_status sfem_setup(sfem_ctx *c, int p, int q, int64_t nelem, const double *e
 
   // ---- rules
   if (!make_rules(p, q, c->rules)) return fail(c, SFEM_E_HIP, "1D rule construction failed");
+  c->h_xyz = xyz;
+  c->h_dofs = dofs;
+  c->h_ess = ess;
   c->p = p;
   c->q = q;
   c->nelem = nelem;
@@ -822,6 +1011,49 @@ sfem_status sfem_apply_noalloc(sfem_ctx *c, int op, int prec, int nbatch, const 
   return do_apply(c, op, prec == SFEM_F32, nbatch, x, y, nullptr, c->scratch);
 }
 
+sfem_status sfem_lor_setup(sfem_ctx *c, int op, sfem_lor_info *info) {
+  sfem_status st = require_ready(c);
+  if (st != SFEM_OK) return st;
+  if ((st = check_op_batch(c, op, 0)) != SFEM_OK) return st;
+  DeviceGuard g(c->device);
+  if ((st = ensure_lor(c, op)) != SFEM_OK) return st;
+  if (info) {
+    const Amg &a = c->lor[op];
+    *info = sfem_lor_info{};
+    info->levels = (int)a.rows.size();
+    for (int l = 0; l < info->levels && l < SFEM_LOR_MAX_LEVELS; ++l) {
+      info->rows[l] = a.rows[(size_t)l];
+      info->nnz[l] = a.nnzs[(size_t)l];
+    }
+    info->setup_ms = a.setup_ms;
+  }
+  return SFEM_OK;
+}
+
+sfem_status sfem_lor_apply(sfem_ctx *c, int op, const double *x, double *y) {
+  sfem_status st = require_ready(c);
+  if (st != SFEM_OK) return st;
+  if ((st = check_op_batch(c, op, 0)) != SFEM_OK) return st;
+  if (c->ndof == 0) return SFEM_OK;
+  if (!x || !y || x == y) return fail(c, SFEM_E_ARG, "x and y must be distinct non-NULL arrays");
+  DeviceGuard g(c->device);
+  if ((st = ensure_lor(c, op)) != SFEM_OK) return st;
+  HIPCHK(c, amg_apply_fine(c->lor[op], x, y, c->stream));
+  return SFEM_OK;
+}
+
+sfem_status sfem_lor_vcycle(sfem_ctx *c, int op, const double *b, double *x) {
+  sfem_status st = require_ready(c);
+  if (st != SFEM_OK) return st;
+  if ((st = check_op_batch(c, op, 0)) != SFEM_OK) return st;
+  if (c->ndof == 0) return SFEM_OK;
+  if (!b || !x || b == x) return fail(c, SFEM_E_ARG, "b and x must be distinct non-NULL arrays");
+  DeviceGuard g(c->device);
+  if ((st = ensure_lor(c, op)) != SFEM_OK) return st;
+  HIPCHK(c, amg_vcycle(c->lor[op], b, x, c->stream));
+  return SFEM_OK;
+}
+
 sfem_status sfem_diagonal(sfem_ctx *c, int op, int prec, void *diag) {
   sfem_status st = require_ready(c);
   if (st != SFEM_OK) return st;
@@ -912,8 +1144,12 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
     return fail(c, SFEM_E_ARG, "invalid options (rtol >= 0, maxit >= 0, check_every >= 1, mode 0/1)");
   if (opts->mode == 1 && (!(opts->inner_rtol > 0.0) || opts->max_outer < 1))
     return fail(c, SFEM_E_ARG, "mode 1 needs inner_rtol > 0 and max_outer >= 1");
-  if (opts->precond != SFEM_PRECOND_JACOBI && opts->precond != SFEM_PRECOND_COLLOCATED_MASS)
-    return fail(c, SFEM_E_ARG, "precond must be SFEM_PRECOND_JACOBI or SFEM_PRECOND_COLLOCATED_MASS");
+  if (opts->precond != SFEM_PRECOND_JACOBI && opts->precond != SFEM_PRECOND_COLLOCATED_MASS &&
+      opts->precond != SFEM_PRECOND_LOR)
+    return fail(c, SFEM_E_ARG,
+                "precond must be SFEM_PRECOND_JACOBI, SFEM_PRECOND_COLLOCATED_MASS or SFEM_PRECOND_LOR");
+  if (opts->precond == SFEM_PRECOND_LOR && opts->mode != 0)
+    return fail(c, SFEM_E_ARG, "the LOR preconditioner runs with FP64 CG (mode 0)");
   const int ns = opts->nullspace ? 1 : 0;
   if (ns && (op != SFEM_DIFFUSION || c->n_ess != 0))
     return fail(c, SFEM_E_ARG, "nullspace solves need op = SFEM_DIFFUSION and no essential DoFs");
@@ -929,6 +1165,10 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
   if ((const void *)b == (const void *)x) return fail(c, SFEM_E_ARG, "b and x must not alias");
   DeviceGuard g(c->device);
   const bool cmass = opts->precond == SFEM_PRECOND_COLLOCATED_MASS;
+  const bool lor = opts->precond == SFEM_PRECOND_LOR;
+  if (lor) {
+    if ((st = ensure_lor(c, op)) != SFEM_OK) return st;
+  }
   if ((st = cmass ? ensure_cmass(c) : ensure_diag(c, op)) != SFEM_OK) return st;
   const int64_t dms = (!cmass && nfields_of(c, op) > 1) ? n : 0;
   const double *dinv64 = cmass ? c->d_cminv : c->d_dinv[op];
@@ -959,10 +1199,19 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
       bs = bc;
     }
     PcgScalars *hs = (PcgScalars *)c->h_pinned;
-    if ((st = run_pcg<double>(c, op, nb, bs, x, opts->x0_zero != 0, opts->rtol, opts->maxit,
-                              opts->check_every, dinv64, dms, w, hs, ns)) != SFEM_OK)
-      return st;
-    std::vector<PcgScalars> fin(hs, hs + nb);
+    std::vector<PcgScalars> fin(nb);
+    if (lor) {
+      // members one after another, each preconditioned by the LOR multigrid V-cycle
+      for (int m = 0; m < nb; ++m)
+        if ((st = run_pcg_lor(c, op, bs + (int64_t)m * n, x + (int64_t)m * n, opts->x0_zero != 0,
+                              opts->rtol, opts->maxit, ns, w.part, fin[m])) != SFEM_OK)
+          return st;
+    } else {
+      if ((st = run_pcg<double>(c, op, nb, bs, x, opts->x0_zero != 0, opts->rtol, opts->maxit,
+                                opts->check_every, dinv64, dms, w, hs, ns)) != SFEM_OK)
+        return st;
+      fin.assign(hs, hs + nb);
+    }
     if (ns) {
       // mean-zero condition: x <- x - (m1^T x / 1^T m1) 1
       HIPCHK(c, VecOps<double>::dot(x, c->d_m1, 0, w.part, nblk, n, nb, s));

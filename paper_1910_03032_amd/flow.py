@@ -42,10 +42,12 @@ class ProjectionStepper:
 
     elem_xyz [nelem, 8, 3], elem_dofs [nelem, (p+1)^3], ndof, p as for Operator; ess [ndof]
     (nonzero = wall DoF); dt, nu; order 1..3; rtol of both solves; pressure_mode 0 (FP64
-    PCG) or 1 (FP32 inner solves in FP64 refinement)."""
+    PCG) or 1 (FP32 inner solves in FP64 refinement) with pressure_precond PRECOND_JACOBI;
+    pressure_precond PRECOND_LOR (the default) preconditions the pressure Poisson solve by
+    the LOR multigrid V-cycle (Section 5.2) in FP64 CG."""
 
     def __init__(self, elem_xyz, elem_dofs, ndof, p, ess, dt, nu, order=3, rtol=1e-10,
-                 pressure_mode=1, device=None, check_every=8, maxit=10000):
+                 pressure_mode=1, device=None, check_every=8, maxit=10000, pressure_precond=None):
         check_mesh_shapes(np.shape(elem_xyz), np.shape(elem_dofs), ndof, p, np.shape(ess))
         if not 1 <= int(order) <= 3:
             raise ValueError("order 1, 2 or 3")
@@ -61,8 +63,9 @@ class ProjectionStepper:
         dofs = torch.as_tensor(elem_dofs, dtype=torch.int32).to(dev).contiguous()
         essd = torch.as_tensor(np.asarray(ess)).to(dev).to(torch.uint8).contiguous()
         nelem = int(xyz.shape[0]) if xyz.ndim == 3 else 0
+        self.pressure_precond = _lib.PRECOND_LOR if pressure_precond is None else int(pressure_precond)
         opts = FlowOpts(self.dt, self.nu, self.rtol, self.order, self.pressure_mode, int(check_every),
-                        int(maxit))
+                        int(maxit), self.pressure_precond)
         h = C.c_void_p()
         with torch.cuda.device(dev):
             st = self._lib.sfem_flow_create(dev.index, C.c_void_p(torch.cuda.current_stream(dev).cuda_stream),

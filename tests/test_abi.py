@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_pure_host_calls(lib):
-    assert lib.sfem_abi_version() == 7
+    assert lib.sfem_abi_version() == 9
     assert isinstance(lib.sfem_last_error(None), bytes)
     from paper_1910_03032_amd._lib import CtxInfo
     ci = CtxInfo()
@@ -52,6 +52,9 @@ def test_pure_host_calls(lib):
     assert lib.sfem_flow_create(0, None, 2, 0, None, None, 0, None, None, None) == -1
     assert isinstance(lib.sfem_flow_last_error(None), bytes)
     lib.sfem_flow_destroy(None)  # no-op
+    assert lib.sfem_lor_setup(None, 1, None) == -1
+    assert lib.sfem_lor_apply(None, 1, None, None) == -1
+    assert lib.sfem_lor_vcycle(None, 1, None, None) == -1
 
 
 def test_structs_match_header_layout():
@@ -63,8 +66,10 @@ def test_structs_match_header_layout():
     # int, int, int64, int64, int, int, int64, int64, int64
     assert C.sizeof(CtxInfo) == 56
     from paper_1910_03032_amd._lib import FlowOpts, FlowInfo
-    assert C.sizeof(FlowOpts) == 40  # 3 doubles, 4 ints
+    assert C.sizeof(FlowOpts) == 48  # 3 doubles, 5 ints (padded)
     assert C.sizeof(FlowInfo) == 136  # int (padded to 8), 4 sfem_pcg_info
+    from paper_1910_03032_amd._lib import LorInfo
+    assert C.sizeof(LorInfo) == 8 + 2 * 12 * 8 + 8
 
 
 def test_library_is_gfx950_code_object():

@@ -113,14 +113,15 @@ def test_hydrostatic_step(ne, p):
     st.close()
 
 
-@pytest.mark.parametrize("p,mode", [(2, 1), (4, 1), (4, 0)])
-def test_three_steps_vs_oracle(p, mode):
+@pytest.mark.parametrize("p,mode,lor", [(2, 1, False), (4, 1, False), (4, 0, False), (4, 0, True)])
+def test_three_steps_vs_oracle(p, mode, lor):
     """Orders 1, 2, 3 on a perturbed 3^3 mesh from a smooth velocity vanishing on the walls,
     with a forcing; both sides solve to 1e-12 (the oracle directly), so the difference is
-    bounded by the solve tolerance times the conditioning (< 1e-8)."""
-    from paper_1910_03032_amd import ProjectionStepper
+    bounded by the solve tolerance times the conditioning (< 1e-8); the pressure solve
+    preconditioned by Jacobi (FP64 or FP32 inner solves) or by the LOR V-cycle."""
+    from paper_1910_03032_amd import PRECOND_JACOBI, PRECOND_LOR, ProjectionStepper
     m = BoxMesh(3, p)
-    say(f"[flow] three steps p={p} ndof={m.ndof} pressure solve mode {mode}")
+    say(f"[flow] three steps p={p} ndof={m.ndof} pressure solve mode {mode} lor {lor}")
     d = Discretization(m.elem_xyz, m.elem_dofs, m.ess, m.ndof, p, p + 2)
     x = node_coords(m, p)
     bump = (x * (1 - x)).prod(axis=1)  # 0 on the walls
@@ -130,7 +131,8 @@ def test_three_steps_vs_oracle(p, mode):
     dt, nu = 0.02, 0.05
     so = OracleStepper(d, dt=dt, nu=nu, order=3)
     sg = ProjectionStepper(m.elem_xyz, m.elem_dofs, m.ndof, p, m.ess, dt=dt, nu=nu, order=3,
-                           rtol=1e-12, pressure_mode=mode)
+                           rtol=1e-12, pressure_mode=mode,
+                           pressure_precond=PRECOND_LOR if lor else PRECOND_JACOBI)
     uo, ug = u.copy(), gpu(u)
     for n in range(3):
         uo, po = so.step(uo, f)

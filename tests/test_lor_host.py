@@ -1,0 +1,115 @@
+"""The library's host-side LOR assembly and multigrid setup (lor_host.cpp, compiled with
+g++ and the address and undefined-behaviour sanitizers) against the oracle: the LOR matrix
+of Section 5.2 entry by entry, and the smoothed-aggregation hierarchy level by level (the
+same aggregates give the same level sizes; operators, prolongators, spectral-radius
+estimates and the coarse pseudo-inverse to rounding)."""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import Discretization
+from oracle.amg import AMG
+from oracle.lor import element_mean_nu, lor_matrix
+from oracle.quadrature import gll
+from workloads import BoxMesh, FanMesh, nu_uniform
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1910_03032_amd", "csrc")
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer"]
+SANITIZE_ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:exitcode=23",
+                    UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+THETA, COARSE, MAXLEV = 0.02, 200, 12
+
+
+@pytest.fixture(scope="module")
+def checker(tmp_path_factory):
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path_factory.mktemp("lor") / "lor_check")
+    r = subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-Wall", *SANITIZE, "-I", CSRC,
+                        os.path.join(ROOT, "tests", "lor_check.cpp"), os.path.join(CSRC, "lor_host.cpp"),
+                        "-o", exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    return exe
+
+
+def run_checker(exe, tmp_path, m, p, alpha, beta, nu_e):
+    fin, fout = str(tmp_path / "in.bin"), str(tmp_path / "out.bin")
+    with open(fin, "wb") as f:
+        np.array([p, m.nelem, m.ndof, COARSE, MAXLEV], dtype=np.int64).tofile(f)
+        np.array([alpha, beta, THETA], dtype=np.float64).tofile(f)
+        np.array([0 if nu_e is None else 1], dtype=np.int32).tofile(f)
+        gll(p)[0].astype(np.float64).tofile(f)
+        np.ascontiguousarray(m.elem_xyz, dtype=np.float64).tofile(f)
+        np.ascontiguousarray(m.elem_dofs, dtype=np.int32).tofile(f)
+        np.ascontiguousarray(m.ess, dtype=np.uint8).tofile(f)
+        if nu_e is not None:
+            np.asarray(nu_e, dtype=np.float64).tofile(f)
+    r = subprocess.run([exe, fin, fout], capture_output=True, text=True, env=SANITIZE_ENV)
+    assert r.returncode == 0 and "runtime error" not in r.stderr and "Sanitizer" not in r.stderr, r.stderr
+    data = open(fout, "rb").read()
+    off = [0]
+
+    def take(dtype, count):
+        a = np.frombuffer(data, dtype=dtype, count=count, offset=off[0])
+        off[0] += a.nbytes
+        return a
+
+    def csr():
+        nr, nc, nnz = take(np.int64, 3)
+        ptr = take(np.int64, int(nr) + 1)
+        col = take(np.int32, int(nnz))
+        val = take(np.float64, int(nnz))
+        return sp.csr_matrix((val, col, ptr), shape=(int(nr), int(nc)))
+
+    L = int(take(np.int64, 1)[0])
+    As, rho = [], []
+    for _ in range(L):
+        As.append(csr())
+        rho.append(float(take(np.float64, 1)[0]))
+    Ps = [csr() for _ in range(L - 1)]
+    n = As[-1].shape[0]
+    coarse = take(np.float64, n * n).reshape(n, n)
+    return As, rho, Ps, coarse
+
+
+def maxrel(a, b):
+    d = abs(a - b)
+    return (d.max() if d.nnz else 0.0) / abs(b).max()
+
+
+@pytest.mark.parametrize("case", ["poisson_3e_p4", "helmholtz_nu_3e_p3", "neumann_4e_p2", "fan_p3"])
+def test_lor_matrix_and_hierarchy_match_the_oracle(checker, tmp_path, case):
+    if case == "fan_p3":
+        m = FanMesh(3)
+        p, alpha, beta, nu = 3, 1.0, 1.0, None
+    else:
+        ne, p = {"poisson_3e_p4": (3, 4), "helmholtz_nu_3e_p3": (3, 3), "neumann_4e_p2": (4, 2)}[case]
+        m = BoxMesh(ne, p)
+        alpha, beta = (0.0, 1.0) if case != "helmholtz_nu_3e_p3" else (1e3, 1.0)
+        nu = nu_uniform(m.nelem, p + 2, seed=2) if case == "helmholtz_nu_3e_p3" else None
+    ess = np.zeros(m.ndof, dtype=np.uint8) if case == "neumann_4e_p2" else m.ess
+    d = Discretization(m.elem_xyz, m.elem_dofs, ess, m.ndof, p, p + 2)
+
+    class Mesh:  # the arrays the checker reads
+        pass
+    mm = Mesh()
+    mm.nelem, mm.ndof, mm.elem_xyz, mm.elem_dofs, mm.ess = m.nelem, m.ndof, m.elem_xyz, m.elem_dofs, ess
+    nu_e = None if nu is None else element_mean_nu(d, nu)
+    As, rho, Ps, coarse = run_checker(checker, tmp_path, mm, p, alpha, beta, nu_e)
+    L_o = lor_matrix(d, alpha, beta, nu)
+    assert maxrel(As[0], L_o) <= 1e-13
+    assert np.diff(As[0].indptr).max() <= (27 if case != "fan_p3" else 64)
+    amg = AMG(L_o, theta=THETA, coarse_size=COARSE, max_levels=MAXLEV)
+    assert len(As) == amg.levels, ([a.shape for a in As], [a.shape for a in amg.A])
+    for l in range(amg.levels):
+        assert As[l].shape == amg.A[l].shape
+        assert maxrel(As[l], amg.A[l]) <= 1e-11, l
+        assert abs(rho[l] - amg.rho[l]) <= 1e-12 * amg.rho[l]
+    for l in range(amg.levels - 1):
+        assert maxrel(Ps[l], amg.P[l]) <= 1e-11, l
+    assert np.abs(coarse - amg.coarse_inv).max() <= 1e-9 * np.abs(amg.coarse_inv).max()
