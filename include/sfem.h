@@ -157,7 +157,7 @@ sfem_status sfem_apply_noalloc(sfem_ctx *ctx, int op, int prec, int nbatch, cons
  * constants, and has at most 27 nonzeros per row on a structured mesh.  Its solver is a
  * smoothed-aggregation algebraic multigrid V-cycle (strength threshold 0.02, three-pass
  * aggregation, Jacobi-smoothed prolongator, Galerkin coarse operators down to <= 200 rows,
- * dense pseudo-inverse there, two damped-Jacobi sweeps before and after each coarse
+ * dense pseudo-inverse there, one damped-Jacobi sweep before and one after each coarse
  * correction): the setup runs on the host (the mesh copy kept by sfem_setup), every step
  * of the V-cycle on the GPU.  sfem_pcg with precond = SFEM_PRECOND_LOR builds it on first
  * use; sfem_set_coeffs discards it.  One nu field only (SFEM_E_ARG otherwise).

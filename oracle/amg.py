@@ -98,7 +98,7 @@ def spectral_radius_dinv_a(A, npower=15):
 class AMG:
     """Smoothed-aggregation hierarchy of A (scipy sparse, SPD or SPSD)."""
 
-    def __init__(self, A, theta=0.25, coarse_size=200, max_levels=12, nu=2, npower=15):
+    def __init__(self, A, theta=0.02, coarse_size=200, max_levels=12, nu=1, npower=15):
         self.A, self.P, self.rho = [], [], []
         self.nu = nu
         A = sp.csr_matrix(A)

@@ -609,7 +609,7 @@ sfem_status run_pcg(sfem_ctx *c, int op, int nb, const T *b, T *x, bool x0_zero,
 constexpr double kLorTheta = 0.02;
 constexpr int64_t kLorCoarse = 200;
 constexpr int kLorMaxLevels = 12;
-constexpr int kLorSweeps = 2;
+constexpr int kLorSweeps = 1;
 
 // Build (once per operator kind and coefficients) A_LOR of op and its multigrid hierarchy.
 sfem_status ensure_lor(sfem_ctx *c, int op) {

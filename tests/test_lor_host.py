@@ -22,7 +22,7 @@ CSRC = os.path.join(ROOT, "paper_1910_03032_amd", "csrc")
 SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer"]
 SANITIZE_ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:exitcode=23",
                     UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
-THETA, COARSE, MAXLEV = 0.02, 200, 12
+THETA, COARSE, MAXLEV, NU = 0.02, 200, 12, 1
 
 
 @pytest.fixture(scope="module")
@@ -104,7 +104,7 @@ def test_lor_matrix_and_hierarchy_match_the_oracle(checker, tmp_path, case):
     L_o = lor_matrix(d, alpha, beta, nu)
     assert maxrel(As[0], L_o) <= 1e-13
     assert np.diff(As[0].indptr).max() <= (27 if case != "fan_p3" else 64)
-    amg = AMG(L_o, theta=THETA, coarse_size=COARSE, max_levels=MAXLEV)
+    amg = AMG(L_o, theta=THETA, coarse_size=COARSE, max_levels=MAXLEV, nu=NU)
     assert len(As) == amg.levels, ([a.shape for a in As], [a.shape for a in amg.A])
     for l in range(amg.levels):
         assert As[l].shape == amg.A[l].shape
