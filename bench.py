@@ -66,9 +66,19 @@ def log(*a):
 # the hash of those sources), otherwise the roofline reports traffic = null.
 KERNEL_SOURCES = ["apply_impl.h", "eo.h", "rules.h", "internal.h", "plan.h", "k_apply_f64.hip", "k_vec.hip"]
 MEASURED_TRAFFIC = {
-    # profiles/helmholtz_apply_p4_32e_hbm_bytes.md
-    ("2edf44f0d6ea3141", "helmholtz_p4_32e"): 558234274,
+    # profiles/helmholtz_apply_p4_32e_hbm_bytes.md (FP64 apply, both dispatches)
+    ("ac463f6e9cdfee9d", "helmholtz_p4_32e"): 560861390,
+    # profiles/vector_helmholtz_p7_24e_counters.md (three-member FP64 apply)
+    ("ac463f6e9cdfee9d", "vector_helmholtz_p7_24e"): 1288659178,
 }
+# Executed floating-point operations of one apply (element kernel + assembly) from the
+# SQ_INSTS_VALU_FLOPS_FP64 / _FP32 counters (x 64 lanes), same keying as the traffic:
+# profiles/helmholtz_apply_p4_32e_counters.md, profiles/vector_helmholtz_p7_24e_counters.md.
+MEASURED_FLOPS = {
+    ("ac463f6e9cdfee9d", "helmholtz_p4_32e"): {"fp64": 961714752, "fp32": 964111936},
+    ("ac463f6e9cdfee9d", "vector_helmholtz_p7_24e"): {"fp64": 6564470208, "fp32": 6260121024},
+}
+FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 vector
 
 
 def code_of(text):
@@ -105,6 +115,18 @@ def algorithmic_bytes(nelem, p, ndof, s, nb=1, nqd=7, nb_qd=1):
 def flops_helmholtz(nelem, p, nb=1):
     n, q = p + 1, p + 2
     return nelem * nb * (2 * (4 * q * n ** 3 + 6 * q * q * n * n + 8 * q ** 3 * n) + 25 * q ** 3)
+
+
+def counter_rate(workload, prec, ms):
+    """Counter-measured flops of one apply of `workload` (keyed by the kernel sources) over
+    `ms` milliseconds, in TFLOP/s; None when the sources differ from the measured ones."""
+    f = MEASURED_FLOPS.get((kernel_source_hash(), workload))
+    return None if f is None else round(f[prec] / (ms * 1e-3) / 1e12, 2)
+
+
+def counter_frac(workload, prec, ms, peak_tflops):
+    r = counter_rate(workload, prec, ms)
+    return None if r is None else round(r / peak_tflops, 4)
 
 
 def copy_calibration(mb, reps=5):
@@ -355,9 +377,14 @@ def run_main(a, wl):
             "algorithmic_bytes_per_apply": r64["algorithmic_bytes"],
             "launches_per_apply": 2,
             "apply_us": r64["us"],
-            "fp64_flop_rate_tflops": round(flops_helmholtz(m.nelem, p) / (ms64 * 1e-3) / 1e12, 2),
+            # executed FP64 flops from the counters (null once the kernel sources change)
+            # over the live apply time, against the 78.6 TFLOP/s FP64 peak
+            "fp64_flop_rate_tflops": counter_rate("helmholtz_p4_32e", "fp64", ms64),
+            "fp64_flop_frac": counter_frac("helmholtz_p4_32e", "fp64", ms64, FP64_PEAK_TFLOPS),
+            "fp64_model_flop_rate_tflops": round(flops_helmholtz(m.nelem, p) / (ms64 * 1e-3) / 1e12, 2),
         },
         "fp32_apply": dict(r32, value=r32["GDoF/s"], unit="GDoF/s",
+                           fp32_flop_rate_tflops=counter_rate("helmholtz_p4_32e", "fp32", r32["us"] * 1e-3),
                            note=f"{r32['buffer_sets']} operator/vector sets of "
                                 f"{r32['algorithmic_bytes'] / 1e6:.0f} MB applied in turn "
                                 f"({r32['buffer_sets'] * r32['algorithmic_bytes'] / 1e6:.0f} MB), so "
@@ -408,6 +435,11 @@ def vector_apply_rates(a, name):
     fl = flops_helmholtz(B.m.nelem, B.p, nb)
     r64["fp64_model_tflops"] = round(fl / (r64["us"] * 1e-6) / 1e12, 2)
     r64["fp64_model_frac"] = round(fl / (r64["us"] * 1e-6) / 1e12 / FP64_PEAK_TFLOPS, 4)
+    r64["fp64_flop_rate_tflops"] = counter_rate(name, "fp64", r64["us"] * 1e-3)
+    r64["fp64_flop_frac"] = counter_frac(name, "fp64", r64["us"] * 1e-3, FP64_PEAK_TFLOPS)
+    r64["traffic"] = MEASURED_TRAFFIC.get((kernel_source_hash(), name))
+    r32["fp32_flop_rate_tflops"] = counter_rate(name, "fp32", r32["us"] * 1e-3)
+    r32["fp32_flop_frac"] = counter_frac(name, "fp32", r32["us"] * 1e-3, FP32_PEAK_TFLOPS)
     log(f"[bench] {name}: fp64 {r64['us']} us ({r64['hbm_frac']:.3f} of HBM, "
         f"{r64['fp64_model_frac']:.3f} of FP64), fp32 {r32['us']} us")
     B.close()
