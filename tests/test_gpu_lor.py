@@ -137,3 +137,30 @@ def test_lor_neumann_poisson_p4_32e():
     assert rj.converged
     assert float((x - xj).norm() / xj.norm()) <= 1e-6
     op.close()
+
+
+def test_lor_error_paths_and_edge_cases():
+    """Several nu fields and refinement mode are rejected; p = 1 (the refined mesh is the
+    mesh), a nonzero initial guess and a zero right-hand side work."""
+    from paper_1910_03032_amd import DIFFUSION, HELMHOLTZ, PRECOND_LOR, SfemError
+    m = BoxMesh(3, 1)
+    d, op = setup(m, 1, m.ess, 1e3, 1.0)
+    b = rhs_uniform(m, seed=1)[0]
+    x, r = op.pcg(gpu(b), op=HELMHOLTZ, rtol=1e-12, precond=PRECOND_LOR)
+    assert r.converged and rel(host(x), spla.spsolve(d.assemble(1e3, 1.0).tocsc(), b)) <= 1e-9
+    x0 = gpu(uniform(m.ndof, seed=9)) * 0.1
+    x0[torch.as_tensor(m.ess.astype(bool), device="cuda")] = 0
+    x1, r1 = op.pcg(gpu(b), x=x0, op=HELMHOLTZ, rtol=1e-12, precond=PRECOND_LOR)
+    assert r1.converged and rel(host(x1), host(x)) <= 1e-9
+    z, rz = op.pcg(gpu(np.zeros(m.ndof)), op=HELMHOLTZ, precond=PRECOND_LOR)
+    assert rz.converged and float(z.abs().max()) == 0.0
+    with pytest.raises(SfemError, match="SFEM_E_ARG"):
+        op.pcg(gpu(b), op=HELMHOLTZ, precond=PRECOND_LOR, mode=1)
+    op.close()
+    m2 = BoxMesh(2, 2)
+    d2, op2 = setup(m2, 2, m2.ess, 1e3, 1.0)
+    nus = np.stack([nu_uniform(m2.nelem, 4, seed=200 + k).reshape(-1) for k in range(2)])
+    op2.set_coeffs(1e3, 1.0, gpu(nus))
+    with pytest.raises(SfemError, match="SFEM_E_ARG"):
+        op2.lor_setup(DIFFUSION)
+    op2.close()
