@@ -9,6 +9,8 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -153,6 +155,20 @@ struct DeviceGuard {
 sfem_status fail(sfem_ctx *c, sfem_status st, const std::string &msg) {
   if (c) c->err = msg;
   return st;
+}
+
+// Runs the body of an entry point whose host-side work allocates (mesh plan, LOR
+// assembly and multigrid set-up): a failed host allocation becomes SFEM_E_NOMEM instead
+// of an exception crossing the C boundary.
+template <class F>
+sfem_status guarded(sfem_ctx *c, F &&body) {
+  try {
+    return body();
+  } catch (const std::bad_alloc &) {
+    return fail(c, SFEM_E_NOMEM, "host allocation failed");
+  } catch (const std::length_error &) {
+    return fail(c, SFEM_E_NOMEM, "host allocation failed (size beyond the allocator's limit)");
+  }
 }
 
 #define HIPCHK(c, expr)                                                                   \
@@ -842,7 +858,7 @@ const char *sfem_last_error(const sfem_ctx *c) {
   return c ? c->err.c_str() : g_create_error.c_str();
 }
 
-sfem_status sfem_setup(sfem_ctx *c, int p, int q, int64_t nelem, const double *elem_xyz,
+static sfem_status sfem_setup_body(sfem_ctx *c, int p, int q, int64_t nelem, const double *elem_xyz,
                        const int32_t *elem_dofs, int64_t ndof, const uint8_t *ess_mask) {
   if (!c) return SFEM_E_ARG;
   DeviceGuard g(c->device);
@@ -956,6 +972,12 @@ sfem_status sfem_setup(sfem_ctx *c, int p, int q, int64_t nelem, const double *e
   return SFEM_OK;
 }
 
+sfem_status sfem_setup(sfem_ctx *c, int p, int q, int64_t nelem, const double *elem_xyz,
+                       const int32_t *elem_dofs, int64_t ndof, const uint8_t *ess_mask) {
+  if (!c) return SFEM_E_ARG;
+  return guarded(c, [&] { return sfem_setup_body(c, p, q, nelem, elem_xyz, elem_dofs, ndof, ess_mask); });
+}
+
 sfem_status sfem_qpoint_coords(sfem_ctx *c, double *xq) {
   sfem_status st = require_ready(c);
   if (st != SFEM_OK) return st;
@@ -966,7 +988,7 @@ sfem_status sfem_qpoint_coords(sfem_ctx *c, double *xq) {
   return SFEM_OK;
 }
 
-sfem_status sfem_set_coeffs(sfem_ctx *c, double alpha, double beta, const double *nu_q, int nbatch_nu) {
+static sfem_status sfem_set_coeffs_body(sfem_ctx *c, double alpha, double beta, const double *nu_q, int nbatch_nu) {
   sfem_status st = require_ready(c);
   if (st != SFEM_OK) return st;
   if (nbatch_nu < 1) return fail(c, SFEM_E_ARG, "nbatch_nu must be >= 1");
@@ -974,6 +996,11 @@ sfem_status sfem_set_coeffs(sfem_ctx *c, double alpha, double beta, const double
   if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(c, SFEM_E_ARG, "alpha and beta must be finite");
   DeviceGuard g(c->device);
   return fold_coeffs(c, nu_q, nbatch_nu, alpha, beta);
+}
+
+sfem_status sfem_set_coeffs(sfem_ctx *c, double alpha, double beta, const double *nu_q, int nbatch_nu) {
+  if (!c) return SFEM_E_ARG;
+  return guarded(c, [&] { return sfem_set_coeffs_body(c, alpha, beta, nu_q, nbatch_nu); });
 }
 
 sfem_status sfem_apply(sfem_ctx *c, int op, int prec, int nbatch, const void *x, void *y) {
@@ -1011,7 +1038,7 @@ sfem_status sfem_apply_noalloc(sfem_ctx *c, int op, int prec, int nbatch, const 
   return do_apply(c, op, prec == SFEM_F32, nbatch, x, y, nullptr, c->scratch);
 }
 
-sfem_status sfem_lor_setup(sfem_ctx *c, int op, sfem_lor_info *info) {
+static sfem_status sfem_lor_setup_body(sfem_ctx *c, int op, sfem_lor_info *info) {
   sfem_status st = require_ready(c);
   if (st != SFEM_OK) return st;
   if ((st = check_op_batch(c, op, 0)) != SFEM_OK) return st;
@@ -1030,7 +1057,12 @@ sfem_status sfem_lor_setup(sfem_ctx *c, int op, sfem_lor_info *info) {
   return SFEM_OK;
 }
 
-sfem_status sfem_lor_apply(sfem_ctx *c, int op, const double *x, double *y) {
+sfem_status sfem_lor_setup(sfem_ctx *c, int op, sfem_lor_info *info) {
+  if (!c) return SFEM_E_ARG;
+  return guarded(c, [&] { return sfem_lor_setup_body(c, op, info); });
+}
+
+static sfem_status sfem_lor_apply_body(sfem_ctx *c, int op, const double *x, double *y) {
   sfem_status st = require_ready(c);
   if (st != SFEM_OK) return st;
   if ((st = check_op_batch(c, op, 0)) != SFEM_OK) return st;
@@ -1042,7 +1074,12 @@ sfem_status sfem_lor_apply(sfem_ctx *c, int op, const double *x, double *y) {
   return SFEM_OK;
 }
 
-sfem_status sfem_lor_vcycle(sfem_ctx *c, int op, const double *b, double *x) {
+sfem_status sfem_lor_apply(sfem_ctx *c, int op, const double *x, double *y) {
+  if (!c) return SFEM_E_ARG;
+  return guarded(c, [&] { return sfem_lor_apply_body(c, op, x, y); });
+}
+
+static sfem_status sfem_lor_vcycle_body(sfem_ctx *c, int op, const double *b, double *x) {
   sfem_status st = require_ready(c);
   if (st != SFEM_OK) return st;
   if ((st = check_op_batch(c, op, 0)) != SFEM_OK) return st;
@@ -1052,6 +1089,11 @@ sfem_status sfem_lor_vcycle(sfem_ctx *c, int op, const double *b, double *x) {
   if ((st = ensure_lor(c, op)) != SFEM_OK) return st;
   HIPCHK(c, amg_vcycle(c->lor[op], b, x, c->stream));
   return SFEM_OK;
+}
+
+sfem_status sfem_lor_vcycle(sfem_ctx *c, int op, const double *b, double *x) {
+  if (!c) return SFEM_E_ARG;
+  return guarded(c, [&] { return sfem_lor_vcycle_body(c, op, b, x); });
 }
 
 sfem_status sfem_diagonal(sfem_ctx *c, int op, int prec, void *diag) {
@@ -1133,7 +1175,7 @@ sfem_status sfem_grad_nu(sfem_ctx *c, int nbatch, const double *u, const double 
   return SFEM_OK;
 }
 
-sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x,
+static sfem_status sfem_pcg_body(sfem_ctx *c, int op, int nbatch, const double *b, double *x,
                      const sfem_pcg_opts *opts, sfem_pcg_info *info) {
   sfem_status st = require_ready(c);
   if (st != SFEM_OK) return st;
@@ -1342,6 +1384,12 @@ sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x
   return ret;
 }
 
+sfem_status sfem_pcg(sfem_ctx *c, int op, int nbatch, const double *b, double *x,
+                     const sfem_pcg_opts *opts, sfem_pcg_info *info) {
+  if (!c) return SFEM_E_ARG;
+  return guarded(c, [&] { return sfem_pcg_body(c, op, nbatch, b, x, opts, info); });
+}
+
 // Coupling factors w |J| J^{-T} at the quadrature points (Stokes blocks, convection),
 // computed on first use.
 sfem_status ensure_cq(sfem_ctx *c) {
@@ -1354,7 +1402,7 @@ sfem_status ensure_cq(sfem_ctx *c) {
   return SFEM_OK;
 }
 
-sfem_status sfem_setup_pressure(sfem_ctx *c, const int32_t *pres_dofs, int64_t npres) {
+static sfem_status sfem_setup_pressure_body(sfem_ctx *c, const int32_t *pres_dofs, int64_t npres) {
   sfem_status st;
   if ((st = require_ready(c)) != SFEM_OK) return st;
   DeviceGuard g(c->device);
@@ -1410,6 +1458,11 @@ sfem_status sfem_setup_pressure(sfem_ctx *c, const int32_t *pres_dofs, int64_t n
   c->npres = npres;
   c->pres_ready = true;
   return SFEM_OK;
+}
+
+sfem_status sfem_setup_pressure(sfem_ctx *c, const int32_t *pres_dofs, int64_t npres) {
+  if (!c) return SFEM_E_ARG;
+  return guarded(c, [&] { return sfem_setup_pressure_body(c, pres_dofs, npres); });
 }
 
 sfem_status sfem_stokes_apply(sfem_ctx *c, const double *u, const double *pres, double *yu,
