@@ -571,7 +571,7 @@ def run_lor(a):
     against Jacobi for the pure-Neumann Poisson problem (the projection step's pressure
     solve) and the Helmholtz workload (alpha = 1e3, beta = 1, nu(x) of the metric)."""
     import torch
-    from paper_1910_03032_amd import DIFFUSION, HELMHOLTZ, PRECOND_LOR, Operator
+    from paper_1910_03032_amd import DIFFUSION, F32, HELMHOLTZ, PRECOND_LOR, PRECOND_LOR32, Operator
     from workloads import BoxMesh, nu_c2, rhs_uniform, uniform
     m = BoxMesh(32, 4)
     out = {"workload": "lor_p4_32e", "p": 4, "elements": "32^3", "ndof": m.ndof}
@@ -599,15 +599,20 @@ def run_lor(a):
             b = torch.as_tensor(uniform(m.ndof, seed=1), device="cuda")
         info = op.lor_setup(opk)
         ms_v = Bench.timed_fn(lambda: op.lor_vcycle(b, opk), 10, 2)
+        op.lor_vcycle(b, opk, prec=F32)  # makes the FP32 copies
+        ms_v32 = Bench.timed_fn(lambda: op.lor_vcycle(b, opk, prec=F32), 10, 2)
         row = {"lor_levels": info["rows"], "lor_nnz": info["nnz"],
-               "lor_setup_ms": round(info["setup_ms"], 1), "vcycle_ms": round(ms_v, 3)}
+               "lor_setup_ms": round(info["setup_ms"], 1), "vcycle_ms": round(ms_v, 3),
+               "vcycle_fp32_ms": round(ms_v32, 3)}
         ns = opk == DIFFUSION
         row["pcg_lor"] = solve(op, b, opk, precond=PRECOND_LOR, nullspace=ns)
+        row["pcg_lor_fp32_vcycle"] = solve(op, b, opk, precond=PRECOND_LOR32, nullspace=ns)
         row["pcg_jacobi"] = solve(op, b, opk, nullspace=ns)
         if ns:
             row["pcg_jacobi_fp32_ir"] = solve(op, b, opk, nullspace=ns, mode=1)
         log(f"[bench] lor {name}: levels {info['rows']}, setup {info['setup_ms']:.0f} ms, "
-            f"v-cycle {ms_v:.3f} ms, lor {row['pcg_lor']}, jacobi {row['pcg_jacobi']}")
+            f"v-cycle {ms_v:.3f} ms (FP32 {ms_v32:.3f} ms), lor {row['pcg_lor']}, "
+            f"lor fp32 v-cycle {row['pcg_lor_fp32_vcycle']}, jacobi {row['pcg_jacobi']}")
         out[name] = row
         op.close()
     return out
@@ -722,14 +727,15 @@ def run_projection(a):
     steps) on 32^3 hexes at p = 4 (3 x 2.1M velocity DoFs + 2.1M pressure DoFs), nu = 0.01,
     dt = 1e-3, no-slip walls, from a smooth velocity vanishing on the walls; solves to a
     relative residual of 1e-10.  Reports the time per step and the iterations of the
-    pressure (pure-Neumann CG preconditioned by the LOR multigrid V-cycle, or by Jacobi with
-    FP32 inner solves in FP64 refinement) and velocity (three-member Jacobi-PCG) solves."""
+    pressure (pure-Neumann CG preconditioned by the LOR multigrid V-cycle in FP64 or FP32
+    arithmetic, or by Jacobi with FP32 inner solves in FP64 refinement) and velocity (three-member Jacobi-PCG) solves."""
     from workloads import BoxMesh
-    from paper_1910_03032_amd import PRECOND_JACOBI, PRECOND_LOR
+    from paper_1910_03032_amd import PRECOND_JACOBI, PRECOND_LOR, PRECOND_LOR32
     ne, p = 32, 4
     m = BoxMesh(ne, p)
     rows = []
-    for name, pre, mode in (("lor", PRECOND_LOR, 0), ("jacobi_fp32_ir", PRECOND_JACOBI, 1)):
+    for name, pre, mode in (("lor", PRECOND_LOR, 0), ("lor_fp32_vcycle", PRECOND_LOR32, 0),
+                            ("jacobi_fp32_ir", PRECOND_JACOBI, 1)):
         rows.append(projection_row(a, m, ne, p, name, pre, mode))
     return {"workload": "projection_32e", "rows": rows}
 

@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define SFEM_ABI_VERSION 9
+#define SFEM_ABI_VERSION 10
 #define SFEM_MAX_P 8
 
 typedef struct sfem_ctx sfem_ctx;
@@ -163,7 +163,11 @@ sfem_status sfem_apply_noalloc(sfem_ctx *ctx, int op, int prec, int nbatch, cons
  * use; sfem_set_coeffs discards it.  One nu field only (SFEM_E_ARG otherwise).
  *   sfem_lor_setup   build it now; info (host, may be NULL) gets the level sizes
  *   sfem_lor_apply   y = A_LOR x  (device [ndof] float64)
- *   sfem_lor_vcycle  x = one V-cycle for A_LOR x = b from x = 0 (device [ndof] float64)
+ *   sfem_lor_vcycle  x = one V-cycle for A_LOR x = b from x = 0 (device [ndof] float64),
+ *                    computed in FP64 (prec = SFEM_F64) or with FP32 copies of the
+ *                    hierarchy's matrices and FP32 vectors (SFEM_F32: b is rounded to
+ *                    float32 on entry, the result widened to float64; the FP32 copies are
+ *                    made on first use and kept with the hierarchy)
  * Synchronous (setup); apply and vcycle are asynchronous on the context stream. */
 #define SFEM_LOR_MAX_LEVELS 12
 typedef struct {
@@ -174,7 +178,7 @@ typedef struct {
 } sfem_lor_info;
 sfem_status sfem_lor_setup(sfem_ctx *ctx, int op, sfem_lor_info *info);
 sfem_status sfem_lor_apply(sfem_ctx *ctx, int op, const double *x, double *y);
-sfem_status sfem_lor_vcycle(sfem_ctx *ctx, int op, const double *b, double *x);
+sfem_status sfem_lor_vcycle(sfem_ctx *ctx, int op, int prec, const double *b, double *x);
 
 /* Exact diagonal of the constrained assembled operator (1 on essential DoFs).
  * diag: [nfield][ndof] with nfield = 1 for MASS (and when nu is NULL), otherwise
@@ -196,8 +200,11 @@ sfem_status sfem_collocated_mass(sfem_ctx *ctx, double *diag);
 typedef enum {
   SFEM_PRECOND_JACOBI = 0,          /* exact diagonal of the (constrained) operator */
   SFEM_PRECOND_COLLOCATED_MASS = 1, /* collocated mass diagonal (for mass solves, Section 5.1) */
-  SFEM_PRECOND_LOR = 2              /* one multigrid V-cycle on the low-order-refined operator
+  SFEM_PRECOND_LOR = 2,             /* one multigrid V-cycle on the low-order-refined operator
                                        (Section 5.2, see sfem_lor_setup); FP64 CG (mode 0) */
+  SFEM_PRECOND_LOR32 = 3            /* the same V-cycle in FP32 arithmetic (sfem_lor_vcycle with
+                                       SFEM_F32) inside FP64 CG (mode 0): half the bytes per
+                                       cycle; the CG, its residuals and scalars stay FP64 */
 } sfem_precond;
 
 typedef struct {
@@ -320,8 +327,9 @@ typedef struct {
   int pressure_mode;  /* pressure Poisson: 0 FP64 Jacobi-PCG, 1 FP32 inner solves in FP64 refinement */
   int check_every;    /* iterations between host convergence checks of the solves (>= 1) */
   int maxit;          /* iteration cap of each solve (>= 1) */
-  int pressure_precond; /* pressure Poisson preconditioner: SFEM_PRECOND_JACOBI or
-                           SFEM_PRECOND_LOR (Section 5.2; FP64 CG, pressure_mode ignored) */
+  int pressure_precond; /* pressure Poisson preconditioner: SFEM_PRECOND_JACOBI,
+                           SFEM_PRECOND_LOR or SFEM_PRECOND_LOR32 (Section 5.2; FP64 CG,
+                           pressure_mode ignored) */
 } sfem_flow_opts;
 
 typedef struct {

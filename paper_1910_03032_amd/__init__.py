@@ -15,7 +15,7 @@ import torch  # loads the HIP runtime the library binds to
 
 from . import _lib
 from ._lib import (F32, F64, MASS, DIFFUSION, HELMHOLTZ, PRECOND_JACOBI, PRECOND_COLLOCATED_MASS,  # noqa: F401
-                   PRECOND_LOR, WEAK_GRADIENT, WEAK_CURL, WEAK_DIVERGENCE, SfemError, PcgOpts, PcgInfo,
+                   PRECOND_LOR, PRECOND_LOR32, WEAK_GRADIENT, WEAK_CURL, WEAK_DIVERGENCE, SfemError, PcgOpts, PcgInfo,
                    CtxInfo, LorInfo)
 
 __all__ = ["Operator", "SfemError", "MASS", "DIFFUSION", "HELMHOLTZ", "F64", "F32", "PcgResult",
@@ -312,21 +312,24 @@ class Operator:
         self._check(self._lib.sfem_lor_apply(self._h, op, _ptr(xv), _ptr(y)))
         return y
 
-    def lor_vcycle(self, b, op=HELMHOLTZ):
-        """One multigrid V-cycle for A_LOR x = b from x = 0 (float64 [ndof])."""
+    def lor_vcycle(self, b, op=HELMHOLTZ, prec=F64):
+        """One multigrid V-cycle for A_LOR x = b from x = 0 (float64 [ndof] in and out);
+        prec=F32 runs it with FP32 copies of the hierarchy and FP32 vectors."""
         self._sync_stream()
         bv = self._vec(b, torch.float64, "b")
         if bv.ndim != 1:
             raise ValueError("b must have shape [ndof]")
         x = torch.empty_like(bv)
-        self._check(self._lib.sfem_lor_vcycle(self._h, op, _ptr(bv), _ptr(x)))
+        self._check(self._lib.sfem_lor_vcycle(self._h, op, int(prec), _ptr(bv), _ptr(x)))
         return x
 
     def pcg(self, b, x=None, op=HELMHOLTZ, rtol=1e-10, maxit=10000, mode=0, inner_rtol=1e-5,
             max_outer=30, check_every=8, precond=PRECOND_JACOBI, nullspace=False):
         """Preconditioned CG (mode 0) or FP32-inner CG inside FP64 refinement (mode 1).
         precond: PRECOND_JACOBI (exact operator diagonal), PRECOND_COLLOCATED_MASS, or
-        PRECOND_LOR (a multigrid V-cycle on the low-order-refined operator; mode 0).  nullspace=True: pure-Neumann diffusion solve (no
+        PRECOND_LOR (a multigrid V-cycle on the low-order-refined operator; mode 0), or
+        PRECOND_LOR32 (that V-cycle in FP32 arithmetic inside FP64 CG; mode 0).
+        nullspace=True: pure-Neumann diffusion solve (no
         essential DoFs) with the preconditioner orthogonalized against the constants and
         the mean-zero solution returned.
 

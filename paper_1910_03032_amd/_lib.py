@@ -16,7 +16,7 @@ STATUS_NAMES = {
     -8: "SFEM_E_STATE",
 }
 F64, F32 = 0, 1
-PRECOND_JACOBI, PRECOND_COLLOCATED_MASS, PRECOND_LOR = 0, 1, 2
+PRECOND_JACOBI, PRECOND_COLLOCATED_MASS, PRECOND_LOR, PRECOND_LOR32 = 0, 1, 2, 3
 LOR_MAX_LEVELS = 12
 MASS, DIFFUSION, HELMHOLTZ = 0, 1, 2
 WEAK_GRADIENT, WEAK_CURL, WEAK_DIVERGENCE = 1, 2, 3
@@ -112,7 +112,7 @@ def load(path: str = LIB_PATH):
         "sfem_flow_step": (i32, [vp, vp, vp, vp, vp, C.POINTER(FlowInfo)]),
         "sfem_lor_setup": (i32, [vp, i32, C.POINTER(LorInfo)]),
         "sfem_lor_apply": (i32, [vp, i32, vp, vp]),
-        "sfem_lor_vcycle": (i32, [vp, i32, vp, vp]),
+        "sfem_lor_vcycle": (i32, [vp, i32, i32, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

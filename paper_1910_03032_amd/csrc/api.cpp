@@ -127,6 +127,7 @@ struct sfem_ctx {
   Amg lor[3];
   double *lor_work = nullptr;      // [5][ndof] vectors of the LOR-preconditioned CG
   double *lor_scal = nullptr;      // [8] device scalars
+  float *lor_work32 = nullptr;     // [2][ndof] FP32 residual and V-cycle output
 
   // ---- E-vector of the apply and solver workspace (grown on demand)
   DevBuf evec;
@@ -238,6 +239,7 @@ void free_all(sfem_ctx *c) {
   free_lor(c);
   c->lor_work = nullptr;
   c->lor_scal = nullptr;
+  c->lor_work32 = nullptr;
   for (auto &b : c->owned) (void)hipFree(b.p);
   c->owned.clear();
   c->bytes = 0;
@@ -628,7 +630,7 @@ constexpr int kLorMaxLevels = 12;
 constexpr int kLorSweeps = 1;
 
 // Build (once per operator kind and coefficients) A_LOR of op and its multigrid hierarchy.
-sfem_status ensure_lor(sfem_ctx *c, int op) {
+sfem_status ensure_lor_f64(sfem_ctx *c, int op) {
   if (c->lor_ok[op]) return SFEM_OK;
   if (op != SFEM_MASS && c->nfield > 1)
     return fail(c, SFEM_E_ARG, "the LOR preconditioner takes one nu field");
@@ -672,6 +674,28 @@ sfem_status ensure_lor(sfem_ctx *c, int op) {
   return SFEM_OK;
 }
 
+// The hierarchy of op with (f32) its FP32 copy and FP32 work vectors.
+sfem_status ensure_lor(sfem_ctx *c, int op, bool f32 = false) {
+  sfem_status st;
+  if ((st = ensure_lor_f64(c, op)) != SFEM_OK) return st;
+  if (!f32) return SFEM_OK;
+  const std::string e = amg_make_f32(c->lor[op], c->stream);
+  if (!e.empty()) return fail(c, SFEM_E_NOMEM, e);
+  if (!c->lor_work32 && (st = dalloc(c, &c->lor_work32, 2 * c->ndof)) != SFEM_OK) return st;
+  return SFEM_OK;
+}
+
+// z = V-cycle(r) of op's hierarchy in FP64 or (f32) in FP32 arithmetic (r and z FP64).
+hipError_t lor_vcycle(sfem_ctx *c, int op, bool f32, const double *r, double *z) {
+  if (!f32) return amg_vcycle<double>(c->lor[op], r, z, c->stream);
+  const int64_t n = c->ndof;
+  float *r32 = c->lor_work32, *z32 = r32 + n;
+  hipError_t e;
+  if ((e = launch_convert<double, float>(r, r32, n, c->stream)) != hipSuccess) return e;
+  if ((e = amg_vcycle<float>(c->lor[op], r32, z32, c->stream)) != hipSuccess) return e;
+  return launch_convert<float, double>(z32, z, n, c->stream);
+}
+
 // Host-side scalar of a device dot product a . b (b == null: sum of a).
 sfem_status dev_dot(sfem_ctx *c, const double *a, const double *b, double *part, double *out_dev,
                     double *out) {
@@ -698,8 +722,9 @@ sfem_status dev_dot_rr_rz(sfem_ctx *c, const double *r, const double *z, double 
 
 // z = M_LOR^-1 r by one V-cycle; orthogonalized against the constants for a null-space
 // solve (Section 5.3).
-sfem_status lor_precond(sfem_ctx *c, int op, const double *r, double *z, int nullspace, double *part) {
-  HIPCHK(c, amg_vcycle(c->lor[op], r, z, c->stream));
+sfem_status lor_precond(sfem_ctx *c, int op, bool f32, const double *r, double *z, int nullspace,
+                        double *part) {
+  HIPCHK(c, lor_vcycle(c, op, f32, r, z));
   if (nullspace) {
     const int64_t n = c->ndof;
     const int nblk = vec_nblk(n);
@@ -713,8 +738,8 @@ sfem_status lor_precond(sfem_ctx *c, int op, const double *r, double *z, int nul
 // CG for one member preconditioned by the LOR multigrid V-cycle, scalars on the host
 // (two synchronizations per iteration: p.Ap, then r.r with r.z).  On return hs holds
 // iters, rr, bb, status, active.
-sfem_status run_pcg_lor(sfem_ctx *c, int op, const double *b, double *x, bool x0_zero, double rtol,
-                        int maxit, int nullspace, double *part, PcgScalars &hs) {
+sfem_status run_pcg_lor(sfem_ctx *c, int op, bool f32, const double *b, double *x, bool x0_zero,
+                        double rtol, int maxit, int nullspace, double *part, PcgScalars &hs) {
   const int64_t n = c->ndof;
   hipStream_t s = c->stream;
   double *r = c->lor_work, *z = r + n, *pv = z + n, *w = pv + n;
@@ -744,7 +769,7 @@ sfem_status run_pcg_lor(sfem_ctx *c, int op, const double *b, double *x, bool x0
   const double tol2 = rtol * rtol * bb;
   hs.rr = rr;
   if (rr <= tol2) return SFEM_OK;
-  if ((st = lor_precond(c, op, r, z, nullspace, part)) != SFEM_OK) return st;
+  if ((st = lor_precond(c, op, f32, r, z, nullspace, part)) != SFEM_OK) return st;
   HIPCHK(c, hipMemcpyAsync(pv, z, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
   double rho = 0.0;
   if ((st = dev_dot(c, r, z, part, sc, &rho)) != SFEM_OK) return st;
@@ -767,7 +792,7 @@ sfem_status run_pcg_lor(sfem_ctx *c, int op, const double *b, double *x, bool x0
     HIPCHK(c, launch_cg_update(n, alpha, pv, w, x, r, s));  // x += alpha p, r -= alpha w
     hs.iters = it + 1;
     // the next preconditioned residual is computed with the convergence test (one sync)
-    if ((st = lor_precond(c, op, r, z, nullspace, part)) != SFEM_OK) return st;
+    if ((st = lor_precond(c, op, f32, r, z, nullspace, part)) != SFEM_OK) return st;
     double two[2];
     if ((st = dev_dot_rr_rz(c, r, z, part, sc, two)) != SFEM_OK) return st;
     rr = two[0];
@@ -1079,21 +1104,23 @@ sfem_status sfem_lor_apply(sfem_ctx *c, int op, const double *x, double *y) {
   return guarded(c, [&] { return sfem_lor_apply_body(c, op, x, y); });
 }
 
-static sfem_status sfem_lor_vcycle_body(sfem_ctx *c, int op, const double *b, double *x) {
+static sfem_status sfem_lor_vcycle_body(sfem_ctx *c, int op, int prec, const double *b, double *x) {
   sfem_status st = require_ready(c);
   if (st != SFEM_OK) return st;
   if ((st = check_op_batch(c, op, 0)) != SFEM_OK) return st;
+  if (prec != SFEM_F64 && prec != SFEM_F32) return fail(c, SFEM_E_ARG, "prec must be SFEM_F64 or SFEM_F32");
   if (c->ndof == 0) return SFEM_OK;
   if (!b || !x || b == x) return fail(c, SFEM_E_ARG, "b and x must be distinct non-NULL arrays");
   DeviceGuard g(c->device);
-  if ((st = ensure_lor(c, op)) != SFEM_OK) return st;
-  HIPCHK(c, amg_vcycle(c->lor[op], b, x, c->stream));
+  const bool f32 = prec == SFEM_F32;
+  if ((st = ensure_lor(c, op, f32)) != SFEM_OK) return st;
+  HIPCHK(c, lor_vcycle(c, op, f32, b, x));
   return SFEM_OK;
 }
 
-sfem_status sfem_lor_vcycle(sfem_ctx *c, int op, const double *b, double *x) {
+sfem_status sfem_lor_vcycle(sfem_ctx *c, int op, int prec, const double *b, double *x) {
   if (!c) return SFEM_E_ARG;
-  return guarded(c, [&] { return sfem_lor_vcycle_body(c, op, b, x); });
+  return guarded(c, [&] { return sfem_lor_vcycle_body(c, op, prec, b, x); });
 }
 
 sfem_status sfem_diagonal(sfem_ctx *c, int op, int prec, void *diag) {
@@ -1187,10 +1214,13 @@ static sfem_status sfem_pcg_body(sfem_ctx *c, int op, int nbatch, const double *
   if (opts->mode == 1 && (!(opts->inner_rtol > 0.0) || opts->max_outer < 1))
     return fail(c, SFEM_E_ARG, "mode 1 needs inner_rtol > 0 and max_outer >= 1");
   if (opts->precond != SFEM_PRECOND_JACOBI && opts->precond != SFEM_PRECOND_COLLOCATED_MASS &&
-      opts->precond != SFEM_PRECOND_LOR)
+      opts->precond != SFEM_PRECOND_LOR && opts->precond != SFEM_PRECOND_LOR32)
     return fail(c, SFEM_E_ARG,
-                "precond must be SFEM_PRECOND_JACOBI, SFEM_PRECOND_COLLOCATED_MASS or SFEM_PRECOND_LOR");
-  if (opts->precond == SFEM_PRECOND_LOR && opts->mode != 0)
+                "precond must be SFEM_PRECOND_JACOBI, SFEM_PRECOND_COLLOCATED_MASS, SFEM_PRECOND_LOR or "
+                "SFEM_PRECOND_LOR32");
+  const bool lor = opts->precond == SFEM_PRECOND_LOR || opts->precond == SFEM_PRECOND_LOR32;
+  const bool lor32 = opts->precond == SFEM_PRECOND_LOR32;
+  if (lor && opts->mode != 0)
     return fail(c, SFEM_E_ARG, "the LOR preconditioner runs with FP64 CG (mode 0)");
   const int ns = opts->nullspace ? 1 : 0;
   if (ns && (op != SFEM_DIFFUSION || c->n_ess != 0))
@@ -1207,9 +1237,8 @@ static sfem_status sfem_pcg_body(sfem_ctx *c, int op, int nbatch, const double *
   if ((const void *)b == (const void *)x) return fail(c, SFEM_E_ARG, "b and x must not alias");
   DeviceGuard g(c->device);
   const bool cmass = opts->precond == SFEM_PRECOND_COLLOCATED_MASS;
-  const bool lor = opts->precond == SFEM_PRECOND_LOR;
   if (lor) {
-    if ((st = ensure_lor(c, op)) != SFEM_OK) return st;
+    if ((st = ensure_lor(c, op, lor32)) != SFEM_OK) return st;
   }
   if ((st = cmass ? ensure_cmass(c) : ensure_diag(c, op)) != SFEM_OK) return st;
   const int64_t dms = (!cmass && nfields_of(c, op) > 1) ? n : 0;
@@ -1245,8 +1274,8 @@ static sfem_status sfem_pcg_body(sfem_ctx *c, int op, int nbatch, const double *
     if (lor) {
       // members one after another, each preconditioned by the LOR multigrid V-cycle
       for (int m = 0; m < nb; ++m)
-        if ((st = run_pcg_lor(c, op, bs + (int64_t)m * n, x + (int64_t)m * n, opts->x0_zero != 0,
-                              opts->rtol, opts->maxit, ns, w.part, fin[m])) != SFEM_OK)
+        if ((st = run_pcg_lor(c, op, lor32, bs + (int64_t)m * n, x + (int64_t)m * n,
+                              opts->x0_zero != 0, opts->rtol, opts->maxit, ns, w.part, fin[m])) != SFEM_OK)
           return st;
     } else {
       if ((st = run_pcg<double>(c, op, nb, bs, x, opts->x0_zero != 0, opts->rtol, opts->maxit,

@@ -160,7 +160,8 @@ sfem_status sfem_flow_create(int device, void *stream, int p, int64_t nelem, con
   if (opts->order < 1 || opts->order > 3) return bad(SFEM_E_ARG, "order must be 1, 2 or 3");
   if (!(opts->rtol > 0.0) || (opts->pressure_mode != 0 && opts->pressure_mode != 1) ||
       opts->check_every < 1 || opts->maxit < 1 ||
-      (opts->pressure_precond != SFEM_PRECOND_JACOBI && opts->pressure_precond != SFEM_PRECOND_LOR))
+      (opts->pressure_precond != SFEM_PRECOND_JACOBI && opts->pressure_precond != SFEM_PRECOND_LOR &&
+       opts->pressure_precond != SFEM_PRECOND_LOR32))
     return bad(SFEM_E_ARG, "rtol > 0, pressure_mode 0 or 1, check_every >= 1, maxit >= 1 and a "
                            "Jacobi or LOR pressure preconditioner are required");
   if (!ess_mask) return bad(SFEM_E_ARG, "ess_mask (the no-slip walls) must not be NULL");
@@ -313,7 +314,7 @@ sfem_status sfem_flow_step(sfem_flow *f, const double *u, const double *frc, dou
   po.max_outer = 30;
   po.check_every = f->o.check_every;
   po.precond = f->o.pressure_precond;
-  if (po.precond == SFEM_PRECOND_LOR) po.mode = 0;  // the LOR V-cycle runs with FP64 CG
+  if (po.precond != SFEM_PRECOND_JACOBI) po.mode = 0;  // the LOR V-cycle runs with FP64 CG
   po.nullspace = 1;
   po.x0_zero = f->nstep == 0 ? 1 : 0;  // later steps start from the previous pressure
   if (!po.x0_zero)

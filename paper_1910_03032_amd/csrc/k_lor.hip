@@ -1,8 +1,12 @@
-// Kernels of the LOR multigrid V-cycle: CSR products with a group of LPR lanes per row (the
-// lanes read consecutive entries of the row, so a wave's loads of values and column
-// indices are contiguous; a fixed shuffle tree sums the group, so results are
-// reproducible), with the residual and the damped-Jacobi update fused into the product,
-// and the dense coarsest-level product.  LPR is picked from the average row length.
+// Kernels of the LOR multigrid V-cycle: products with the level operators and the
+// prolongators in sliced ELL form (a thread per row), with the residual and the
+// damped-Jacobi update fused in; products with the restrictions (long rows) in CSR form
+// with a group of LPR lanes per row (the lanes read consecutive entries of the row, so a
+// wave's loads of values and column indices are contiguous; a fixed shuffle tree sums the
+// group, so results are reproducible; LPR is picked from the average row length); the
+// dense coarsest-level product.  The V-cycle kernels exist in FP64 and in FP32 (values
+// and vectors of one type T; the FP32 V-cycle reads half the bytes and serves as a
+// preconditioner inside FP64 CG).
 #include <hip/hip_runtime.h>
 
 #include "lor.h"
@@ -18,15 +22,15 @@ enum CsrMode { kSpmv = 0, kSpmvAdd = 1, kResidual = 2, kJacobi = 3 };
 // y_i = (A x)_i combined per MODE:
 //   kSpmv      out = A x            kSpmvAdd  out += A x
 //   kResidual  out = b - A x        kJacobi   out = x + omega dinv (b - A x)
-template <int LPR, int MODE>
+template <int LPR, int MODE, typename T>
 __global__ void __launch_bounds__(kRowBlock)
 csr_kernel(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
-           const double *__restrict__ val, const double *__restrict__ x, const double *__restrict__ b,
-           const double *__restrict__ dinv, double omega, double *__restrict__ out, int64_t n) {
+           const T *__restrict__ val, const T *__restrict__ x, const T *__restrict__ b,
+           const T *__restrict__ dinv, T omega, T *__restrict__ out, int64_t n) {
   const int lane = threadIdx.x % LPR;
   const int64_t groups = (int64_t)gridDim.x * (kRowBlock / LPR);
   for (int64_t i = ((int64_t)blockIdx.x * kRowBlock + threadIdx.x) / LPR; i < n; i += groups) {
-    double s = 0.0;
+    T s = T(0);
     const int32_t k1 = ptr[i + 1];
     for (int32_t k = ptr[i] + lane; k < k1; k += LPR) s += val[k] * x[col[k]];
 #pragma unroll
@@ -40,10 +44,36 @@ csr_kernel(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
   }
 }
 
-// out = omega dinv b (a Jacobi sweep from x = 0)
+// The same products with the operator in sliced ELL form (DevSell): one thread per row,
+// the slice's entries read entry-major, so a wave's loads of values and column indices
+// are contiguous; the row's terms are summed in entry order.
+template <int MODE, typename T>
 __global__ void __launch_bounds__(kRowBlock)
-scaled_copy_kernel(const double *__restrict__ dinv, double omega, const double *__restrict__ b,
-                   double *__restrict__ out, int64_t n) {
+sell_kernel(const int32_t *__restrict__ off, const int32_t *__restrict__ col, const T *__restrict__ val,
+            const T *__restrict__ x, const T *__restrict__ b, const T *__restrict__ dinv, T omega,
+            T *__restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+  if (i >= n) return;
+  const int64_t sl = i / kSellRows;
+  const int lane = (int)(i - sl * kSellRows);
+  const int32_t k0 = off[sl];
+  const int len = (off[sl + 1] - k0) / kSellRows;
+  const int32_t *c = col + k0 + lane;
+  const T *v = val + k0 + lane;
+  T s = T(0);
+#pragma unroll 4
+  for (int k = 0; k < len; ++k) s += v[(int64_t)k * kSellRows] * x[c[(int64_t)k * kSellRows]];
+  if constexpr (MODE == kSpmv) out[i] = s;
+  else if constexpr (MODE == kSpmvAdd) out[i] += s;
+  else if constexpr (MODE == kResidual) out[i] = b[i] - s;
+  else out[i] = x[i] + omega * dinv[i] * (b[i] - s);
+}
+
+// out = omega dinv b (a Jacobi sweep from x = 0)
+template <typename T>
+__global__ void __launch_bounds__(kRowBlock)
+scaled_copy_kernel(const T *__restrict__ dinv, T omega, const T *__restrict__ b, T *__restrict__ out,
+                   int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * kRowBlock + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kRowBlock)
     out[i] = omega * dinv[i] * b[i];
@@ -95,18 +125,26 @@ dot2_kernel(int64_t n, const double *__restrict__ r, const double *__restrict__ 
 }
 
 // y = C x, one wave per row of the dense [n][n] C
+template <typename T>
 __global__ void __launch_bounds__(kRowBlock)
-dense_matvec_kernel(const double *__restrict__ C, int64_t n, const double *__restrict__ x,
-                    double *__restrict__ y) {
+dense_matvec_kernel(const T *__restrict__ C, int64_t n, const T *__restrict__ x, T *__restrict__ y) {
   const int lane = threadIdx.x % 64;
   const int64_t waves = (int64_t)gridDim.x * (kRowBlock / 64);
   for (int64_t i = ((int64_t)blockIdx.x * kRowBlock + threadIdx.x) / 64; i < n; i += waves) {
-    double s = 0.0;
+    T s = T(0);
     for (int64_t j = lane; j < n; j += 64) s += C[i * n + j] * x[j];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
     if (lane == 0) y[i] = s;
   }
+}
+
+// out = (TO) in, elementwise
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(kRowBlock)
+convert_kernel(const TI *__restrict__ in, TO *__restrict__ out, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kRowBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRowBlock)
+    out[i] = (TO)in[i];
 }
 
 unsigned grid_for_rows(int64_t n, int lpr) {
@@ -116,14 +154,16 @@ unsigned grid_for_rows(int64_t n, int lpr) {
   return (unsigned)b;
 }
 
-template <int MODE>
-hipError_t launch_csr(const DevCsr &A, const double *x, const double *b, const double *dinv,
-                      double omega, double *out, hipStream_t s) {
+template <int MODE, typename T>
+hipError_t launch_csr(const DevCsr &A, const T *x, const T *b, const T *dinv, T omega, T *out,
+                      hipStream_t s) {
   if (A.nrows <= 0) return hipSuccess;
+  const T *val = csr_vals<T>(A);
+  if (!val) return hipErrorInvalidValue;
   const double avg = A.nrows > 0 ? (double)A.nnz / (double)A.nrows : 0.0;
 #define SFEM_CSR(L)                                                                          \
-  hipLaunchKernelGGL((csr_kernel<L, MODE>), dim3(grid_for_rows(A.nrows, L)), dim3(kRowBlock), 0, s, \
-                     A.ptr, A.col, A.val, x, b, dinv, omega, out, A.nrows)
+  hipLaunchKernelGGL((csr_kernel<L, MODE, T>), dim3(grid_for_rows(A.nrows, L)), dim3(kRowBlock), 0, s, \
+                     A.ptr, A.col, val, x, b, dinv, omega, out, A.nrows)
   if (avg <= 6.0) SFEM_CSR(4);
   else if (avg <= 16.0) SFEM_CSR(8);
   else if (avg <= 40.0) SFEM_CSR(16);
@@ -133,28 +173,79 @@ hipError_t launch_csr(const DevCsr &A, const double *x, const double *b, const d
   return hipGetLastError();
 }
 
+template <int MODE, typename T>
+hipError_t launch_sell(const DevSell &A, const T *x, const T *b, const T *dinv, T omega, T *out,
+                       hipStream_t s) {
+  if (A.nrows <= 0) return hipSuccess;
+  const T *val = sell_vals<T>(A);
+  if (!val) return hipErrorInvalidValue;
+  const int64_t nblk = (A.nrows + kRowBlock - 1) / kRowBlock;
+  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((sell_kernel<MODE, T>), dim3((unsigned)nblk), dim3(kRowBlock), 0, s, A.off, A.col, val,
+                     x, b, dinv, omega, out, A.nrows);
+  return hipGetLastError();
+}
+
+template <int MODE, typename T>
+hipError_t launch_mat(const DevMat &A, const T *x, const T *b, const T *dinv, T omega, T *out,
+                      hipStream_t s) {
+  return A.sell ? launch_sell<MODE, T>(A.S, x, b, dinv, omega, out, s)
+                : launch_csr<MODE, T>(A.C, x, b, dinv, omega, out, s);
+}
+
 }  // namespace
 
-hipError_t launch_csr_jacobi(const DevCsr &A, const double *dinv, double omega, const double *b,
-                             const double *x_in, double *x_out, hipStream_t s) {
-  if (A.nrows <= 0) return hipSuccess;
+template <typename T>
+hipError_t launch_mat_jacobi(const DevMat &A, const T *dinv, T omega, const T *b, const T *x_in,
+                             T *x_out, hipStream_t s) {
+  const int64_t n = A.nrows();
+  if (n <= 0) return hipSuccess;
   if (!x_in) {
-    hipLaunchKernelGGL(scaled_copy_kernel, dim3(grid_for_rows(A.nrows, 1)), dim3(kRowBlock), 0, s, dinv,
-                       omega, b, x_out, A.nrows);
+    hipLaunchKernelGGL((scaled_copy_kernel<T>), dim3(grid_for_rows(n, 1)), dim3(kRowBlock), 0, s, dinv,
+                       omega, b, x_out, n);
     return hipGetLastError();
   }
-  return launch_csr<kJacobi>(A, x_in, b, dinv, omega, x_out, s);
+  return launch_mat<kJacobi, T>(A, x_in, b, dinv, omega, x_out, s);
 }
 
-hipError_t launch_csr_residual(const DevCsr &A, const double *b, const double *x, double *r,
-                               hipStream_t s) {
-  return launch_csr<kResidual>(A, x, b, nullptr, 0.0, r, s);
+template <typename T>
+hipError_t launch_mat_residual(const DevMat &A, const T *b, const T *x, T *r, hipStream_t s) {
+  return launch_mat<kResidual, T>(A, x, b, nullptr, T(0), r, s);
 }
 
-hipError_t launch_csr_spmv(const DevCsr &M, const double *x, double *y, bool accumulate, hipStream_t s) {
-  return accumulate ? launch_csr<kSpmvAdd>(M, x, nullptr, nullptr, 0.0, y, s)
-                    : launch_csr<kSpmv>(M, x, nullptr, nullptr, 0.0, y, s);
+template <typename T>
+hipError_t launch_mat_spmv(const DevMat &M, const T *x, T *y, bool accumulate, hipStream_t s) {
+  return accumulate ? launch_mat<kSpmvAdd, T>(M, x, nullptr, nullptr, T(0), y, s)
+                    : launch_mat<kSpmv, T>(M, x, nullptr, nullptr, T(0), y, s);
 }
+
+template <typename T>
+hipError_t launch_dense_matvec(const T *C, int64_t n, const T *x, T *y, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((dense_matvec_kernel<T>), dim3(grid_for_rows(n, 64)), dim3(kRowBlock), 0, s, C, n, x,
+                     y);
+  return hipGetLastError();
+}
+
+template <typename TI, typename TO>
+hipError_t launch_convert(const TI *in, TO *out, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((convert_kernel<TI, TO>), dim3(grid_for_rows(n, 1)), dim3(kRowBlock), 0, s, in, out,
+                     n);
+  return hipGetLastError();
+}
+
+#define SFEM_LOR_INST(T)                                                                              \
+  template hipError_t launch_mat_jacobi<T>(const DevMat &, const T *, T, const T *, const T *, T *,  \
+                                           hipStream_t);                                            \
+  template hipError_t launch_mat_residual<T>(const DevMat &, const T *, const T *, T *, hipStream_t); \
+  template hipError_t launch_mat_spmv<T>(const DevMat &, const T *, T *, bool, hipStream_t);          \
+  template hipError_t launch_dense_matvec<T>(const T *, int64_t, const T *, T *, hipStream_t);
+SFEM_LOR_INST(double)
+SFEM_LOR_INST(float)
+#undef SFEM_LOR_INST
+template hipError_t launch_convert<double, float>(const double *, float *, int64_t, hipStream_t);
+template hipError_t launch_convert<float, double>(const float *, double *, int64_t, hipStream_t);
 
 hipError_t launch_axpby(int64_t n, double a, const double *x, double b, const double *y, double *out,
                         hipStream_t s) {
@@ -175,10 +266,5 @@ hipError_t launch_dot2(int64_t n, const double *r, const double *z, double *part
   return hipGetLastError();
 }
 
-hipError_t launch_dense_matvec(const double *C, int64_t n, const double *x, double *y, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(dense_matvec_kernel, dim3(grid_for_rows(n, 64)), dim3(kRowBlock), 0, s, C, n, x, y);
-  return hipGetLastError();
-}
 
 }  // namespace sfem

@@ -37,6 +37,44 @@ std::string upload(Amg &amg, T **dst, const T *src, int64_t count) {
   return "";
 }
 
+// Sliced ELL copy of H (see DevSell).
+std::string upload_sell(Amg &amg, const HostCsr &H, DevSell &D) {
+  D.nrows = H.nrows;
+  D.ncols = H.ncols;
+  D.nnz = H.nnz();
+  const int64_t nsl = (H.nrows + kSellRows - 1) / kSellRows;
+  std::vector<int64_t> off((size_t)nsl + 1, 0);
+  for (int64_t s = 0; s < nsl; ++s) {
+    int64_t len = 0;
+    for (int64_t r = s * kSellRows; r < std::min(H.nrows, (s + 1) * kSellRows); ++r)
+      len = std::max(len, H.ptr[r + 1] - H.ptr[r]);
+    off[s + 1] = off[s] + len * kSellRows;
+  }
+  D.padded = off[nsl];
+  if (D.padded >= (int64_t)INT32_MAX) return "LOR multigrid: matrix too large (padded nnz >= 2^31)";
+  std::vector<int32_t> off32(off.begin(), off.end());
+  std::vector<int32_t> col((size_t)D.padded);
+  std::vector<double> val((size_t)D.padded, 0.0);
+  for (int64_t s = 0; s < nsl; ++s) {
+    const int64_t len = (off[s + 1] - off[s]) / kSellRows;
+    for (int64_t r = s * kSellRows; r < (s + 1) * kSellRows; ++r) {
+      const int64_t lane = r - s * kSellRows;
+      const int64_t b = r < H.nrows ? H.ptr[r] : 0, e = r < H.nrows ? H.ptr[r + 1] : 0;
+      const int32_t last = e > b ? H.col[(size_t)(e - 1)] : 0;  // a valid column near the row's
+      for (int64_t k = 0; k < len; ++k) {
+        const size_t at = (size_t)(off[s] + k * kSellRows + lane);
+        const bool in = b + k < e;
+        col[at] = in ? H.col[(size_t)(b + k)] : last;
+        val[at] = in ? H.val[(size_t)(b + k)] : 0.0;
+      }
+    }
+  }
+  std::string e;
+  if (!(e = upload(amg, &D.off, off32.data(), (int64_t)off32.size())).empty()) return e;
+  if (!(e = upload(amg, &D.col, col.data(), D.padded)).empty()) return e;
+  return upload(amg, &D.val, val.data(), D.padded);
+}
+
 std::string upload_csr(Amg &amg, const HostCsr &H, DevCsr &D) {
   D.nrows = H.nrows;
   D.ncols = H.ncols;
@@ -47,6 +85,22 @@ std::string upload_csr(Amg &amg, const HostCsr &H, DevCsr &D) {
   if (!(e = upload(amg, &D.ptr, p32.data(), (int64_t)p32.size())).empty()) return e;
   if (!(e = upload(amg, &D.col, H.col.data(), D.nnz)).empty()) return e;
   return upload(amg, &D.val, H.val.data(), D.nnz);
+}
+
+// The form of H on the device: sliced ELL for at least 16384 rows of at most 48 entries
+// on average, padded by at most half (the level operators and prolongators of the fine
+// levels), CSR otherwise (the restrictions' long rows, the small coarse levels).
+std::string upload_mat(Amg &amg, const HostCsr &H, DevMat &D) {
+  int64_t padded = 0;
+  const int64_t nsl = (H.nrows + kSellRows - 1) / kSellRows;
+  for (int64_t s = 0; s < nsl; ++s) {
+    int64_t len = 0;
+    for (int64_t r = s * kSellRows; r < std::min(H.nrows, (s + 1) * kSellRows); ++r)
+      len = std::max(len, H.ptr[r + 1] - H.ptr[r]);
+    padded += len * kSellRows;
+  }
+  D.sell = H.nrows >= 16384 && H.nnz() <= 48 * H.nrows && 2 * padded <= 3 * H.nnz();
+  return D.sell ? upload_sell(amg, H, D.S) : upload_csr(amg, H, D.C);
 }
 
 }  // namespace
@@ -71,23 +125,23 @@ std::string amg_setup(const HostCsr &A0, double theta, int64_t coarse_size, int 
     out.nnzs.push_back(As[l].nnz());
     v.omega = 4.0 / (3.0 * rhos[l]);
     if (l + 1 < L) {
-      if (!(e = upload_csr(out, As[l], v.A)).empty()) return e;
+      if (!(e = upload_mat(out, As[l], v.A)).empty()) return e;
       std::vector<double> dinv((size_t)As[l].nrows);
       for (int64_t i = 0; i < As[l].nrows; ++i) dinv[i] = 1.0 / As[l].val[diag_pos(As[l], i)];
-      if (!(e = upload(out, &v.dinv, dinv.data(), (int64_t)dinv.size())).empty()) return e;
+      if (!(e = upload(out, &v.d.dinv, dinv.data(), (int64_t)dinv.size())).empty()) return e;
       HostCsr R;
       csr_transpose(Ps[l], R);
-      if (!(e = upload_csr(out, Ps[l], v.P)).empty()) return e;
-      if (!(e = upload_csr(out, R, v.R)).empty()) return e;
+      if (!(e = upload_mat(out, Ps[l], v.P)).empty()) return e;
+      if (!(e = upload_mat(out, R, v.R)).empty()) return e;
     } else if (l == 0) {
-      if (!(e = upload_csr(out, As[l], v.A)).empty()) return e;
+      if (!(e = upload_mat(out, As[l], v.A)).empty()) return e;
     }
     const int64_t n = As[l].nrows;
     if (l > 0) {
-      if (!(e = upload<double>(out, &v.b, nullptr, n)).empty()) return e;
-      if (!(e = upload<double>(out, &v.x, nullptr, n)).empty()) return e;
+      if (!(e = upload<double>(out, &v.d.b, nullptr, n)).empty()) return e;
+      if (!(e = upload<double>(out, &v.d.x, nullptr, n)).empty()) return e;
     }
-    if (!(e = upload<double>(out, &v.t, nullptr, n)).empty()) return e;
+    if (!(e = upload<double>(out, &v.d.t, nullptr, n)).empty()) return e;
   }
   out.ncoarse = As.back().nrows;
   if (!(e = upload(out, &out.coarse, H.coarse.data(), (int64_t)H.coarse.size())).empty()) return e;
@@ -102,47 +156,103 @@ void amg_free(Amg &amg) {
   amg.rows.clear();
   amg.nnzs.clear();
   amg.coarse = nullptr;
+  amg.coarse32 = nullptr;
+  amg.has32 = false;
   amg.ncoarse = 0;
 }
 
 namespace {
 
-hipError_t vcycle_level(const Amg &amg, size_t l, const double *b, double *x, hipStream_t s) {
+// FP32 copy of count device values src (allocated into amg.bufs).
+std::string to_f32(Amg &amg, float **dst, const double *src, int64_t count, hipStream_t s) {
+  *dst = nullptr;
+  if (count <= 0 || !src) return "";
+  std::string e = upload<float>(amg, dst, nullptr, count);
+  if (!e.empty()) return e;
+  if (launch_convert<double, float>(src, *dst, count, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return "LOR multigrid: FP32 conversion launch failed";
+  }
+  return "";
+}
+
+}  // namespace
+
+std::string amg_make_f32(Amg &amg, hipStream_t s) {
+  if (amg.has32) return "";
+  if (amg.lv.empty()) return "LOR multigrid: no hierarchy";
+  std::string e;
+  const size_t L = amg.lv.size();
+  for (size_t l = 0; l < L; ++l) {
+    AmgLevel &v = amg.lv[l];
+    const int64_t n = amg.rows[l];
+    if (l + 1 < L) {
+      for (DevMat *M : {&v.A, &v.P, &v.R})
+        e = M->sell ? to_f32(amg, &M->S.val32, M->S.val, M->S.padded, s)
+                    : to_f32(amg, &M->C.val32, M->C.val, M->C.nnz, s);
+      if (!e.empty()) return e;
+      if (!(e = to_f32(amg, &v.f.dinv, v.d.dinv, n, s)).empty()) return e;
+    }
+    if (l > 0) {
+      if (!(e = upload<float>(amg, &v.f.b, nullptr, n)).empty()) return e;
+      if (!(e = upload<float>(amg, &v.f.x, nullptr, n)).empty()) return e;
+    }
+    if (!(e = upload<float>(amg, &v.f.t, nullptr, n)).empty()) return e;
+  }
+  if (!(e = to_f32(amg, &amg.coarse32, amg.coarse, amg.ncoarse * amg.ncoarse, s)).empty()) return e;
+  amg.has32 = true;
+  return "";
+}
+
+namespace {
+
+template <typename T>
+hipError_t vcycle_level(const Amg &amg, size_t l, const T *b, T *x, hipStream_t s) {
   const AmgLevel &v = amg.lv[l];
-  if (l + 1 == amg.lv.size()) return launch_dense_matvec(amg.coarse, amg.ncoarse, b, x, s);
+  if (l + 1 == amg.lv.size()) {
+    const T *C;
+    if constexpr (sizeof(T) == 8) C = amg.coarse;
+    else C = amg.coarse32;
+    return launch_dense_matvec<T>(C, amg.ncoarse, b, x, s);
+  }
+  const LevelVecs<T> &w = v.vecs<T>();
+  const T omega = (T)v.omega;
   hipError_t e;
   // pre-smoothing from x = 0: the first sweep is omega D^-1 b
-  if ((e = launch_csr_jacobi(v.A, v.dinv, v.omega, b, nullptr, x, s)) != hipSuccess) return e;
-  double *cur = x, *oth = v.t;
+  if ((e = launch_mat_jacobi<T>(v.A, w.dinv, omega, b, nullptr, x, s)) != hipSuccess) return e;
+  T *cur = x, *oth = w.t;
   for (int it = 1; it < amg.nu; ++it) {
-    if ((e = launch_csr_jacobi(v.A, v.dinv, v.omega, b, cur, oth, s)) != hipSuccess) return e;
+    if ((e = launch_mat_jacobi<T>(v.A, w.dinv, omega, b, cur, oth, s)) != hipSuccess) return e;
     std::swap(cur, oth);
   }
   // residual, restriction, coarse correction, prolongation
-  if ((e = launch_csr_residual(v.A, b, cur, oth, s)) != hipSuccess) return e;
-  const AmgLevel &c = amg.lv[l + 1];
-  if ((e = launch_csr_spmv(v.R, oth, c.b, false, s)) != hipSuccess) return e;
-  if ((e = vcycle_level(amg, l + 1, c.b, c.x, s)) != hipSuccess) return e;
-  if ((e = launch_csr_spmv(v.P, c.x, cur, true, s)) != hipSuccess) return e;
+  if ((e = launch_mat_residual<T>(v.A, b, cur, oth, s)) != hipSuccess) return e;
+  const LevelVecs<T> &c = amg.lv[l + 1].vecs<T>();
+  if ((e = launch_mat_spmv<T>(v.R, oth, c.b, false, s)) != hipSuccess) return e;
+  if ((e = vcycle_level<T>(amg, l + 1, c.b, c.x, s)) != hipSuccess) return e;
+  if ((e = launch_mat_spmv<T>(v.P, c.x, cur, true, s)) != hipSuccess) return e;
   for (int it = 0; it < amg.nu; ++it) {
-    if ((e = launch_csr_jacobi(v.A, v.dinv, v.omega, b, cur, oth, s)) != hipSuccess) return e;
+    if ((e = launch_mat_jacobi<T>(v.A, w.dinv, omega, b, cur, oth, s)) != hipSuccess) return e;
     std::swap(cur, oth);
   }
-  if (cur != x)
-    e = hipMemcpyAsync(x, cur, (size_t)v.A.nrows * sizeof(double), hipMemcpyDeviceToDevice, s);
+  if (cur != x) e = hipMemcpyAsync(x, cur, (size_t)v.A.nrows() * sizeof(T), hipMemcpyDeviceToDevice, s);
   return e;
 }
 
 }  // namespace
 
-hipError_t amg_vcycle(const Amg &amg, const double *b, double *x, hipStream_t s) {
+template <typename T>
+hipError_t amg_vcycle(const Amg &amg, const T *b, T *x, hipStream_t s) {
   if (amg.lv.empty()) return hipErrorInvalidValue;
-  return vcycle_level(amg, 0, b, x, s);
+  if (sizeof(T) == 4 && !amg.has32) return hipErrorInvalidValue;
+  return vcycle_level<T>(amg, 0, b, x, s);
 }
+template hipError_t amg_vcycle<double>(const Amg &, const double *, double *, hipStream_t);
+template hipError_t amg_vcycle<float>(const Amg &, const float *, float *, hipStream_t);
 
 hipError_t amg_apply_fine(const Amg &amg, const double *x, double *y, hipStream_t s) {
   if (amg.lv.empty()) return hipErrorInvalidValue;
-  return launch_csr_spmv(amg.lv[0].A, x, y, false, s);
+  return launch_mat_spmv<double>(amg.lv[0].A, x, y, false, s);
 }
 
 }  // namespace sfem

@@ -13,24 +13,73 @@
 
 namespace sfem {
 
-// Device copy of a CSR matrix (int32 row offsets: nnz < 2^31).
+// Device copy of a CSR matrix (int32 row offsets: nnz < 2^31); val32 is the FP32 copy of
+// the values (made with the FP32 V-cycle's data, else null).
 struct DevCsr {
   int64_t nrows = 0, ncols = 0, nnz = 0;
   int32_t *ptr = nullptr, *col = nullptr;
   double *val = nullptr;
+  float *val32 = nullptr;
+};
+template <typename T>
+inline const T *csr_vals(const DevCsr &A) {
+  if constexpr (sizeof(T) == 8) return A.val;
+  else return A.val32;
+}
+
+// Device copy of a level operator in sliced ELL form: rows in slices of kSellRows (one
+// wave); slice s holds len_s = (off[s+1] - off[s]) / kSellRows entries per row, stored
+// entry-major (entry k of the slice's row r at off[s] + k kSellRows + r), rows shorter
+// than len_s padded with (their last column, 0).  A thread per row then reads the values
+// and column indices of its slice in contiguous runs.
+constexpr int kSellRows = 64;
+struct DevSell {
+  int64_t nrows = 0, ncols = 0, nnz = 0, padded = 0;
+  int32_t *off = nullptr, *col = nullptr;  // off: [nslices + 1]
+  double *val = nullptr;
+  float *val32 = nullptr;
+};
+template <typename T>
+inline const T *sell_vals(const DevSell &A) {
+  if constexpr (sizeof(T) == 8) return A.val;
+  else return A.val32;
+}
+
+// A matrix of the hierarchy in one of the two forms: sliced ELL for many short rows of
+// similar length (a thread per row), CSR otherwise (a group of lanes per row: few or long
+// rows, where a thread per row would leave the GPU idle or pad much).
+struct DevMat {
+  bool sell = false;
+  DevSell S;
+  DevCsr C;
+  int64_t nrows() const { return sell ? S.nrows : C.nrows; }
+};
+
+// Per-level data in the precision T of a V-cycle.
+template <typename T>
+struct LevelVecs {
+  T *dinv = nullptr;                           // 1 / diag(A)
+  T *b = nullptr, *x = nullptr, *t = nullptr;  // work vectors (nrows)
 };
 
 struct AmgLevel {
-  DevCsr A, P, R;              // operator, prolongator (to this level from the next), P^T
-  double *dinv = nullptr;      // 1 / diag(A)
+  DevMat A, P, R;              // operator, prolongator (to this level from the next), P^T
   double omega = 0.0;          // Jacobi damping 4 / (3 rho(D^-1 A))
-  double *b = nullptr, *x = nullptr, *t = nullptr;  // work vectors (nrows)
+  LevelVecs<double> d;         // FP64 V-cycle
+  LevelVecs<float> f;          // FP32 V-cycle (after amg_make_f32)
+  template <typename T>
+  const LevelVecs<T> &vecs() const {
+    if constexpr (sizeof(T) == 8) return d;
+    else return f;
+  }
 };
 
 // Smoothed-aggregation hierarchy (setup on the host, data on the device).
 struct Amg {
   std::vector<AmgLevel> lv;
   double *coarse = nullptr;    // dense pseudo-inverse of the coarsest operator [n][n]
+  float *coarse32 = nullptr;   // its FP32 copy (after amg_make_f32)
+  bool has32 = false;
   int64_t ncoarse = 0;
   int nu = 2;                  // Jacobi sweeps before and after the coarse correction
   std::vector<int64_t> rows, nnzs;
@@ -43,20 +92,30 @@ struct Amg {
 std::string amg_setup(const HostCsr &A, double theta, int64_t coarse_size, int max_levels, int nu,
                       Amg &out);
 void amg_free(Amg &amg);
-// x = V-cycle(b) on the finest level (b, x: device [n], distinct).
-hipError_t amg_vcycle(const Amg &amg, const double *b, double *x, hipStream_t s);
+// FP32 copies of the hierarchy's values, diagonals and coarse inverse, and FP32 work
+// vectors, for amg_vcycle<float> (the FP64 data stays).  Empty string or an error message.
+std::string amg_make_f32(Amg &amg, hipStream_t s);
+// x = V-cycle(b) on the finest level in precision T (b, x: device [n], distinct; T = float
+// after amg_make_f32).
+template <typename T>
+hipError_t amg_vcycle(const Amg &amg, const T *b, T *x, hipStream_t s);
 // y = A_0 x (the finest operator).
 hipError_t amg_apply_fine(const Amg &amg, const double *x, double *y, hipStream_t s);
 
-// Kernel launchers (k_lor.hip).
+// Kernel launchers (k_lor.hip); T = double or float (the matrix values of that precision).
 // x_out = x_in + omega dinv (b - A x_in); x_in == null: x_out = omega dinv b
-hipError_t launch_csr_jacobi(const DevCsr &A, const double *dinv, double omega, const double *b,
-                             const double *x_in, double *x_out, hipStream_t s);
+template <typename T>
+hipError_t launch_mat_jacobi(const DevMat &A, const T *dinv, T omega, const T *b, const T *x_in,
+                             T *x_out, hipStream_t s);
 // r = b - A x
-hipError_t launch_csr_residual(const DevCsr &A, const double *b, const double *x, double *r,
-                               hipStream_t s);
+template <typename T>
+hipError_t launch_mat_residual(const DevMat &A, const T *b, const T *x, T *r, hipStream_t s);
 // y = M x (accumulate: y += M x)
-hipError_t launch_csr_spmv(const DevCsr &M, const double *x, double *y, bool accumulate, hipStream_t s);
+template <typename T>
+hipError_t launch_mat_spmv(const DevMat &M, const T *x, T *y, bool accumulate, hipStream_t s);
+// out = (TO) in
+template <typename TI, typename TO>
+hipError_t launch_convert(const TI *in, TO *out, int64_t n, hipStream_t s);
 // out = a x + b y (out may alias x or y)
 hipError_t launch_axpby(int64_t n, double a, const double *x, double b, const double *y, double *out,
                         hipStream_t s);
@@ -65,6 +124,7 @@ hipError_t launch_cg_update(int64_t n, double a, const double *p, const double *
                             hipStream_t s);
 hipError_t launch_dot2(int64_t n, const double *r, const double *z, double *part, int nblk, hipStream_t s);
 // y = C x for a dense row-major [n][n] C
-hipError_t launch_dense_matvec(const double *C, int64_t n, const double *x, double *y, hipStream_t s);
+template <typename T>
+hipError_t launch_dense_matvec(const T *C, int64_t n, const T *x, T *y, hipStream_t s);
 
 }  // namespace sfem

@@ -43,8 +43,9 @@ class ProjectionStepper:
     elem_xyz [nelem, 8, 3], elem_dofs [nelem, (p+1)^3], ndof, p as for Operator; ess [ndof]
     (nonzero = wall DoF); dt, nu; order 1..3; rtol of both solves; pressure_mode 0 (FP64
     PCG) or 1 (FP32 inner solves in FP64 refinement) with pressure_precond PRECOND_JACOBI;
-    pressure_precond PRECOND_LOR (the default) preconditions the pressure Poisson solve by
-    the LOR multigrid V-cycle (Section 5.2) in FP64 CG."""
+    pressure_precond PRECOND_LOR32 (the default) preconditions the pressure Poisson solve
+    by the LOR multigrid V-cycle (Section 5.2) in FP32 arithmetic inside FP64 CG,
+    PRECOND_LOR by the same V-cycle in FP64."""
 
     def __init__(self, elem_xyz, elem_dofs, ndof, p, ess, dt, nu, order=3, rtol=1e-10,
                  pressure_mode=1, device=None, check_every=8, maxit=10000, pressure_precond=None):
@@ -63,7 +64,7 @@ class ProjectionStepper:
         dofs = torch.as_tensor(elem_dofs, dtype=torch.int32).to(dev).contiguous()
         essd = torch.as_tensor(np.asarray(ess)).to(dev).to(torch.uint8).contiguous()
         nelem = int(xyz.shape[0]) if xyz.ndim == 3 else 0
-        self.pressure_precond = _lib.PRECOND_LOR if pressure_precond is None else int(pressure_precond)
+        self.pressure_precond = _lib.PRECOND_LOR32 if pressure_precond is None else int(pressure_precond)
         opts = FlowOpts(self.dt, self.nu, self.rtol, self.order, self.pressure_mode, int(check_every),
                         int(maxit), self.pressure_precond)
         h = C.c_void_p()

@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_pure_host_calls(lib):
-    assert lib.sfem_abi_version() == 9
+    assert lib.sfem_abi_version() == 10
     assert isinstance(lib.sfem_last_error(None), bytes)
     from paper_1910_03032_amd._lib import CtxInfo
     ci = CtxInfo()
@@ -54,7 +54,7 @@ def test_pure_host_calls(lib):
     lib.sfem_flow_destroy(None)  # no-op
     assert lib.sfem_lor_setup(None, 1, None) == -1
     assert lib.sfem_lor_apply(None, 1, None, None) == -1
-    assert lib.sfem_lor_vcycle(None, 1, None, None) == -1
+    assert lib.sfem_lor_vcycle(None, 1, 0, None, None) == -1
 
 
 def test_structs_match_header_layout():

@@ -113,15 +113,17 @@ def test_hydrostatic_step(ne, p):
     st.close()
 
 
-@pytest.mark.parametrize("p,mode,lor", [(2, 1, False), (4, 1, False), (4, 0, False), (4, 0, True)])
-def test_three_steps_vs_oracle(p, mode, lor):
+@pytest.mark.parametrize("p,mode,pre", [(2, 1, "jacobi"), (4, 1, "jacobi"), (4, 0, "jacobi"), (4, 0, "lor"),
+                                        (4, 0, "lor32")])
+def test_three_steps_vs_oracle(p, mode, pre):
     """Orders 1, 2, 3 on a perturbed 3^3 mesh from a smooth velocity vanishing on the walls,
     with a forcing; both sides solve to 1e-12 (the oracle directly), so the difference is
     bounded by the solve tolerance times the conditioning (< 1e-8); the pressure solve
-    preconditioned by Jacobi (FP64 or FP32 inner solves) or by the LOR V-cycle."""
-    from paper_1910_03032_amd import PRECOND_JACOBI, PRECOND_LOR, ProjectionStepper
+    preconditioned by Jacobi (FP64 or FP32 inner solves) or by the LOR V-cycle (FP64 or
+    FP32 arithmetic)."""
+    from paper_1910_03032_amd import PRECOND_JACOBI, PRECOND_LOR, PRECOND_LOR32, ProjectionStepper
     m = BoxMesh(3, p)
-    say(f"[flow] three steps p={p} ndof={m.ndof} pressure solve mode {mode} lor {lor}")
+    say(f"[flow] three steps p={p} ndof={m.ndof} pressure solve mode {mode} preconditioner {pre}")
     d = Discretization(m.elem_xyz, m.elem_dofs, m.ess, m.ndof, p, p + 2)
     x = node_coords(m, p)
     bump = (x * (1 - x)).prod(axis=1)  # 0 on the walls
@@ -132,7 +134,8 @@ def test_three_steps_vs_oracle(p, mode, lor):
     so = OracleStepper(d, dt=dt, nu=nu, order=3)
     sg = ProjectionStepper(m.elem_xyz, m.elem_dofs, m.ndof, p, m.ess, dt=dt, nu=nu, order=3,
                            rtol=1e-12, pressure_mode=mode,
-                           pressure_precond=PRECOND_LOR if lor else PRECOND_JACOBI)
+                           pressure_precond={"jacobi": PRECOND_JACOBI, "lor": PRECOND_LOR,
+                                             "lor32": PRECOND_LOR32}[pre])
     uo, ug = u.copy(), gpu(u)
     for n in range(3):
         uo, po = so.step(uo, f)

@@ -54,8 +54,14 @@ def test_lor_apply_and_vcycle_vs_oracle(case):
         b = b - b.mean()
     z = host(op.lor_vcycle(gpu(b), opk))
     zo = amg.vcycle(b)
-    say(f"  v-cycle vs oracle {rel(z, zo):.2e}")
+    # the FP32 V-cycle: every product rounds to u = 2^-24 = 6e-8 with up to ~100 terms per
+    # row and a few products in sequence per level, so it stays within 1e-4 (~1700 u) of
+    # the FP64 one
+    from paper_1910_03032_amd import F32
+    z32 = host(op.lor_vcycle(gpu(b), opk, prec=F32))
+    say(f"  v-cycle vs oracle {rel(z, zo):.2e}, FP32 v-cycle vs oracle {rel(z32, zo):.2e}")
     assert rel(z, zo) <= 1e-11
+    assert rel(z32, zo) <= 1e-4
     op.close()
 
 
@@ -76,6 +82,12 @@ def test_lor_pcg_vs_oracle_and_direct(case):
         b = b - b.mean()
     x, res = op.pcg(gpu(b), op=opk, rtol=1e-10, precond=PRECOND_LOR, nullspace=neumann)
     assert res.converged and res.true_rel_res[0] <= 1e-10
+    # the FP32 V-cycle inside FP64 CG: the same solution, at most 2 more iterations
+    from paper_1910_03032_amd import PRECOND_LOR32
+    x32, res32 = op.pcg(gpu(b), op=opk, rtol=1e-10, precond=PRECOND_LOR32, nullspace=neumann)
+    say(f"  FP64 v-cycle {res.iters[0]} iterations, FP32 v-cycle {res32.iters[0]}")
+    assert res32.converged and res32.true_rel_res[0] <= 1e-10
+    assert res32.iters[0] <= res.iters[0] + 2
     amg = AMG(lor_matrix(d, alpha, beta, nu), theta=THETA, coarse_size=COARSE, max_levels=MAXLEV, nu=NU)
     _, it_o, _ = oracle_pcg(lambda v: d.apply(v, alpha, beta, nu), b, None, rtol=1e-10,
                             precond=amg.vcycle, nullspace=neumann)
@@ -90,6 +102,7 @@ def test_lor_pcg_vs_oracle_and_direct(case):
     else:
         xd = spla.spsolve(A.tocsc(), b)
     assert rel(host(x), xd) <= 1e-8
+    assert rel(host(x32), xd) <= 1e-8
     op.close()
 
 
@@ -120,7 +133,7 @@ def test_lor_neumann_poisson_p4_32e():
     """The projection step's pressure-Poisson size (32^3 p = 4, 2.1M DoFs, pure Neumann):
     CG with the LOR V-cycle reaches 1e-10 in under 80 iterations (Jacobi: ~1100) and its
     solution agrees with the Jacobi-preconditioned one."""
-    from paper_1910_03032_amd import DIFFUSION, PRECOND_LOR
+    from paper_1910_03032_amd import DIFFUSION, PRECOND_LOR, PRECOND_LOR32
     m = BoxMesh(32, 4)
     free = np.zeros(m.ndof, dtype=np.uint8)
     from paper_1910_03032_amd import Operator
@@ -132,10 +145,14 @@ def test_lor_neumann_poisson_p4_32e():
     x, r = op.pcg(b, op=DIFFUSION, rtol=1e-10, precond=PRECOND_LOR, nullspace=True, check_every=16)
     say(f"  lor {r}")
     assert r.converged and r.true_rel_res[0] <= 1e-10 and r.iters[0] < 80
+    x32, r32 = op.pcg(b, op=DIFFUSION, rtol=1e-10, precond=PRECOND_LOR32, nullspace=True)
+    say(f"  lor fp32 v-cycle {r32}")
+    assert r32.converged and r32.true_rel_res[0] <= 1e-10 and r32.iters[0] <= r.iters[0] + 2
     xj, rj = op.pcg(b, op=DIFFUSION, rtol=1e-10, nullspace=True, check_every=16)
     say(f"  jacobi {rj}")
     assert rj.converged
     assert float((x - xj).norm() / xj.norm()) <= 1e-6
+    assert float((x32 - xj).norm() / xj.norm()) <= 1e-6
     op.close()
 
 
@@ -156,6 +173,13 @@ def test_lor_error_paths_and_edge_cases():
     assert rz.converged and float(z.abs().max()) == 0.0
     with pytest.raises(SfemError, match="SFEM_E_ARG"):
         op.pcg(gpu(b), op=HELMHOLTZ, precond=PRECOND_LOR, mode=1)
+    from paper_1910_03032_amd import PRECOND_LOR32
+    with pytest.raises(SfemError, match="SFEM_E_ARG"):
+        op.pcg(gpu(b), op=HELMHOLTZ, precond=PRECOND_LOR32, mode=1)
+    with pytest.raises(SfemError, match="SFEM_E_ARG"):
+        op.lor_vcycle(gpu(b), HELMHOLTZ, prec=7)
+    x32, r32 = op.pcg(gpu(b), op=HELMHOLTZ, rtol=1e-12, precond=PRECOND_LOR32)
+    assert r32.converged and rel(host(x32), host(x)) <= 1e-9
     op.close()
     m2 = BoxMesh(2, 2)
     d2, op2 = setup(m2, 2, m2.ess, 1e3, 1.0)
