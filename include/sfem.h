@@ -175,6 +175,10 @@ typedef struct {
   int64_t rows[SFEM_LOR_MAX_LEVELS];   /* rows per level */
   int64_t nnz[SFEM_LOR_MAX_LEVELS];    /* nonzeros per level */
   double setup_ms;                     /* host setup time of the hierarchy */
+  int32_t sliced[SFEM_LOR_MAX_LEVELS]; /* device storage per level: bit 0 the operator, bit 1
+                                          the prolongator, bit 2 the restriction in sliced
+                                          ELL (64-row slices), else CSR (the coarsest
+                                          level: a dense inverse) */
 } sfem_lor_info;
 sfem_status sfem_lor_setup(sfem_ctx *ctx, int op, sfem_lor_info *info);
 sfem_status sfem_lor_apply(sfem_ctx *ctx, int op, const double *x, double *y);

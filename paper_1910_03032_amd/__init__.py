@@ -300,7 +300,7 @@ class Operator:
         self._check(self._lib.sfem_lor_setup(self._h, op, C.byref(info)))
         L = info.levels
         return {"levels": L, "rows": list(info.rows[:L]), "nnz": list(info.nnz[:L]),
-                "setup_ms": info.setup_ms}
+                "setup_ms": info.setup_ms, "sliced": list(info.sliced[:L])}
 
     def lor_apply(self, x, op=HELMHOLTZ):
         """y = A_LOR x (float64 [ndof])."""

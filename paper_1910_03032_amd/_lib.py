@@ -61,7 +61,8 @@ class FlowInfo(C.Structure):
 
 class LorInfo(C.Structure):
     _fields_ = [("levels", C.c_int), ("rows", C.c_int64 * LOR_MAX_LEVELS),
-                ("nnz", C.c_int64 * LOR_MAX_LEVELS), ("setup_ms", C.c_double)]
+                ("nnz", C.c_int64 * LOR_MAX_LEVELS), ("setup_ms", C.c_double),
+                ("sliced", C.c_int32 * LOR_MAX_LEVELS)]
 
 
 class SfemError(RuntimeError):

@@ -1076,6 +1076,7 @@ static sfem_status sfem_lor_setup_body(sfem_ctx *c, int op, sfem_lor_info *info)
     for (int l = 0; l < info->levels && l < SFEM_LOR_MAX_LEVELS; ++l) {
       info->rows[l] = a.rows[(size_t)l];
       info->nnz[l] = a.nnzs[(size_t)l];
+      info->sliced[l] = a.sliced[(size_t)l];
     }
     info->setup_ms = a.setup_ms;
   }

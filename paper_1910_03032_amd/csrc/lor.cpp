@@ -143,6 +143,8 @@ std::string amg_setup(const HostCsr &A0, double theta, int64_t coarse_size, int 
     }
     if (!(e = upload<double>(out, &v.d.t, nullptr, n)).empty()) return e;
   }
+  for (const AmgLevel &v : out.lv)
+    out.sliced.push_back((v.A.sell ? 1 : 0) | (v.P.sell ? 2 : 0) | (v.R.sell ? 4 : 0));
   out.ncoarse = As.back().nrows;
   if (!(e = upload(out, &out.coarse, H.coarse.data(), (int64_t)H.coarse.size())).empty()) return e;
   out.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -155,6 +157,7 @@ void amg_free(Amg &amg) {
   amg.lv.clear();
   amg.rows.clear();
   amg.nnzs.clear();
+  amg.sliced.clear();
   amg.coarse = nullptr;
   amg.coarse32 = nullptr;
   amg.has32 = false;

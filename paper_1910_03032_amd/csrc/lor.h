@@ -83,6 +83,7 @@ struct Amg {
   int64_t ncoarse = 0;
   int nu = 2;                  // Jacobi sweeps before and after the coarse correction
   std::vector<int64_t> rows, nnzs;
+  std::vector<int32_t> sliced;  // per level: bit 0 A, bit 1 P, bit 2 R in sliced ELL
   std::vector<void *> bufs;    // every device allocation
   double setup_ms = 0.0;
 };

@@ -19,6 +19,30 @@ pytestmark = pytest.mark.gpu
 THETA, COARSE, MAXLEV, NU = 0.02, 200, 12, 1
 
 
+def sliced_storage(M):
+    """The library's storage rule: sliced ELL (64-row slices) for at least 16384 rows of at
+    most 48 entries on average that pad by at most half, CSR otherwise."""
+    rl = np.diff(M.indptr)
+    n = len(rl)
+    ns = (n + 63) // 64
+    padded = int(np.pad(rl, (0, ns * 64 - n)).reshape(ns, 64).max(axis=1).sum()) * 64
+    return n >= 16384 and M.nnz <= 48 * n and 2 * padded <= 3 * M.nnz
+
+
+def expected_sliced(amg):
+    L = len(amg.A)
+    flags = []
+    for l in range(L):
+        f = 0
+        if l + 1 < L or l == 0:
+            f |= 1 if sliced_storage(amg.A[l]) else 0
+        if l + 1 < L:
+            f |= 2 if sliced_storage(amg.P[l]) else 0
+            f |= 4 if sliced_storage(amg.P[l].T.tocsr()) else 0
+        flags.append(f)
+    return flags
+
+
 def setup(m, p, ess, alpha, beta, nu=None):
     from paper_1910_03032_amd import Operator
     d = Discretization(m.elem_xyz, m.elem_dofs, ess, m.ndof, p, p + 2)
@@ -27,19 +51,28 @@ def setup(m, p, ess, alpha, beta, nu=None):
     return d, op
 
 
-@pytest.mark.parametrize("case", ["poisson_3e_p4", "helmholtz_nu_3e_p3", "neumann_3e_p5", "fan_p3"])
+CASES = {"poisson_3e_p4": (3, 4), "helmholtz_nu_3e_p3": (3, 3), "neumann_3e_p5": (3, 5),
+         "poisson_8e_p4": (8, 4), "helmholtz_nu_7e_p4": (7, 4), "neumann_6e_p5": (6, 5)}
+
+
+@pytest.mark.parametrize("case", ["poisson_3e_p4", "helmholtz_nu_3e_p3", "neumann_3e_p5", "fan_p3",
+                                  "poisson_8e_p4", "helmholtz_nu_7e_p4", "neumann_6e_p5"])
 def test_lor_apply_and_vcycle_vs_oracle(case):
+    """The small meshes keep every matrix in CSR; from 16384 rows (8^3 and 7^3 at p = 4, 6^3
+    at p = 5) the finest operator is in sliced ELL, and the prolongator where its padding
+    stays within half (the reported storage matches the rule applied to the oracle's
+    hierarchy)."""
     from paper_1910_03032_amd import DIFFUSION, HELMHOLTZ
     if case == "fan_p3":
         m, p = FanMesh(3), 3
         ess, opk, alpha, beta, nu = m.ess, HELMHOLTZ, 1.0, 1.0, None
     else:
-        ne, p = {"poisson_3e_p4": (3, 4), "helmholtz_nu_3e_p3": (3, 3), "neumann_3e_p5": (3, 5)}[case]
+        ne, p = CASES[case]
         m = BoxMesh(ne, p)
-        ess = np.zeros(m.ndof, dtype=np.uint8) if case == "neumann_3e_p5" else m.ess
-        opk = HELMHOLTZ if case == "helmholtz_nu_3e_p3" else DIFFUSION
+        ess = np.zeros(m.ndof, dtype=np.uint8) if case.startswith("neumann") else m.ess
+        opk = HELMHOLTZ if case.startswith("helmholtz") else DIFFUSION
         alpha, beta = (1e3, 1.0) if opk == HELMHOLTZ else (0.0, 1.0)
-        nu = nu_uniform(m.nelem, p + 2, seed=2) if case == "helmholtz_nu_3e_p3" else None
+        nu = nu_uniform(m.nelem, p + 2, seed=2) if opk == HELMHOLTZ else None
     say(f"[lor] {case} ndof={m.ndof}")
     d, op = setup(m, p, ess, alpha, beta, nu)
     info = op.lor_setup(opk)
@@ -47,6 +80,9 @@ def test_lor_apply_and_vcycle_vs_oracle(case):
     amg = AMG(L, theta=THETA, coarse_size=COARSE, max_levels=MAXLEV, nu=NU)
     say(f"  levels {info['rows']} (oracle {[a.shape[0] for a in amg.A]}), setup {info['setup_ms']:.1f} ms")
     assert info["rows"] == [a.shape[0] for a in amg.A]
+    say(f"  storage per level (bit 0 operator, 1 prolongator, 2 restriction sliced): {info['sliced']}")
+    assert info["sliced"] == expected_sliced(amg)
+    assert (info["sliced"][0] & 1) == (1 if m.ndof >= 16384 else 0)
     x = uniform(m.ndof, seed=5)
     assert rel(host(op.lor_apply(gpu(x), opk)), L @ x) <= 1e-13
     b = uniform(m.ndof, seed=6)
