@@ -60,7 +60,8 @@ std::string upload_sell(Amg &amg, const HostCsr &H, DevSell &D) {
     for (int64_t r = s * kSellRows; r < (s + 1) * kSellRows; ++r) {
       const int64_t lane = r - s * kSellRows;
       const int64_t b = r < H.nrows ? H.ptr[r] : 0, e = r < H.nrows ? H.ptr[r + 1] : 0;
-      const int32_t last = e > b ? H.col[(size_t)(e - 1)] : 0;  // a valid column near the row's
+      // padding: the row's last column (a valid index near its others) with value 0
+      const int32_t last = e > b ? H.col[(size_t)(e - 1)] : 0;
       for (int64_t k = 0; k < len; ++k) {
         const size_t at = (size_t)(off[s] + k * kSellRows + lane);
         const bool in = b + k < e;
@@ -190,10 +191,11 @@ std::string amg_make_f32(Amg &amg, hipStream_t s) {
     AmgLevel &v = amg.lv[l];
     const int64_t n = amg.rows[l];
     if (l + 1 < L) {
-      for (DevMat *M : {&v.A, &v.P, &v.R})
+      for (DevMat *M : {&v.A, &v.P, &v.R}) {
         e = M->sell ? to_f32(amg, &M->S.val32, M->S.val, M->S.padded, s)
                     : to_f32(amg, &M->C.val32, M->C.val, M->C.nnz, s);
-      if (!e.empty()) return e;
+        if (!e.empty()) return e;
+      }
       if (!(e = to_f32(amg, &v.f.dinv, v.d.dinv, n, s)).empty()) return e;
     }
     if (l > 0) {
