@@ -126,7 +126,7 @@ struct sfem_ctx {
   bool lor_ok[3] = {false, false, false};
   Amg lor[3];
   double *lor_work = nullptr;      // [5][ndof] vectors of the LOR-preconditioned CG
-  double *lor_scal = nullptr;      // [8] device scalars
+  double *lor_scal = nullptr;      // device scalars: [kLorScalarSlots] doubles, then 2 PcgScalars
   float *lor_work32 = nullptr;     // [2][ndof] FP32 residual and V-cycle output
 
   // ---- E-vector of the apply and solver workspace (grown on demand)
@@ -628,6 +628,9 @@ constexpr double kLorTheta = 0.02;
 constexpr int64_t kLorCoarse = 200;
 constexpr int kLorMaxLevels = 12;
 constexpr int kLorSweeps = 1;
+// device scalar doubles of the LOR solves ahead of the CG scalars (the null-space mean)
+constexpr int64_t kLorScalarSlots = 8;
+static_assert(sizeof(PcgScalars) % sizeof(double) == 0, "PcgScalars packs into doubles");
 
 // Build (once per operator kind and coefficients) A_LOR of op and its multigrid hierarchy.
 sfem_status ensure_lor_f64(sfem_ctx *c, int op) {
@@ -668,7 +671,7 @@ sfem_status ensure_lor_f64(sfem_ctx *c, int op) {
   if (!c->lor_work) {
     sfem_status st;
     if ((st = dalloc(c, &c->lor_work, 5 * c->ndof)) != SFEM_OK) return st;
-    if ((st = dalloc(c, &c->lor_scal, 8)) != SFEM_OK) return st;
+    if ((st = dalloc(c, &c->lor_scal, kLorScalarSlots + 2 * (int64_t)(sizeof(PcgScalars) / sizeof(double)))) != SFEM_OK) return st;
   }
   c->lor_ok[op] = true;
   return SFEM_OK;
@@ -696,32 +699,6 @@ hipError_t lor_vcycle(sfem_ctx *c, int op, bool f32, const double *r, double *z)
   return launch_convert<float, double>(z32, z, n, c->stream);
 }
 
-// Host-side scalar of a device dot product a . b (b == null: sum of a).
-sfem_status dev_dot(sfem_ctx *c, const double *a, const double *b, double *part, double *out_dev,
-                    double *out) {
-  const int64_t n = c->ndof;
-  const int nblk = vec_nblk(n);
-  HIPCHK(c, VecOps<double>::dot(a, b, 0, part, nblk, n, 1, c->stream));
-  HIPCHK(c, launch_reduce1(part, nblk, 1, out_dev, c->stream));
-  HIPCHK(c, hipMemcpyAsync(out, out_dev, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  return SFEM_OK;
-}
-
-// Host-side scalars r . r and r . z (one pass over both vectors, one synchronization).
-sfem_status dev_dot_rr_rz(sfem_ctx *c, const double *r, const double *z, double *part, double *out_dev,
-                          double *out) {
-  const int64_t n = c->ndof;
-  const int nblk = vec_nblk(n);
-  HIPCHK(c, launch_dot2(n, r, z, part, nblk, c->stream));
-  HIPCHK(c, launch_reduce1(part, nblk, 2, out_dev, c->stream));
-  HIPCHK(c, hipMemcpyAsync(out, out_dev, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  return SFEM_OK;
-}
-
-// z = M_LOR^-1 r by one V-cycle; orthogonalized against the constants for a null-space
-// solve (Section 5.3).
 sfem_status lor_precond(sfem_ctx *c, int op, bool f32, const double *r, double *z, int nullspace,
                         double *part) {
   HIPCHK(c, lor_vcycle(c, op, f32, r, z));
@@ -735,28 +712,24 @@ sfem_status lor_precond(sfem_ctx *c, int op, bool f32, const double *r, double *
   return SFEM_OK;
 }
 
-// CG for one member preconditioned by the LOR multigrid V-cycle, scalars on the host
-// (two synchronizations per iteration: p.Ap, then r.r with r.z).  On return hs holds
-// iters, rr, bb, status, active.
+// CG for one member preconditioned by the LOR multigrid V-cycle.  The scalars stay on the
+// device (step length, direction and stopping test formed by the kernels from partial
+// sums); after each iteration they are copied to pinned host memory behind an event, and
+// the host reads the previous iteration's copy once the next iteration is queued, so the
+// GPU never waits for the host.  When that copy shows the solve stopped, the iteration
+// queued after it changes nothing (alpha = 0 once inactive).  dpart: the apply's partials;
+// part: [5][vec_nblk(n)] partials.  On return hs holds the final scalars.
 sfem_status run_pcg_lor(sfem_ctx *c, int op, bool f32, const double *b, double *x, bool x0_zero,
-                        double rtol, int maxit, int nullspace, double *part, PcgScalars &hs) {
+                        double rtol, int maxit, int nullspace, double *dpart, double *part,
+                        PcgScalars &hs) {
   const int64_t n = c->ndof;
   hipStream_t s = c->stream;
   double *r = c->lor_work, *z = r + n, *pv = z + n, *w = pv + n;
-  double *sc = c->lor_scal + 1;
+  PcgScalars *sc = reinterpret_cast<PcgScalars *>(c->lor_scal + kLorScalarSlots);  // [2]
+  PcgScalars *h = reinterpret_cast<PcgScalars *>(c->h_pinned);                       // [2]
+  const int nblk = vec_nblk(n);
   sfem_status st;
   hs = PcgScalars{};
-  double bb = 0.0;
-  if ((st = dev_dot(c, b, b, part, sc, &bb)) != SFEM_OK) return st;
-  hs.bb = bb;
-  if (!std::isfinite(bb)) {
-    hs.status = SFEM_E_NAN;
-    return SFEM_OK;
-  }
-  if (bb == 0.0) {
-    HIPCHK(c, VecOps<double>::fill(x, 0.0, n, s));
-    return SFEM_OK;
-  }
   if (x0_zero) {
     HIPCHK(c, VecOps<double>::fill(x, 0.0, n, s));
     HIPCHK(c, hipMemcpyAsync(r, b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -764,49 +737,52 @@ sfem_status run_pcg_lor(sfem_ctx *c, int op, bool f32, const double *b, double *
     if ((st = do_apply(c, op, false, 1, x, w)) != SFEM_OK) return st;
     HIPCHK(c, launch_axpby(n, 1.0, b, -1.0, w, r, s));  // r = b - A x
   }
-  double rr = 0.0;
-  if ((st = dev_dot(c, r, r, part, sc, &rr)) != SFEM_OK) return st;
-  const double tol2 = rtol * rtol * bb;
-  hs.rr = rr;
-  if (rr <= tol2) return SFEM_OK;
   if ((st = lor_precond(c, op, f32, r, z, nullspace, part)) != SFEM_OK) return st;
   HIPCHK(c, hipMemcpyAsync(pv, z, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
-  double rho = 0.0;
-  if ((st = dev_dot(c, r, z, part, sc, &rho)) != SFEM_OK) return st;
-  hs.active = 1;
-  for (int it = 0; it < maxit; ++it) {
-    if ((st = do_apply(c, op, false, 1, pv, w)) != SFEM_OK) return st;
-    double pw = 0.0;
-    if ((st = dev_dot(c, pv, w, part, sc, &pw)) != SFEM_OK) return st;
-    if (!std::isfinite(pw) || !std::isfinite(rho)) {
-      hs.status = SFEM_E_NAN;
-      hs.active = 0;
-      return SFEM_OK;
-    }
-    if (!(pw > 0.0)) {
-      hs.status = SFEM_E_BREAKDOWN;
-      hs.active = 0;
-      return SFEM_OK;
-    }
-    const double alpha = rho / pw;
-    HIPCHK(c, launch_cg_update(n, alpha, pv, w, x, r, s));  // x += alpha p, r -= alpha w
-    hs.iters = it + 1;
-    // the next preconditioned residual is computed with the convergence test (one sync)
-    if ((st = lor_precond(c, op, f32, r, z, nullspace, part)) != SFEM_OK) return st;
-    double two[2];
-    if ((st = dev_dot_rr_rz(c, r, z, part, sc, two)) != SFEM_OK) return st;
-    rr = two[0];
-    hs.rr = rr;
-    if (rr <= tol2) {
-      hs.active = 0;
-      return SFEM_OK;
-    }
-    const double rho_new = two[1];
-    const double beta = rho_new / rho;
-    rho = rho_new;
-    HIPCHK(c, launch_axpby(n, 1.0, z, beta, pv, pv, s));   // p = z + beta p
+  HIPCHK(c, launch_gpcg_dots(r, z, b, part, nblk, n, s));
+  HIPCHK(c, launch_pcg_init(part, nblk, 1, rtol, sc, s));
+  HIPCHK(c, hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  hs = h[0];
+  if (hs.bb == 0.0) {  // b = 0: the solution is x = 0
+    HIPCHK(c, VecOps<double>::fill(x, 0.0, n, s));
+    return SFEM_OK;
   }
-  return SFEM_OK;  // active stays 1: not converged within maxit
+  if (!hs.active) return SFEM_OK;
+  const double *dp = dpart + apply_final_off(c, false, 1);
+  const int dcount = apply_final_count(c, false, 1);
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  for (hipEvent_t &e : ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      for (hipEvent_t &d : ev)
+        if (d) (void)hipEventDestroy(d);
+      return fail(c, SFEM_E_HIP, "LOR CG: event creation failed");
+    }
+  auto body = [&]() -> sfem_status {
+    int cur = 0, last = -1;
+    for (int it = 0; it < maxit; ++it) {
+      if ((st = do_apply(c, op, false, 1, pv, w, dpart)) != SFEM_OK) return st;
+      HIPCHK(c, launch_gpcg_update(x, pv, r, w, sc + cur, dp, dcount, n, s));
+      if ((st = lor_precond(c, op, f32, r, z, nullspace, part)) != SFEM_OK) return st;
+      HIPCHK(c, launch_gpcg_dots(r, z, nullptr, part, nblk, n, s));
+      HIPCHK(c, launch_gpcg_newdir(z, pv, sc + cur, sc + 1 - cur, dp, dcount, part, nblk, n, s));
+      cur = 1 - cur;
+      HIPCHK(c, hipMemcpyAsync(h + (it & 1), sc + cur, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipEventRecord(ev[it & 1], s));
+      last = it;
+      if (it > 0) {
+        HIPCHK(c, hipEventSynchronize(ev[(it - 1) & 1]));
+        if (!h[(it - 1) & 1].active) break;
+      }
+    }
+    HIPCHK(c, hipEventSynchronize(ev[last & 1]));
+    hs = h[last & 1];
+    return SFEM_OK;
+  };
+  st = body();
+  for (hipEvent_t &e : ev) (void)hipEventDestroy(e);
+  return st;
 }
 
 sfem_status require_ready(sfem_ctx *c) {
@@ -1255,7 +1231,9 @@ static sfem_status sfem_pcg_body(sfem_ctx *c, int op, int nbatch, const double *
     const size_t bytes = pcg_work_bytes<double>(c, n, nb) + align_up((size_t)nb * sizeof(double)) +
                          (ns ? align_up((size_t)n * nb * sizeof(double)) : 0);
     if ((st = ensure_ws(c, bytes)) != SFEM_OK) return st;
-    if ((st = ensure_pinned(c, std::max(sizeof(PcgScalars), sizeof(double)) * nb)) != SFEM_OK) return st;
+    // (the LOR CG keeps two scalar copies in flight)
+    if ((st = ensure_pinned(c, std::max(sizeof(PcgScalars), sizeof(double)) * std::max(nb, 2))) != SFEM_OK)
+      return st;
     Carver cv{(char *)c->ws.p};
     PcgWork<double> w = carve_pcg<double>(c, cv, n, nb);
     double *d_out = cv.take<double>(nb);
@@ -1276,7 +1254,8 @@ static sfem_status sfem_pcg_body(sfem_ctx *c, int op, int nbatch, const double *
       // members one after another, each preconditioned by the LOR multigrid V-cycle
       for (int m = 0; m < nb; ++m)
         if ((st = run_pcg_lor(c, op, lor32, bs + (int64_t)m * n, x + (int64_t)m * n,
-                              opts->x0_zero != 0, opts->rtol, opts->maxit, ns, w.part, fin[m])) != SFEM_OK)
+                              opts->x0_zero != 0, opts->rtol, opts->maxit, ns, w.dpart, w.part,
+                              fin[m])) != SFEM_OK)
           return st;
     } else {
       if ((st = run_pcg<double>(c, op, nb, bs, x, opts->x0_zero != 0, opts->rtol, opts->maxit,

@@ -86,44 +86,6 @@ axpby_kernel(int64_t n, double a, const double *x, double b, const double *y, do
     out[i] = a * x[i] + b * y[i];
 }
 
-// x += a p, r -= a w
-__global__ void __launch_bounds__(kRowBlock)
-cg_update_kernel(int64_t n, double a, const double *__restrict__ p, const double *__restrict__ w,
-                 double *__restrict__ x, double *__restrict__ r) {
-  for (int64_t i = (int64_t)blockIdx.x * kRowBlock + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kRowBlock) {
-    x[i] += a * p[i];
-    r[i] -= a * w[i];
-  }
-}
-
-// block partials of r.r (part[blk]) and r.z (part[nblk + blk]); fixed order within a block
-__global__ void __launch_bounds__(kRowBlock)
-dot2_kernel(int64_t n, const double *__restrict__ r, const double *__restrict__ z,
-            double *__restrict__ part, int nblk) {
-  __shared__ double sh[2][kRowBlock];
-  double rr = 0.0, rz = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kRowBlock + threadIdx.x; i < n; i += (int64_t)nblk * kRowBlock) {
-    const double ri = r[i];
-    rr += ri * ri;
-    rz += ri * z[i];
-  }
-  sh[0][threadIdx.x] = rr;
-  sh[1][threadIdx.x] = rz;
-  __syncthreads();
-  for (int off = kRowBlock / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) {
-      sh[0][threadIdx.x] += sh[0][threadIdx.x + off];
-      sh[1][threadIdx.x] += sh[1][threadIdx.x + off];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = sh[0][0];
-    part[nblk + blockIdx.x] = sh[1][0];
-  }
-}
-
 // y = C x, one wave per row of the dense [n][n] C
 template <typename T>
 __global__ void __launch_bounds__(kRowBlock)
@@ -253,18 +215,5 @@ hipError_t launch_axpby(int64_t n, double a, const double *x, double b, const do
   hipLaunchKernelGGL(axpby_kernel, dim3(grid_for_rows(n, 1)), dim3(kRowBlock), 0, s, n, a, x, b, y, out);
   return hipGetLastError();
 }
-
-hipError_t launch_cg_update(int64_t n, double a, const double *p, const double *w, double *x, double *r,
-                            hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(cg_update_kernel, dim3(grid_for_rows(n, 1)), dim3(kRowBlock), 0, s, n, a, p, w, x, r);
-  return hipGetLastError();
-}
-
-hipError_t launch_dot2(int64_t n, const double *r, const double *z, double *part, int nblk, hipStream_t s) {
-  hipLaunchKernelGGL(dot2_kernel, dim3(nblk), dim3(kRowBlock), 0, s, n, r, z, part, nblk);
-  return hipGetLastError();
-}
-
 
 }  // namespace sfem

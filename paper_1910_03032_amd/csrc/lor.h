@@ -120,10 +120,6 @@ hipError_t launch_convert(const TI *in, TO *out, int64_t n, hipStream_t s);
 // out = a x + b y (out may alias x or y)
 hipError_t launch_axpby(int64_t n, double a, const double *x, double b, const double *y, double *out,
                         hipStream_t s);
-// CG vector steps: x += a p, r -= a w; block partials of r.r and r.z ([2][nblk])
-hipError_t launch_cg_update(int64_t n, double a, const double *p, const double *w, double *x, double *r,
-                            hipStream_t s);
-hipError_t launch_dot2(int64_t n, const double *r, const double *z, double *part, int nblk, hipStream_t s);
 // y = C x for a dense row-major [n][n] C
 template <typename T>
 hipError_t launch_dense_matvec(const T *C, int64_t n, const T *x, T *y, hipStream_t s);

@@ -216,6 +216,17 @@ def test_lor_error_paths_and_edge_cases():
         op.lor_vcycle(gpu(b), HELMHOLTZ, prec=7)
     x32, r32 = op.pcg(gpu(b), op=HELMHOLTZ, rtol=1e-12, precond=PRECOND_LOR32)
     assert r32.converged and rel(host(x32), host(x)) <= 1e-9
+    # an iteration cap: SFEM_NOCONV with exactly that many iterations and the last iterate
+    # (the iteration queued after the stop changes nothing)
+    assert r.iters[0] >= 3
+    for cap in range(1, r.iters[0]):
+        xc, rc = op.pcg(gpu(b), op=HELMHOLTZ, rtol=1e-12, precond=PRECOND_LOR, maxit=cap)
+        assert rc.status == 1 and rc.iters[0] == cap, rc
+        assert rc.rel_res[0] > 1e-12
+    # the stop is seen one iteration late: the solution equals the one of a cap at the
+    # iteration count the converged solve reported
+    xk, rk = op.pcg(gpu(b), op=HELMHOLTZ, rtol=1e-12, precond=PRECOND_LOR, maxit=r.iters[0])
+    assert rk.iters[0] == r.iters[0] and float((xk - x).abs().max()) == 0.0
     op.close()
     m2 = BoxMesh(2, 2)
     d2, op2 = setup(m2, 2, m2.ess, 1e3, 1.0)
