@@ -277,6 +277,11 @@ struct SDims {
   static constexpr int TPE = D::TPE, E = D::E, THREADS = D::THREADS;
   static_assert(D::BUF >= 3 * N * Q * Q && D::BUF >= 3 * Q * Q * NP && D::BUF >= 2 * Q * N * N,
                 "element buffer");
+  // minimum waves per SIMD the kernels below are compiled for: 2 (at most 256 registers)
+  // up to p = 7, where the second wave outweighs a small spill (convection at 28^3 p = 5:
+  // 338 -> 302 us, 24^3 p = 7: 577 -> 472 us); at p = 8 the spill is large and one wave
+  // with more registers is faster
+  static constexpr int OCC = P <= 7 ? 2 : 1;
 };
 
 // Output of a velocity element vector that adds into y: sole DoFs y[g] += v (each has
@@ -311,7 +316,7 @@ __device__ __forceinline__ void emit_add_vel(const double *buf, int t, bool acti
 // pressure space (element-ordered E-vector Yp, sole DoFs of yp).  cq: [nelem][9][q^3],
 // slot 3c + d holds C_cd.
 template <int P, bool POS>
-__global__ void __launch_bounds__(Dims<P>::THREADS)
+__global__ void __launch_bounds__(Dims<P>::THREADS, SDims<P>::OCC)
 coupling_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ vpos, int vcompact,
                 const int32_t *__restrict__ pmap, int pcompact, const double *__restrict__ cq,
                 int64_t nelem, const double *__restrict__ u, const double *__restrict__ pres,
@@ -613,7 +618,7 @@ __device__ __forceinline__ void phi_test_body(const int32_t *__restrict__ vmap,
 }
 
 template <int P, bool POS>
-__global__ void __launch_bounds__(Dims<P>::THREADS)
+__global__ void __launch_bounds__(Dims<P>::THREADS, SDims<P>::OCC)
 convection_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ vpos,
                   int vcompact, const double *__restrict__ cq, int64_t nelem,
                   const double *__restrict__ u, int64_t nv, double *__restrict__ Yv,
@@ -623,7 +628,7 @@ convection_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ 
 
 // Weak curl (MODE = kCurl) or weak gradient (MODE = kGradient) of the projection step.
 template <int P, bool POS, int MODE>
-__global__ void __launch_bounds__(Dims<P>::THREADS)
+__global__ void __launch_bounds__(Dims<P>::THREADS, SDims<P>::OCC)
 weak_phi_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ vpos,
                 int vcompact, const double *__restrict__ cq, int64_t nelem,
                 const double *__restrict__ u, int64_t nv, double *__restrict__ Yv,
@@ -727,7 +732,7 @@ __device__ __forceinline__ void bwd_grad(double *buf, int t, const double (&v)[3
 // and interpolated (values only), C^T V is formed per point, and one backward
 // reference-gradient pass gives the single output (member 0 of the E-vector and of y).
 template <int P, bool POS>
-__global__ void __launch_bounds__(Dims<P>::THREADS)
+__global__ void __launch_bounds__(Dims<P>::THREADS, SDims<P>::OCC)
 weak_div_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ vpos,
                 int vcompact, const double *__restrict__ cq, int64_t nelem,
                 const double *__restrict__ u, int64_t nv, double *__restrict__ Yv,
