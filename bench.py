@@ -734,18 +734,20 @@ def run_projection(a):
     ne, p = 32, 4
     m = BoxMesh(ne, p)
     rows = []
-    for name, pre, mode in (("lor", PRECOND_LOR, 0), ("lor_fp32_vcycle", PRECOND_LOR32, 0),
-                            ("jacobi_fp32_ir", PRECOND_JACOBI, 1)):
-        rows.append(projection_row(a, m, ne, p, name, pre, mode))
+    for name, pre, mode, vmode in (("lor", PRECOND_LOR, 0, 0), ("lor_fp32_vcycle", PRECOND_LOR32, 0, 0),
+                                   ("lor_fp32_vcycle_velocity_ir", PRECOND_LOR32, 0, 1),
+                                   ("jacobi_fp32_ir", PRECOND_JACOBI, 1, 0)):
+        rows.append(projection_row(a, m, ne, p, name, pre, mode, vmode))
     return {"workload": "projection_32e", "rows": rows}
 
 
-def projection_row(a, m, ne, p, name, pressure_precond, pressure_mode):
+def projection_row(a, m, ne, p, name, pressure_precond, pressure_mode, velocity_mode=0):
     import torch
     from paper_1910_03032_amd import ProjectionStepper
     t0 = time.perf_counter()
     st = ProjectionStepper(m.elem_xyz, m.elem_dofs, m.ndof, p, m.ess, dt=1e-3, nu=0.01, order=3,
-                           rtol=1e-10, pressure_precond=pressure_precond, pressure_mode=pressure_mode)
+                           rtol=1e-10, pressure_precond=pressure_precond, pressure_mode=pressure_mode,
+                           velocity_mode=velocity_mode)
     xyz = torch.as_tensor(node_positions(m, p), device=st.device)
     bump = (xyz * (1 - xyz)).prod(dim=1) * 64.0
     u = torch.stack([bump * torch.sin(torch.pi * xyz[:, 1]), bump * torch.cos(torch.pi * xyz[:, 2]),

@@ -334,6 +334,8 @@ typedef struct {
   int pressure_precond; /* pressure Poisson preconditioner: SFEM_PRECOND_JACOBI,
                            SFEM_PRECOND_LOR or SFEM_PRECOND_LOR32 (Section 5.2; FP64 CG,
                            pressure_mode ignored) */
+  int velocity_mode;  /* Helmholtz velocity solve (Jacobi-preconditioned, three members): 0 FP64
+                         PCG, 1 FP32 inner solves in FP64 refinement */
 } sfem_flow_opts;
 
 typedef struct {

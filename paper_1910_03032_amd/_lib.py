@@ -52,7 +52,7 @@ class CtxInfo(C.Structure):
 class FlowOpts(C.Structure):
     _fields_ = [("dt", C.c_double), ("nu", C.c_double), ("rtol", C.c_double), ("order", C.c_int),
                 ("pressure_mode", C.c_int), ("check_every", C.c_int), ("maxit", C.c_int),
-                ("pressure_precond", C.c_int)]
+                ("pressure_precond", C.c_int), ("velocity_mode", C.c_int)]
 
 
 class FlowInfo(C.Structure):

@@ -159,11 +159,11 @@ sfem_status sfem_flow_create(int device, void *stream, int p, int64_t nelem, con
     return bad(SFEM_E_ARG, "dt > 0 and nu >= 0 (finite) are required");
   if (opts->order < 1 || opts->order > 3) return bad(SFEM_E_ARG, "order must be 1, 2 or 3");
   if (!(opts->rtol > 0.0) || (opts->pressure_mode != 0 && opts->pressure_mode != 1) ||
-      opts->check_every < 1 || opts->maxit < 1 ||
+      (opts->velocity_mode != 0 && opts->velocity_mode != 1) || opts->check_every < 1 || opts->maxit < 1 ||
       (opts->pressure_precond != SFEM_PRECOND_JACOBI && opts->pressure_precond != SFEM_PRECOND_LOR &&
        opts->pressure_precond != SFEM_PRECOND_LOR32))
-    return bad(SFEM_E_ARG, "rtol > 0, pressure_mode 0 or 1, check_every >= 1, maxit >= 1 and a "
-                           "Jacobi or LOR pressure preconditioner are required");
+    return bad(SFEM_E_ARG, "rtol > 0, pressure_mode and velocity_mode 0 or 1, check_every >= 1, "
+                           "maxit >= 1 and a Jacobi or LOR pressure preconditioner are required");
   if (!ess_mask) return bad(SFEM_E_ARG, "ess_mask (the no-slip walls) must not be NULL");
   sfem_flow *f = new (std::nothrow) sfem_flow();
   if (!f) return bad(SFEM_E_NOMEM, "host allocation failed");
@@ -339,7 +339,7 @@ sfem_status sfem_flow_step(sfem_flow *f, const double *u, const double *frc, dou
   // start from the extrapolated velocity
   FHIP(f, hipMemcpyAsync(u_out, f->ustar, (size_t)3 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
   sfem_pcg_opts vo = po;
-  vo.mode = 0;
+  vo.mode = f->o.velocity_mode;
   vo.precond = SFEM_PRECOND_JACOBI;
   vo.nullspace = 0;
   vo.x0_zero = 0;

@@ -45,10 +45,13 @@ class ProjectionStepper:
     PCG) or 1 (FP32 inner solves in FP64 refinement) with pressure_precond PRECOND_JACOBI;
     pressure_precond PRECOND_LOR32 (the default) preconditions the pressure Poisson solve
     by the LOR multigrid V-cycle (Section 5.2) in FP32 arithmetic inside FP64 CG,
-    PRECOND_LOR by the same V-cycle in FP64."""
+    PRECOND_LOR by the same V-cycle in FP64.  velocity_mode 0 (FP64 PCG) or 1 (the default:
+    FP32 inner solves in FP64 refinement) for the three-member Jacobi-preconditioned
+    Helmholtz solve."""
 
     def __init__(self, elem_xyz, elem_dofs, ndof, p, ess, dt, nu, order=3, rtol=1e-10,
-                 pressure_mode=1, device=None, check_every=8, maxit=10000, pressure_precond=None):
+                 pressure_mode=1, device=None, check_every=8, maxit=10000, pressure_precond=None,
+                 velocity_mode=1):
         check_mesh_shapes(np.shape(elem_xyz), np.shape(elem_dofs), ndof, p, np.shape(ess))
         if not 1 <= int(order) <= 3:
             raise ValueError("order 1, 2 or 3")
@@ -65,8 +68,9 @@ class ProjectionStepper:
         essd = torch.as_tensor(np.asarray(ess)).to(dev).to(torch.uint8).contiguous()
         nelem = int(xyz.shape[0]) if xyz.ndim == 3 else 0
         self.pressure_precond = _lib.PRECOND_LOR32 if pressure_precond is None else int(pressure_precond)
+        self.velocity_mode = int(velocity_mode)
         opts = FlowOpts(self.dt, self.nu, self.rtol, self.order, self.pressure_mode, int(check_every),
-                        int(maxit), self.pressure_precond)
+                        int(maxit), self.pressure_precond, self.velocity_mode)
         h = C.c_void_p()
         with torch.cuda.device(dev):
             st = self._lib.sfem_flow_create(dev.index, C.c_void_p(torch.cuda.current_stream(dev).cuda_stream),

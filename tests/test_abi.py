@@ -66,7 +66,7 @@ def test_structs_match_header_layout():
     # int, int, int64, int64, int, int, int64, int64, int64
     assert C.sizeof(CtxInfo) == 56
     from paper_1910_03032_amd._lib import FlowOpts, FlowInfo
-    assert C.sizeof(FlowOpts) == 48  # 3 doubles, 5 ints (padded)
+    assert C.sizeof(FlowOpts) == 48  # 3 doubles, 6 ints
     assert C.sizeof(FlowInfo) == 136  # int (padded to 8), 4 sfem_pcg_info
     from paper_1910_03032_amd._lib import LorInfo
     assert C.sizeof(LorInfo) == 8 + 2 * 12 * 8 + 8 + 12 * 4

@@ -1,6 +1,7 @@
 """Host logic of the projection stepper (no GPU): the BDF/EXT weights the library derives
 from their exactness conditions (sfem_bdf_ext_weights, a host computation behind the C
-ABI) equal the oracle's table."""
+ABI) equal the oracle's table, and bad stepper options are rejected before any device
+work."""
 import numpy as np
 import pytest
 
@@ -28,3 +29,20 @@ def test_bdf_ext_weights_c_abi_rejects_bad_arguments():
     assert lib.sfem_bdf_ext_weights(0, b, a) == -1
     assert lib.sfem_bdf_ext_weights(4, b, a) == -1
     assert lib.sfem_bdf_ext_weights(2, None, a) == -1
+
+
+@pytest.mark.parametrize("field,value", [("order", 4), ("pressure_mode", 2), ("velocity_mode", 2),
+                                         ("check_every", 0), ("maxit", 0), ("pressure_precond", 1),
+                                         ("dt", 0.0), ("rtol", 0.0)])
+def test_flow_create_rejects_bad_options(field, value):
+    """The stepper's options are checked before any device work, so a bad option returns
+    SFEM_E_ARG with a message and no stepper (no GPU needed)."""
+    import ctypes as C
+    from paper_1910_03032_amd import _lib
+    lib = _lib.load()
+    o = _lib.FlowOpts(1e-3, 0.01, 1e-10, 3, 1, 8, 100, _lib.PRECOND_LOR32, 0)
+    setattr(o, field, value)
+    h = C.c_void_p(123)
+    st = lib.sfem_flow_create(0, None, 4, 1, None, None, 125, None, C.byref(o), C.byref(h))
+    assert st == -1 and h.value is None
+    assert lib.sfem_flow_last_error(None).decode()

@@ -113,17 +113,19 @@ def test_hydrostatic_step(ne, p):
     st.close()
 
 
-@pytest.mark.parametrize("p,mode,pre", [(2, 1, "jacobi"), (4, 1, "jacobi"), (4, 0, "jacobi"), (4, 0, "lor"),
-                                        (4, 0, "lor32")])
-def test_three_steps_vs_oracle(p, mode, pre):
+@pytest.mark.parametrize("p,mode,pre,vmode", [(2, 1, "jacobi", 0), (4, 1, "jacobi", 0), (4, 0, "jacobi", 0),
+                                              (4, 0, "lor", 0), (4, 0, "lor32", 0), (3, 0, "lor32", 1)])
+def test_three_steps_vs_oracle(p, mode, pre, vmode):
     """Orders 1, 2, 3 on a perturbed 3^3 mesh from a smooth velocity vanishing on the walls,
     with a forcing; both sides solve to 1e-12 (the oracle directly), so the difference is
     bounded by the solve tolerance times the conditioning (< 1e-8); the pressure solve
     preconditioned by Jacobi (FP64 or FP32 inner solves) or by the LOR V-cycle (FP64 or
-    FP32 arithmetic)."""
+    FP32 arithmetic); the velocity solve in FP64 or with FP32 inner solves in FP64
+    refinement (vmode 1)."""
     from paper_1910_03032_amd import PRECOND_JACOBI, PRECOND_LOR, PRECOND_LOR32, ProjectionStepper
     m = BoxMesh(3, p)
-    say(f"[flow] three steps p={p} ndof={m.ndof} pressure solve mode {mode} preconditioner {pre}")
+    say(f"[flow] three steps p={p} ndof={m.ndof} pressure solve mode {mode} preconditioner {pre}, "
+        f"velocity solve mode {vmode}")
     d = Discretization(m.elem_xyz, m.elem_dofs, m.ess, m.ndof, p, p + 2)
     x = node_coords(m, p)
     bump = (x * (1 - x)).prod(axis=1)  # 0 on the walls
@@ -135,7 +137,7 @@ def test_three_steps_vs_oracle(p, mode, pre):
     sg = ProjectionStepper(m.elem_xyz, m.elem_dofs, m.ndof, p, m.ess, dt=dt, nu=nu, order=3,
                            rtol=1e-12, pressure_mode=mode,
                            pressure_precond={"jacobi": PRECOND_JACOBI, "lor": PRECOND_LOR,
-                                             "lor32": PRECOND_LOR32}[pre])
+                                             "lor32": PRECOND_LOR32}[pre], velocity_mode=vmode)
     uo, ug = u.copy(), gpu(u)
     for n in range(3):
         uo, po = so.step(uo, f)
