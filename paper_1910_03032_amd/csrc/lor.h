@@ -27,7 +27,7 @@ inline const T *csr_vals(const DevCsr &A) {
   else return A.val32;
 }
 
-// Device copy of a level operator in sliced ELL form: rows in slices of kSellRows (one
+// Device copy of a matrix in sliced ELL form: rows in slices of kSellRows (one
 // wave); slice s holds len_s = (off[s+1] - off[s]) / kSellRows entries per row, stored
 // entry-major (entry k of the slice's row r at off[s] + k kSellRows + r), rows shorter
 // than len_s padded with (their last column, 0).  A thread per row then reads the values
