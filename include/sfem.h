@@ -366,10 +366,11 @@ sfem_status sfem_flow_set_stream(sfem_flow *flow, void *stream);
  *   N^n = -B^{-1} C(u^n) (the convection term, rows of wall DoFs 0);
  *   F* = sum_j a_j N^{n+1-j} - sum_j (b_j / dt) u^{n+1-j} + f^{n+1};
  *   u* = sum_j a_j u^{n+1-j};  L* = -nu B^{-1} curl_w(B^{-1} curl_w u*);
- *   K p = div_w(F* + L*) with int p = 0, by the orthogonalized pure-Neumann Jacobi-PCG
- *   (pressure_mode), from the previous step's pressure;
+ *   K p = div_w(F* + L*) with int p = 0, by the orthogonalized pure-Neumann CG
+ *   (pressure_precond, pressure_mode), from the previous step's pressure (an EXT
+ *   extrapolation of the previous pressures took more iterations on the 32^3 p = 4 runs);
  *   (b_0/dt) M u + nu K u = M F* - grad_w p on the free rows, u = 0 on the walls, by
- *   three-member Jacobi-PCG from u*.
+ *   three-member Jacobi-PCG (velocity_mode) from u*.
  * Writes u_out = u^{n+1} [3][ndof] and p_out = p^{n+1} [ndof] (device, not aliasing u) and
  * shifts the history; info (host, may be NULL) gets the order and the solves' outcomes.
  * Returns SFEM_NOCONV (the step is taken) if a solve reached maxit, negative on error.
