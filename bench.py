@@ -14,11 +14,12 @@ the same workload.  Prints one JSON line.
 
 Other workloads (`--workload`): vector_helmholtz_p7_24e, adjoint_p5_20e, large_p8_40e,
 stokes_32e (Taylor-Hood block operator apply, 32^3 hexes, p = 2..6), convection (the
-N(u) term, 32^3 p = 4 and 24^3 p = 7),
+N(u) term for p = 1..8 on 1.8-4.8M DoFs per component),
 poisson_p2_4e, `sweep` (FP64/FP32 apply for p = 4..8 on meshes of 15-33M DoFs),
 `mass_neumann` (collocated-mass-preconditioned mass solve and pure-Neumann Poisson solve),
-`projection_32e` (projection time steps) and `lor_p4_32e` (the LOR multigrid preconditioner
-against Jacobi).
+`projection_32e` (projection time steps), `lor_p4_32e` (the LOR multigrid preconditioner
+against Jacobi) and `lor_sweep` (the LOR-preconditioned pure-Neumann solve for p = 2..8 on
+~2.1M DoFs).
 """
 from __future__ import annotations
 
@@ -618,6 +619,41 @@ def run_lor(a):
     return out
 
 
+LOR_SWEEP = [(2, 64), (3, 43), (4, 32), (5, 26), (6, 21), (7, 18), (8, 16)]
+
+
+def run_lor_sweep(a):
+    """The LOR preconditioner across orders (Section 7.1's question: iterations against p
+    and h): the pure-Neumann Poisson problem to 1e-10 on ~2.1M-DoF meshes for p = 2..8,
+    CG preconditioned by the FP32 V-cycle against Jacobi; iterations, time and the host
+    set-up of the multigrid."""
+    import torch
+    from paper_1910_03032_amd import DIFFUSION, PRECOND_LOR32, Operator
+    from workloads import BoxMesh, uniform
+    rows = []
+    for p, ne in LOR_SWEEP:
+        m = BoxMesh(ne, p)
+        op = Operator(m.elem_xyz, m.elem_dofs, m.ndof, p, ess=np_zeros(m.ndof))
+        op.set_coeffs(0.0, 1.0, None)
+        info = op.lor_setup(DIFFUSION)
+        b = torch.as_tensor(uniform(m.ndof, seed=1), device="cuda")
+        row = {"p": p, "elements": f"{ne}^3", "ndof": m.ndof, "lor_levels": info["rows"],
+               "lor_setup_ms": round(info["setup_ms"], 1)}
+        for name, kw in (("lor_fp32_vcycle", {"precond": PRECOND_LOR32}), ("jacobi", {})):
+            op.pcg(b, op=DIFFUSION, rtol=1e-10, nullspace=True, check_every=16, maxit=20000, **kw)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, res = op.pcg(b, op=DIFFUSION, rtol=1e-10, nullspace=True, check_every=16, maxit=20000, **kw)
+            torch.cuda.synchronize()
+            row[name] = {"ms": round((time.perf_counter() - t) * 1e3, 2), "iters": res.iters[0],
+                         "true_rel_res": res.true_rel_res[0], "status": res.status}
+        log(f"[bench] lor sweep p={p} {ne}^3 ndof={m.ndof}: lor {row['lor_fp32_vcycle']}, "
+            f"jacobi {row['jacobi']}, setup {row['lor_setup_ms']} ms")
+        rows.append(row)
+        op.close()
+    return {"workload": "lor_sweep", "rows": rows}
+
+
 def np_zeros(n):
     import numpy as np
     return np.zeros(n, dtype=np.uint8)
@@ -864,6 +900,8 @@ def main():
         out = run_projection(a)
     elif a.workload == "lor_p4_32e":
         out = run_lor(a)
+    elif a.workload == "lor_sweep":
+        out = run_lor_sweep(a)
     else:
         wl = WORKLOADS[a.workload]
         if a.workload == "vector_helmholtz_p7_24e":
