@@ -68,16 +68,16 @@ def log(*a):
 KERNEL_SOURCES = ["apply_impl.h", "eo.h", "rules.h", "internal.h", "plan.h", "k_apply_f64.hip", "k_vec.hip"]
 MEASURED_TRAFFIC = {
     # profiles/helmholtz_apply_p4_32e_hbm_bytes.md (FP64 apply, both dispatches)
-    ("ab1a1ae25e734e25", "helmholtz_p4_32e"): 560959227,
+    ("f363edc1f93a0d49", "helmholtz_p4_32e"): 554255119,
     # profiles/vector_helmholtz_p7_24e_counters.md (three-member FP64 apply)
-    ("ab1a1ae25e734e25", "vector_helmholtz_p7_24e"): 1288703860,
+    ("f363edc1f93a0d49", "vector_helmholtz_p7_24e"): 1288642074,
 }
 # Executed floating-point operations of one apply (element kernel + assembly) from the
 # SQ_INSTS_VALU_FLOPS_FP64 / _FP32 counters (x 64 lanes), same keying as the traffic:
 # profiles/helmholtz_apply_p4_32e_counters.md, profiles/vector_helmholtz_p7_24e_counters.md.
 MEASURED_FLOPS = {
-    ("ab1a1ae25e734e25", "helmholtz_p4_32e"): {"fp64": 961714752, "fp32": 964111936},
-    ("ab1a1ae25e734e25", "vector_helmholtz_p7_24e"): {"fp64": 6564470208, "fp32": 6260121024},
+    ("f363edc1f93a0d49", "helmholtz_p4_32e"): {"fp64": 961714752, "fp32": 964111936},
+    ("f363edc1f93a0d49", "vector_helmholtz_p7_24e"): {"fp64": 6564470208, "fp32": 6260121024},
 }
 FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 vector
 

@@ -107,7 +107,7 @@ struct sfem_ctx {
   double alpha = 1.0, beta = 1.0;
   int nfield = 1;
   bool has_nu = false;
-  double *d_fold64 = nullptr;  // [nfield][nelem][7][q^3]
+  double *d_fold64 = nullptr;  // [nfield][nelem][7 q^3], slice-pair order (k_setup.hip: fold_kernel)
   float *d_fold32 = nullptr;
   double *d_nu64 = nullptr;    // [nfield][nelem][q^3]
   float *d_nu32 = nullptr;

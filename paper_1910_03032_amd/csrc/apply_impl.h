@@ -471,8 +471,11 @@ apply_kernel(const int32_t *__restrict__ map, const T *__restrict__ qd,
       if constexpr (OP == 0) {
         dst[0] = qe[qi];
       } else if constexpr (OP == 2) {
+        // the folded factors are stored by slice pair, then slice, then slot
+        const int pc = c <= Q - 1 - c ? c : Q - 1 - c;
+        const int base = (2 * pc + (c > Q - 1 - c ? 1 : 0)) * 7 * Q2 + t;
 #pragma unroll
-        for (int s = 0; s < 7; ++s) dst[s] = qe[s * Q3 + qi];
+        for (int s = 0; s < 7; ++s) dst[s] = qe[base + s * Q2];
       } else {
 #pragma unroll
         for (int s = 0; s < 6; ++s) dst[s] = qe[(s + 1) * Q3 + qi];

@@ -177,8 +177,12 @@ __global__ void qpoint_coords_kernel(GaussArg g, int q, const double *__restrict
   xq[2 * plane + o] = pos[2];
 }
 
-// fold[f][e][s][qi]: s = 0: alpha w|J|; s = 1..6: beta nu_f w|J| J^-1 J^-T
-__global__ void fold_kernel(int q3, const double *__restrict__ qd,
+// Folded Helmholtz factors, slot s = 0: alpha w|J|; s = 1..6: beta nu_f w|J| J^-1 J^-T, stored
+// per element in the order the element kernel reads them: slice pairs (c, q-1-c) in turn,
+// within a pair slice c then slice q-1-c (the middle slice of an odd q alone), within a
+// slice the 7 slots, each the q^2 points of the slice:
+//   fold[f][e][(2 min(c, q-1-c) + [c > q-1-c]) 7 q^2 + s q^2 + a + q b]   (point (a, b, c))
+__global__ void fold_kernel(int q, int q3, const double *__restrict__ qd,
                             const double *__restrict__ nu_user, int64_t nei, int nfield,
                             double alpha, double beta,
                             double *__restrict__ fold64, float *__restrict__ fold32,
@@ -192,11 +196,14 @@ __global__ void fold_kernel(int q3, const double *__restrict__ qd,
   const int qi = (int)(r - e * q3);
   const double nv = nu_user ? nu_user[f * per_field + r] : 1.0;
   const double *src = qd + e * (int64_t)(kQdSlots * q3) + qi;
-  const int64_t o = (f * nei + e) * (int64_t)(kQdSlots * q3) + qi;
+  const int q2 = q * q, c = qi / q2, t = qi - c * q2;
+  const int pc = c <= q - 1 - c ? c : q - 1 - c;
+  const int64_t o = (f * nei + e) * (int64_t)(kQdSlots * q3) +
+                    (int64_t)(2 * pc + (c > q - 1 - c ? 1 : 0)) * kQdSlots * q2 + t;
   for (int s = 0; s < kQdSlots; ++s) {
     const double v = (s == 0) ? alpha * src[0] : beta * nv * src[(int64_t)s * q3];
-    fold64[o + (int64_t)s * q3] = v;
-    fold32[o + (int64_t)s * q3] = (float)v;
+    fold64[o + (int64_t)s * q2] = v;
+    fold32[o + (int64_t)s * q2] = (float)v;
   }
   nu64[f * per_field + r] = nv;
   nu32[f * per_field + r] = (float)nv;
@@ -254,7 +261,7 @@ hipError_t launch_fold(int q, const double *qd, const double *nu_user, int64_t n
   const int q3 = q * q * q;
   const int64_t n = nei * (int64_t)q3 * nfield;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(fold_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s, q3, qd, nu_user,
+  hipLaunchKernelGGL(fold_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s, q, q3, qd, nu_user,
                      nei, nfield, alpha, beta, fold64, fold32, nu64, nu32);
   return hipGetLastError();
 }
