@@ -101,7 +101,7 @@ struct sfem_ctx {
   int pcompact = 0;
   int64_t pnentries = 0;           // pressure E-vector entries (element-ordered)
   AsmPlan pplan{};
-  double *d_cq = nullptr;          // [nelem][9][q^3] coupling factors w |J| J^{-T}
+  double *d_cq = nullptr;          // [nelem][9 q^3] coupling factors w |J| J^{-T}, slice-pair order
 
   // ---- coefficients
   double alpha = 1.0, beta = 1.0;

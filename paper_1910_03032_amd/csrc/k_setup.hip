@@ -131,7 +131,9 @@ __global__ void qdata_setup_kernel(GaussArg g, int q, const double *__restrict__
 }
 
 // Coupling factors of the Stokes blocks: C = w |J| J^{-T} = w adj(J)^T, slot 3c + d
-// holds C_cd = w adj(J)_dc.
+// holds C_cd = w adj(J)_dc; per element stored like the folded Helmholtz factors, in the
+// order of the kernels' xi_3 loops: slice pairs (k, q-1-k) in turn, within a pair the two
+// slices, within a slice the 9 slots of its q^2 points.
 __global__ void coupling_setup_kernel(GaussArg g, int q, const double *__restrict__ xyz,
                                       int64_t nei, double *__restrict__ cq) {
   const int64_t q3 = (int64_t)q * q * q;
@@ -154,9 +156,11 @@ __global__ void coupling_setup_kernel(GaussArg g, int q, const double *__restric
   A[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
   A[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
   A[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-  double *o = cq + e * (int64_t)(9 * q3) + qi;
+  const int q2 = q * q, t = qi - c * q2;
+  const int pc = c <= q - 1 - c ? c : q - 1 - c;
+  double *o = cq + e * (int64_t)(9 * q3) + (int64_t)(2 * pc + (c > q - 1 - c ? 1 : 0)) * 9 * q2 + t;
   for (int r = 0; r < 3; ++r)
-    for (int d = 0; d < 3; ++d) o[(3 * r + d) * q3] = w * A[d][r];
+    for (int d = 0; d < 3; ++d) o[(3 * r + d) * q2] = w * A[d][r];
 }
 
 __global__ void qpoint_coords_kernel(GaussArg g, int q, const double *__restrict__ xyz,

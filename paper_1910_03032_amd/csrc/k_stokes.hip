@@ -270,6 +270,14 @@ __device__ __forceinline__ void vel_entries(int t, const int32_t *emap, int32_t 
   __syncthreads();
 }
 
+// Offset of slot z at slice c (points a + q b follow) within an element's coupling
+// factors, stored by slice pair (c, q-1-c), then slice, then slot.
+template <int Q>
+__device__ __forceinline__ int cq_at(int c, int z) {
+  const int pc = c <= Q - 1 - c ? c : Q - 1 - c;
+  return ((2 * pc + (c > Q - 1 - c ? 1 : 0)) * 9 + z) * Q * Q;
+}
+
 template <int P>
 struct SDims {
   using D = Dims<P>;
@@ -313,8 +321,8 @@ __device__ __forceinline__ void emit_add_vel(const double *buf, int t, bool acti
 // Both coupling blocks in one pass over the elements, so that the coupling factors are
 // read once: G p added into the three velocity components (their E-vector for the shared
 // nodes, members at stride vestride; the sole DoFs of yv directly) and -D P u into the
-// pressure space (element-ordered E-vector Yp, sole DoFs of yp).  cq: [nelem][9][q^3],
-// slot 3c + d holds C_cd.
+// pressure space (element-ordered E-vector Yp, sole DoFs of yp).  cq: [nelem][9 q^3]
+// (cq_at order), slot 3c + d holds C_cd.
 template <int P, bool POS>
 __global__ void __launch_bounds__(Dims<P>::THREADS, SDims<P>::OCC)
 coupling_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ vpos, int vcompact,
@@ -382,11 +390,11 @@ coupling_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ vp
       ugb = eo::split(zg);
       ubg = eo::split(zx);
     }
-    const double *cr = ce + (int64_t)(3 * r) * Q3;
     double v[1][Q];
     // row r of C times grad_ref p (G) and times grad_ref u_r (D) at slice c
     auto point = [&](int c, double ux, double uy, double uz, double px, double py, double pz) {
-      const double c0 = cr[c * Q2], c1 = cr[Q3 + c * Q2], c2 = cr[2 * Q3 + c * Q2];
+      const double *cr = ce + cq_at<Q>(c, 3 * r);
+      const double c0 = cr[0], c1 = cr[Q2], c2 = cr[2 * Q2];
       v[0][c] = c0 * px + c1 * py + c2 * pz;
       s[0][c] -= c0 * ux + c1 * uy + c2 * uz;
     };
@@ -560,10 +568,10 @@ __device__ __forceinline__ void phi_test_body(const int32_t *__restrict__ vmap,
   // the three outputs at the points of the line
   double n[3][Q];
   auto point = [&](int c, const double (&uv)[NIN], const double (&g)[NIN][3]) {
-    const double *cp = ce + c * Q2;
+    const double *cp = ce + cq_at<Q>(c, 0);
     double cm[9];
 #pragma unroll
-    for (int z = 0; z < 9; ++z) cm[z] = cp[z * Q3];
+    for (int z = 0; z < 9; ++z) cm[z] = cp[z * Q2];
     // Gamma_dr = (C grad_ref u_r)_d
     auto gam = [&](int d, int r) {
       return cm[3 * d] * g[r][0] + cm[3 * d + 1] * g[r][1] + cm[3 * d + 2] * g[r][2];
@@ -768,10 +776,10 @@ weak_div_kernel(const int32_t *__restrict__ vmap, const int32_t *__restrict__ vp
   const double *ce = cq + (int64_t)es * (9 * Q3) + t0;
   double h[3][Q];  // (C^T V)_k at the points of the line
   auto point = [&](int c, const double (&vv)[3]) {
-    const double *cp = ce + c * Q2;
+    const double *cp = ce + cq_at<Q>(c, 0);
     double cm[9];
 #pragma unroll
-    for (int z = 0; z < 9; ++z) cm[z] = cp[z * Q3];
+    for (int z = 0; z < 9; ++z) cm[z] = cp[z * Q2];
 #pragma unroll
     for (int k = 0; k < 3; ++k) h[k][c] = cm[k] * vv[0] + cm[3 + k] * vv[1] + cm[6 + k] * vv[2];
   };
