@@ -739,7 +739,7 @@ sfem_status run_pcg_lor(sfem_ctx *c, int op, bool f32, const double *b, double *
   }
   if ((st = lor_precond(c, op, f32, r, z, nullspace, part)) != SFEM_OK) return st;
   HIPCHK(c, hipMemcpyAsync(pv, z, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
-  HIPCHK(c, launch_gpcg_dots(r, z, b, part, nblk, n, s));
+  HIPCHK(c, launch_gpcg_dots<double>(r, z, b, 0, part, nblk, n, s));
   HIPCHK(c, launch_pcg_init(part, nblk, 1, rtol, sc, s));
   HIPCHK(c, hipMemcpyAsync(h, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
@@ -759,14 +759,25 @@ sfem_status run_pcg_lor(sfem_ctx *c, int op, bool f32, const double *b, double *
         if (d) (void)hipEventDestroy(d);
       return fail(c, SFEM_E_HIP, "LOR CG: event creation failed");
     }
+  // in the loop the V-cycle's FP32 input comes from the update and its output is read by
+  // the dots and the new direction as it is; the null-space shift is folded into those
+  float *r32 = f32 ? c->lor_work32 : nullptr, *z32 = f32 ? c->lor_work32 + n : nullptr;
   auto body = [&]() -> sfem_status {
     int cur = 0, last = -1;
     for (int it = 0; it < maxit; ++it) {
       if ((st = do_apply(c, op, false, 1, pv, w, dpart)) != SFEM_OK) return st;
-      HIPCHK(c, launch_gpcg_update(x, pv, r, w, sc + cur, dp, dcount, n, s));
-      if ((st = lor_precond(c, op, f32, r, z, nullspace, part)) != SFEM_OK) return st;
-      HIPCHK(c, launch_gpcg_dots(r, z, nullptr, part, nblk, n, s));
-      HIPCHK(c, launch_gpcg_newdir(z, pv, sc + cur, sc + 1 - cur, dp, dcount, part, nblk, n, s));
+      HIPCHK(c, launch_gpcg_update(x, pv, r, w, r32, sc + cur, dp, dcount, n, s));
+      if (f32) {
+        HIPCHK(c, amg_vcycle<float>(c->lor[op], r32, z32, s));
+        HIPCHK(c, launch_gpcg_dots<float>(r, z32, nullptr, nullspace, part, nblk, n, s));
+        HIPCHK(c, launch_gpcg_newdir<float>(z32, pv, sc + cur, sc + 1 - cur, dp, dcount, part, nblk, nullspace,
+                                            n, s));
+      } else {
+        HIPCHK(c, amg_vcycle<double>(c->lor[op], r, z, s));
+        HIPCHK(c, launch_gpcg_dots<double>(r, z, nullptr, nullspace, part, nblk, n, s));
+        HIPCHK(c, launch_gpcg_newdir<double>(z, pv, sc + cur, sc + 1 - cur, dp, dcount, part, nblk, nullspace,
+                                             n, s));
+      }
       cur = 1 - cur;
       HIPCHK(c, hipMemcpyAsync(h + (it & 1), sc + cur, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
       HIPCHK(c, hipEventRecord(ev[it & 1], s));

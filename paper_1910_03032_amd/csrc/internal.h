@@ -195,19 +195,24 @@ hipError_t launch_zshift(T *v, const PcgScalars *sc, int64_t n, int nb, hipStrea
 // v[m][i] -= c[m] * scale (member-wise constant shift)
 hipError_t launch_shift(double *v, const double *c, double scale, int64_t n, int nb, hipStream_t s);
 hipError_t launch_reduce1(const double *part, int nblk, int nb, double *out, hipStream_t s);
-// CG around a preconditioner applied between the launches (one member, z given):
-//   update  x += alpha p, r -= alpha w (alpha from sc and the apply's partials dpart[0..dcount))
-//   dots    partials of r.z, r.r ([2][nblk]); with b != null of r.z, r.r, b.b, 0, 0 ([5][nblk],
-//           the input of launch_pcg_init)
-//   newdir  p = z + beta p; scalars of the next iteration to sc_next
-hipError_t launch_gpcg_update(double *x, const double *p, double *r, const double *w,
+// CG around a preconditioner applied between the launches (one member, z given in FP64
+// or FP32):
+//   update  x += alpha p, r -= alpha w (alpha from sc and the apply's partials dpart[0..dcount));
+//           r32 != null: also r32 = (float) r
+//   dots    partials of r.z, r.r ([2][nblk]); nullspace: also sum z, sum r ([4][nblk]); with
+//           b != null of r.z, r.r, b.b, 0, 0 ([5][nblk], the input of launch_pcg_init)
+//   newdir  p = (z - zs) + beta p with zs = mean(z) when nullspace (else 0); scalars of the
+//           next iteration to sc_next
+hipError_t launch_gpcg_update(double *x, const double *p, double *r, const double *w, float *r32,
                               const PcgScalars *sc, const double *dpart, int dcount, int64_t n,
                               hipStream_t s);
-hipError_t launch_gpcg_dots(const double *r, const double *z, const double *b, double *part, int nblk,
-                            int64_t n, hipStream_t s);
-hipError_t launch_gpcg_newdir(const double *z, double *p, const PcgScalars *sc, PcgScalars *sc_next,
-                              const double *dpart, int dcount, const double *upart, int unblk, int64_t n,
-                              hipStream_t s);
+template <typename TZ>
+hipError_t launch_gpcg_dots(const double *r, const TZ *z, const double *b, int nullspace, double *part,
+                            int nblk, int64_t n, hipStream_t s);
+template <typename TZ>
+hipError_t launch_gpcg_newdir(const TZ *z, double *p, const PcgScalars *sc, PcgScalars *sc_next,
+                              const double *dpart, int dcount, const double *upart, int unblk,
+                              int nullspace, int64_t n, hipStream_t s);
 hipError_t launch_ir_norm(const double *part, int nblk, int nb, int set_bb, double rtol, double *ir,
                           hipStream_t s);
 hipError_t launch_ir_cast(const double *r, const double *ir, float *r32, int64_t n, int nb,

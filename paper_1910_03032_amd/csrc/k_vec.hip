@@ -238,55 +238,70 @@ __global__ void newdir_kernel(const T *__restrict__ r, const T *__restrict__ din
 // sums, as in the Jacobi CG, so that the host only reads the scalars to stop.
 
 // x += alpha p; r -= alpha w, alpha formed by every block from the scalars and the apply's
-// partials of p.Ap.
+// partials of p.Ap; with r32 also r32 = (float) r (the input of an FP32 preconditioner).
 __global__ void gpcg_update_kernel(double *__restrict__ x, const double *__restrict__ p,
                                    double *__restrict__ r, const double *__restrict__ w,
-                                   const PcgScalars *__restrict__ sc, const double *__restrict__ dpart,
-                                   int dcount, int64_t n) {
+                                   float *__restrict__ r32, const PcgScalars *__restrict__ sc,
+                                   const double *__restrict__ dpart, int dcount, int64_t n) {
   double pw[1];
   reduce_parts_m<1, VB>(dpart, dcount, 0, pw);
   const double alpha = step_alpha(sc[0], pw[0]);
   for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
     x[i] += alpha * p[i];
-    r[i] -= alpha * w[i];
+    const double ri = r[i] - alpha * w[i];
+    r[i] = ri;
+    if (r32) r32[i] = (float)ri;
   }
 }
 
-// Partials of r.z and r.r; with b also of b.b and two zeros (the five quantities the
-// scalar initialization reads).
-template <int NV>
-__global__ void gpcg_dots_kernel(const double *__restrict__ r, const double *__restrict__ z,
+// Partials of r.z and r.r, then by NV: 4, sum z and sum r (for the null-space shift);
+// 5, b.b and two zeros (the five quantities the scalar initialization reads).
+template <int NV, typename TZ>
+__global__ void gpcg_dots_kernel(const double *__restrict__ r, const TZ *__restrict__ z,
                                  const double *__restrict__ b, double *__restrict__ part, int nblk,
                                  int64_t n) {
   double v[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)nblk * VB) {
-    const double ri = r[i];
-    v[0] += ri * z[i];
+    const double ri = r[i], zi = (double)z[i];
+    v[0] += ri * zi;
     v[1] += ri * ri;
-    if constexpr (NV > 2) v[2] += b[i] * b[i];
+    if constexpr (NV == 4) {
+      v[2] += zi;
+      v[3] += ri;
+    }
+    if constexpr (NV == 5) v[2] += b[i] * b[i];
   }
   write_part<NV>(v, part, nblk);
 }
 
-// p = z + beta p, with alpha (for the failure state), beta and the stopping test formed by
-// every block from the scalars and the partials of p.Ap, r.z and r.r; block 0 writes the
-// next scalars to sc_next (double-buffered).
-__global__ void gpcg_newdir_kernel(const double *__restrict__ z, double *__restrict__ p,
+// p = (z - zs) + beta p, with alpha (for the failure state), beta and the stopping test
+// formed by every block from the scalars and the partials of p.Ap and of r.z, r.r (and,
+// with NS, sum z and sum r: zs = mean(z), the preconditioned residual orthogonalized
+// against the constants, whose r.(z - zs) = r.z - zs sum r); block 0 writes the next
+// scalars to sc_next (double-buffered).
+template <typename TZ, bool NS>
+__global__ void gpcg_newdir_kernel(const TZ *__restrict__ z, double *__restrict__ p,
                                    const PcgScalars *__restrict__ sc, PcgScalars *__restrict__ sc_next,
                                    const double *__restrict__ dpart, int dcount,
                                    const double *__restrict__ upart, int unblk, int64_t n) {
-  double pw[1], u[2];
+  constexpr int NU = NS ? 4 : 2;
+  double pw[1], u[NU];
   reduce_parts_m<1, VB>(dpart, dcount, 0, pw);
-  reduce_parts_m<2, VB>(upart, unblk, 0, u);
+  reduce_parts_m<NU, VB>(upart, unblk, 0, u);
   PcgScalars s = sc[0];
   set_alpha(s, pw[0]);
-  set_beta(s, u[0], u[1]);
+  double zs = 0.0, rz = u[0];
+  if constexpr (NS) {
+    zs = u[2] / (double)n;
+    rz = u[0] - zs * u[3];
+  }
+  set_beta(s, rz, u[1]);
   if (blockIdx.x == 0 && threadIdx.x == 0) sc_next[0] = s;
   const double beta = s.beta;
   for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB)
-    p[i] = z[i] + beta * p[i];
+    p[i] = ((double)z[i] - zs) + beta * p[i];
 }
 
 // r = b - w with partial r.r (w may be null: r = b); r may be null (norm only)
@@ -577,32 +592,50 @@ template hipError_t launch_assemble<float>(const AsmPlan &, const float *, int64
 template struct VecOps<double>;
 template struct VecOps<float>;
 
-hipError_t launch_gpcg_update(double *x, const double *p, double *r, const double *w,
+hipError_t launch_gpcg_update(double *x, const double *p, double *r, const double *w, float *r32,
                               const PcgScalars *sc, const double *dpart, int dcount, int64_t n,
                               hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gpcg_update_kernel, dim3(vec_nblk(n)), dim3(VB), 0, s, x, p, r, w, sc, dpart, dcount,
-                     n);
+  hipLaunchKernelGGL(gpcg_update_kernel, dim3(vec_nblk(n)), dim3(VB), 0, s, x, p, r, w, r32, sc, dpart,
+                     dcount, n);
   return hipGetLastError();
 }
 
-hipError_t launch_gpcg_dots(const double *r, const double *z, const double *b, double *part, int nblk,
-                            int64_t n, hipStream_t s) {
+template <typename TZ>
+hipError_t launch_gpcg_dots(const double *r, const TZ *z, const double *b, int nullspace, double *part,
+                            int nblk, int64_t n, hipStream_t s) {
   if (b)
-    hipLaunchKernelGGL((gpcg_dots_kernel<5>), dim3(nblk), dim3(VB), 0, s, r, z, b, part, nblk, n);
+    hipLaunchKernelGGL((gpcg_dots_kernel<5, TZ>), dim3(nblk), dim3(VB), 0, s, r, z, b, part, nblk, n);
+  else if (nullspace)
+    hipLaunchKernelGGL((gpcg_dots_kernel<4, TZ>), dim3(nblk), dim3(VB), 0, s, r, z, b, part, nblk, n);
   else
-    hipLaunchKernelGGL((gpcg_dots_kernel<2>), dim3(nblk), dim3(VB), 0, s, r, z, b, part, nblk, n);
+    hipLaunchKernelGGL((gpcg_dots_kernel<2, TZ>), dim3(nblk), dim3(VB), 0, s, r, z, b, part, nblk, n);
   return hipGetLastError();
 }
 
-hipError_t launch_gpcg_newdir(const double *z, double *p, const PcgScalars *sc, PcgScalars *sc_next,
-                              const double *dpart, int dcount, const double *upart, int unblk, int64_t n,
-                              hipStream_t s) {
+template <typename TZ>
+hipError_t launch_gpcg_newdir(const TZ *z, double *p, const PcgScalars *sc, PcgScalars *sc_next,
+                              const double *dpart, int dcount, const double *upart, int unblk,
+                              int nullspace, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gpcg_newdir_kernel, dim3(vec_nblk(n)), dim3(VB), 0, s, z, p, sc, sc_next, dpart, dcount,
-                     upart, unblk, n);
+  if (nullspace)
+    hipLaunchKernelGGL((gpcg_newdir_kernel<TZ, true>), dim3(vec_nblk(n)), dim3(VB), 0, s, z, p, sc, sc_next,
+                       dpart, dcount, upart, unblk, n);
+  else
+    hipLaunchKernelGGL((gpcg_newdir_kernel<TZ, false>), dim3(vec_nblk(n)), dim3(VB), 0, s, z, p, sc,
+                       sc_next, dpart, dcount, upart, unblk, n);
   return hipGetLastError();
 }
+template hipError_t launch_gpcg_dots<double>(const double *, const double *, const double *, int, double *,
+                                             int, int64_t, hipStream_t);
+template hipError_t launch_gpcg_dots<float>(const double *, const float *, const double *, int, double *,
+                                            int, int64_t, hipStream_t);
+template hipError_t launch_gpcg_newdir<double>(const double *, double *, const PcgScalars *, PcgScalars *,
+                                               const double *, int, const double *, int, int, int64_t,
+                                               hipStream_t);
+template hipError_t launch_gpcg_newdir<float>(const float *, double *, const PcgScalars *, PcgScalars *,
+                                              const double *, int, const double *, int, int, int64_t,
+                                              hipStream_t);
 
 hipError_t launch_sub_norm(const double *b, const double *w, double *r, double *part, int nblk,
                            int64_t n, int nb, hipStream_t s) {
