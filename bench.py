@@ -68,16 +68,16 @@ def log(*a):
 KERNEL_SOURCES = ["apply_impl.h", "eo.h", "rules.h", "internal.h", "plan.h", "k_apply_f64.hip", "k_vec.hip"]
 MEASURED_TRAFFIC = {
     # profiles/helmholtz_apply_p4_32e_hbm_bytes.md (FP64 apply, both dispatches)
-    ("3f29b064b0ef7d6c", "helmholtz_p4_32e"): 553369353,
+    ("a7986bae1c3cc88f", "helmholtz_p4_32e"): 553476720,
     # profiles/vector_helmholtz_p7_24e_counters.md (three-member FP64 apply)
-    ("3f29b064b0ef7d6c", "vector_helmholtz_p7_24e"): 1288642944,
+    ("a7986bae1c3cc88f", "vector_helmholtz_p7_24e"): 1288660473,
 }
 # Executed floating-point operations of one apply (element kernel + assembly) from the
 # SQ_INSTS_VALU_FLOPS_FP64 / _FP32 counters (x 64 lanes), same keying as the traffic:
 # profiles/helmholtz_apply_p4_32e_counters.md, profiles/vector_helmholtz_p7_24e_counters.md.
 MEASURED_FLOPS = {
-    ("3f29b064b0ef7d6c", "helmholtz_p4_32e"): {"fp64": 961714752, "fp32": 964111936},
-    ("3f29b064b0ef7d6c", "vector_helmholtz_p7_24e"): {"fp64": 6564470208, "fp32": 6260121024},
+    ("a7986bae1c3cc88f", "helmholtz_p4_32e"): {"fp64": 961714752, "fp32": 964111936},
+    ("a7986bae1c3cc88f", "vector_helmholtz_p7_24e"): {"fp64": 6564470208, "fp32": 6260121024},
 }
 FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 vector
 
