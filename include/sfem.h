@@ -178,7 +178,9 @@ typedef struct {
   int32_t sliced[SFEM_LOR_MAX_LEVELS]; /* device storage per level: bit 0 the operator, bit 1
                                           the prolongator, bit 2 the restriction in sliced
                                           ELL (64-row slices), else CSR (the coarsest
-                                          level: a dense inverse) */
+                                          level: a dense inverse); bit 3: slices of the
+                                          operator whose rows share their column offsets
+                                          store those once instead of column indices */
 } sfem_lor_info;
 sfem_status sfem_lor_setup(sfem_ctx *ctx, int op, sfem_lor_info *info);
 sfem_status sfem_lor_apply(sfem_ctx *ctx, int op, const double *x, double *y);

@@ -1,12 +1,12 @@
 // Kernels of the LOR multigrid V-cycle: products with the level operators and the
-// prolongators in sliced ELL form (a thread per row), with the residual and the
-// damped-Jacobi update fused in; products with the restrictions (long rows) in CSR form
-// with a group of LPR lanes per row (the lanes read consecutive entries of the row, so a
-// wave's loads of values and column indices are contiguous; a fixed shuffle tree sums the
-// group, so results are reproducible; LPR is picked from the average row length); the
-// dense coarsest-level product.  The V-cycle kernels exist in FP64 and in FP32 (values
-// and vectors of one type T; the FP32 V-cycle reads half the bytes and serves as a
-// preconditioner inside FP64 CG).
+// prolongators in sliced ELL form (a thread per row; explicit columns or a column-offset
+// pattern per slice), with the residual and the damped-Jacobi update fused in; products
+// with the restrictions (long rows) in CSR form with a group of LPR lanes per row (the
+// lanes read consecutive entries of the row, so a wave's loads of values and column
+// indices are contiguous; a fixed shuffle tree sums the group, so results are
+// reproducible; LPR is picked from the average row length); the dense coarsest-level
+// product.  The V-cycle kernels exist in FP64 and in FP32 (values and vectors of one type
+// T; the FP32 V-cycle reads half the bytes and serves as a preconditioner inside FP64 CG).
 #include <hip/hip_runtime.h>
 
 #include "lor.h"
@@ -16,6 +16,7 @@ namespace sfem {
 namespace {
 
 constexpr int kRowBlock = 256;
+static_assert(kRowBlock % kSellRows == 0 && kSellRows == 64, "a wave per slice");
 
 enum CsrMode { kSpmv = 0, kSpmvAdd = 1, kResidual = 2, kJacobi = 3 };
 
@@ -45,24 +46,39 @@ csr_kernel(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
 }
 
 // The same products with the operator in sliced ELL form (DevSell): one thread per row,
-// the slice's entries read entry-major, so a wave's loads of values and column indices
-// are contiguous; the row's terms are summed in entry order.
+// the slice's values read entry-major, so a wave's loads of values (and explicit column
+// indices) are contiguous; in a slice with a column-offset pattern the wave reads the
+// pattern through scalar loads and forms the columns itself.  The row's terms are summed
+// in column order.
 template <int MODE, typename T>
 __global__ void __launch_bounds__(kRowBlock)
-sell_kernel(const int32_t *__restrict__ off, const int32_t *__restrict__ col, const T *__restrict__ val,
+sell_kernel(const int32_t *__restrict__ off, const int32_t *__restrict__ pinfo,
+            const int32_t *__restrict__ col, const int32_t *__restrict__ pat, const T *__restrict__ val,
             const T *__restrict__ x, const T *__restrict__ b, const T *__restrict__ dinv, T omega,
-            T *__restrict__ out, int64_t n) {
+            T *__restrict__ out, int64_t n, int64_t ncols) {
   const int64_t i = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
   if (i >= n) return;
-  const int64_t sl = i / kSellRows;
-  const int lane = (int)(i - sl * kSellRows);
+  // the wave's 64 rows form one slice (kRowBlock is a multiple of kSellRows)
+  const int sl = __builtin_amdgcn_readfirstlane((int)(i / kSellRows));
+  const int lane = (int)(i - (int64_t)sl * kSellRows);
   const int32_t k0 = off[sl];
   const int len = (off[sl + 1] - k0) / kSellRows;
-  const int32_t *c = col + k0 + lane;
+  const int32_t pi = pinfo[sl];
   const T *v = val + k0 + lane;
   T s = T(0);
+  if (pi >= 0) {
+    const int32_t *c = col + pi + lane;
 #pragma unroll 4
-  for (int k = 0; k < len; ++k) s += v[(int64_t)k * kSellRows] * x[c[(int64_t)k * kSellRows]];
+    for (int k = 0; k < len; ++k) s += v[(int64_t)k * kSellRows] * x[c[(int64_t)k * kSellRows]];
+  } else {
+    const int32_t *po = pat + (-1 - pi);
+#pragma unroll 4
+    for (int k = 0; k < len; ++k) {
+      int64_t c = i + po[k];
+      c = c < 0 ? 0 : (c >= ncols ? ncols - 1 : c);  // absent entries (value 0) of edge rows
+      s += v[(int64_t)k * kSellRows] * x[c];
+    }
+  }
   if constexpr (MODE == kSpmv) out[i] = s;
   else if constexpr (MODE == kSpmvAdd) out[i] += s;
   else if constexpr (MODE == kResidual) out[i] = b[i] - s;
@@ -143,8 +159,8 @@ hipError_t launch_sell(const DevSell &A, const T *x, const T *b, const T *dinv, 
   if (!val) return hipErrorInvalidValue;
   const int64_t nblk = (A.nrows + kRowBlock - 1) / kRowBlock;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((sell_kernel<MODE, T>), dim3((unsigned)nblk), dim3(kRowBlock), 0, s, A.off, A.col, val,
-                     x, b, dinv, omega, out, A.nrows);
+  hipLaunchKernelGGL((sell_kernel<MODE, T>), dim3((unsigned)nblk), dim3(kRowBlock), 0, s, A.off, A.pinfo,
+                     A.col, A.pat, val, x, b, dinv, omega, out, A.nrows, A.ncols);
   return hipGetLastError();
 }
 

@@ -37,43 +37,21 @@ std::string upload(Amg &amg, T **dst, const T *src, int64_t count) {
   return "";
 }
 
-// Sliced ELL copy of H (see DevSell).
-std::string upload_sell(Amg &amg, const HostCsr &H, DevSell &D) {
+// Sliced ELL copy of H (see DevSell), built on the host by sell_build.
+std::string upload_sell(Amg &amg, const HostCsr &H, DevSell &D, bool patterns) {
+  HostSell S;
+  std::string e = sell_build(H, patterns, S);
+  if (!e.empty()) return e;
   D.nrows = H.nrows;
   D.ncols = H.ncols;
   D.nnz = H.nnz();
-  const int64_t nsl = (H.nrows + kSellRows - 1) / kSellRows;
-  std::vector<int64_t> off((size_t)nsl + 1, 0);
-  for (int64_t s = 0; s < nsl; ++s) {
-    int64_t len = 0;
-    for (int64_t r = s * kSellRows; r < std::min(H.nrows, (s + 1) * kSellRows); ++r)
-      len = std::max(len, H.ptr[r + 1] - H.ptr[r]);
-    off[s + 1] = off[s] + len * kSellRows;
-  }
-  D.padded = off[nsl];
-  if (D.padded >= (int64_t)INT32_MAX) return "LOR multigrid: matrix too large (padded nnz >= 2^31)";
-  std::vector<int32_t> off32(off.begin(), off.end());
-  std::vector<int32_t> col((size_t)D.padded);
-  std::vector<double> val((size_t)D.padded, 0.0);
-  for (int64_t s = 0; s < nsl; ++s) {
-    const int64_t len = (off[s + 1] - off[s]) / kSellRows;
-    for (int64_t r = s * kSellRows; r < (s + 1) * kSellRows; ++r) {
-      const int64_t lane = r - s * kSellRows;
-      const int64_t b = r < H.nrows ? H.ptr[r] : 0, e = r < H.nrows ? H.ptr[r + 1] : 0;
-      // padding: the row's last column (a valid index near its others) with value 0
-      const int32_t last = e > b ? H.col[(size_t)(e - 1)] : 0;
-      for (int64_t k = 0; k < len; ++k) {
-        const size_t at = (size_t)(off[s] + k * kSellRows + lane);
-        const bool in = b + k < e;
-        col[at] = in ? H.col[(size_t)(b + k)] : last;
-        val[at] = in ? H.val[(size_t)(b + k)] : 0.0;
-      }
-    }
-  }
-  std::string e;
-  if (!(e = upload(amg, &D.off, off32.data(), (int64_t)off32.size())).empty()) return e;
-  if (!(e = upload(amg, &D.col, col.data(), D.padded)).empty()) return e;
-  return upload(amg, &D.val, val.data(), D.padded);
+  D.padded = (int64_t)S.val.size();
+  D.pattern_slices = S.pattern_slices;
+  if (!(e = upload(amg, &D.off, S.off.data(), (int64_t)S.off.size())).empty()) return e;
+  if (!(e = upload(amg, &D.pinfo, S.pinfo.data(), (int64_t)S.pinfo.size())).empty()) return e;
+  if (!(e = upload(amg, &D.col, S.col.data(), (int64_t)S.col.size())).empty()) return e;
+  if (!(e = upload(amg, &D.pat, S.pat.data(), (int64_t)S.pat.size())).empty()) return e;
+  return upload(amg, &D.val, S.val.data(), D.padded);
 }
 
 std::string upload_csr(Amg &amg, const HostCsr &H, DevCsr &D) {
@@ -90,7 +68,8 @@ std::string upload_csr(Amg &amg, const HostCsr &H, DevCsr &D) {
 
 // The form of H on the device: sliced ELL for at least 16384 rows of at most 48 entries
 // on average, padded by at most half (the level operators and prolongators of the fine
-// levels), CSR otherwise (the restrictions' long rows, the small coarse levels).
+// levels; column-offset patterns for the square operators), CSR otherwise (the
+// restrictions' long rows, the small coarse levels).
 std::string upload_mat(Amg &amg, const HostCsr &H, DevMat &D) {
   int64_t padded = 0;
   const int64_t nsl = (H.nrows + kSellRows - 1) / kSellRows;
@@ -101,7 +80,7 @@ std::string upload_mat(Amg &amg, const HostCsr &H, DevMat &D) {
     padded += len * kSellRows;
   }
   D.sell = H.nrows >= 16384 && H.nnz() <= 48 * H.nrows && 2 * padded <= 3 * H.nnz();
-  return D.sell ? upload_sell(amg, H, D.S) : upload_csr(amg, H, D.C);
+  return D.sell ? upload_sell(amg, H, D.S, H.nrows == H.ncols) : upload_csr(amg, H, D.C);
 }
 
 }  // namespace
@@ -145,7 +124,8 @@ std::string amg_setup(const HostCsr &A0, double theta, int64_t coarse_size, int 
     if (!(e = upload<double>(out, &v.d.t, nullptr, n)).empty()) return e;
   }
   for (const AmgLevel &v : out.lv)
-    out.sliced.push_back((v.A.sell ? 1 : 0) | (v.P.sell ? 2 : 0) | (v.R.sell ? 4 : 0));
+    out.sliced.push_back((v.A.sell ? 1 : 0) | (v.P.sell ? 2 : 0) | (v.R.sell ? 4 : 0) |
+                         (v.A.sell && v.A.S.pattern_slices > 0 ? 8 : 0));
   out.ncoarse = As.back().nrows;
   if (!(e = upload(out, &out.coarse, H.coarse.data(), (int64_t)H.coarse.size())).empty()) return e;
   out.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

@@ -28,14 +28,23 @@ inline const T *csr_vals(const DevCsr &A) {
 }
 
 // Device copy of a matrix in sliced ELL form: rows in slices of kSellRows (one
-// wave); slice s holds len_s = (off[s+1] - off[s]) / kSellRows entries per row, stored
-// entry-major (entry k of the slice's row r at off[s] + k kSellRows + r), rows shorter
-// than len_s padded with (their last column, 0).  A thread per row then reads the values
-// and column indices of its slice in contiguous runs.
-constexpr int kSellRows = 64;
+// wave); slice s holds len_s = (off[s+1] - off[s]) / kSellRows values per row, stored
+// entry-major (entry k of the slice's row r at off[s] + k kSellRows + r), so that a thread
+// per row reads the values of its slice in contiguous runs.  The columns of a slice come
+// in one of two forms (pinfo[s]):
+//   pinfo[s] >= 0: explicit, entry k of row r in column col[pinfo[s] + k kSellRows + r],
+//     rows shorter than len_s padded with (their last column, 0);
+//   pinfo[s] < 0: a column-offset pattern shared by the slice's rows, entry k of row i in
+//     column i + pat[-pinfo[s] - 1 + k] (clamped to [0, ncols)), value 0 where the row
+//     has no entry there.  The rows of a square operator on a structured numbering (the
+//     27-point couplings of a Q1 operator) share their offsets, so such slices read no
+//     column indices at all.
+// (kSellRows and the host-side construction, sell_build, are in lor_host.h.)
 struct DevSell {
-  int64_t nrows = 0, ncols = 0, nnz = 0, padded = 0;
-  int32_t *off = nullptr, *col = nullptr;  // off: [nslices + 1]
+  int64_t nrows = 0, ncols = 0, nnz = 0, padded = 0;  // padded: stored values
+  int64_t pattern_slices = 0;
+  int32_t *off = nullptr, *pinfo = nullptr;  // [nslices + 1], [nslices]
+  int32_t *col = nullptr, *pat = nullptr;    // explicit columns, offset patterns
   double *val = nullptr;
   float *val32 = nullptr;
 };
@@ -83,7 +92,8 @@ struct Amg {
   int64_t ncoarse = 0;
   int nu = 2;                  // Jacobi sweeps before and after the coarse correction
   std::vector<int64_t> rows, nnzs;
-  std::vector<int32_t> sliced;  // per level: bit 0 A, bit 1 P, bit 2 R in sliced ELL
+  std::vector<int32_t> sliced;  // per level: bit 0 A, bit 1 P, bit 2 R in sliced ELL,
+                               // bit 3 slices of A with a column-offset pattern
   std::vector<void *> bufs;    // every device allocation
   double setup_ms = 0.0;
 };

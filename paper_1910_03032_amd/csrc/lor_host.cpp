@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -349,6 +350,114 @@ void lor_assemble(int p, const double *gll, int64_t nelem, const double *xyz, co
 }
 
 void csr_transpose(const HostCsr &A, HostCsr &T) { transpose(A, T); }
+
+namespace {
+
+// Column offsets (col - row) of the rows of slice s of H, sorted and unique.  Fast path:
+// when every row's offsets are among those of the slice's longest row (rows are sorted,
+// so a merge per row checks it), that row's offsets are the union.
+std::vector<int32_t> slice_offsets(const HostCsr &H, int64_t s) {
+  const int64_t r0 = s * kSellRows, r1 = std::min(H.nrows, (s + 1) * kSellRows);
+  int64_t longest = r0;
+  for (int64_t r = r0; r < r1; ++r)
+    if (H.ptr[(size_t)r + 1] - H.ptr[(size_t)r] > H.ptr[(size_t)longest + 1] - H.ptr[(size_t)longest]) longest = r;
+  std::vector<int32_t> u;
+  for (int64_t k = H.ptr[(size_t)longest]; k < H.ptr[(size_t)longest + 1]; ++k)
+    u.push_back((int32_t)(H.col[(size_t)k] - longest));
+  bool subset = true;
+  for (int64_t r = r0; r < r1 && subset; ++r) {
+    size_t j = 0;
+    for (int64_t k = H.ptr[(size_t)r]; k < H.ptr[(size_t)r + 1] && subset; ++k) {
+      const int32_t o = (int32_t)(H.col[(size_t)k] - r);
+      while (j < u.size() && u[j] < o) ++j;
+      subset = j < u.size() && u[j] == o;
+    }
+  }
+  if (subset) return u;
+  u.clear();
+  for (int64_t r = r0; r < r1; ++r)
+    for (int64_t k = H.ptr[(size_t)r]; k < H.ptr[(size_t)r + 1]; ++k)
+      u.push_back((int32_t)(H.col[(size_t)k] - r));
+  std::sort(u.begin(), u.end());
+  u.erase(std::unique(u.begin(), u.end()), u.end());
+  return u;
+}
+
+}  // namespace
+
+std::string sell_build(const HostCsr &H, bool patterns, HostSell &S) {
+  S = HostSell{};
+  S.nrows = H.nrows;
+  S.ncols = H.ncols;
+  patterns = patterns && H.nrows == H.ncols;
+  const int64_t nsl = (H.nrows + kSellRows - 1) / kSellRows;
+  std::vector<int64_t> off((size_t)nsl + 1, 0), len((size_t)nsl, 0);
+  S.pinfo.assign((size_t)nsl, 0);
+  std::vector<std::vector<int32_t>> sofs((size_t)nsl);
+  std::map<std::vector<int32_t>, int32_t> known;  // pattern -> its start in S.pat
+  int64_t ncol = 0;
+  for (int64_t s = 0; s < nsl; ++s) {
+    int64_t l = 0;
+    for (int64_t r = s * kSellRows; r < std::min(H.nrows, (s + 1) * kSellRows); ++r)
+      l = std::max(l, H.ptr[(size_t)r + 1] - H.ptr[(size_t)r]);
+    bool use_pat = false;
+    if (patterns && l > 0) {
+      sofs[(size_t)s] = slice_offsets(H, s);
+      use_pat = (int64_t)sofs[(size_t)s].size() <= l + l / 8;
+    }
+    if (use_pat) {
+      auto it = known.find(sofs[(size_t)s]);
+      if (it == known.end()) {
+        if ((int64_t)S.pat.size() + (int64_t)sofs[(size_t)s].size() >= (int64_t)INT32_MAX)
+          return "sliced ELL: too many column-offset patterns";
+        it = known.emplace(sofs[(size_t)s], (int32_t)S.pat.size()).first;
+        S.pat.insert(S.pat.end(), sofs[(size_t)s].begin(), sofs[(size_t)s].end());
+      }
+      S.pinfo[(size_t)s] = -1 - it->second;
+      len[(size_t)s] = (int64_t)sofs[(size_t)s].size();
+      ++S.pattern_slices;
+    } else {
+      sofs[(size_t)s].clear();
+      if (ncol + l * kSellRows >= (int64_t)INT32_MAX) return "sliced ELL: matrix too large (padded nnz >= 2^31)";
+      S.pinfo[(size_t)s] = (int32_t)ncol;
+      len[(size_t)s] = l;
+      ncol += l * kSellRows;
+    }
+    off[(size_t)s + 1] = off[(size_t)s] + len[(size_t)s] * kSellRows;
+    if (off[(size_t)s + 1] >= (int64_t)INT32_MAX) return "sliced ELL: matrix too large (padded nnz >= 2^31)";
+  }
+  S.off.assign(off.begin(), off.end());
+  S.col.assign((size_t)ncol, 0);
+  S.val.assign((size_t)off[(size_t)nsl], 0.0);
+  for (int64_t s = 0; s < nsl; ++s) {
+    const int64_t o = off[(size_t)s];
+    const int32_t pi = S.pinfo[(size_t)s];
+    const std::vector<int32_t> &u = sofs[(size_t)s];
+    for (int64_t r = s * kSellRows; r < (s + 1) * kSellRows; ++r) {
+      const int64_t lane = r - s * kSellRows;
+      const int64_t b = r < H.nrows ? H.ptr[(size_t)r] : 0, e = r < H.nrows ? H.ptr[(size_t)r + 1] : 0;
+      if (pi < 0) {
+        // each entry of the row at its offset's place in the pattern (both sorted)
+        size_t k = 0;
+        for (int64_t q = b; q < e; ++q) {
+          const int32_t d = (int32_t)(H.col[(size_t)q] - r);
+          while (u[k] != d) ++k;
+          S.val[(size_t)(o + (int64_t)k * kSellRows + lane)] = H.val[(size_t)q];
+        }
+        continue;
+      }
+      // padding: the row's last column (a valid index near its others) with value 0
+      const int32_t last = e > b ? H.col[(size_t)(e - 1)] : 0;
+      for (int64_t k = 0; k < len[(size_t)s]; ++k) {
+        const bool in = b + k < e;
+        S.col[(size_t)(pi + k * kSellRows + lane)] = in ? H.col[(size_t)(b + k)] : last;
+        S.val[(size_t)(o + k * kSellRows + lane)] = in ? H.val[(size_t)(b + k)] : 0.0;
+      }
+    }
+  }
+  return "";
+}
+
 
 std::string amg_build_host(const HostCsr &A0, double theta, int64_t coarse_size, int max_levels,
                            HostAmg &H) {

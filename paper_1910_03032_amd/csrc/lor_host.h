@@ -39,6 +39,20 @@ struct HostAmg {
 // T = A^T (sorted columns).
 void csr_transpose(const HostCsr &A, HostCsr &T);
 
+// Sliced ELL form of a matrix (rows in slices of kSellRows; see DevSell in lor.h for the
+// layout): value array, per-slice offsets and column forms, explicit columns, patterns.
+constexpr int kSellRows = 64;
+struct HostSell {
+  int64_t nrows = 0, ncols = 0, pattern_slices = 0;
+  std::vector<int32_t> off, pinfo, col, pat;
+  std::vector<double> val;
+};
+// Build S from H.  With patterns (square H only), a slice whose rows' column offsets
+// (col - row) number at most 1/8 more than its longest row stores that union of offsets
+// once (shared by every slice that has the same one) instead of a column index per entry.
+// Returns an empty string or an error message.
+std::string sell_build(const HostCsr &H, bool patterns, HostSell &S);
+
 // Smoothed-aggregation setup of A0 (strength threshold theta; stop at <= coarse_size
 // rows or max_levels levels).  Returns an empty string or an error message.
 std::string amg_build_host(const HostCsr &A0, double theta, int64_t coarse_size, int max_levels,

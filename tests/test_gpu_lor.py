@@ -29,6 +29,22 @@ def sliced_storage(M):
     return n >= 16384 and M.nnz <= 48 * n and 2 * padded <= 3 * M.nnz
 
 
+def pattern_slices(M):
+    """The library's pattern rule: slices of a square matrix whose rows' column offsets
+    (col - row) number at most 1/8 more than the slice's longest row."""
+    n = M.shape[0]
+    if M.shape[1] != n:
+        return 0
+    rl = np.diff(M.indptr)
+    offs = M.indices - np.repeat(np.arange(n), rl)
+    count = 0
+    for s in range((n + 63) // 64):
+        a, b = M.indptr[s * 64], M.indptr[min(n, (s + 1) * 64)]
+        ln = int(rl[s * 64:(s + 1) * 64].max())
+        count += ln > 0 and len(np.unique(offs[a:b])) <= ln + ln // 8
+    return count
+
+
 def expected_sliced(amg):
     L = len(amg.A)
     flags = []
@@ -36,6 +52,7 @@ def expected_sliced(amg):
         f = 0
         if l + 1 < L or l == 0:
             f |= 1 if sliced_storage(amg.A[l]) else 0
+            f |= 8 if (f & 1) and pattern_slices(amg.A[l]) > 0 else 0
         if l + 1 < L:
             f |= 2 if sliced_storage(amg.P[l]) else 0
             f |= 4 if sliced_storage(amg.P[l].T.tocsr()) else 0
@@ -59,8 +76,9 @@ CASES = {"poisson_3e_p4": (3, 4), "helmholtz_nu_3e_p3": (3, 3), "neumann_3e_p5":
                                   "poisson_8e_p4", "helmholtz_nu_7e_p4", "neumann_6e_p5"])
 def test_lor_apply_and_vcycle_vs_oracle(case):
     """The small meshes keep every matrix in CSR; from 16384 rows (8^3 and 7^3 at p = 4, 6^3
-    at p = 5) the finest operator is in sliced ELL, and the prolongator where its padding
-    stays within half (the reported storage matches the rule applied to the oracle's
+    at p = 5) the finest operator is in sliced ELL with shared column-offset patterns (the
+    box meshes' lexicographic numbering), and the prolongator where its padding stays
+    within half (the reported storage matches the rules applied to the oracle's
     hierarchy)."""
     from paper_1910_03032_amd import DIFFUSION, HELMHOLTZ
     if case == "fan_p3":
@@ -80,9 +98,9 @@ def test_lor_apply_and_vcycle_vs_oracle(case):
     amg = AMG(L, theta=THETA, coarse_size=COARSE, max_levels=MAXLEV, nu=NU)
     say(f"  levels {info['rows']} (oracle {[a.shape[0] for a in amg.A]}), setup {info['setup_ms']:.1f} ms")
     assert info["rows"] == [a.shape[0] for a in amg.A]
-    say(f"  storage per level (bit 0 operator, 1 prolongator, 2 restriction sliced): {info['sliced']}")
+    say(f"  storage per level (bit 0 operator, 1 prolongator, 2 restriction sliced, 3 patterns): {info['sliced']}")
     assert info["sliced"] == expected_sliced(amg)
-    assert (info["sliced"][0] & 1) == (1 if m.ndof >= 16384 else 0)
+    assert (info["sliced"][0] & 9) == (9 if m.ndof >= 16384 else 0)
     x = uniform(m.ndof, seed=5)
     assert rel(host(op.lor_apply(gpu(x), opk)), L @ x) <= 1e-13
     b = uniform(m.ndof, seed=6)

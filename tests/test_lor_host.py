@@ -2,7 +2,9 @@
 g++ and the address and undefined-behaviour sanitizers) against the oracle: the LOR matrix
 of Section 5.2 entry by entry, and the smoothed-aggregation hierarchy level by level (the
 same aggregates give the same level sizes; operators, prolongators, spectral-radius
-estimates and the coarse pseudo-inverse to rounding)."""
+estimates and the coarse pseudo-inverse to rounding).  The checker also requires the
+sliced ELL form of every level (explicit columns or shared column-offset patterns) to
+give the CSR product exactly."""
 import os
 import shutil
 import subprocess
@@ -74,7 +76,10 @@ def run_checker(exe, tmp_path, m, p, alpha, beta, nu_e):
     Ps = [csr() for _ in range(L - 1)]
     n = As[-1].shape[0]
     coarse = take(np.float64, n * n).reshape(n, n)
-    return As, rho, Ps, coarse
+    # sliced ELL check passed (else exit 3): pattern slices per level
+    pats = [(int(ln.split()[3]), int(ln.split()[5].rstrip(","))) for ln in r.stdout.splitlines()
+            if ln.startswith("pattern slices")]
+    return As, rho, Ps, coarse, pats
 
 
 def maxrel(a, b):
@@ -100,7 +105,13 @@ def test_lor_matrix_and_hierarchy_match_the_oracle(checker, tmp_path, case):
     mm = Mesh()
     mm.nelem, mm.ndof, mm.elem_xyz, mm.elem_dofs, mm.ess = m.nelem, m.ndof, m.elem_xyz, m.elem_dofs, ess
     nu_e = None if nu is None else element_mean_nu(d, nu)
-    As, rho, Ps, coarse = run_checker(checker, tmp_path, mm, p, alpha, beta, nu_e)
+    As, rho, Ps, coarse, pats = run_checker(checker, tmp_path, mm, p, alpha, beta, nu_e)
+    print(case, "pattern slices per level (of all slices):", pats)
+    # every level's sliced ELL product matched CSR (else the checker fails); on the box
+    # meshes' lexicographic numbering the fine operator's slices share column offsets
+    assert len(pats) == len(As)
+    if case != "fan_p3":
+        assert pats[0][0] >= 0.9 * pats[0][1], pats
     L_o = lor_matrix(d, alpha, beta, nu)
     assert maxrel(As[0], L_o) <= 1e-13
     assert np.diff(As[0].indptr).max() <= (27 if case != "fan_p3" else 64)
