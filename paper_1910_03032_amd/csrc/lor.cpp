@@ -203,9 +203,11 @@ hipError_t vcycle_level(const Amg &amg, size_t l, const T *b, T *x, hipStream_t 
   const LevelVecs<T> &w = v.vecs<T>();
   const T omega = (T)v.omega;
   hipError_t e;
-  // pre-smoothing from x = 0: the first sweep is omega D^-1 b
-  if ((e = launch_mat_jacobi<T>(v.A, w.dinv, omega, b, nullptr, x, s)) != hipSuccess) return e;
-  T *cur = x, *oth = w.t;
+  // pre-smoothing from x = 0: the first sweep is omega D^-1 b.  It goes to the work
+  // vector, so that after the 2 nu - 1 alternations between the two vectors the last
+  // post-smoothing sweep lands in x (x serves as scratch until then).
+  if ((e = launch_mat_jacobi<T>(v.A, w.dinv, omega, b, nullptr, w.t, s)) != hipSuccess) return e;
+  T *cur = w.t, *oth = x;
   for (int it = 1; it < amg.nu; ++it) {
     if ((e = launch_mat_jacobi<T>(v.A, w.dinv, omega, b, cur, oth, s)) != hipSuccess) return e;
     std::swap(cur, oth);
