@@ -414,6 +414,16 @@ def run_main(a, wl):
         torch.cuda.empty_cache()
         out["sweep_p4_8"] = run_sweep(a, steps=10, warmup=2)["rows"]
         out["vector_helmholtz_p7_24e"] = vector_apply_rates(a, WORKLOADS_VECTOR)
+        torch.cuda.empty_cache()
+        if not a.no_solves:
+            # the flow solver's timings in the same run: the pressure Poisson solve with the
+            # LOR preconditioner, and one projection time step with the stepper's defaults
+            from paper_1910_03032_amd import PRECOND_LOR32
+            from workloads import BoxMesh
+            out["lor_neumann_poisson_p4_32e"] = lor_poisson_row()
+            out["projection_step_p4_32e"] = projection_row(a, BoxMesh(32, 4), 32, 4,
+                                                           "lor_fp32_vcycle_velocity_ir",
+                                                           PRECOND_LOR32, 0, 1)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(m, p, wl["alpha"], wl["beta"], a.cpu_elements)
     return out
@@ -566,6 +576,43 @@ def run_mass_neumann(a):
     return out
 
 
+def timed_solve(op, b, opk, **kw):
+    """Best of two PCG solves to 1e-10 (wall time around the call, synchronized)."""
+    import torch
+    best, res = None, None
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, res = op.pcg(b, op=opk, rtol=1e-10, check_every=16, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        best = dt if best is None else min(best, dt)
+    return {"ms": round(best * 1e3, 2), "iters": res.iters, "true_rel_res": res.true_rel_res,
+            "status": res.status}
+
+
+def lor_poisson_row():
+    """The projection step's pressure solve alone: the pure-Neumann Poisson problem on
+    32^3 hexes at p = 4 to 1e-10, CG preconditioned by the LOR V-cycle in FP32 arithmetic
+    against Jacobi."""
+    import torch
+    from paper_1910_03032_amd import DIFFUSION, PRECOND_LOR32, Operator
+    from workloads import BoxMesh, uniform
+    m = BoxMesh(32, 4)
+    op = Operator(m.elem_xyz, m.elem_dofs, m.ndof, 4, ess=np_zeros(m.ndof))
+    op.set_coeffs(0.0, 1.0, None)
+    b = torch.as_tensor(uniform(m.ndof, seed=1), device="cuda")
+    info = op.lor_setup(DIFFUSION)
+    row = {"elements": "32^3", "p": 4, "ndof": m.ndof, "lor_levels": info["rows"],
+           "lor_setup_ms": round(info["setup_ms"], 1),
+           "pcg_lor_fp32_vcycle": timed_solve(op, b, DIFFUSION, precond=PRECOND_LOR32, nullspace=True),
+           "pcg_jacobi": timed_solve(op, b, DIFFUSION, nullspace=True)}
+    row["lor_speedup"] = round(row["pcg_jacobi"]["ms"] / row["pcg_lor_fp32_vcycle"]["ms"], 2)
+    log(f"[bench] lor neumann_poisson (default line): {row}")
+    op.close()
+    return row
+
+
 def run_lor(a):
     """The LOR preconditioner (Section 5.2) at 32^3, p = 4: host setup time and levels of
     the multigrid on A_LOR, the time of one V-cycle, and CG to 1e-10 preconditioned by it
@@ -577,18 +624,7 @@ def run_lor(a):
     m = BoxMesh(32, 4)
     out = {"workload": "lor_p4_32e", "p": 4, "elements": "32^3", "ndof": m.ndof}
 
-    def solve(op, b, opk, **kw):
-        best, res = None, None
-        for _ in range(2):
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            _, res = op.pcg(b, op=opk, rtol=1e-10, check_every=16, **kw)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t
-            best = dt if best is None else min(best, dt)
-        return {"ms": round(best * 1e3, 2), "iters": res.iters, "true_rel_res": res.true_rel_res,
-                "status": res.status}
-
+    solve = timed_solve
     for name, ess, opk in (("neumann_poisson", np_zeros(m.ndof), DIFFUSION), ("helmholtz", m.ess, HELMHOLTZ)):
         op = Operator(m.elem_xyz, m.elem_dofs, m.ndof, 4, ess=ess)
         if opk == HELMHOLTZ:
