@@ -294,7 +294,9 @@ class Operator:
 
     def lor_setup(self, op=HELMHOLTZ):
         """Build the LOR multigrid of operator kind op (Section 5.2); returns its level sizes
-        and the host setup time."""
+        and nonzeros, the host setup time and the device storage per level ("sliced": bit 0
+        the operator, bit 1 the prolongator, bit 2 the restriction in sliced ELL, bit 3
+        operator slices with a shared column-offset pattern)."""
         self._sync_stream()
         info = LorInfo()
         self._check(self._lib.sfem_lor_setup(self._h, op, C.byref(info)))
