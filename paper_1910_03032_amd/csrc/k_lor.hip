@@ -20,6 +20,20 @@ static_assert(kRowBlock % kSellRows == 0 && kSellRows == 64, "a wave per slice")
 
 enum CsrMode { kSpmv = 0, kSpmvAdd = 1, kResidual = 2, kJacobi = 3 };
 
+// Block index remapped so that each of the 8 XCDs (workgroups are dispatched to them in
+// turn) takes one contiguous range of the grid's blocks, i.e. of the rows: the rows of a
+// range gather their x values mostly from one region, which then stays in that XCD's L2
+// instead of being fetched from HBM by several XCDs.  A bijection of [0, gridDim.x).
+// Used by the CSR products (the restriction's gathers: 1.6x -> 1.0x the algorithmic
+// HBM bytes); the sliced ELL products keep the dispatch order, which is faster for them
+// although it fetches about 10 % more.
+__device__ __forceinline__ int64_t row_block() {
+  const unsigned nblk = gridDim.x, b = blockIdx.x;
+  const unsigned xcd = b & 7u, k = b >> 3;
+  const unsigned q8 = nblk >> 3, r8 = nblk & 7u;
+  return (int64_t)(xcd * q8 + (xcd < r8 ? xcd : r8) + k);
+}
+
 // y_i = (A x)_i combined per MODE:
 //   kSpmv      out = A x            kSpmvAdd  out += A x
 //   kResidual  out = b - A x        kJacobi   out = x + omega dinv (b - A x)
@@ -30,7 +44,7 @@ csr_kernel(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
            const T *__restrict__ dinv, T omega, T *__restrict__ out, int64_t n) {
   const int lane = threadIdx.x % LPR;
   const int64_t groups = (int64_t)gridDim.x * (kRowBlock / LPR);
-  for (int64_t i = ((int64_t)blockIdx.x * kRowBlock + threadIdx.x) / LPR; i < n; i += groups) {
+  for (int64_t i = (row_block() * kRowBlock + threadIdx.x) / LPR; i < n; i += groups) {
     T s = T(0);
     const int32_t k1 = ptr[i + 1];
     for (int32_t k = ptr[i] + lane; k < k1; k += LPR) s += val[k] * x[col[k]];
