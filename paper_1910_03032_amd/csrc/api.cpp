@@ -389,8 +389,10 @@ sfem_status ensure_cmass(sfem_ctx *c) {
   return SFEM_OK;
 }
 
+// (assemble = false: the element kernel only; y holds the sole DoFs and evec the shared
+// nodes' contributions, for a caller that adds more before assembling)
 sfem_status do_apply(sfem_ctx *c, int op, bool f32, int nbatch, const void *x, void *y,
-                     double *part = nullptr, void *evec = nullptr);
+                     double *part = nullptr, void *evec = nullptr, bool assemble = true);
 
 // m1 = M 1 and 1^T M 1 (geometry only), for the mean-zero condition int x = m1^T x.
 sfem_status ensure_m1(sfem_ctx *c, double *tmp_ones, double *tmp_part, double *tmp_out) {
@@ -443,7 +445,7 @@ int apply_final_count(const sfem_ctx *c, bool f32, int nb) {
 // evec: E-vector storage of at least nbatch * nentries values given by the caller, or
 // null for the context's own (grown on demand).
 sfem_status do_apply(sfem_ctx *c, int op, bool f32, int nbatch, const void *x, void *y,
-                     double *part, void *evec) {
+                     double *part, void *evec, bool assemble) {
   if (nbatch == 0 || c->ndof == 0) return SFEM_OK;
   const int64_t estride = c->nentries;
   const size_t esz = f32 ? sizeof(float) : sizeof(double);
@@ -486,6 +488,7 @@ sfem_status do_apply(sfem_ctx *c, int op, bool f32, int nbatch, const void *x, v
   }
   hipError_t e = f32 ? launch_apply_f32(a, c->stream) : launch_apply_f64(a, c->stream);
   if (e != hipSuccess) return fail(c, SFEM_E_HIP, std::string("apply launch: ") + hipGetErrorString(e));
+  if (!assemble) return SFEM_OK;
   double *pa = part ? part + nblk_e : nullptr;
   if (f32)
     e = launch_assemble<float>(c->plan, (const float *)evec, estride, (const float *)x, (float *)y,
@@ -1501,10 +1504,15 @@ sfem_status sfem_stokes_apply(sfem_ctx *c, const double *u, const double *pres, 
   // workspace: the pressure E-vector
   if ((st = ensure_ws(c, align_up((size_t)c->pnentries * sizeof(double)) + 256)) != SFEM_OK) return st;
   double *Yp = (double *)c->ws.p;
-  // y_u = H u (constrained: essential rows copy u)
-  if ((st = do_apply(c, SFEM_HELMHOLTZ, false, 3, u, yu)) != SFEM_OK) return st;
-  // y_u += P G p (essential rows untouched), y_p = -D P u
+  // y_u = H u + P G p (essential rows copy u), y_p = -D P u.  With the DoF-ordered
+  // E-vector the coupling kernel adds G p into the Helmholtz element kernel's output (sole
+  // DoFs of y_u, E-vector entries) and one assembly follows; with the element-ordered one
+  // H u is assembled first and G p goes through an E-vector of its own and an additive
+  // assembly.
+  const bool one_asm = evec_dof_ordered(c->p);
   if ((st = ensure_evec(c, (size_t)c->nentries * 3 * sizeof(double))) != SFEM_OK) return st;
+  if ((st = do_apply(c, SFEM_HELMHOLTZ, false, 3, u, yu, nullptr, c->evec.p, !one_asm)) != SFEM_OK)
+    return st;
   StokesArgs a{};
   a.p = c->p;
   a.nelem = c->nelem;
@@ -1523,8 +1531,8 @@ sfem_status sfem_stokes_apply(sfem_ctx *c, const double *u, const double *pres, 
   a.Yp = Yp;
   a.yp = yp;
   HIPCHK(c, launch_stokes(a, c->stream));
-  HIPCHK(c, launch_assemble<double>(c->plan, (const double *)c->evec.p, c->nentries, nullptr, yu, nv, 3,
-                                    kEssAdd, nullptr, 0, c->stream));
+  HIPCHK(c, launch_assemble<double>(c->plan, (const double *)c->evec.p, c->nentries, one_asm ? u : nullptr,
+                                    yu, nv, 3, one_asm ? kEssCopyX : kEssAdd, nullptr, 0, c->stream));
   HIPCHK(c, launch_assemble<double>(c->pplan, Yp, 0, nullptr, yp, np, 1, kEssZero, nullptr, 0,
                                     c->stream));
   return SFEM_OK;

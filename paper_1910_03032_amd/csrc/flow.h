@@ -10,9 +10,11 @@ namespace sfem {
 
 // Coupling blocks of the Taylor-Hood Stokes operator (velocity order p, pressure p - 1),
 // one pass over the elements: G p added into the velocity vector yv ([3][nv]; sole DoFs
-// directly, shared nodes into the velocity E-vector Yv, members at stride vestride, to be
-// assembled with kEssAdd) and -D P u into the pressure space (sole DoFs of yp, shared
-// nodes into the element-ordered pressure E-vector Yp).
+// directly, shared nodes through the velocity E-vector Yv, members at stride vestride:
+// with the DoF-ordered E-vector added into the entries of the Helmholtz element kernel's
+// output, assembled once with kEssCopyX, else stored and assembled with kEssAdd) and
+// -D P u into the pressure space (sole DoFs of yp, shared nodes into the element-ordered
+// pressure E-vector Yp).
 struct StokesArgs {
   int p;
   int64_t nelem;

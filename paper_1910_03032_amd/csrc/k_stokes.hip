@@ -292,9 +292,13 @@ struct SDims {
   static constexpr int OCC = P <= 7 ? 2 : 1;
 };
 
-// Output of a velocity element vector that adds into y: sole DoFs y[g] += v (each has
-// exactly one writer), shared nodes -> their E-vector entry (as the apply), essential ->
-// nothing.
+// Output of a velocity element vector that adds into an apply's output: sole DoFs
+// y[g] += v (each has exactly one writer), shared nodes -> their E-vector entry, essential
+// -> nothing.  With the DoF-ordered E-vector (POS) the value is added into the entry the
+// Helmholtz element kernel wrote, and one assembly sums both; with the element-ordered
+// one (p >= 5) it is stored into an E-vector of its own, assembled into y afterwards
+// (adding into the element-ordered entries measured 1-2 % slower than the second
+// assembly).
 template <int P, bool POS>
 __device__ __forceinline__ void emit_add_vel(const double *buf, int t, bool active,
                                              const int32_t *smap, int64_t e, bool compact,
@@ -311,7 +315,7 @@ __device__ __forceinline__ void emit_add_vel(const double *buf, int t, bool acti
     if (c & kSoleBit) {
       y[c & kDofMask] += v;
     } else if constexpr (POS) {
-      Y[c] = v;
+      Y[c] += v;
     } else {
       Y[compact ? e * surf_count<P>() + surf_rank<P>(l) : e * D::N3 + l] = v;
     }
@@ -319,9 +323,10 @@ __device__ __forceinline__ void emit_add_vel(const double *buf, int t, bool acti
 }
 
 // Both coupling blocks in one pass over the elements, so that the coupling factors are
-// read once: G p added into the three velocity components (their E-vector for the shared
-// nodes, members at stride vestride; the sole DoFs of yv directly) and -D P u into the
-// pressure space (element-ordered E-vector Yp, sole DoFs of yp).  cq: [nelem][9 q^3]
+// read once: G p added into the three velocity components (the sole DoFs of yv directly,
+// the shared nodes through the E-vector, members at stride vestride, as emit_add_vel
+// describes) and -D P u into the pressure space (element-ordered E-vector Yp, sole DoFs
+// of yp).  cq: [nelem][9 q^3]
 // (cq_at order), slot 3c + d holds C_cd.
 template <int P, bool POS>
 __global__ void __launch_bounds__(Dims<P>::THREADS, SDims<P>::OCC)
