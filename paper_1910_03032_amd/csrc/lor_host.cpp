@@ -1,11 +1,14 @@
 // Host side of the low-order-refined preconditioner (Section 5.2): assembly of A_LOR on the
 // GLL-refined mesh and the smoothed-aggregation multigrid setup (strength, aggregation,
-// Jacobi-smoothed prolongator, Galerkin products, coarse pseudo-inverse).  Plain C++ (no
-// device code), also compiled by the host tests.
+// Jacobi-smoothed prolongator, Galerkin products, coarse pseudo-inverse) and the sliced
+// ELL forms.  Plain C++ on the host threads (no device code), also compiled by the host
+// tests; the parallel parts combine their results in a fixed order.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <atomic>
 #include <map>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -14,6 +17,33 @@
 namespace sfem {
 
 namespace {
+
+// Host threads of the set-up (at most 16).
+int host_threads() {
+  const unsigned h = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(h, 16u));
+}
+
+// f(lo, hi, c) for the chunks [c chunk, min(n, (c + 1) chunk)) of [0, n), spread over the
+// host threads.  Results that f keeps per chunk and combines in chunk order do not depend
+// on the number of threads.
+template <class F>
+void for_chunks(int64_t n, int64_t chunk, F &&f) {
+  const int64_t nc = n > 0 ? (n + chunk - 1) / chunk : 0;
+  const int nt = (int)std::min<int64_t>(host_threads(), nc);
+  std::atomic<int64_t> next{0};
+  auto work = [&]() {
+    for (int64_t c = next++; c < nc; c = next++) f(c * chunk, std::min(n, (c + 1) * chunk), c);
+  };
+  if (nt <= 1) {
+    work();
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t) th.emplace_back(work);
+  work();
+  for (std::thread &t : th) t.join();
+}
 
 // Trilinear vertex functions and their reference derivatives at eta (vertex v = a + 2b + 4c
 // at corner (2a-1, 2b-1, 2c-1)).
@@ -74,38 +104,53 @@ int64_t find_col(const HostCsr &A, int64_t row, int32_t c) {
   return (it != e && *it == c) ? (int64_t)(it - A.col.data()) : -1;
 }
 
-// C = A B (both CSR with sorted columns); dense accumulator over B's columns.
+// C = A B (both CSR with sorted columns); dense accumulator over B's columns.  Rows in
+// chunks over the host threads, each chunk's rows kept apart and concatenated in order.
 void spgemm(const HostCsr &A, const HostCsr &B, HostCsr &C) {
   C.nrows = A.nrows;
   C.ncols = B.ncols;
   C.ptr.assign((size_t)C.nrows + 1, 0);
-  C.col.clear();
-  C.val.clear();
-  std::vector<int64_t> mark((size_t)B.ncols, -1);
-  std::vector<double> acc((size_t)B.ncols, 0.0);
-  std::vector<int32_t> cols;
-  for (int64_t i = 0; i < A.nrows; ++i) {
-    cols.clear();
-    for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
-      const int32_t j = A.col[k];
-      const double a = A.val[k];
-      for (int64_t m = B.ptr[j]; m < B.ptr[j + 1]; ++m) {
-        const int32_t c = B.col[m];
-        if (mark[c] != i) {
-          mark[c] = i;
-          acc[c] = 0.0;
-          cols.push_back(c);
+  constexpr int64_t kChunk = 8192;
+  const int64_t nc = (A.nrows + kChunk - 1) / kChunk;
+  std::vector<std::vector<int32_t>> ccol((size_t)nc);
+  std::vector<std::vector<double>> cval((size_t)nc);
+  for_chunks(A.nrows, kChunk, [&](int64_t lo, int64_t hi, int64_t ch) {
+    std::vector<int64_t> mark((size_t)B.ncols, -1);
+    std::vector<double> acc((size_t)B.ncols, 0.0);
+    std::vector<int32_t> cols;
+    std::vector<int32_t> &oc = ccol[(size_t)ch];
+    std::vector<double> &ov = cval[(size_t)ch];
+    for (int64_t i = lo; i < hi; ++i) {
+      cols.clear();
+      for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+        const int32_t j = A.col[k];
+        const double a = A.val[k];
+        for (int64_t m = B.ptr[j]; m < B.ptr[j + 1]; ++m) {
+          const int32_t c = B.col[m];
+          if (mark[c] != i) {
+            mark[c] = i;
+            acc[c] = 0.0;
+            cols.push_back(c);
+          }
+          acc[c] += a * B.val[m];
         }
-        acc[c] += a * B.val[m];
       }
+      std::sort(cols.begin(), cols.end());
+      for (int32_t c : cols) {
+        oc.push_back(c);
+        ov.push_back(acc[c]);
+      }
+      C.ptr[(size_t)i + 1] = (int64_t)cols.size();
     }
-    std::sort(cols.begin(), cols.end());
-    for (int32_t c : cols) {
-      C.col.push_back(c);
-      C.val.push_back(acc[c]);
-    }
-    C.ptr[i + 1] = (int64_t)C.col.size();
-  }
+  });
+  for (int64_t i = 0; i < C.nrows; ++i) C.ptr[(size_t)i + 1] += C.ptr[(size_t)i];
+  C.col.resize((size_t)C.ptr[(size_t)C.nrows]);
+  C.val.resize(C.col.size());
+  for_chunks(nc, 1, [&](int64_t ch, int64_t, int64_t) {
+    const int64_t at = C.ptr[(size_t)(ch * kChunk)];
+    std::copy(ccol[(size_t)ch].begin(), ccol[(size_t)ch].end(), C.col.begin() + at);
+    std::copy(cval[(size_t)ch].begin(), cval[(size_t)ch].end(), C.val.begin() + at);
+  });
 }
 
 void transpose(const HostCsr &A, HostCsr &T) {
@@ -131,14 +176,26 @@ double spectral_radius(const HostCsr &A, const std::vector<double> &dinv, int np
   std::vector<double> v((size_t)n), w((size_t)n);
   for (int64_t i = 0; i < n; ++i) v[i] = 1.0 + (double)(i % 7) / 7.0;
   double rho = 0.0;
+  constexpr int64_t kChunk = 16384;
+  const int64_t nc = (n + kChunk - 1) / kChunk;
+  std::vector<double> pv((size_t)nc), pw((size_t)nc);
   for (int it = 0; it < npower; ++it) {
+    for_chunks(n, kChunk, [&](int64_t lo, int64_t hi, int64_t ch) {
+      double sv = 0.0, sw = 0.0;
+      for (int64_t i = lo; i < hi; ++i) {
+        double s = 0.0;
+        for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) s += A.val[k] * v[A.col[k]];
+        w[i] = dinv[i] * s;
+        sv += v[i] * v[i];
+        sw += w[i] * w[i];
+      }
+      pv[(size_t)ch] = sv;
+      pw[(size_t)ch] = sw;
+    });
     double nv = 0.0, nw = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-      double s = 0.0;
-      for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) s += A.val[k] * v[A.col[k]];
-      w[i] = dinv[i] * s;
-      nv += v[i] * v[i];
-      nw += w[i] * w[i];
+    for (int64_t ch = 0; ch < nc; ++ch) {
+      nv += pv[(size_t)ch];
+      nw += pw[(size_t)ch];
     }
     rho = std::sqrt(nw) / std::sqrt(nv);
     const double inw = 1.0 / std::sqrt(nw);
@@ -299,23 +356,58 @@ void lor_assemble(int p, const double *gll, int64_t nelem, const double *xyz, co
     }
   A.nrows = A.ncols = ndof;
   A.ptr.assign((size_t)ndof + 1, 0);
-  A.col.clear();
-  for (int64_t g = 0; g < ndof; ++g) {
-    if (is_ess((int32_t)g) || cnt[g] == cnt[g + 1]) {
-      A.col.push_back((int32_t)g);  // essential (or unused) row: the diagonal alone
-    } else {
+  // each row's candidates sorted and made unique in place (rows over the host threads);
+  // an essential (or unused) row keeps the diagonal alone
+  constexpr int64_t kRows = 16384;
+  auto lone = [&](int64_t g) { return is_ess((int32_t)g) || cnt[g] == cnt[g + 1]; };
+  for_chunks(ndof, kRows, [&](int64_t lo, int64_t hi, int64_t) {
+    for (int64_t g = lo; g < hi; ++g) {
+      if (lone(g)) {
+        A.ptr[g + 1] = 1;
+        continue;
+      }
       auto b = cand.begin() + cnt[g], e = cand.begin() + cnt[g + 1];
       std::sort(b, e);
-      auto last = std::unique(b, e);
-      A.col.insert(A.col.end(), b, last);
+      A.ptr[g + 1] = (int64_t)(std::unique(b, e) - b);
     }
-    A.ptr[g + 1] = (int64_t)A.col.size();
-  }
+  });
+  for (int64_t g = 0; g < ndof; ++g) A.ptr[g + 1] += A.ptr[g];
+  A.col.resize((size_t)A.ptr[ndof]);
+  for_chunks(ndof, kRows, [&](int64_t lo, int64_t hi, int64_t) {
+    for (int64_t g = lo; g < hi; ++g) {
+      if (lone(g))
+        A.col[(size_t)A.ptr[g]] = (int32_t)g;
+      else
+        std::copy(cand.begin() + cnt[g], cand.begin() + cnt[g] + (A.ptr[g + 1] - A.ptr[g]),
+                  A.col.begin() + A.ptr[g]);
+    }
+  });
   std::vector<int32_t>().swap(cand);
   A.val.assign(A.col.size(), 0.0);
-  // values: element by element, sub-element by sub-element
-  const double *x1 = gll;
+  // values: element by element, sub-element by sub-element.  The elements are colored
+  // greedily in index order so that no two of one color share a DoF; the colors run one
+  // after another and the elements of a color over the host threads, so every entry gets
+  // its terms in one fixed order whatever the number of threads (a mesh that needs more
+  // than 32 colors runs its elements one after another).
+  std::vector<uint32_t> dmask((size_t)ndof, 0u);
+  std::vector<std::vector<int64_t>> byc;
   for (int64_t e = 0; e < nelem; ++e) {
+    uint32_t forb = 0;
+    for (int64_t l = 0; l < n3; ++l) forb |= dmask[(size_t)dofs[e * n3 + l]];
+    if (forb == 0xffffffffu) {
+      byc.assign(1, std::vector<int64_t>());
+      break;
+    }
+    int c = 0;
+    while (forb & (1u << c)) ++c;
+    for (int64_t l = 0; l < n3; ++l) dmask[(size_t)dofs[e * n3 + l]] |= 1u << c;
+    if ((int)byc.size() <= c) byc.resize((size_t)c + 1);
+    byc[(size_t)c].push_back(e);
+  }
+  const bool serial = byc.size() == 1 && (int64_t)byc[0].size() != nelem;
+  std::vector<uint32_t>().swap(dmask);
+  const double *x1 = gll;
+  auto element_values = [&](int64_t e) {
     const double *X = xyz + e * 24;
     const double nu = nu_e ? nu_e[e] : 1.0;
     for (int64_t s = 0; s < nsub; ++s) {
@@ -344,6 +436,14 @@ void lor_assemble(int p, const double *gll, int64_t nelem, const double *xyz, co
         }
       }
     }
+  };
+  if (serial) {
+    for (int64_t e = 0; e < nelem; ++e) element_values(e);
+  } else {
+    for (const std::vector<int64_t> &els : byc)
+      for_chunks((int64_t)els.size(), 64, [&](int64_t lo, int64_t hi, int64_t) {
+        for (int64_t i = lo; i < hi; ++i) element_values(els[(size_t)i]);
+      });
   }
   for (int64_t g = 0; g < ndof; ++g)
     if (is_ess((int32_t)g)) A.val[A.ptr[g]] = 1.0;  // constrained row: the identity

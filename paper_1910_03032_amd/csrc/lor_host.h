@@ -1,5 +1,7 @@
 // Host side of the low-order-refined preconditioner (Section 5.2): the sparse LOR matrix
-// and its smoothed-aggregation multigrid hierarchy (plain C++, no device code).
+// and its smoothed-aggregation multigrid hierarchy (plain C++ on the host threads, no
+// device code; every sum in a fixed order, so the results do not depend on the number of
+// threads).
 #pragma once
 
 #include <stdint.h>

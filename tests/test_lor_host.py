@@ -32,7 +32,7 @@ def checker(tmp_path_factory):
     if shutil.which("g++") is None:
         pytest.skip("g++ not available")
     exe = str(tmp_path_factory.mktemp("lor") / "lor_check")
-    r = subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-Wall", *SANITIZE, "-I", CSRC,
+    r = subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-Wall", "-pthread", *SANITIZE, "-I", CSRC,
                         os.path.join(ROOT, "tests", "lor_check.cpp"), os.path.join(CSRC, "lor_host.cpp"),
                         "-o", exe], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
