@@ -158,8 +158,9 @@ sfem_status sfem_apply_noalloc(sfem_ctx *ctx, int op, int prec, int nbatch, cons
  * smoothed-aggregation algebraic multigrid V-cycle (strength threshold 0.02, three-pass
  * aggregation, Jacobi-smoothed prolongator, Galerkin coarse operators down to <= 200 rows,
  * dense pseudo-inverse there, one damped-Jacobi sweep before and one after each coarse
- * correction): the setup runs on the host (the mesh copy kept by sfem_setup), every step
- * of the V-cycle on the GPU.  sfem_pcg with precond = SFEM_PRECOND_LOR builds it on first
+ * correction): the setup runs on the host (the mesh copy kept by sfem_setup; up to 16
+ * host threads, SFEM_HOST_THREADS in the environment sets their number, the result does
+ * not depend on it), every step of the V-cycle on the GPU.  sfem_pcg with precond = SFEM_PRECOND_LOR builds it on first
  * use; sfem_set_coeffs discards it.  One nu field only (SFEM_E_ARG otherwise).
  *   sfem_lor_setup   build it now; info (host, may be NULL) gets the level sizes
  *   sfem_lor_apply   y = A_LOR x  (device [ndof] float64)

@@ -5,6 +5,7 @@
 // tests; the parallel parts combine their results in a fixed order.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <atomic>
 #include <map>
@@ -18,8 +19,13 @@ namespace sfem {
 
 namespace {
 
-// Host threads of the set-up (at most 16).
+// Host threads of the set-up: SFEM_HOST_THREADS if set (1..16), else the hardware's, at
+// most 16.
 int host_threads() {
+  if (const char *env = std::getenv("SFEM_HOST_THREADS")) {
+    const int v = std::atoi(env);
+    if (v >= 1) return std::min(v, 16);
+  }
   const unsigned h = std::thread::hardware_concurrency();
   return (int)std::max(1u, std::min(h, 16u));
 }

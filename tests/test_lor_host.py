@@ -124,3 +124,27 @@ def test_lor_matrix_and_hierarchy_match_the_oracle(checker, tmp_path, case):
     for l in range(amg.levels - 1):
         assert maxrel(Ps[l], amg.P[l]) <= 1e-11, l
     assert np.abs(coarse - amg.coarse_inv).max() <= 1e-9 * np.abs(amg.coarse_inv).max()
+
+
+def test_setup_is_independent_of_the_thread_count(checker, tmp_path):
+    """The host set-up (threaded assembly over element colors, chunked products and power
+    iterations) gives the same bits on one thread and on several: a mesh with several row
+    chunks and element chunks per color, run with SFEM_HOST_THREADS = 1 and 4."""
+    m = BoxMesh(10, 4)
+    outs = []
+    for nt in ("1", "4"):
+        fin, fout = str(tmp_path / f"in{nt}.bin"), str(tmp_path / f"out{nt}.bin")
+        with open(fin, "wb") as f:
+            np.array([4, m.nelem, m.ndof, COARSE, MAXLEV], dtype=np.int64).tofile(f)
+            np.array([1e3, 1.0, THETA], dtype=np.float64).tofile(f)
+            np.array([0], dtype=np.int32).tofile(f)
+            gll(4)[0].astype(np.float64).tofile(f)
+            np.ascontiguousarray(m.elem_xyz, dtype=np.float64).tofile(f)
+            np.ascontiguousarray(m.elem_dofs, dtype=np.int32).tofile(f)
+            np.ascontiguousarray(m.ess, dtype=np.uint8).tofile(f)
+        env = dict(SANITIZE_ENV, SFEM_HOST_THREADS=nt)
+        r = subprocess.run([checker, fin, fout], capture_output=True, text=True, env=env)
+        assert r.returncode == 0 and "Sanitizer" not in r.stderr, r.stderr
+        outs.append(open(fout, "rb").read())
+    assert m.ndof > 4 * 16384  # several row chunks
+    assert outs[0] == outs[1]
